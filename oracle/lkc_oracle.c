@@ -1,0 +1,332 @@
+/*
+ * lkc_oracle.c -- plain FP64 CPU oracle for the nearest-points search and
+ * per-point covariance of the GICP registration step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference the GPU library is checked against.  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it; the product
+ * path never does.  It shares no code, header or constant with the HIP
+ * library.
+ *
+ * What it computes (paper, Sec. III-C.1 "Efficient registration method",
+ * Eqs. eq_trans_err .. eq_trans_likelihood and the paragraph after them):
+ * every point of a scan is modelled as a Gaussian N(p_i, C_i); C_i is
+ * estimated from the point's corresponding (nearest) points in the other
+ * cloud, and that nearest-points search plus covariance is the part the
+ * paper moves to the GPU.  The readings below fix what the paper leaves open:
+ *
+ *   kNN      D_j = sum over axes of (q - t_j)^2 in FP64 for every target j
+ *            (brute force).  Candidates with D_j <= r^2 are ordered by the
+ *            key (D_j, j) ascending -- the lower index wins an exact tie --
+ *            and the first min(k, #kept) are returned; idx is padded with -1
+ *            and d2 with +inf.  r = +inf means no cap.  A non-finite query
+ *            returns count 0.
+ *   mean/cov two-pass over the n = count returned neighbours:
+ *            mu = sum t_j / n,  C = sum (t_j - mu)(t_j - mu)^T / n
+ *            (maximum-likelihood 1/n normalisation); n = 0 gives mu = C = 0.
+ *   regular. GICP plane regularisation: eigen-decompose C (cyclic Jacobi),
+ *            v0 = unit eigenvector of the smallest eigenvalue, and
+ *            C_reg = V diag(1, 1, eps) V^T = I - (1 - eps) v0 v0^T with the
+ *            eigenvalues ordered descending; valid = (n >= 3), else C_reg = I.
+ *
+ * The k-smallest selection keeps a sorted buffer of the best k keys seen so
+ * far; this is the definition "sort all candidates by (D, j) and take the
+ * first k" evaluated without materialising the full sort.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- kNN --- */
+
+typedef struct {
+    const float *target;
+    int64_t n;
+    const float *queries;
+    int64_t q_begin, q_end;
+    int32_t k;
+    double r2;
+    int32_t *idx;
+    double *d2;
+    int32_t *count;
+} knn_job;
+
+static int key_less(double da, int64_t ia, double db, int64_t ib)
+{
+    return da < db || (da == db && ia < ib);
+}
+
+static void knn_one(const knn_job *jb, int64_t qi, double *bd, int64_t *bi)
+{
+    const float *qp = jb->queries + 3 * qi;
+    const double qx = qp[0], qy = qp[1], qz = qp[2];
+    const int32_t k = jb->k;
+    int32_t m = 0; /* entries held in the sorted buffer */
+    if (isfinite(qx) && isfinite(qy) && isfinite(qz)) {
+        for (int64_t j = 0; j < jb->n; ++j) {
+            const float *tp = jb->target + 3 * j;
+            const double dx = qx - (double)tp[0];
+            const double dy = qy - (double)tp[1];
+            const double dz = qz - (double)tp[2];
+            const double d = dx * dx + dy * dy + dz * dz;
+            if (!(d <= jb->r2))
+                continue;
+            if (m == k && !key_less(d, j, bd[k - 1], bi[k - 1]))
+                continue;
+            int32_t pos = (m < k) ? m : k - 1; /* slot freed at the end */
+            while (pos > 0 && key_less(d, j, bd[pos - 1], bi[pos - 1])) {
+                bd[pos] = bd[pos - 1];
+                bi[pos] = bi[pos - 1];
+                --pos;
+            }
+            bd[pos] = d;
+            bi[pos] = j;
+            if (m < k)
+                ++m;
+        }
+    }
+    for (int32_t s = 0; s < k; ++s) {
+        jb->idx[qi * k + s] = (s < m) ? (int32_t)bi[s] : -1;
+        jb->d2[qi * k + s] = (s < m) ? bd[s] : INFINITY;
+    }
+    jb->count[qi] = m;
+}
+
+static void *knn_worker(void *arg)
+{
+    knn_job *jb = (knn_job *)arg;
+    double *bd = (double *)malloc(sizeof(double) * (size_t)jb->k);
+    int64_t *bi = (int64_t *)malloc(sizeof(int64_t) * (size_t)jb->k);
+    for (int64_t qi = jb->q_begin; qi < jb->q_end; ++qi)
+        knn_one(jb, qi, bd, bi);
+    free(bd);
+    free(bi);
+    return NULL;
+}
+
+/* kNN by brute force.  target [n,3], queries [q,3] float32 row-major;
+ * outputs idx [q,k] int32, d2 [q,k] float64, count [q] int32.
+ * radius <= 0 or NaN is rejected (-1); radius = +inf means uncapped. */
+int oracle_knn(const float *target, int64_t n, const float *queries, int64_t q, int32_t k,
+               double radius, int32_t nthreads, int32_t *idx, double *d2, int32_t *count)
+{
+    if (k < 1 || n < 0 || q < 0 || !(radius > 0.0))
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((int64_t)nthreads > q)
+        nthreads = (int32_t)(q > 0 ? q : 1);
+    knn_job *jobs = (knn_job *)calloc((size_t)nthreads, sizeof(knn_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    const double r2 = isinf(radius) ? INFINITY : radius * radius;
+    for (int32_t t = 0; t < nthreads; ++t) {
+        knn_job *jb = &jobs[t];
+        jb->target = target;
+        jb->n = n;
+        jb->queries = queries;
+        jb->q_begin = q * t / nthreads;
+        jb->q_end = q * (t + 1) / nthreads;
+        jb->k = k;
+        jb->r2 = r2;
+        jb->idx = idx;
+        jb->d2 = d2;
+        jb->count = count;
+        pthread_create(&th[t], NULL, knn_worker, jb);
+    }
+    for (int32_t t = 0; t < nthreads; ++t)
+        pthread_join(th[t], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}
+
+/* ------------------------------------------------------ eigen (Jacobi) --- */
+
+/* Cyclic Jacobi for a symmetric 3x3 matrix (Golub & Van Loan, "Matrix
+ * Computations", Sec. 8.5: the 2x2 symmetric Schur step applied to each
+ * off-diagonal pair in turn until the off-diagonal mass vanishes).
+ * a: row-major 3x3 (only the symmetric part is read).  On return evals is
+ * ascending and column c of evecs (row-major, evecs[3*r + c]) is the unit
+ * eigenvector of evals[c]. */
+void oracle_sym3_eig(const double *a_in, double *evals, double *evecs)
+{
+    double a[3][3], v[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            a[r][c] = 0.5 * (a_in[3 * r + c] + a_in[3 * c + r]);
+            v[r][c] = (r == c) ? 1.0 : 0.0;
+        }
+    static const int P[3] = {0, 0, 1}, Q[3] = {1, 2, 2};
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off == 0.0 || off <= 1e-34 * dia)
+            break;
+        for (int e = 0; e < 3; ++e) {
+            const int p = P[e], q = Q[e];
+            if (a[p][q] == 0.0)
+                continue;
+            const double tau = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+            const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                          : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+            const double c = 1.0 / sqrt(1.0 + t * t);
+            const double s = t * c;
+            /* A <- J^T A J, J = identity except J[p][p]=c, J[p][q]=s,
+             * J[q][p]=-s, J[q][q]=c. */
+            for (int r = 0; r < 3; ++r) { /* A <- A J (columns p, q) */
+                const double arp = a[r][p], arq = a[r][q];
+                a[r][p] = c * arp - s * arq;
+                a[r][q] = s * arp + c * arq;
+            }
+            for (int cc = 0; cc < 3; ++cc) { /* A <- J^T A (rows p, q) */
+                const double apc = a[p][cc], aqc = a[q][cc];
+                a[p][cc] = c * apc - s * aqc;
+                a[q][cc] = s * apc + c * aqc;
+            }
+            a[p][q] = a[q][p] = 0.0;
+            for (int r = 0; r < 3; ++r) { /* V <- V J */
+                const double vrp = v[r][p], vrq = v[r][q];
+                v[r][p] = c * vrp - s * vrq;
+                v[r][q] = s * vrp + c * vrq;
+            }
+        }
+    }
+    int order[3] = {0, 1, 2};
+    for (int i = 0; i < 3; ++i) /* stable selection sort, ascending */
+        for (int j = i + 1; j < 3; ++j)
+            if (a[order[j]][order[j]] < a[order[i]][order[i]]) {
+                int tmp = order[i];
+                order[i] = order[j];
+                order[j] = tmp;
+            }
+    for (int c = 0; c < 3; ++c) {
+        evals[c] = a[order[c]][order[c]];
+        for (int r = 0; r < 3; ++r)
+            evecs[3 * r + c] = v[r][order[c]];
+    }
+}
+
+/* ---------------------------------------------------------- covariance --- */
+
+typedef struct {
+    const float *target;
+    int64_t n;
+    const int32_t *idx;
+    const int32_t *count;
+    int64_t q_begin, q_end;
+    int32_t k;
+    double eps;
+    double *mean, *cov, *reg, *evals, *evec0;
+    uint8_t *valid;
+    int bad;
+} cov_job;
+
+static void cov_one(cov_job *jb, int64_t qi)
+{
+    const int32_t n = jb->count[qi];
+    const int32_t *nb = jb->idx + qi * jb->k;
+    double mu[3] = {0.0, 0.0, 0.0};
+    double c[9] = {0.0};
+    if (n < 0 || n > jb->k) {
+        jb->bad = 1;
+        return;
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (nb[j] < 0 || nb[j] >= jb->n) {
+            jb->bad = 1;
+            return;
+        }
+    }
+    if (n > 0) {
+        for (int32_t j = 0; j < n; ++j)
+            for (int a = 0; a < 3; ++a)
+                mu[a] += (double)jb->target[3 * (int64_t)nb[j] + a];
+        for (int a = 0; a < 3; ++a)
+            mu[a] /= (double)n;
+        for (int32_t j = 0; j < n; ++j) {
+            double d[3];
+            for (int a = 0; a < 3; ++a)
+                d[a] = (double)jb->target[3 * (int64_t)nb[j] + a] - mu[a];
+            for (int r = 0; r < 3; ++r)
+                for (int cc = 0; cc < 3; ++cc)
+                    c[3 * r + cc] += d[r] * d[cc];
+        }
+        for (int e = 0; e < 9; ++e)
+            c[e] /= (double)n;
+    }
+    double ev[3], V[9];
+    oracle_sym3_eig(c, ev, V);
+    const int ok = (n >= 3);
+    for (int a = 0; a < 3; ++a)
+        jb->mean[3 * qi + a] = mu[a];
+    for (int e = 0; e < 9; ++e)
+        jb->cov[9 * qi + e] = c[e];
+    for (int r = 0; r < 3; ++r)
+        for (int cc = 0; cc < 3; ++cc) {
+            const double eye = (r == cc) ? 1.0 : 0.0;
+            jb->reg[9 * qi + 3 * r + cc] =
+                ok ? eye - (1.0 - jb->eps) * V[3 * r + 0] * V[3 * cc + 0] : eye;
+        }
+    jb->valid[qi] = (uint8_t)ok;
+    if (jb->evals)
+        for (int a = 0; a < 3; ++a)
+            jb->evals[3 * qi + a] = ev[a];
+    if (jb->evec0)
+        for (int a = 0; a < 3; ++a)
+            jb->evec0[3 * qi + a] = V[3 * a + 0];
+}
+
+static void *cov_worker(void *arg)
+{
+    cov_job *jb = (cov_job *)arg;
+    for (int64_t qi = jb->q_begin; qi < jb->q_end; ++qi)
+        cov_one(jb, qi);
+    return NULL;
+}
+
+/* Mean, covariance and regularised covariance of each query's neighbours.
+ * target [n,3] float32; idx [q,k], count [q] (the kNN output layout).
+ * Outputs (float64): mean [q,3], cov [q,9], reg [q,9]; valid [q] uint8;
+ * evals [q,3] ascending and evec0 [q,3] (smallest) are optional (NULL).
+ * Returns -1 on bad arguments or an out-of-range neighbour index. */
+int oracle_covariances(const float *target, int64_t n, const int32_t *idx, const int32_t *count,
+                       int64_t q, int32_t k, double eps, int32_t nthreads, double *mean,
+                       double *cov, double *reg, uint8_t *valid, double *evals, double *evec0)
+{
+    if (k < 1 || n < 0 || q < 0)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((int64_t)nthreads > q)
+        nthreads = (int32_t)(q > 0 ? q : 1);
+    cov_job *jobs = (cov_job *)calloc((size_t)nthreads, sizeof(cov_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int32_t t = 0; t < nthreads; ++t) {
+        cov_job *jb = &jobs[t];
+        jb->target = target;
+        jb->n = n;
+        jb->idx = idx;
+        jb->count = count;
+        jb->q_begin = q * t / nthreads;
+        jb->q_end = q * (t + 1) / nthreads;
+        jb->k = k;
+        jb->eps = eps;
+        jb->mean = mean;
+        jb->cov = cov;
+        jb->reg = reg;
+        jb->valid = valid;
+        jb->evals = evals;
+        jb->evec0 = evec0;
+        pthread_create(&th[t], NULL, cov_worker, jb);
+    }
+    int bad = 0;
+    for (int32_t t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], NULL);
+        bad |= jobs[t].bad;
+    }
+    free(jobs);
+    free(th);
+    return bad ? -1 : 0;
+}

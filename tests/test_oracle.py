@@ -1,0 +1,316 @@
+"""Pins for the FP64 CPU oracle (no GPU needed).
+
+The paper prints no worked example for the nearest-points search or the
+covariance step (Sec. III-C.1; its only CPU/GPU comparison is a figure with
+no numbers), so the oracle is pinned to what mathematics fixes instead:
+an independent exhaustive search written with plain Python loops, integer
+lattices with closed-form neighbour sets and covariances, library routines
+on tie-free data (``scipy.spatial.cKDTree``, ``numpy.cov``,
+``numpy.linalg.eigh``), and invariants.  Each check is chosen so that a
+plausible mistake in the oracle (a dropped coordinate term, the wrong
+tie-break, an exclusive radius, 1/(n-1) for 1/n, the largest instead of the
+smallest eigenvector, a transposed operand) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2308_07173_amd import workloads
+
+INF = float("inf")
+
+
+# ------------------------------------------------------------------ kNN ---
+
+def _exhaustive_python(target, queries, k, radius):
+    """Plain-Python brute force: sort (D, j) tuples, keep D <= r^2."""
+    out = []
+    r2 = radius * radius if radius != INF else INF
+    for q in queries.tolist():
+        if not all(math.isfinite(v) for v in q):
+            out.append(([], []))
+            continue
+        cand = []
+        for j, t in enumerate(target.tolist()):
+            dx, dy, dz = q[0] - t[0], q[1] - t[1], q[2] - t[2]
+            d = dx * dx + dy * dy + dz * dz
+            if d <= r2:
+                cand.append((d, j))
+        cand.sort()
+        cand = cand[:k]
+        out.append(([j for _, j in cand], [d for d, _ in cand]))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("radius", [INF, 0.7])
+def test_knn_matches_exhaustive_python(seed, radius):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 65))
+    target = workloads.random_cloud(n, seed, scale=1.0)
+    queries = workloads.random_cloud(17, seed + 100, scale=1.2)
+    # include exact duplicates of target points and of each other
+    queries[:3] = target[: min(3, n)][0]
+    k = int(rng.integers(1, 12))
+    idx, d2, cnt = oracle.knn(target, queries, k, radius)
+    ref = _exhaustive_python(target.astype(np.float64), queries.astype(np.float64), k, radius)
+    for i, (ji, di) in enumerate(ref):
+        assert cnt[i] == len(ji)
+        assert idx[i, : cnt[i]].tolist() == ji
+        assert np.array_equal(d2[i, : cnt[i]], np.array(di))
+        assert np.all(idx[i, cnt[i]:] == -1)
+        assert np.all(np.isinf(d2[i, cnt[i]:]))
+
+
+def test_knn_numpy_twin_agrees():
+    target = workloads.plane_wall(256, seed=7)
+    for radius in (INF, 0.5, 2.0):
+        a = oracle.knn(target, target, 10, radius)
+        b = oracle.knn_np(target, target, 10, radius)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_knn_1d_lattice_windows_and_tiebreak():
+    """t_i = (a i, 0, 0): the k nearest of lattice point i are a window.
+
+    k = 2m+1 gives {i-m .. i+m}; k = 2m gives {i-m .. i+m-1} because the two
+    points at distance m tie and the lower index wins; near the ends the
+    window shifts inwards.  d^2 = a^2 (j - i)^2 exactly.
+    """
+    n, a = 64, 1.0
+    lat = workloads.lattice_1d(n, a)
+    for k in range(1, 14):
+        idx, d2, cnt = oracle.knn(lat, lat, k)
+        for i in range(n):
+            m = k // 2
+            lo = i - m
+            hi = lo + k - 1
+            if lo < 0:
+                lo, hi = 0, k - 1
+            if hi > n - 1:
+                hi = n - 1
+                lo = n - k
+            expect = sorted(range(lo, hi + 1), key=lambda j: (abs(j - i), j))
+            assert idx[i].tolist() == expect, (k, i)
+            assert np.array_equal(d2[i], (a * (np.array(expect) - i)) ** 2)
+            assert cnt[i] == k
+
+
+def test_knn_2d_3d_lattice_ties_and_dropped_terms():
+    """Integer lattices: exact shells, lower index first within a shell.
+
+    A dropped y or z term in D would put off-axis points at distance 0 or
+    1 and change these sets.
+    """
+    for shape in [(9, 9), (5, 5, 5)]:
+        lat = workloads.lattice_nd(shape)
+        centre = np.array([s // 2 for s in shape] + [0] * (3 - len(shape)), np.float32)
+        ci = int(np.flatnonzero((lat == centre).all(axis=1))[0])
+        k = 1 + 2 * len(shape) + 2   # self, the whole unit shell, 2 of the sqrt2 shell
+        idx, d2, cnt = oracle.knn(lat, lat[ci:ci + 1], k)
+        d = ((lat.astype(np.float64) - centre) ** 2).sum(1)
+        order = np.lexsort((np.arange(lat.shape[0]), d))[:k]
+        assert idx[0].tolist() == order.tolist()
+        assert d2[0, 0] == 0 and np.all(d2[0, 1:1 + 2 * len(shape)] == 1.0)
+        assert np.all(d2[0, 1 + 2 * len(shape):] == 2.0)
+
+
+def test_knn_radius_is_inclusive_and_caps_count():
+    lat = workloads.lattice_1d(16, 1.0)
+    idx, d2, cnt = oracle.knn(lat, lat[8:9], 10, radius=2.0)
+    assert cnt[0] == 5                      # distances 0,1,1,2,2 (2 = r exactly kept)
+    assert idx[0, :5].tolist() == [8, 7, 9, 6, 10]
+    assert np.all(idx[0, 5:] == -1) and np.all(np.isinf(d2[0, 5:]))
+    idx, d2, cnt = oracle.knn(lat, lat[8:9], 10, radius=np.nextafter(2.0, 0.0))
+    assert cnt[0] == 3
+
+
+def test_knn_k_larger_than_n_and_nonfinite_query():
+    t = workloads.random_cloud(5, 3)
+    q = np.array([[0, 0, 0], [np.nan, 0, 0], [np.inf, 1, 1]], np.float32)
+    idx, d2, cnt = oracle.knn(t, q, 8)
+    assert cnt.tolist() == [5, 0, 0]
+    assert sorted(idx[0, :5].tolist()) == list(range(5))
+    assert np.all(idx[1:] == -1) and np.all(np.isinf(d2[1:]))
+
+
+def test_knn_empty_target():
+    t = np.zeros((0, 3), np.float32)
+    idx, d2, cnt = oracle.knn(t, workloads.random_cloud(4, 1), 3)
+    assert np.all(cnt == 0) and np.all(idx == -1)
+
+
+def test_knn_matches_ckdtree_on_tie_free_data():
+    scipy_spatial = pytest.importorskip("scipy.spatial")
+    target = workloads.random_cloud(3000, 11, scale=5.0)
+    queries = workloads.random_cloud(500, 12, scale=5.0)
+    idx, d2, cnt = oracle.knn(target, queries, 20)
+    tree = scipy_spatial.cKDTree(target.astype(np.float64))
+    dd, ii = tree.query(queries.astype(np.float64), k=20)
+    assert np.array_equal(idx, ii.astype(np.int32))
+    np.testing.assert_allclose(d2, dd ** 2, rtol=1e-12, atol=1e-14)
+    # radius-capped: cKDTree ball query gives the in-radius set
+    idx, d2, cnt = oracle.knn(target, queries, 20, radius=0.6)
+    balls = tree.query_ball_point(queries.astype(np.float64), r=0.6)
+    for i, b in enumerate(balls):
+        assert cnt[i] == min(20, len(b))
+
+
+def test_knn_self_query_includes_self():
+    p = workloads.plane_wall(512, seed=5)
+    idx, d2, cnt = oracle.knn(p, p, 6)
+    assert np.array_equal(idx[:, 0], np.arange(p.shape[0]))
+    assert np.all(d2[:, 0] == 0.0)
+
+
+# ------------------------------------------------------------ covariance ---
+
+def test_cov_1d_lattice_closed_form():
+    """Interior window of odd k on t_i = (a i, 0, 0): mean a i, C_xx = a^2 (k^2-1)/12."""
+    n, a = 64, 0.5
+    lat = workloads.lattice_1d(n, a)
+    for k in (3, 5, 9, 21):
+        idx, _, cnt = oracle.knn(lat, lat, k)
+        out = oracle.covariances(lat, idx, cnt)
+        m = k // 2
+        for i in range(m, n - m):
+            assert out["mean"][i, 0] == pytest.approx(a * i, rel=1e-14)
+            assert out["mean"][i, 1] == 0 and out["mean"][i, 2] == 0
+            cxx = a * a * (k * k - 1) / 12.0
+            expect = np.zeros((3, 3))
+            expect[0, 0] = cxx
+            np.testing.assert_allclose(out["cov"][i], expect, rtol=1e-12, atol=1e-15)
+
+
+def test_cov_matches_numpy_cov_bias_and_twin():
+    target = workloads.plane_wall(400, seed=2)
+    idx, _, cnt = oracle.knn(target, target, 12)
+    out = oracle.covariances(target, idx, cnt, with_eig=True)
+    twin = oracle.covariances_np(target, idx, cnt)
+    np.testing.assert_allclose(out["mean"], twin["mean"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(out["cov"], twin["cov"], rtol=1e-9, atol=1e-15)
+    assert np.array_equal(out["valid"], twin["valid"])
+    # reg depends only on the line of v0 -> compare where the gap is healthy
+    ev = out["evals"]
+    ok = (ev[:, 1] - ev[:, 0]) > 1e-3 * ev[:, 2]
+    np.testing.assert_allclose(out["reg"][ok], twin["reg"][ok], atol=1e-9)
+
+
+def test_cov_invariants():
+    # coordinates on a 2^-12 m grid so that the shifted copy below is exact
+    target = np.round(workloads.random_cloud(800, 4, scale=2.0) * 4096) / 4096
+    target = target.astype(np.float32)
+    idx, _, cnt = oracle.knn(target, target, 15)
+    out = oracle.covariances(target, idx, cnt, with_eig=True)
+    C = out["cov"]
+    assert np.array_equal(C, np.transpose(C, (0, 2, 1)))
+    assert np.all(out["evals"][:, 0] >= -1e-12)
+    t64 = target.astype(np.float64)
+    for i in range(0, 800, 37):
+        p = t64[idx[i, : cnt[i]]]
+        tr = ((p - p.mean(0)) ** 2).sum() / cnt[i]
+        assert np.trace(C[i]) == pytest.approx(tr, rel=1e-12)
+    # translation: cov unchanged, mean shifted
+    shift = np.array([100.0, 50.0, 0.0], np.float32)
+    out2 = oracle.covariances(target + shift, idx, cnt)
+    np.testing.assert_allclose(out2["cov"], C, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(out2["mean"] - out["mean"], np.broadcast_to(shift, (800, 3)),
+                               rtol=0, atol=1e-9)
+    # exact axis permutation permutes the covariance
+    perm = [2, 0, 1]
+    out3 = oracle.covariances(np.ascontiguousarray(target[:, perm]), idx, cnt)
+    np.testing.assert_array_equal(out3["cov"], C[:, perm][:, :, perm])
+
+
+def test_cov_small_counts():
+    t = workloads.random_cloud(10, 9)
+    idx = np.full((4, 5), -1, np.int32)
+    cnt = np.array([0, 1, 2, 3], np.int32)
+    idx[1, :1] = [4]
+    idx[2, :2] = [1, 2]
+    idx[3, :3] = [1, 2, 3]
+    out = oracle.covariances(t, idx, cnt)
+    assert out["valid"].tolist() == [0, 0, 0, 1]
+    assert np.all(out["mean"][0] == 0) and np.all(out["cov"][0] == 0)
+    np.testing.assert_allclose(out["mean"][1], t[4].astype(np.float64))
+    assert np.all(out["cov"][1] == 0)
+    for i in range(3):
+        assert np.array_equal(out["reg"][i], np.eye(3))
+    with pytest.raises(ValueError):
+        bad = idx.copy()
+        bad[3, 0] = 99
+        oracle.covariances(t, bad, cnt)
+
+
+# ------------------------------------------------------ eigen / regulariser ---
+
+def test_jacobi_matches_eigh():
+    rng = np.random.default_rng(0)
+    for _ in range(300):
+        M = rng.normal(size=(3, 3))
+        A = M @ M.T * rng.uniform(1e-4, 10)
+        ev, V = oracle.sym3_eig(A)
+        w, U = np.linalg.eigh(A)
+        np.testing.assert_allclose(ev, w, rtol=1e-10, atol=1e-13 * abs(w).max())
+        np.testing.assert_allclose(V @ np.diag(ev) @ V.T, A, atol=1e-12 * abs(A).max())
+        np.testing.assert_allclose(V.T @ V, np.eye(3), atol=1e-13)
+        gap = w[1] - w[0]
+        if gap > 1e-6 * w[2]:
+            assert abs(abs(V[:, 0] @ U[:, 0]) - 1) < 1e-9
+
+
+def test_jacobi_special_cases():
+    ev, V = oracle.sym3_eig(np.diag([3.0, 1.0, 2.0]))
+    assert ev.tolist() == [1.0, 2.0, 3.0]
+    assert np.array_equal(np.abs(V[:, 0]), [0, 1, 0])
+    ev, V = oracle.sym3_eig(np.zeros((3, 3)))
+    assert ev.tolist() == [0.0, 0.0, 0.0]
+    # repeated eigenvalue: any basis of the eigenspace, still orthonormal
+    A = np.diag([1.0, 1.0, 5.0])
+    R = np.linalg.qr(np.random.default_rng(1).normal(size=(3, 3)))[0]
+    ev, V = oracle.sym3_eig(R @ A @ R.T)
+    np.testing.assert_allclose(ev, [1, 1, 5], atol=1e-12)
+    np.testing.assert_allclose(V.T @ V, np.eye(3), atol=1e-12)
+
+
+def test_regulariser_eigenvalues_and_closed_form():
+    target = workloads.plane_wall(600, seed=3)
+    idx, _, cnt = oracle.knn(target, target, 10)
+    eps = 1e-3
+    out = oracle.covariances(target, idx, cnt, eps=eps, with_eig=True)
+    for i in range(0, 600, 7):
+        R = out["reg"][i]
+        np.testing.assert_allclose(R, R.T, atol=0)
+        w = np.linalg.eigvalsh(R)
+        np.testing.assert_allclose(w, [eps, 1.0, 1.0], atol=1e-12)
+        # the eps-eigenvector is the smallest-eigenvalue direction of C
+        u = np.linalg.eigh(R)[1][:, 0]
+        assert u @ out["cov"][i] @ u == pytest.approx(out["evals"][i, 0], rel=1e-6, abs=1e-15)
+
+
+def test_noisy_plane_and_wall_normals():
+    """Plane points: v0 ~ z and lambda0 ~ sigma^2; wall points: v0 ~ x."""
+    sigma = 0.02
+    p = workloads.plane_wall(2048, seed=0)
+    idx, _, cnt = oracle.knn(p, p, 10)
+    out = oracle.covariances(p, idx, cnt, with_eig=True)
+    n_plane = int(math.floor(0.7 * 2048))
+    plane = np.arange(n_plane)[p[:n_plane, 0] < 4.0]
+    ang = np.degrees(np.arccos(np.clip(np.abs(out["evec0"][plane, 2]), 0, 1)))
+    assert (ang < 5.0).mean() >= 0.95
+    lam_ratio = np.median(out["evals"][plane, 0]) / sigma ** 2
+    assert 0.5 <= lam_ratio <= 1.05, lam_ratio
+    wall = n_plane + np.flatnonzero((p[n_plane:, 2] > 0.5) & (p[n_plane:, 2] < 1.5))
+    ang = np.degrees(np.arccos(np.clip(np.abs(out["evec0"][wall, 0]), 0, 1)))
+    # the wall is sparser (about 15 points per m^2), so its normals scatter
+    # more: calibrated over seeds 0-7, >= 98.9 % lie within 10 degrees and
+    # the median is 2.0-2.5 degrees
+    assert (ang < 10.0).mean() >= 0.95
+    assert np.median(ang) < 4.0
+    # on the plane C_reg ~ diag(1, 1, eps)
+    R = out["reg"][plane]
+    assert (np.abs(R[:, 2, 2] - 1e-3) < 0.01).mean() >= 0.95
+    assert (np.abs(R[:, 0, 0] - 1.0) < 0.01).mean() >= 0.95
