@@ -1,0 +1,222 @@
+/*
+ * lkc.h -- LiDAR kNN + covariance library for MI355X (gfx950).
+ *
+ * The operation (paper, Sec. III-C.1 "Efficient registration method"): GICP
+ * models every point p_i of a scan as a Gaussian N(p_i, C_i); C_i is
+ * estimated from the point's corresponding nearest points, and that
+ * nearest-points search plus covariance computation is the step the paper
+ * runs on the GPU.  Sec. III-C.3 adds that the target map is held in a GPU
+ * hash structure so that map queries are cheap.  This library exposes those
+ * steps as a plain C ABI:
+ *
+ *   lkc_build_target    points -> device-resident hashed voxel grid
+ *   lkc_knn_query       queries -> k nearest target points (within a radius)
+ *   lkc_covariances     neighbour lists -> mean, covariance, regularised cov
+ *   lkc_knn_cov         the two steps above fused in one launch
+ *   lkc_knn_cov_batched many scans against several targets in one persistent
+ *                       launch (graph-capturable)
+ *
+ * Conventions shared by every call:
+ *  - Point arrays are float32 xyz, row-major [n][3], 4-byte aligned.
+ *  - Pointers are DEVICE pointers unless a parameter says "host".  The caller
+ *    owns every input and output buffer; the library owns lkc_target and
+ *    lkc_ctx objects and the memory behind them.
+ *  - Every call is stream-ordered on the context's HIP stream and returns
+ *    before the GPU finishes, except where "synchronises" is stated.
+ *  - Errors are returned as lkc_status; the message of the last failing call
+ *    on a context is available from lkc_last_error.  No C++ exception crosses
+ *    the ABI.  A call that returns an error has enqueued no work unless it
+ *    says otherwise.
+ *  - One context per host thread; a built target is read-only and may be
+ *    used from several contexts.
+ *
+ * Results (the exact definition the GPU reaches):
+ *  - kNN: for query q, every target point t_j with
+ *    d2_j = |q - t_j|^2 <= radius^2 (inclusive; radius = +INFINITY means no
+ *    cap) is ordered by the key (d2_j, j) -- the lower original index wins an
+ *    exact tie -- and the first min(k, #in radius) are returned in ascending
+ *    order.  idx is padded with -1 and d2 with +INFINITY.  d2 is float32,
+ *    computed from coordinate differences.  A query with a non-finite
+ *    coordinate gets count 0.  k > n is allowed (count <= n).
+ *  - Covariance of the n = count neighbours t_1..t_n: mean mu = sum t / n and
+ *    C = sum (t - mu)(t - mu)^T / n (two-pass, 1/n), evaluated in float32
+ *    relative to the query point to keep precision at map coordinates.
+ *    reg_cov = I - (1 - eps) v0 v0^T, v0 the unit eigenvector of the smallest
+ *    eigenvalue of C (so reg_cov has eigenvalues 1, 1, eps: the GICP plane
+ *    model).  valid = (n >= 3); when not valid reg_cov = I.  n = 0 gives
+ *    mean = 0 and C = 0.
+ */
+#ifndef LKC_H
+#define LKC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LKC_VERSION 100 /* 1.0.0 */
+#define LKC_MAX_K 64
+
+typedef struct lkc_ctx lkc_ctx;
+typedef struct lkc_target lkc_target;
+typedef struct lkc_target_set lkc_target_set;
+
+typedef enum lkc_status {
+    LKC_OK = 0,
+    LKC_ERR_INVALID_ARG = -1, /* bad argument; nothing enqueued */
+    LKC_ERR_OOM = -2,         /* device or host allocation failed */
+    LKC_ERR_HIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
+    LKC_ERR_BUDGET = -4,      /* request exceeds a size limit fixed at creation */
+    LKC_ERR_NONFINITE = -5,   /* a target point has a NaN/Inf coordinate */
+    LKC_ERR_UNSUPPORTED = -6  /* no usable gfx950 device */
+} lkc_status;
+
+/* Launch shape of the search kernels.  Any field <= 0 takes the default.
+ *  tile_queries      queries one wavefront handles back to back; their
+ *                    covariances are then computed one query per lane
+ *                    (1..64, default 64)
+ *  waves_per_block   wavefronts per workgroup (1..16, default 4)
+ *  merge_min         a batch of candidates with at least this many entries
+ *                    below the current k-th distance is merged by a bitonic
+ *                    network instead of one insertion per entry (1..65,
+ *                    default 12; 65 disables the network)
+ *  blocks_per_cu     persistent workgroups per compute unit for the batched
+ *                    call (default 8) */
+typedef struct lkc_launch_cfg {
+    int32_t tile_queries;
+    int32_t waves_per_block;
+    int32_t merge_min;
+    int32_t blocks_per_cu;
+} lkc_launch_cfg;
+
+/* Static description of a built target (host struct). */
+typedef struct lkc_target_info {
+    int64_t n_points;
+    int64_t n_cells;         /* occupied cells */
+    int64_t hash_capacity;   /* slots, power of two >= 2 * n_cells */
+    int32_t cell_min[3];     /* occupied cell bounding box (integer cell coords) */
+    int32_t cell_max[3];
+    int32_t key_bits;        /* bits of the compact cell key */
+    int32_t sort_passes;     /* 8-bit radix passes the build ran */
+    float cell_size;
+    int64_t device_bytes;    /* device memory the target holds */
+} lkc_target_info;
+
+/* Scan descriptor for the batched call: queries [q_offset, q_offset+q_count)
+ * of the concatenated query array are searched in target `target_index` of
+ * the target set. */
+typedef struct lkc_scan_desc {
+    int64_t q_offset;
+    int64_t q_count;
+    int32_t target_index;
+    int32_t reserved;
+} lkc_scan_desc;
+
+int32_t lkc_version(void);
+
+/* Create a context bound to `hip_stream` (a hipStream_t; NULL = the null
+ * stream) on the current HIP device.  Allocates a few KB of device and
+ * pinned host memory.  Fails with LKC_ERR_UNSUPPORTED when the current
+ * device is not gfx950-compatible or no device is present. */
+lkc_status lkc_ctx_create(void *hip_stream, lkc_ctx **out);
+lkc_status lkc_ctx_destroy(lkc_ctx *ctx);
+/* Rebind the context to another stream (host-side only). */
+lkc_status lkc_ctx_set_stream(lkc_ctx *ctx, void *hip_stream);
+/* Message of the last failing call on `ctx` (or of the last failing call
+ * with ctx = NULL on this thread).  Host string owned by the library, valid
+ * until the next call on the same context. */
+const char *lkc_last_error(const lkc_ctx *ctx);
+/* Wait for the context's stream; synchronises. */
+lkc_status lkc_synchronize(lkc_ctx *ctx);
+
+/* Build the hashed voxel grid of `points` [n][3] (device) with cubic cells
+ * of edge `cell_size` (metres, > 0).  Points are keyed by integer cell
+ * coordinates floor(p / cell_size) (clamped to [-2^20, 2^20)), sorted by a
+ * compact key with an LSD radix sort, reordered into cell runs, and the
+ * occupied cells are inserted into an open-addressed hash (Sec. III-C.3's
+ * GPU hash map).  Synchronises twice (to size the sort and the hash).  The
+ * caller's buffer may be reused once this call returns.  n = 0 builds an
+ * empty target.  A non-finite coordinate fails with LKC_ERR_NONFINITE and
+ * returns no target. */
+lkc_status lkc_build_target(lkc_ctx *ctx, const float *points, int64_t n, float cell_size,
+                            lkc_target **out);
+/* Rebuild `target` in place from new points (same cell size), reusing its
+ * device memory when large enough.  Same semantics as lkc_build_target; on
+ * error the target is left empty (n = 0) but still valid to free. */
+lkc_status lkc_target_rebuild(lkc_ctx *ctx, lkc_target *target, const float *points, int64_t n);
+/* Free a target.  Synchronises the context's stream first, so work already
+ * enqueued that reads the target completes.  NULL is a no-op. */
+lkc_status lkc_target_free(lkc_ctx *ctx, lkc_target *target);
+/* Fill `info` (host). */
+lkc_status lkc_target_get_info(const lkc_target *target, lkc_target_info *info);
+/* Device pointers of the built arrays, for inspection and tests:
+ * pts float4[n] (reordered, .w = original index bits), cell_start
+ * uint32[n_cells + 1], cell_keys uint64[n_cells].  Any out pointer may be
+ * NULL. */
+lkc_status lkc_target_arrays(const lkc_target *target, const void **pts, const void **cell_start,
+                             const void **cell_keys);
+
+/* k nearest neighbours of each query (device [q][3]) in `target`:
+ * idx int32 [q][k] (original target indices, -1 padding), d2 float [q][k]
+ * (+INFINITY padding), count int32 [q].  1 <= k <= LKC_MAX_K; radius > 0
+ * (INFINITY = uncapped).  cfg may be NULL. */
+lkc_status lkc_knn_query(lkc_ctx *ctx, const lkc_target *target, const float *queries, int64_t q,
+                         int32_t k, float radius, int32_t *idx, float *d2, int32_t *count,
+                         const lkc_launch_cfg *cfg);
+
+/* Mean, covariance and regularised covariance of each query's neighbours.
+ * idx/count are in the layout lkc_knn_query writes (original indices into
+ * `target`).  queries [q][3] is the origin of the query-relative arithmetic;
+ * NULL takes each query's first neighbour as origin.  Outputs: mean float
+ * [q][3], cov float [q][3][3], reg_cov float [q][3][3], valid uint8 [q];
+ * any output except valid may be NULL to skip it.  plane_eps in (0, 1].
+ * count values are clamped to [0, k]; a neighbour index outside
+ * [0, n_points) ends that query's list at that position. */
+lkc_status lkc_covariances(lkc_ctx *ctx, const lkc_target *target, const float *queries,
+                           const int32_t *idx, const int32_t *count, int64_t q, int32_t k,
+                           float plane_eps, float *mean, float *cov, float *reg_cov,
+                           uint8_t *valid);
+
+/* lkc_knn_query followed by lkc_covariances (queries as origin) in one
+ * launch: the neighbour lists stay on chip and the covariance gathers read
+ * the reordered points.  Results are bit-identical to the two calls. */
+lkc_status lkc_knn_cov(lkc_ctx *ctx, const lkc_target *target, const float *queries, int64_t q,
+                       int32_t k, float radius, float plane_eps, int32_t *idx, float *d2,
+                       int32_t *count, float *mean, float *cov, float *reg_cov, uint8_t *valid,
+                       const lkc_launch_cfg *cfg);
+
+/* A set of targets addressable by the batched call.  Creating a set uploads
+ * one small descriptor per target and sizes the set's scan table for at
+ * most `max_scans` scans (host array of target pointers).  The targets must
+ * outlive the set and must not be rebuilt while the set is in use. */
+lkc_status lkc_target_set_create(lkc_ctx *ctx, const lkc_target *const *targets,
+                                 int32_t n_targets, int32_t max_scans, lkc_target_set **out);
+lkc_status lkc_target_set_free(lkc_ctx *ctx, lkc_target_set *set);
+
+/* Stage a batch description: copy `n_scans` scan descriptors (host array)
+ * into the set's device scan table (one stream-ordered copy from the set's
+ * pinned staging buffer).  Fails with LKC_ERR_BUDGET when n_scans exceeds
+ * max_scans.  Descriptors must not overlap and must lie inside the query
+ * array passed to lkc_knn_cov_batched. */
+lkc_status lkc_target_set_stage(lkc_ctx *ctx, lkc_target_set *set, const lkc_scan_desc *scans,
+                                int32_t n_scans);
+
+/* Search + covariance for every scan staged in `set`, in one persistent
+ * launch that pulls 64-query tiles from a device work counter.  queries is
+ * the concatenated query array; the outputs are concatenated in the same
+ * query order, in the layouts of lkc_knn_cov.  The launch reads the staged
+ * table from device memory and allocates nothing, so it may be captured
+ * once in a HIP graph and replayed after each lkc_target_set_stage.  Per
+ * query the results are bit-identical to lkc_knn_cov on that scan alone. */
+lkc_status lkc_knn_cov_batched(lkc_ctx *ctx, lkc_target_set *set, const float *queries,
+                               int64_t total_q, int32_t k, float radius, float plane_eps,
+                               int32_t *idx, float *d2, int32_t *count, float *mean, float *cov,
+                               float *reg_cov, uint8_t *valid, const lkc_launch_cfg *cfg);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LKC_H */

@@ -1,0 +1,381 @@
+// api.hip -- the C ABI: argument checking, object lifetimes, error strings.
+// Every entry point validates its arguments on the host before enqueuing any
+// work, so an invalid call returns LKC_ERR_INVALID_ARG with nothing on the
+// stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lkc_internal.h"
+
+namespace lkc {
+
+static thread_local std::string g_err;  // errors of calls made with ctx == NULL
+
+lkc_status set_error(lkc_ctx* ctx, lkc_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_err = buf;
+    return st;
+}
+
+lkc_status hip_error(lkc_ctx* ctx, hipError_t e, const char* what) {
+    return set_error(ctx, e == hipErrorOutOfMemory ? LKC_ERR_OOM : LKC_ERR_HIP, "%s: %s (%d)",
+                     what, hipGetErrorString(e), (int)e);
+}
+
+}  // namespace lkc
+
+using lkc::set_error;
+
+namespace {
+
+constexpr size_t META_BYTES = 256;
+
+bool device_is_gfx950(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+    return std::strncmp(p.gcnArchName, "gfx950", 6) == 0;
+}
+
+lkc_status check_ctx(lkc_ctx* ctx) {
+    if (!ctx) return set_error(nullptr, LKC_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->err.clear();
+    return LKC_OK;
+}
+
+lkc_status check_k_radius(lkc_ctx* ctx, int32_t k, float radius) {
+    if (k < 1 || k > LKC_MAX_K)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "k = %d outside [1, %d]", k, LKC_MAX_K);
+    if (!(radius > 0.0f))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "radius must be > 0 (INFINITY = no cap)");
+    return LKC_OK;
+}
+
+lkc_status check_target(lkc_ctx* ctx, const lkc_target* t) {
+    if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
+    if (!t->cell_mem) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is not built");
+    return LKC_OK;
+}
+
+lkc_status check_eps(lkc_ctx* ctx, float eps) {
+    if (!(eps > 0.0f && eps <= 1.0f))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "plane_eps must be in (0, 1]");
+    return LKC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lkc_version(void) { return LKC_VERSION; }
+
+lkc_status lkc_ctx_create(void* hip_stream, lkc_ctx** out) {
+    if (!out) return set_error(nullptr, LKC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int dev = 0, ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+        return set_error(nullptr, LKC_ERR_UNSUPPORTED, "no HIP device");
+    if (hipGetDevice(&dev) != hipSuccess)
+        return set_error(nullptr, LKC_ERR_UNSUPPORTED, "hipGetDevice failed");
+    if (!device_is_gfx950(dev))
+        return set_error(nullptr, LKC_ERR_UNSUPPORTED, "device %d is not gfx950", dev);
+    lkc_ctx* c = new (std::nothrow) lkc_ctx();
+    if (!c) return set_error(nullptr, LKC_ERR_OOM, "host allocation");
+    c->stream = (hipStream_t)hip_stream;
+    c->device = dev;
+    (void)hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (c->num_cus <= 0) c->num_cus = 256;
+    if (hipMalloc(&c->meta_dev, META_BYTES) != hipSuccess ||
+        hipHostMalloc(&c->meta_host, META_BYTES, hipHostMallocDefault) != hipSuccess) {
+        if (c->meta_dev) (void)hipFree(c->meta_dev);
+        delete c;
+        return set_error(nullptr, LKC_ERR_OOM, "context buffers");
+    }
+    *out = c;
+    return LKC_OK;
+}
+
+lkc_status lkc_ctx_destroy(lkc_ctx* ctx) {
+    if (!ctx) return LKC_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->build_scratch) (void)hipFree(ctx->build_scratch);
+    if (ctx->meta_dev) (void)hipFree(ctx->meta_dev);
+    if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
+    delete ctx;
+    return LKC_OK;
+}
+
+lkc_status lkc_ctx_set_stream(lkc_ctx* ctx, void* hip_stream) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    ctx->stream = (hipStream_t)hip_stream;
+    return LKC_OK;
+}
+
+const char* lkc_last_error(const lkc_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : lkc::g_err.c_str();
+}
+
+lkc_status lkc_synchronize(lkc_ctx* ctx) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return LKC_OK;
+}
+
+lkc_status lkc_build_target(lkc_ctx* ctx, const float* points, int64_t n, float cell_size,
+                            lkc_target** out) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!out) return set_error(ctx, LKC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (n > 0 && !points) return set_error(ctx, LKC_ERR_INVALID_ARG, "points is NULL");
+    if (!(cell_size > 0.0f) || !std::isfinite(cell_size) || !std::isfinite(1.0f / cell_size))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "cell_size must be finite and > 0");
+    lkc_target* t = new (std::nothrow) lkc_target();
+    if (!t) return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    t->cell_size = cell_size;
+    s = lkc::build_into(ctx, t, points, n);
+    if (s != LKC_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        lkc::free_target_memory(t);
+        delete t;
+        return s;
+    }
+    *out = t;
+    return LKC_OK;
+}
+
+lkc_status lkc_target_rebuild(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (n > 0 && !points) return set_error(ctx, LKC_ERR_INVALID_ARG, "points is NULL");
+    s = lkc::build_into(ctx, t, points, n);
+    if (s != LKC_OK) {
+        // leave a valid empty target behind
+        const lkc_status keep = s;
+        const std::string msg = ctx->err;
+        if (lkc::build_into(ctx, t, nullptr, 0) == LKC_OK) ctx->err = msg;
+        return keep;
+    }
+    return LKC_OK;
+}
+
+lkc_status lkc_target_free(lkc_ctx* ctx, lkc_target* t) {
+    if (!t) return LKC_OK;
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    lkc::free_target_memory(t);
+    delete t;
+    return LKC_OK;
+}
+
+lkc_status lkc_target_get_info(const lkc_target* t, lkc_target_info* info) {
+    if (!t || !info) return set_error(nullptr, LKC_ERR_INVALID_ARG, "NULL argument");
+    info->n_points = t->view.n;
+    info->n_cells = t->view.n_cells;
+    info->hash_capacity = t->hash_capacity;
+    for (int a = 0; a < 3; ++a) {
+        info->cell_min[a] = t->view.cmin[a];
+        info->cell_max[a] = t->view.cmax[a];
+    }
+    info->key_bits = t->key_bits;
+    info->sort_passes = t->sort_passes;
+    info->cell_size = t->cell_size;
+    info->device_bytes = (int64_t)(t->point_bytes + t->cell_bytes);
+    return LKC_OK;
+}
+
+lkc_status lkc_target_arrays(const lkc_target* t, const void** pts, const void** cell_start,
+                             const void** cell_keys) {
+    if (!t) return set_error(nullptr, LKC_ERR_INVALID_ARG, "target is NULL");
+    if (pts) *pts = t->view.pts;
+    if (cell_start) *cell_start = t->view.cell_start;
+    if (cell_keys) *cell_keys = t->view.cell_keys;
+    return LKC_OK;
+}
+
+lkc_status lkc_knn_query(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
+                         int32_t k, float radius, int32_t* idx, float* d2, int32_t* count,
+                         const lkc_launch_cfg* cfg) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if ((s = check_k_radius(ctx, k, radius)) != LKC_OK) return s;
+    if (q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "q < 0");
+    if (q > 0 && (!queries || !idx || !d2 || !count))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
+    return lkc::launch_knn(ctx, t, queries, q, k, radius, idx, d2, count, lkc::resolve_cfg(cfg));
+}
+
+lkc_status lkc_covariances(lkc_ctx* ctx, const lkc_target* t, const float* queries,
+                           const int32_t* idx, const int32_t* count, int64_t q, int32_t k,
+                           float plane_eps, float* mean, float* cov, float* reg_cov,
+                           uint8_t* valid) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if (k < 1 || k > LKC_MAX_K)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "k = %d outside [1, %d]", k, LKC_MAX_K);
+    if ((s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
+    if (q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "q < 0");
+    if (q > 0 && (!idx || !count || !valid))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL idx, count or valid pointer");
+    return lkc::launch_cov(ctx, t, queries, idx, count, q, k, plane_eps, mean, cov, reg_cov,
+                           valid);
+}
+
+lkc_status lkc_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
+                       int32_t k, float radius, float plane_eps, int32_t* idx, float* d2,
+                       int32_t* count, float* mean, float* cov, float* reg_cov, uint8_t* valid,
+                       const lkc_launch_cfg* cfg) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if ((s = check_k_radius(ctx, k, radius)) != LKC_OK) return s;
+    if ((s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
+    if (q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "q < 0");
+    if (q > 0 && (!queries || !idx || !d2 || !count || !valid))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
+    return lkc::launch_knn_cov(ctx, t, queries, q, k, radius, plane_eps, idx, d2, count, mean,
+                               cov, reg_cov, valid, lkc::resolve_cfg(cfg));
+}
+
+lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,
+                                 int32_t n_targets, int32_t max_scans, lkc_target_set** out) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!out) return set_error(ctx, LKC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_targets < 1 || !targets)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "need at least one target");
+    if (max_scans < 1 || max_scans > (1 << 20))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "max_scans outside [1, 2^20]");
+    for (int i = 0; i < n_targets; ++i)
+        if ((s = check_target(ctx, targets[i])) != LKC_OK) return s;
+    lkc_target_set* set = new (std::nothrow) lkc_target_set();
+    if (!set) return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    set->n_targets = n_targets;
+    set->max_scans = max_scans;
+    set->table_bytes = sizeof(BatchHeader) + sizeof(BatchScan) * (size_t)max_scans;
+    const size_t vb = sizeof(lkc::TargetView) * (size_t)n_targets;
+    hipError_t e = hipMalloc((void**)&set->views_dev, vb);
+    if (e == hipSuccess) e = hipMalloc((void**)&set->header_dev, set->table_bytes);
+    if (e == hipSuccess) e = hipHostMalloc(&set->staging_host, set->table_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        if (set->views_dev) (void)hipFree(set->views_dev);
+        if (set->header_dev) (void)hipFree(set->header_dev);
+        delete set;
+        return lkc::hip_error(ctx, e, "target set allocation");
+    }
+    set->scans_dev = (BatchScan*)(set->header_dev + 1);
+    std::memset(set->staging_host, 0, set->table_bytes);
+    // descriptors: copied from a host buffer, synchronously (set-up time)
+    lkc::TargetView* hv = new (std::nothrow) lkc::TargetView[n_targets];
+    if (!hv) {
+        lkc_target_set_free(ctx, set);
+        return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    }
+    for (int i = 0; i < n_targets; ++i) hv[i] = targets[i]->view;
+    e = hipMemcpyAsync(set->views_dev, hv, vb, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(set->header_dev, set->staging_host, set->table_bytes,
+                           hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    delete[] hv;
+    if (e != hipSuccess) {
+        lkc_target_set_free(ctx, set);
+        return lkc::hip_error(ctx, e, "target set upload");
+    }
+    *out = set;
+    return LKC_OK;
+}
+
+lkc_status lkc_target_set_free(lkc_ctx* ctx, lkc_target_set* set) {
+    if (!set) return LKC_OK;
+    if (ctx) (void)hipStreamSynchronize(ctx->stream);
+    if (set->views_dev) (void)hipFree(set->views_dev);
+    if (set->header_dev) (void)hipFree(set->header_dev);
+    if (set->staging_host) (void)hipHostFree(set->staging_host);
+    delete set;
+    return LKC_OK;
+}
+
+lkc_status lkc_target_set_stage(lkc_ctx* ctx, lkc_target_set* set, const lkc_scan_desc* scans,
+                                int32_t n_scans) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!set) return set_error(ctx, LKC_ERR_INVALID_ARG, "set is NULL");
+    if (n_scans < 0 || (n_scans > 0 && !scans))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "bad scan list");
+    if (n_scans > set->max_scans)
+        return set_error(ctx, LKC_ERR_BUDGET, "%d scans exceed the set's max_scans = %d", n_scans,
+                         set->max_scans);
+    // validate everything before touching the staging buffer
+    int64_t tiles = 0, qend = 0;
+    for (int i = 0; i < n_scans; ++i) {
+        const lkc_scan_desc& d = scans[i];
+        if (d.q_offset < 0 || d.q_count < 0 || d.target_index < 0 ||
+            d.target_index >= set->n_targets)
+            return set_error(ctx, LKC_ERR_INVALID_ARG, "scan %d: bad offset, count or target", i);
+        if (d.q_offset + d.q_count > 0x7fffffffLL)
+            return set_error(ctx, LKC_ERR_INVALID_ARG, "scan %d exceeds 2^31 queries", i);
+        tiles += (d.q_count + 63) / 64;
+        if (d.q_offset + d.q_count > qend) qend = d.q_offset + d.q_count;
+    }
+    if (tiles > 0x7fffffffLL) return set_error(ctx, LKC_ERR_INVALID_ARG, "too many tiles");
+    // the host buffer may still be read by a previous stage's copy
+    LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    auto* h = (BatchHeader*)set->staging_host;
+    auto* hs = (BatchScan*)(h + 1);
+    int64_t tb = 0;
+    for (int i = 0; i < n_scans; ++i) {
+        hs[i].q_offset = scans[i].q_offset;
+        hs[i].q_count = scans[i].q_count;
+        hs[i].target_index = scans[i].target_index;
+        hs[i].tile_begin = (int32_t)tb;
+        tb += (scans[i].q_count + 63) / 64;
+    }
+    h->n_scans = n_scans;
+    h->n_tiles = (int32_t)tiles;
+    h->work_counter = 0;
+    h->waves_done = 0;
+    const size_t bytes = sizeof(BatchHeader) + sizeof(BatchScan) * (size_t)(n_scans > 0 ? n_scans : 0);
+    LKC_HIP_TRY(ctx, hipMemcpyAsync(set->header_dev, set->staging_host, bytes,
+                                    hipMemcpyHostToDevice, ctx->stream));
+    set->max_query_end = qend;
+    return LKC_OK;
+}
+
+lkc_status lkc_knn_cov_batched(lkc_ctx* ctx, lkc_target_set* set, const float* queries,
+                               int64_t total_q, int32_t k, float radius, float plane_eps,
+                               int32_t* idx, float* d2, int32_t* count, float* mean, float* cov,
+                               float* reg_cov, uint8_t* valid, const lkc_launch_cfg* cfg) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!set) return set_error(ctx, LKC_ERR_INVALID_ARG, "set is NULL");
+    if ((s = check_k_radius(ctx, k, radius)) != LKC_OK) return s;
+    if ((s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
+    if (total_q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "total_q < 0");
+    if (total_q > 0 && (!queries || !idx || !d2 || !count || !valid))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
+    lkc::LaunchCfg c = lkc::resolve_cfg(cfg);
+    if (!cfg || cfg->tile_queries <= 0) c.tile_queries = 64;
+    return lkc::launch_batched(ctx, set, queries, total_q, k, radius, plane_eps, idx, d2, count,
+                               mean, cov, reg_cov, valid, c);
+}
+
+}  // extern "C"

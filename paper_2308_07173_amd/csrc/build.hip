@@ -1,0 +1,538 @@
+// build.hip -- device-resident hashed voxel grid of a target cloud.
+//
+// The paper keeps its target map in a GPU hash structure so that the points
+// near a query can be fetched without scanning the whole map (Sec. III-C.3,
+// "GPU-hash data structure"); the grid is an exact accelerator for the
+// nearest-points search of Sec. III-C.1.  The build here is sort-based:
+//
+//   1. scan_points   cell coordinates floor(p / cell), occupied-cell bounding
+//                    box, finiteness flag, copy of the points as float4
+//   2. make_keys     compact key (only the bits the bounding box needs)
+//   3. radix sort    stable LSD, 8-bit digits, only as many passes as the
+//                    key has bits (3 for a 400 m x 150 m track at 1 m cells)
+//   4. cell runs     run boundaries of the sorted keys -> occupied cells
+//   5. hash insert   open addressing, linear probing, capacity 2^ceil(log2 2C)
+//   6. reorder       points into cell order as float4 (x, y, z, original idx)
+//
+// Within a cell the points keep their original order (the sort is stable),
+// so the layout is deterministic.
+#include <climits>
+#include <cstring>
+
+#include "lkc_internal.h"
+
+namespace lkc {
+
+namespace {
+
+constexpr int BT = 256;          // threads per block for the build kernels
+constexpr int RS_ITEMS = 8;      // radix items per thread per tile
+constexpr int RS_TILE = BT * RS_ITEMS;
+constexpr int RADIX = 256;
+
+struct BuildMeta {
+    int cmin[3];
+    int cmax[3];
+    int nonfinite;
+    uint32_t n_cells;
+    uint32_t max_abs_bits;  // float bits of max |coordinate| (non-negative floats order as uints)
+    uint32_t pad[7];
+};
+static_assert(sizeof(BuildMeta) == 64, "BuildMeta layout");
+
+__global__ void k_meta_init(BuildMeta* m) {
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            m->cmin[a] = INT_MAX;
+            m->cmax[a] = INT_MIN;
+        }
+        m->nonfinite = 0;
+        m->n_cells = 0;
+        m->max_abs_bits = 0;
+    }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = min(v, __shfl_xor(v, s));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = max(v, __shfl_xor(v, s));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_maxu(uint32_t v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, s));
+    return v;
+}
+
+__global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p, int64_t n,
+                                                    float inv_cell, float4* __restrict__ orig,
+                                                    BuildMeta* __restrict__ meta) {
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    int mn[3] = {INT_MAX, INT_MAX, INT_MAX};
+    int mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+    uint32_t mabs = 0;
+    bool bad = false;
+    if (i < n) {
+        const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
+        orig[i] = make_float4(x, y, z, 0.0f);
+        if (!finite3(x, y, z)) {
+            bad = true;
+        } else {
+            const int c[3] = {cell_coord(x, inv_cell), cell_coord(y, inv_cell),
+                              cell_coord(z, inv_cell)};
+            for (int a = 0; a < 3; ++a) mn[a] = mx[a] = c[a];
+            mabs = __float_as_uint(fmaxf(fabsf(x), fmaxf(fabsf(y), fabsf(z))));
+        }
+    }
+    __shared__ int s_mn[3][BT / WAVE], s_mx[3][BT / WAVE];
+    __shared__ uint32_t s_abs[BT / WAVE];
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
+    if (bad) s_bad = 1;
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    for (int a = 0; a < 3; ++a) {
+        const int vmn = wave_min(mn[a]), vmx = wave_max(mx[a]);
+        if (l == 0) {
+            s_mn[a][w] = vmn;
+            s_mx[a][w] = vmx;
+        }
+    }
+    const uint32_t vab = wave_maxu(mabs);
+    if (l == 0) s_abs[w] = vab;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            int vmn = INT_MAX, vmx = INT_MIN;
+            for (int j = 0; j < BT / WAVE; ++j) {
+                vmn = min(vmn, s_mn[a][j]);
+                vmx = max(vmx, s_mx[a][j]);
+            }
+            if (vmn != INT_MAX) atomicMin(&meta->cmin[a], vmn);
+            if (vmx != INT_MIN) atomicMax(&meta->cmax[a], vmx);
+        }
+        uint32_t ab = 0;
+        for (int j = 0; j < BT / WAVE; ++j) ab = max(ab, s_abs[j]);
+        if (ab) atomicMax(&meta->max_abs_bits, ab);
+        if (s_bad) atomicOr(&meta->nonfinite, 1);
+    }
+}
+
+struct KeyParams {
+    float inv_cell;
+    int cmin[3];
+    int sh_y, sh_z;
+};
+
+__global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ orig, int64_t n,
+                                                  KeyParams kp, unsigned long long* __restrict__ keys,
+                                                  uint32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    const float4 p = orig[i];
+    const int cx = cell_coord(p.x, kp.inv_cell) - kp.cmin[0];
+    const int cy = cell_coord(p.y, kp.inv_cell) - kp.cmin[1];
+    const int cz = cell_coord(p.z, kp.inv_cell) - kp.cmin[2];
+    keys[i] = (unsigned long long)(uint32_t)cx | ((unsigned long long)(uint32_t)cy << kp.sh_y) |
+              ((unsigned long long)(uint32_t)cz << kp.sh_z);
+    vals[i] = (uint32_t)i;
+}
+
+// Per-tile digit histogram, stored digit-major: counts[d * nblocks + b].
+__global__ void __launch_bounds__(BT) k_radix_hist(const unsigned long long* __restrict__ keys,
+                                                   int64_t n, int shift,
+                                                   uint32_t* __restrict__ counts, int nblocks) {
+    __shared__ uint32_t hist[RADIX];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int64_t i = base + it * BT + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(uint32_t)(keys[i] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Exclusive prefix sum of m words in place, one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t* __restrict__ data, int64_t m,
+                                                         uint32_t* __restrict__ total) {
+    constexpr int T = 1024;
+    __shared__ uint32_t s_part[T / WAVE];
+    const int64_t per = (m + T - 1) / T;
+    const int64_t b = per * threadIdx.x, e = min(b + per, m);
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += data[i];
+    // block exclusive scan of `sum`
+    const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    const int incl = wave_incl_scan((int)sum);
+    if (l == WAVE - 1) s_part[w] = (uint32_t)incl;
+    __syncthreads();
+    if (w == 0) {
+        int v = (l < T / WAVE) ? (int)s_part[l] : 0;
+        const int vi = wave_incl_scan(v);
+        if (l < T / WAVE) s_part[l] = (uint32_t)(vi - v);
+    }
+    __syncthreads();
+    uint32_t run = s_part[w] + (uint32_t)incl - sum;
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t v = data[i];
+        data[i] = run;
+        run += v;
+    }
+    if (total && threadIdx.x == T - 1) *total = run;
+}
+
+// Stable scatter of one 8-bit digit.  Items of a tile are visited in index
+// order (256 consecutive items per step); within a step the rank of an item
+// among equal digits is (items of that digit in earlier steps) + (in earlier
+// wavefronts of this step) + (in lower lanes of its wavefront).
+__global__ void __launch_bounds__(BT) k_radix_scatter(
+    const unsigned long long* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n,
+    int shift, const uint32_t* __restrict__ offsets, int nblocks) {
+    constexpr int NW = BT / WAVE;
+    __shared__ uint32_t goff[RADIX];
+    __shared__ uint32_t run[RADIX];
+    __shared__ uint32_t wcnt[NW][RADIX];
+    const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
+    goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+    run[tid] = 0;
+    const unsigned long long lt_mask = (1ull << l) - 1ull;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int64_t i = base + it * BT + tid;
+        const bool valid = i < n;
+        const unsigned long long key = valid ? keys_in[i] : 0ull;
+        const uint32_t d = (uint32_t)(key >> shift) & (RADIX - 1);
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool b = (d >> bit) & 1u;
+            const unsigned long long bal = __ballot(b);
+            peers &= b ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        __syncthreads();  // previous step's reads of wcnt are done
+#pragma unroll
+        for (int j = 0; j < NW; ++j) wcnt[j][tid] = 0;
+        __syncthreads();
+        if (valid && rank == 0) wcnt[w][d] = cnt;
+        __syncthreads();
+        {
+            uint32_t r = run[tid];
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                const uint32_t c = wcnt[j][tid];
+                wcnt[j][tid] = r;
+                r += c;
+            }
+            run[tid] = r;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = goff[d] + wcnt[w][d] + rank;
+            keys_out[pos] = key;
+            vals_out[pos] = vals_in[i];
+        }
+    }
+}
+
+// Cell runs: flag(i) = key[i] != key[i-1].  Pass 1 counts flags per block.
+__global__ void __launch_bounds__(BT) k_cell_count(const unsigned long long* __restrict__ keys,
+                                                   int64_t n, uint32_t* __restrict__ bcount) {
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    const bool f = i < n && (i == 0 || keys[i] != keys[i - 1]);
+    const int c = __syncthreads_count(f);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)c;
+}
+
+__global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __restrict__ keys,
+                                                   int64_t n, const uint32_t* __restrict__ boff,
+                                                   unsigned long long* __restrict__ ckeys,
+                                                   uint32_t* __restrict__ cstart,
+                                                   BuildMeta* __restrict__ meta) {
+    __shared__ uint32_t s_w[BT / WAVE];
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    const bool f = i < n && (i == 0 || keys[i] != keys[i - 1]);
+    const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    const unsigned long long bal = __ballot(f);
+    const uint32_t pre = (uint32_t)__popcll(bal & ((1ull << l) - 1ull));
+    if (l == 0) s_w[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t wo = 0;
+    for (int j = 0; j < w; ++j) wo += s_w[j];
+    const uint32_t cid = boff[blockIdx.x] + wo + pre;
+    if (f) {
+        ckeys[cid] = keys[i];
+        cstart[cid] = (uint32_t)i;
+    }
+    if (i == n - 1) meta->n_cells = cid + (f ? 1u : 0u);
+}
+
+__global__ void k_hash_clear(HashSlot* __restrict__ h, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cap) h[i] = HashSlot{EMPTY_KEY, 0u, 0u};
+}
+
+__global__ void __launch_bounds__(BT) k_hash_insert(const unsigned long long* __restrict__ tkeys,
+                                                    const uint32_t* __restrict__ tstart,
+                                                    int64_t n_cells, int64_t n,
+                                                    unsigned long long* __restrict__ ckeys,
+                                                    uint32_t* __restrict__ cstart,
+                                                    HashSlot* __restrict__ hash, int bits,
+                                                    uint32_t mask) {
+    const int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (c >= n_cells) return;
+    const unsigned long long key = tkeys[c];
+    const uint32_t st = tstart[c];
+    const uint32_t en = (c + 1 < n_cells) ? tstart[c + 1] : (uint32_t)n;
+    ckeys[c] = key;
+    cstart[c] = st;
+    if (c == n_cells - 1) cstart[n_cells] = (uint32_t)n;
+    uint32_t s = hash_slot(key, bits);
+    for (;;) {
+        const unsigned long long old = atomicCAS(&hash[s].key, EMPTY_KEY, key);
+        if (old == EMPTY_KEY) {
+            hash[s].start = st;
+            hash[s].count = en - st;
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+__global__ void __launch_bounds__(BT) k_reorder(const float4* __restrict__ orig,
+                                                const uint32_t* __restrict__ vals, int64_t n,
+                                                float4* __restrict__ pts) {
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t o = vals[i];
+    const float4 p = orig[o];
+    pts[i] = make_float4(p.x, p.y, p.z, __int_as_float((int)o));
+}
+
+__global__ void k_iota(uint32_t* __restrict__ v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (uint32_t)i;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+inline unsigned grid_for(int64_t n, int bt) { return (unsigned)((n + bt - 1) / bt); }
+
+int bit_width(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
+
+lkc_status ensure_scratch(lkc_ctx* ctx, size_t bytes) {
+    if (ctx->build_scratch_bytes >= bytes) return LKC_OK;
+    if (ctx->build_scratch) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_error(ctx, e, "hipStreamSynchronize");
+        (void)hipFree(ctx->build_scratch);
+        ctx->build_scratch = nullptr;
+        ctx->build_scratch_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->build_scratch, bytes);
+    if (e != hipSuccess) {
+        ctx->build_scratch = nullptr;
+        return set_error(ctx, LKC_ERR_OOM, "build scratch of %zu bytes: %s", bytes,
+                         hipGetErrorString(e));
+    }
+    ctx->build_scratch_bytes = bytes;
+    return LKC_OK;
+}
+
+}  // namespace
+
+void free_target_memory(lkc_target* t) {
+    if (t->point_mem) (void)hipFree(t->point_mem);
+    if (t->cell_mem) (void)hipFree(t->cell_mem);
+    t->point_mem = t->cell_mem = nullptr;
+    t->point_bytes = t->cell_bytes = 0;
+}
+
+lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n) {
+    hipStream_t st = ctx->stream;
+    const float cell = t->cell_size;
+    const float inv_cell = 1.0f / cell;
+    TargetView& V = t->view;
+    V = TargetView{};
+    V.cell = cell;
+    V.inv_cell = inv_cell;
+    t->key_bits = 0;
+    t->sort_passes = 0;
+
+    // ---- point storage (pts + orig), grow-only
+    const size_t pbytes = align256(sizeof(float4) * (size_t)(n > 0 ? n : 1));
+    if (t->point_bytes < 2 * pbytes) {
+        if (t->point_mem) {
+            LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+            (void)hipFree(t->point_mem);
+            t->point_mem = nullptr;
+            t->point_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&t->point_mem, 2 * pbytes);
+        if (e != hipSuccess) {
+            t->point_mem = nullptr;
+            return set_error(ctx, LKC_ERR_OOM, "target points (%zu bytes): %s", 2 * pbytes,
+                             hipGetErrorString(e));
+        }
+        t->point_bytes = 2 * pbytes;
+    }
+    float4* pts = (float4*)t->point_mem;
+    float4* orig = (float4*)((char*)t->point_mem + pbytes);
+
+    // ---- scratch: keys a/b, vals a/b, radix counts, block counts, cell temps
+    const int64_t nb_rs = (n + RS_TILE - 1) / RS_TILE;
+    const int64_t nb_bt = (n + BT - 1) / BT;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    const size_t o_ka = carve(8 * nn), o_kb = carve(8 * nn);
+    const size_t o_va = carve(4 * nn), o_vb = carve(4 * nn);
+    const size_t o_cnt = carve(4 * (size_t)RADIX * (size_t)(nb_rs > 0 ? nb_rs : 1));
+    const size_t o_bc = carve(4 * (size_t)(nb_bt > 0 ? nb_bt : 1) + 4);
+    const size_t o_tk = carve(8 * nn), o_ts = carve(4 * nn + 4);
+    lkc_status s = ensure_scratch(ctx, off);
+    if (s != LKC_OK) return s;
+    char* sb = (char*)ctx->build_scratch;
+    auto* keys_a = (unsigned long long*)(sb + o_ka);
+    auto* keys_b = (unsigned long long*)(sb + o_kb);
+    auto* vals_a = (uint32_t*)(sb + o_va);
+    auto* vals_b = (uint32_t*)(sb + o_vb);
+    auto* rcounts = (uint32_t*)(sb + o_cnt);
+    auto* bcounts = (uint32_t*)(sb + o_bc);
+    auto* tkeys = (unsigned long long*)(sb + o_tk);
+    auto* tstart = (uint32_t*)(sb + o_ts);
+    auto* meta = (BuildMeta*)ctx->meta_dev;
+    auto* hmeta = (BuildMeta*)ctx->meta_host;
+
+    int64_t n_cells = 0;
+    if (n > 0) {
+        // ---- 1. cell coordinates, bounding box, finiteness
+        hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(1), 0, st, meta);
+        hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
+                           inv_cell, orig, meta);
+        LKC_HIP_TRY(ctx, hipGetLastError());
+        LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
+        LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+        if (hmeta->nonfinite) {
+            V.n = 0;
+            return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
+        }
+        int bits[3];
+        for (int a = 0; a < 3; ++a) {
+            V.cmin[a] = hmeta->cmin[a];
+            V.cmax[a] = hmeta->cmax[a];
+            bits[a] = bit_width((uint32_t)(hmeta->cmax[a] - hmeta->cmin[a]));
+        }
+        V.max_abs = __builtin_bit_cast(float, hmeta->max_abs_bits);
+        V.sh_y = bits[0];
+        V.sh_z = bits[0] + bits[1];
+        t->key_bits = bits[0] + bits[1] + bits[2];
+        t->sort_passes = (t->key_bits + 7) / 8;
+
+        // ---- 2. keys
+        KeyParams kp;
+        kp.inv_cell = inv_cell;
+        for (int a = 0; a < 3; ++a) kp.cmin[a] = V.cmin[a];
+        kp.sh_y = V.sh_y;
+        kp.sh_z = V.sh_z;
+        hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, n, kp,
+                           keys_a, vals_a);
+
+        // ---- 3. LSD radix sort on the occupied key bits
+        for (int pass = 0; pass < t->sort_passes; ++pass) {
+            const int shift = 8 * pass;
+            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb_rs), dim3(BT), 0, st, keys_a, n,
+                               shift, rcounts, (int)nb_rs);
+            hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, rcounts,
+                               (int64_t)RADIX * nb_rs, (uint32_t*)nullptr);
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb_rs), dim3(BT), 0, st, keys_a,
+                               vals_a, keys_b, vals_b, n, shift, rcounts, (int)nb_rs);
+            std::swap(keys_a, keys_b);
+            std::swap(vals_a, vals_b);
+        }
+        LKC_HIP_TRY(ctx, hipGetLastError());
+
+        // ---- 4. cell runs
+        hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a, n,
+                           bcounts);
+        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, bcounts, nb_bt,
+                           (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a, n,
+                           bcounts, tkeys, tstart, meta);
+        // ---- 6. reorder (independent of the cell count)
+        hipLaunchKernelGGL(k_reorder, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, vals_a, n,
+                           pts);
+        LKC_HIP_TRY(ctx, hipGetLastError());
+        LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
+        LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+        n_cells = hmeta->n_cells;
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            V.cmin[a] = 0;
+            V.cmax[a] = -1;
+        }
+    }
+
+    // ---- 5. cell arrays + hash (sized by the cell count)
+    int hbits = 6;
+    while (((int64_t)1 << hbits) < 2 * n_cells) ++hbits;
+    const int64_t cap = (int64_t)1 << hbits;
+    const size_t ck_b = align256(8 * (size_t)(n_cells > 0 ? n_cells : 1));
+    const size_t cs_b = align256(4 * (size_t)(n_cells + 1));
+    const size_t h_b = align256(sizeof(HashSlot) * (size_t)cap);
+    const size_t cbytes = ck_b + cs_b + h_b;
+    if (t->cell_bytes < cbytes) {
+        if (t->cell_mem) {
+            LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+            (void)hipFree(t->cell_mem);
+            t->cell_mem = nullptr;
+            t->cell_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&t->cell_mem, cbytes);
+        if (e != hipSuccess) {
+            t->cell_mem = nullptr;
+            V.n = 0;
+            return set_error(ctx, LKC_ERR_OOM, "target cells (%zu bytes): %s", cbytes,
+                             hipGetErrorString(e));
+        }
+        t->cell_bytes = cbytes;
+    }
+    auto* ckeys = (unsigned long long*)t->cell_mem;
+    auto* cstart = (uint32_t*)((char*)t->cell_mem + ck_b);
+    auto* hash = (HashSlot*)((char*)t->cell_mem + ck_b + cs_b);
+    hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap, BT)), dim3(BT), 0, st, hash, cap);
+    if (n_cells > 0) {
+        hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n_cells, BT)), dim3(BT), 0, st, tkeys,
+                           tstart, n_cells, n, ckeys, cstart, hash, hbits, (uint32_t)(cap - 1));
+    } else {
+        LKC_HIP_TRY(ctx, hipMemsetAsync(cstart, 0, 4, st));
+    }
+    LKC_HIP_TRY(ctx, hipGetLastError());
+
+    V.pts = pts;
+    V.orig = orig;
+    V.hash = hash;
+    V.cell_keys = ckeys;
+    V.cell_start = cstart;
+    V.n = n;
+    V.n_cells = (int32_t)n_cells;
+    V.hash_bits = hbits;
+    V.hash_mask = (uint32_t)(cap - 1);
+    t->hash_capacity = cap;
+    return LKC_OK;
+}
+
+}  // namespace lkc

@@ -1,0 +1,160 @@
+// lkc_device.h -- device-side data layout and wavefront helpers shared by the
+// HIP kernels of the nearest-points search and covariance library.
+//
+// Layout of a built target in HBM (all arrays 16-byte aligned):
+//   pts   float4[n]      points reordered by cell key; .w holds the original
+//                        index (bit-cast int32), so a cell's candidates are one
+//                        contiguous, coalesced run of 16-byte records
+//   orig  float4[n]      the caller's points in original order (.w = 0); the
+//                        gather source when neighbours are named by original
+//                        index
+//   hash  HashSlot[cap]  open-addressed cell table (cap = power of two >= 2C):
+//                        64-bit compact cell key -> (first point, point count)
+//   cell_keys u64[C], cell_start u32[C+1]
+//                        the occupied cells in key order (used for the full
+//                        sweep that bounds uncapped searches)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lkc {
+
+constexpr int WAVE = 64;
+constexpr unsigned long long EMPTY_KEY = ~0ull;
+constexpr int32_t IDX_SENTINEL = 0x7fffffff;
+constexpr int CELL_CLAMP = 1 << 20;  // integer cell coordinates live in [-2^20, 2^20)
+
+struct HashSlot {
+    unsigned long long key;
+    uint32_t start;
+    uint32_t count;
+};
+
+// Everything a kernel needs to search one target.  Passed by value as a
+// kernel argument, or stored in a device array for the batched path.
+struct TargetView {
+    const float4* pts;
+    const float4* orig;
+    const HashSlot* hash;
+    const unsigned long long* cell_keys;
+    const uint32_t* cell_start;
+    int64_t n;
+    int32_t n_cells;
+    int32_t hash_bits;
+    uint32_t hash_mask;
+    float cell;
+    float inv_cell;
+    int32_t cmin[3];
+    int32_t cmax[3];
+    int32_t sh_y, sh_z;   // compact key = kx | ky << sh_y | kz << sh_z
+    float max_abs;        // max |coordinate| over the target (for error margins)
+};
+
+// --------------------------------------------------------------- scalars --
+
+__device__ __forceinline__ bool finite3(float x, float y, float z) {
+    return __builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z);
+}
+
+__device__ __forceinline__ int cell_coord(float x, float inv_cell) {
+    float c = floorf(x * inv_cell);
+    c = fminf(fmaxf(c, -(float)CELL_CLAMP), (float)(CELL_CLAMP - 1));
+    return (int)c;
+}
+
+__device__ __forceinline__ unsigned long long pack_key(const TargetView& T, int cx, int cy, int cz) {
+    return (unsigned long long)(uint32_t)(cx - T.cmin[0]) |
+           ((unsigned long long)(uint32_t)(cy - T.cmin[1]) << T.sh_y) |
+           ((unsigned long long)(uint32_t)(cz - T.cmin[2]) << T.sh_z);
+}
+
+__device__ __forceinline__ uint32_t hash_slot(unsigned long long key, int bits) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - bits));
+}
+
+// Probe the cell table; returns false when the cell is empty.
+__device__ __forceinline__ bool hash_find(const TargetView& T, unsigned long long key,
+                                          uint32_t& start, uint32_t& count) {
+    uint32_t s = hash_slot(key, T.hash_bits);
+    for (;;) {
+        const HashSlot h = T.hash[s];
+        if (h.key == key) {
+            start = h.start;
+            count = h.count;
+            return true;
+        }
+        if (h.key == EMPTY_KEY) return false;
+        s = (s + 1) & T.hash_mask;
+    }
+}
+
+// Squared distance from the query, as coordinate differences (never the
+// |q|^2 + |t|^2 - 2 q.t expansion, which cancels catastrophically at
+// map-frame coordinates).  Written with explicit fmaf so that every kernel
+// that evaluates it rounds identically.
+__device__ __forceinline__ float dist2(float qx, float qy, float qz, float tx, float ty, float tz) {
+    const float dx = qx - tx, dy = qy - ty, dz = qz - tz;
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+// Lexicographic order on (squared distance, original index): the lower index
+// wins an exact tie.
+__device__ __forceinline__ bool key_less(float da, int32_t ia, float db, int32_t ib) {
+    return da < db || (da == db && ia < ib);
+}
+
+// --------------------------------------------------------------- wavefront --
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+
+template <typename T>
+__device__ __forceinline__ T readlane(T v, int lane) {
+    static_assert(sizeof(T) == 4, "32-bit only");
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// value of lane-1 (lane 0 gets `fill`), one DPP move across the whole wave
+template <typename T>
+__device__ __forceinline__ T shift_up1(T v, T fill) {
+    static_assert(sizeof(T) == 4, "32-bit only");
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill), __builtin_bit_cast(int, v),
+                                       0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor(T v, int mask) {
+    static_assert(sizeof(T) == 4, "32-bit only");
+    return __builtin_bit_cast(T, __shfl_xor(__builtin_bit_cast(int, v), mask));
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) {
+    static_assert(sizeof(T) == 4, "32-bit only");
+    return __builtin_bit_cast(T, __shfl(__builtin_bit_cast(int, v), src));
+}
+
+// inclusive prefix sum across the wave (Hillis-Steele with shuffles)
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int s = 1; s < WAVE; s <<= 1) {
+        const int o = __shfl_up(v, s);
+        if (l >= s) v += o;
+    }
+    return v;
+}
+
+// Map a hardware workgroup id to a logical tile id so that each XCD (the
+// hardware deals workgroups round-robin over 8 XCDs, each with its own L2)
+// works on one contiguous range of tiles.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t bid, uint32_t nb) {
+    constexpr uint32_t NX = 8;
+    const uint32_t q = nb / NX, r = nb % NX;
+    const uint32_t x = bid % NX, i = bid / NX;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+}  // namespace lkc

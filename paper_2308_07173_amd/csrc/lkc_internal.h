@@ -1,0 +1,103 @@
+// lkc_internal.h -- host-side objects behind the C ABI (context, target,
+// target set) and the error plumbing.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "../../include/lkc.h"
+#include "lkc_device.h"
+
+struct lkc_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cus = 0;
+    std::string err;
+    // grow-only device scratch for target builds (sort buffers, histograms)
+    void* build_scratch = nullptr;
+    size_t build_scratch_bytes = 0;
+    // small device/pinned words for build metadata read-back
+    void* meta_dev = nullptr;
+    void* meta_host = nullptr;
+};
+
+struct lkc_target {
+    lkc::TargetView view{};
+    float cell_size = 1.0f;
+    int32_t key_bits = 0;
+    int32_t sort_passes = 0;
+    int64_t hash_capacity = 0;
+    // owned allocations and their capacities (bytes)
+    void* point_mem = nullptr;   // pts + orig
+    size_t point_bytes = 0;
+    void* cell_mem = nullptr;    // cell_keys + cell_start + hash
+    size_t cell_bytes = 0;
+};
+
+// Device-side staged batch: header + scan table.
+struct BatchScan {
+    int64_t q_offset;
+    int64_t q_count;
+    int32_t target_index;
+    int32_t tile_begin;   // first tile of this scan (exclusive prefix)
+};
+
+struct BatchHeader {
+    int32_t n_scans;
+    int32_t n_tiles;
+    uint32_t work_counter;   // next tile to hand out
+    uint32_t waves_done;     // waves that found the queue empty
+};
+
+struct lkc_target_set {
+    int32_t n_targets = 0;
+    int32_t max_scans = 0;
+    lkc::TargetView* views_dev = nullptr;   // [n_targets]
+    BatchHeader* header_dev = nullptr;      // header followed by BatchScan[max_scans]
+    BatchScan* scans_dev = nullptr;
+    void* staging_host = nullptr;           // pinned, same layout as header_dev
+    size_t table_bytes = 0;
+    int64_t max_query_end = 0;              // largest q_offset + q_count staged
+};
+
+namespace lkc {
+
+lkc_status set_error(lkc_ctx* ctx, lkc_status st, const char* fmt, ...);
+lkc_status hip_error(lkc_ctx* ctx, hipError_t e, const char* what);
+
+// implemented in build.hip
+lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n);
+void free_target_memory(lkc_target* t);
+
+// implemented in search.hip
+struct LaunchCfg {
+    int tile_queries;
+    int waves_per_block;
+    int merge_min;
+    int blocks_per_cu;
+};
+LaunchCfg resolve_cfg(const lkc_launch_cfg* cfg);
+lkc_status launch_knn(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
+                      int32_t k, float radius, int32_t* idx, float* d2, int32_t* count,
+                      const LaunchCfg& cfg);
+lkc_status launch_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries,
+                      const int32_t* idx, const int32_t* count, int64_t q, int32_t k, float eps,
+                      float* mean, float* cov, float* reg, uint8_t* valid);
+lkc_status launch_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
+                          int32_t k, float radius, float eps, int32_t* idx, float* d2,
+                          int32_t* count, float* mean, float* cov, float* reg, uint8_t* valid,
+                          const LaunchCfg& cfg);
+lkc_status launch_batched(lkc_ctx* ctx, lkc_target_set* set, const float* queries,
+                          int64_t total_q, int32_t k, float radius, float eps, int32_t* idx,
+                          float* d2, int32_t* count, float* mean, float* cov, float* reg,
+                          uint8_t* valid, const LaunchCfg& cfg);
+
+}  // namespace lkc
+
+#define LKC_HIP_TRY(ctx, call)                                   \
+    do {                                                         \
+        hipError_t _e = (call);                                  \
+        if (_e != hipSuccess) return lkc::hip_error(ctx, _e, #call); \
+    } while (0)

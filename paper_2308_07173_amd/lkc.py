@@ -1,0 +1,396 @@
+"""Thin Python binding of ``liblkc.so`` (the C ABI in ``include/lkc.h``).
+
+Argument marshalling only: every step of the search and covariance runs in
+the HIP kernels of the library.  Torch is used for device memory and
+streams -- tensors are passed by ``data_ptr()`` and every call is enqueued
+on ``torch.cuda.current_stream()``.  If the library is not built, or no
+gfx950 device is present, the calls raise; there is no CPU fallback.
+
+The functions keep the C names (``lkc_build_target``, ``lkc_knn_query``,
+``lkc_covariances``, ``lkc_knn_cov``, ``lkc_knn_cov_batched`` ...); the
+``Context`` / ``Target`` / ``TargetSet`` classes own the C objects.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+from dataclasses import dataclass
+from typing import Dict, Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblkc.so")
+
+LKC_OK = 0
+LKC_ERR_INVALID_ARG = -1
+LKC_ERR_OOM = -2
+LKC_ERR_HIP = -3
+LKC_ERR_BUDGET = -4
+LKC_ERR_NONFINITE = -5
+LKC_ERR_UNSUPPORTED = -6
+LKC_MAX_K = 64
+
+_STATUS_NAMES = {0: "LKC_OK", -1: "LKC_ERR_INVALID_ARG", -2: "LKC_ERR_OOM", -3: "LKC_ERR_HIP",
+                 -4: "LKC_ERR_BUDGET", -5: "LKC_ERR_NONFINITE", -6: "LKC_ERR_UNSUPPORTED"}
+
+# every symbol include/lkc.h declares
+EXPORTED_SYMBOLS = (
+    "lkc_version", "lkc_ctx_create", "lkc_ctx_destroy", "lkc_ctx_set_stream", "lkc_last_error",
+    "lkc_synchronize", "lkc_build_target", "lkc_target_rebuild", "lkc_target_free",
+    "lkc_target_get_info", "lkc_target_arrays", "lkc_knn_query", "lkc_covariances",
+    "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
+    "lkc_knn_cov_batched",
+)
+
+
+class LkcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class LaunchCfg(ctypes.Structure):
+    _fields_ = [("tile_queries", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("merge_min", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TargetInfo(ctypes.Structure):
+    _fields_ = [("n_points", ctypes.c_int64), ("n_cells", ctypes.c_int64),
+                ("hash_capacity", ctypes.c_int64), ("cell_min", ctypes.c_int32 * 3),
+                ("cell_max", ctypes.c_int32 * 3), ("key_bits", ctypes.c_int32),
+                ("sort_passes", ctypes.c_int32), ("cell_size", ctypes.c_float),
+                ("device_bytes", ctypes.c_int64)]
+
+
+class ScanDesc(ctypes.Structure):
+    _fields_ = [("q_offset", ctypes.c_int64), ("q_count", ctypes.c_int64),
+                ("target_index", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load ``liblkc.so``; raises if it has not been built."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run `python __graft_entry__.py build` "
+                               "(or paper_2308_07173_amd/build_lib.py) first")
+        lib = ctypes.CDLL(path)
+        P, I32, I64, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        PP = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "lkc_version": ([], I32),
+            "lkc_ctx_create": ([P, PP], I32),
+            "lkc_ctx_destroy": ([P], I32),
+            "lkc_ctx_set_stream": ([P, P], I32),
+            "lkc_last_error": ([P], ctypes.c_char_p),
+            "lkc_synchronize": ([P], I32),
+            "lkc_build_target": ([P, P, I64, F, PP], I32),
+            "lkc_target_rebuild": ([P, P, P, I64], I32),
+            "lkc_target_free": ([P, P], I32),
+            "lkc_target_get_info": ([P, ctypes.POINTER(TargetInfo)], I32),
+            "lkc_target_arrays": ([P, PP, PP, PP], I32),
+            "lkc_knn_query": ([P, P, P, I64, I32, F, P, P, P, P], I32),
+            "lkc_covariances": ([P, P, P, P, P, I64, I32, F, P, P, P, P], I32),
+            "lkc_knn_cov": ([P, P, P, I64, I32, F, F, P, P, P, P, P, P, P, P], I32),
+            "lkc_target_set_create": ([P, P, I32, I32, PP], I32),
+            "lkc_target_set_free": ([P, P], I32),
+            "lkc_target_set_stage": ([P, P, P, I32], I32),
+            "lkc_knn_cov_batched": ([P, P, P, I64, I32, F, F, P, P, P, P, P, P, P, P], I32),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _check_dev(t, name, dtype=None, shape_tail=None):
+    torch = _torch()
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape_tail is not None and tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [*, {shape_tail}], got {tuple(t.shape)}")
+    del torch
+
+
+def _cfg_ptr(cfg) -> Optional[ctypes.POINTER(LaunchCfg)]:
+    if cfg is None:
+        return None
+    if isinstance(cfg, dict):
+        c = LaunchCfg(**{k: int(v) for k, v in cfg.items()})
+    else:
+        c = cfg
+    return ctypes.byref(c)
+
+
+class Context:
+    """Owns an ``lkc_ctx``; every call rebinds it to torch's current stream."""
+
+    def __init__(self):
+        torch = _torch()
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.lkc_ctx_create(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                     ctypes.byref(h))
+        if st != LKC_OK:
+            raise LkcError(st, self.lib.lkc_last_error(None).decode())
+        self.handle = h
+
+    def _bind(self):
+        torch = _torch()
+        self.lib.lkc_ctx_set_stream(self.handle,
+                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+    def check(self, st: int):
+        if st != LKC_OK:
+            raise LkcError(st, self.lib.lkc_last_error(self.handle).decode())
+
+    def synchronize(self):
+        self._bind()
+        self.check(self.lib.lkc_synchronize(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lkc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass
+
+
+class Target:
+    """A built ``lkc_target`` (device-resident hashed voxel grid)."""
+
+    def __init__(self, ctx: Context, handle: ctypes.c_void_p):
+        self.ctx = ctx
+        self.handle = handle
+
+    def info(self) -> Dict:
+        inf = TargetInfo()
+        self.ctx.check(self.ctx.lib.lkc_target_get_info(self.handle, ctypes.byref(inf)))
+        return dict(n_points=inf.n_points, n_cells=inf.n_cells,
+                    hash_capacity=inf.hash_capacity, cell_min=list(inf.cell_min),
+                    cell_max=list(inf.cell_max), key_bits=inf.key_bits,
+                    sort_passes=inf.sort_passes, cell_size=inf.cell_size,
+                    device_bytes=inf.device_bytes)
+
+    def arrays(self):
+        """(pts float4 [n,4], cell_start int32 [C+1], cell_keys int64 [C]) copied to host."""
+        torch = _torch()
+        a, b, c = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        self.ctx.check(self.ctx.lib.lkc_target_arrays(self.handle, ctypes.byref(a),
+                                                      ctypes.byref(b), ctypes.byref(c)))
+        inf = self.info()
+        n, C = inf["n_points"], inf["n_cells"]
+        self.ctx.synchronize()
+        pts = _copy_device(a.value, 16 * n, torch.float32).view(n, 4) if n else \
+            torch.zeros(0, 4)
+        cs = _copy_device(b.value, 4 * (C + 1), torch.int32)
+        ck = _copy_device(c.value, 8 * C, torch.int64) if C else torch.zeros(0, dtype=torch.int64)
+        return pts, cs, ck
+
+    def rebuild(self, points):
+        _check_dev(points, "points", _torch().float32, (3,))
+        self.ctx._bind()
+        self.ctx.check(self.ctx.lib.lkc_target_rebuild(self.ctx.handle, self.handle,
+                                                       ctypes.c_void_p(_ptr(points)),
+                                                       points.shape[0]))
+
+    def free(self):
+        if self.handle:
+            self.ctx._bind()
+            self.ctx.lib.lkc_target_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and self.ctx.handle:
+                self.free()
+        except Exception:  # pragma: no cover
+            pass
+
+
+def _copy_device(addr: int, nbytes: int, dtype):
+    """Copy raw device memory into a host tensor (hipMemcpy via torch)."""
+    torch = _torch()
+    out = torch.empty(nbytes // torch.empty(0, dtype=dtype).element_size(), dtype=dtype)
+    if nbytes == 0:
+        return out
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    rc = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(addr), nbytes, 2)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+    return out
+
+
+# ------------------------------------------------------------------ calls --
+
+def lkc_build_target(ctx: Context, points, cell_size: float) -> Target:
+    torch = _torch()
+    _check_dev(points, "points", torch.float32, (3,))
+    ctx._bind()
+    h = ctypes.c_void_p()
+    ctx.check(ctx.lib.lkc_build_target(ctx.handle, ctypes.c_void_p(_ptr(points)),
+                                       points.shape[0], float(cell_size), ctypes.byref(h)))
+    return Target(ctx, h)
+
+
+def lkc_knn_query(ctx: Context, target: Target, queries, k: int,
+                  radius: float = math.inf, out=None, cfg=None):
+    """Returns (idx int32 [q,k], d2 float32 [q,k], count int32 [q])."""
+    torch = _torch()
+    _check_dev(queries, "queries", torch.float32, (3,))
+    q = queries.shape[0]
+    if out is None:
+        dev = queries.device
+        out = (torch.empty(q, k, dtype=torch.int32, device=dev),
+               torch.empty(q, k, dtype=torch.float32, device=dev),
+               torch.empty(q, dtype=torch.int32, device=dev))
+    idx, d2, cnt = out
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_knn_query(ctx.handle, target.handle, ctypes.c_void_p(_ptr(queries)),
+                                    q, int(k), float(radius), ctypes.c_void_p(_ptr(idx)),
+                                    ctypes.c_void_p(_ptr(d2)), ctypes.c_void_p(_ptr(cnt)),
+                                    _cfg_ptr(cfg)))
+    return idx, d2, cnt
+
+
+def _cov_out(q, dev):
+    torch = _torch()
+    return dict(mean=torch.empty(q, 3, dtype=torch.float32, device=dev),
+                cov=torch.empty(q, 3, 3, dtype=torch.float32, device=dev),
+                reg=torch.empty(q, 3, 3, dtype=torch.float32, device=dev),
+                valid=torch.empty(q, dtype=torch.uint8, device=dev))
+
+
+def lkc_covariances(ctx: Context, target: Target, idx, count, queries=None,
+                    plane_eps: float = 1e-3, out: Optional[Dict] = None):
+    torch = _torch()
+    _check_dev(idx, "idx", torch.int32)
+    _check_dev(count, "count", torch.int32)
+    _check_dev(queries, "queries", torch.float32, (3,))
+    q, k = idx.shape
+    out = out or _cov_out(q, idx.device)
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_covariances(
+        ctx.handle, target.handle, ctypes.c_void_p(_ptr(queries)), ctypes.c_void_p(_ptr(idx)),
+        ctypes.c_void_p(_ptr(count)), q, int(k), float(plane_eps),
+        ctypes.c_void_p(_ptr(out.get("mean"))), ctypes.c_void_p(_ptr(out.get("cov"))),
+        ctypes.c_void_p(_ptr(out.get("reg"))), ctypes.c_void_p(_ptr(out["valid"]))))
+    return out
+
+
+def lkc_knn_cov(ctx: Context, target: Target, queries, k: int, radius: float = math.inf,
+                plane_eps: float = 1e-3, out: Optional[Dict] = None, cfg=None):
+    torch = _torch()
+    _check_dev(queries, "queries", torch.float32, (3,))
+    q = queries.shape[0]
+    if out is None:
+        out = _cov_out(q, queries.device)
+        out.update(idx=torch.empty(q, k, dtype=torch.int32, device=queries.device),
+                   d2=torch.empty(q, k, dtype=torch.float32, device=queries.device),
+                   count=torch.empty(q, dtype=torch.int32, device=queries.device))
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_knn_cov(
+        ctx.handle, target.handle, ctypes.c_void_p(_ptr(queries)), q, int(k), float(radius),
+        float(plane_eps), ctypes.c_void_p(_ptr(out["idx"])), ctypes.c_void_p(_ptr(out["d2"])),
+        ctypes.c_void_p(_ptr(out["count"])), ctypes.c_void_p(_ptr(out.get("mean"))),
+        ctypes.c_void_p(_ptr(out.get("cov"))), ctypes.c_void_p(_ptr(out.get("reg"))),
+        ctypes.c_void_p(_ptr(out["valid"])), _cfg_ptr(cfg)))
+    return out
+
+
+class TargetSet:
+    """``lkc_target_set``: several targets + a staged scan table for batching."""
+
+    def __init__(self, ctx: Context, targets: Sequence[Target], max_scans: int):
+        self.ctx = ctx
+        self.targets = list(targets)
+        arr = (ctypes.c_void_p * len(self.targets))(*[t.handle.value for t in self.targets])
+        h = ctypes.c_void_p()
+        ctx._bind()
+        ctx.check(ctx.lib.lkc_target_set_create(ctx.handle, arr, len(self.targets),
+                                                int(max_scans), ctypes.byref(h)))
+        self.handle = h
+        self.max_scans = max_scans
+
+    def stage(self, scans: Sequence[Tuple[int, int, int]]):
+        """scans: (q_offset, q_count, target_index) per scan."""
+        arr = (ScanDesc * max(1, len(scans)))()
+        for i, (o, c, t) in enumerate(scans):
+            arr[i].q_offset, arr[i].q_count, arr[i].target_index = int(o), int(c), int(t)
+        self.ctx._bind()
+        self.ctx.check(self.ctx.lib.lkc_target_set_stage(self.ctx.handle, self.handle, arr,
+                                                         len(scans)))
+
+    def free(self):
+        if self.handle:
+            self.ctx._bind()
+            self.ctx.lib.lkc_target_set_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and self.ctx.handle:
+                self.free()
+        except Exception:  # pragma: no cover
+            pass
+
+
+def lkc_knn_cov_batched(ctx: Context, tset: TargetSet, queries, k: int,
+                        radius: float = math.inf, plane_eps: float = 1e-3,
+                        out: Optional[Dict] = None, cfg=None):
+    torch = _torch()
+    _check_dev(queries, "queries", torch.float32, (3,))
+    q = queries.shape[0]
+    if out is None:
+        out = _cov_out(q, queries.device)
+        out.update(idx=torch.empty(q, k, dtype=torch.int32, device=queries.device),
+                   d2=torch.empty(q, k, dtype=torch.float32, device=queries.device),
+                   count=torch.empty(q, dtype=torch.int32, device=queries.device))
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_knn_cov_batched(
+        ctx.handle, tset.handle, ctypes.c_void_p(_ptr(queries)), q, int(k), float(radius),
+        float(plane_eps), ctypes.c_void_p(_ptr(out["idx"])), ctypes.c_void_p(_ptr(out["d2"])),
+        ctypes.c_void_p(_ptr(out["count"])), ctypes.c_void_p(_ptr(out.get("mean"))),
+        ctypes.c_void_p(_ptr(out.get("cov"))), ctypes.c_void_p(_ptr(out.get("reg"))),
+        ctypes.c_void_p(_ptr(out["valid"])), _cfg_ptr(cfg)))
+    return out
+
+
+# pythonic aliases
+build_target = lkc_build_target
+knn_query = lkc_knn_query
+covariances = lkc_covariances
+knn_cov = lkc_knn_cov
+knn_cov_batched = lkc_knn_cov_batched

@@ -1,0 +1,116 @@
+"""Comparison rules between the GPU results and the FP64 oracle.
+
+kNN (float32 GPU vs FP64 oracle): the returned ``d2`` must be within
+``1e-6 * D + 1e-12`` of the FP64 squared distance recomputed for the returned
+index; each list must be ascending in (d2, index); the GPU and oracle sets
+may differ only by indices whose oracle distance lies within
+``1e-5 * D_k`` of the oracle's k-th distance ``D_k`` (a float32 near-tie), and
+counts may differ only by points within ``1e-5 * r^2`` of the radius.
+Where every distance is exact in float32 (integer lattices) the match must be
+exact.
+
+Covariance is compared on the GPU's own neighbour sets (the oracle is run on
+the GPU's idx/count), so kNN near-ties do not leak into it:
+``|C_gpu - C_or|_F <= 1e-4 max(|C_or|_F, 1e-10)``,
+``|mu_gpu - mu_or| <= 1e-5 max(|mu_or|, 1 m)``; the regularised covariance is
+compared at 1e-4 relative Frobenius where the oracle's eigen-gap
+``(l1 - l0) / l2 >= 1e-2``, else checked for symmetry, eigenvalues
+{eps, 1, 1} and for its eps-direction being a near-minimiser of C.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle
+
+KNN_D2_REL = 1e-6
+KNN_D2_ABS = 1e-12
+NEAR_TIE_REL = 1e-5
+COV_REL = 1e-4
+MEAN_REL = 1e-5
+GAP_MIN = 1e-2
+
+
+def check_knn(target, queries, k, radius, g_idx, g_d2, g_cnt, rows=None, exact=False):
+    """Compare GPU kNN rows with the oracle; returns the number of near-tie rows."""
+    target = np.asarray(target, np.float32)
+    queries = np.asarray(queries, np.float32)
+    rows = np.arange(queries.shape[0]) if rows is None else np.asarray(rows)
+    qs = queries[rows]
+    o_idx, o_d2, o_cnt = oracle.knn(target, qs, k, radius)
+    g_idx, g_d2, g_cnt = g_idx[rows], g_d2[rows], g_cnt[rows]
+    if exact:
+        assert np.array_equal(g_cnt, o_cnt), "count differs"
+        assert np.array_equal(g_idx, o_idx), "idx differs"
+        fin = np.isfinite(o_d2)
+        assert np.array_equal(g_d2[fin].astype(np.float64), o_d2[fin]), "d2 differs"
+        assert np.all(np.isinf(g_d2[~fin]))
+        return 0
+    t64 = target.astype(np.float64)
+    q64 = qs.astype(np.float64)
+    r2 = np.inf if np.isinf(radius) else float(np.float32(radius)) ** 2
+    near = 0
+    for r in range(qs.shape[0]):
+        gc, oc = int(g_cnt[r]), int(o_cnt[r])
+        gi = g_idx[r, :gc]
+        assert gc <= k and np.all(g_idx[r, gc:] == -1) and np.all(np.isinf(g_d2[r, gc:])), \
+            f"row {rows[r]}: bad padding"
+        assert np.all((gi >= 0) & (gi < target.shape[0])), f"row {rows[r]}: index out of range"
+        assert len(set(gi.tolist())) == gc, f"row {rows[r]}: duplicate index"
+        rec = ((t64[gi] - q64[r]) ** 2).sum(axis=1)
+        gd = g_d2[r, :gc].astype(np.float64)
+        assert np.all(np.abs(gd - rec) <= KNN_D2_REL * rec + KNN_D2_ABS), \
+            f"row {rows[r]}: d2 off the FP64 distance"
+        for a in range(gc - 1):
+            assert (gd[a], gi[a]) <= (gd[a + 1], gi[a + 1]), f"row {rows[r]}: not ascending"
+        assert np.all(rec <= r2 * (1 + NEAR_TIE_REL)), f"row {rows[r]}: beyond radius"
+        oi = o_idx[r, :oc]
+        if gc == oc and np.array_equal(np.sort(gi), np.sort(oi)):
+            continue
+        near += 1
+        # differing members must be near-ties of the k-th distance or the radius
+        dk = o_d2[r, oc - 1] if oc > 0 else 0.0
+        edge = [dk] + ([r2] if np.isfinite(r2) else [])
+        for j in set(gi.tolist()) ^ set(oi.tolist()):
+            dj = ((t64[j] - q64[r]) ** 2).sum()
+            assert any(abs(dj - e) <= NEAR_TIE_REL * max(e, 1e-30) for e in edge), \
+                f"row {rows[r]}: index {j} (D={dj}) is not a near-tie of D_k={dk}"
+        if gc != oc:
+            assert np.isfinite(r2), f"row {rows[r]}: count {gc} != {oc} without a radius"
+    return near
+
+
+def check_cov(target, g_idx, g_cnt, mean, cov, reg, valid, eps=1e-3, rows=None):
+    """Compare GPU covariance outputs with the oracle run on the GPU's neighbours."""
+    rows = np.arange(g_idx.shape[0]) if rows is None else np.asarray(rows)
+    ref = oracle.covariances(target, g_idx[rows], g_cnt[rows], eps=eps, with_eig=True)
+    assert np.array_equal(valid[rows], ref["valid"]), "valid differs"
+    C = cov[rows].astype(np.float64)
+    err = np.linalg.norm(C - ref["cov"], axis=(1, 2))
+    scale = np.maximum(np.linalg.norm(ref["cov"], axis=(1, 2)), 1e-10)
+    worst = float((err / scale).max()) if rows.size else 0.0
+    assert np.all(err <= COV_REL * scale), f"covariance rel. error {worst}"
+    assert np.array_equal(C, np.transpose(C, (0, 2, 1))), "covariance not symmetric"
+    M = mean[rows].astype(np.float64)
+    merr = np.linalg.norm(M - ref["mean"], axis=1)
+    assert np.all(merr <= MEAN_REL * np.maximum(np.linalg.norm(ref["mean"], axis=1), 1.0)), \
+        f"mean error {float(merr.max())}"
+    R = reg[rows].astype(np.float64)
+    ev = ref["evals"]
+    gap = (ev[:, 1] - ev[:, 0]) / np.maximum(ev[:, 2], 1e-300)
+    v = ref["valid"].astype(bool)
+    good = v & (gap >= GAP_MIN)
+    rerr = np.linalg.norm(R - ref["reg"], axis=(1, 2)) / np.linalg.norm(ref["reg"], axis=(1, 2))
+    assert np.all(rerr[good] <= COV_REL), f"reg_cov rel. error {float(rerr[good].max())}"
+    assert np.array_equal(R[~v], np.broadcast_to(np.eye(3), R[~v].shape)), "invalid rows not I"
+    small = v & ~good
+    if small.any():
+        Rs = R[small]
+        assert np.allclose(Rs, np.transpose(Rs, (0, 2, 1)), atol=1e-6)
+        w, U = np.linalg.eigh(Rs)
+        assert np.allclose(w, np.broadcast_to([eps, 1.0, 1.0], w.shape), atol=1e-5)
+        u = U[:, :, 0]
+        quad = np.einsum("ni,nij,nj->n", u, ref["cov"][small], u)
+        bound = ev[small, 1] + 1e-5 * np.linalg.norm(ref["cov"][small], axis=(1, 2))
+        assert np.all(quad <= bound), "eps-direction is not a near-minimiser of C"
+    return dict(cov_rel=worst, n_small_gap=int(small.sum()))

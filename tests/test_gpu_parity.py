@@ -1,0 +1,346 @@
+"""GPU parity: the HIP kernels against the FP64 oracle, through the C ABI.
+
+Sizes are chosen so the oracle finishes in seconds while spanning several
+64-query tiles, several workgroups and ragged tails; the full-size workloads
+are checked on seeded samples of queries (the oracle computes those one by
+one) plus properties that hold at every size.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2308_07173_amd import workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+INF = math.inf
+
+
+@pytest.fixture(scope="module")
+def lk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_07173_amd import lkc
+    ctx = lkc.Context()
+    yield lkc, ctx
+    ctx.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def run_knn(lk, target_np, queries_np, k, radius, cell, cfg=None):
+    lkc, ctx = lk
+    t = lkc.lkc_build_target(ctx, dev(target_np), cell)
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(queries_np), k, radius, cfg=cfg)
+    torch.cuda.synchronize()
+    out = host(idx), host(d2), host(cnt)
+    t.free()
+    return out
+
+
+# ------------------------------------------------------------ grid build --
+
+@pytest.mark.parametrize("n,cell,seed", [(1, 1.0, 0), (777, 0.25, 1), (40_000, 0.5, 2),
+                                         (70_001, 3.0, 3)])
+def test_build_cells_partition_points(lk, n, cell, seed):
+    """Every point lies in exactly one cell run; the runs tile [0, n); each
+    point's cell is the floor of its coordinates; within a cell the original
+    order is kept."""
+    lkc, ctx = lk
+    p = workloads.random_cloud(n, seed, scale=20.0, offset=(100.0, -40.0, 3.0))
+    t = lkc.lkc_build_target(ctx, dev(p), cell)
+    info = t.info()
+    pts, cs, ck = t.arrays()
+    pts, cs, ck = pts.numpy(), cs.numpy().astype(np.int64), ck.numpy()
+    C = info["n_cells"]
+    assert info["n_points"] == n and cs[0] == 0 and cs[C] == n
+    assert np.all(np.diff(cs) > 0)
+    orig = pts[:, 3].view(np.int32)
+    assert np.array_equal(np.sort(orig), np.arange(n))
+    np.testing.assert_array_equal(pts[:, :3], p[orig])
+    inv = np.float32(1.0) / np.float32(cell)
+    c = np.floor(p[orig] * inv).astype(np.int64)
+    cell_of = np.repeat(np.arange(C), np.diff(cs))
+    for a in range(3):
+        lo = c[:, a]
+        assert lo.min() == info["cell_min"][a] and lo.max() == info["cell_max"][a]
+    key = (c - np.array(info["cell_min"])).astype(np.uint64)
+    bx = int(info["cell_max"][0] - info["cell_min"][0]).bit_length()
+    by = int(info["cell_max"][1] - info["cell_min"][1]).bit_length()
+    packed = key[:, 0] | (key[:, 1] << np.uint64(bx)) | (key[:, 2] << np.uint64(bx + by))
+    assert np.array_equal(packed, ck.astype(np.uint64)[cell_of])
+    assert np.all(np.diff(ck.astype(np.uint64)) > 0)
+    for j in range(C):
+        seg = orig[cs[j]:cs[j + 1]]
+        assert np.all(np.diff(seg) > 0)
+    assert info["hash_capacity"] >= 2 * C
+    t.free()
+
+
+def test_build_empty_and_nonfinite(lk):
+    lkc, ctx = lk
+    t = lkc.lkc_build_target(ctx, torch.zeros(0, 3, device="cuda"), 1.0)
+    assert t.info()["n_points"] == 0
+    q = dev(workloads.random_cloud(100, 1))
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, q, 5)
+    assert int(cnt.sum()) == 0 and bool((idx == -1).all())
+    t.free()
+    p = workloads.random_cloud(300, 2)
+    p[123, 1] = np.nan
+    with pytest.raises(lkc.LkcError) as e:
+        lkc.lkc_build_target(ctx, dev(p), 1.0)
+    assert e.value.status == lkc.LKC_ERR_NONFINITE
+
+
+# ------------------------------------------------------------------ kNN --
+
+@pytest.mark.parametrize("shape,k", [((64,), 1), ((64,), 2), ((64,), 7), ((64,), 8),
+                                     ((9, 9), 7), ((5, 5, 5), 9), ((6, 7, 5), 27), ((10, 10), 64)])
+@pytest.mark.parametrize("cell", [0.7, 1.0, 2.5])
+def test_knn_lattice_exact(lk, shape, k, cell):
+    """Integer lattices: every d2 is exact in float32, so indices, order
+    (lower index first on ties) and d2 must match the oracle exactly."""
+    lat = workloads.lattice_nd(shape) if len(shape) > 1 else workloads.lattice_1d(shape[0])
+    g = run_knn(lk, lat, lat, k, INF, cell)
+    parity.check_knn(lat, lat, k, INF, *g, exact=True)
+    g = run_knn(lk, lat, lat, k, 2.0, cell)
+    parity.check_knn(lat, lat, k, 2.0, *g, exact=True)
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("k", [1, 5, 20, 32, 64])
+def test_knn_random_clouds(lk, seed, k):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(500, 6000))
+    t = workloads.random_cloud(n, seed, scale=3.0, offset=(250.0, -120.0, 1.0))
+    q = workloads.random_cloud(1000 + 37 * seed, seed + 50, scale=3.5, offset=(250.0, -120.0, 1.0))
+    for radius, cell in [(INF, 0.5), (0.6, 0.5), (0.3, 1.0), (1.5, 0.25)]:
+        g = run_knn(lk, t, q, k, radius, cell)
+        parity.check_knn(t, q, k, radius, *g)
+
+
+def test_knn_plane_wall_tiny_config(lk):
+    """2,048-point plane + wall, self-query, k = 10, no radius cap."""
+    p = workloads.plane_wall(2048, seed=0)
+    g = run_knn(lk, p, p, 10, INF, 1.0)
+    parity.check_knn(p, p, 10, INF, *g)
+    assert np.array_equal(g[0][:, 0], np.arange(2048))   # self at distance 0
+
+
+def test_knn_edge_cases(lk):
+    lkc, ctx = lk
+    t = workloads.random_cloud(50, 3, scale=1.0)
+    # k > n, duplicates, non-finite queries, a query far outside the grid
+    q = np.concatenate([t[:5], t[:5], np.array([[np.nan, 0, 0], [0, np.inf, 0],
+                                                [1e4, -1e4, 5e3]], np.float32)])
+    g = run_knn(lk, np.concatenate([t, t[:10]]), q, 64, INF, 0.3)
+    parity.check_knn(np.concatenate([t, t[:10]]), q, 64, INF, *g)
+    assert g[2][10] == 0 and g[2][11] == 0 and g[2][12] == 60
+    # one far outlier: the uncapped search must reach it (sweep path)
+    t2 = np.concatenate([workloads.random_cloud(300, 4, scale=2.0),
+                         np.array([[900.0, -700.0, 40.0]], np.float32)])
+    g = run_knn(lk, t2, t2, 5, INF, 0.1)
+    parity.check_knn(t2, t2, 5, INF, *g)
+    # empty query set
+    tt = lkc.lkc_build_target(ctx, dev(t), 1.0)
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, tt, torch.zeros(0, 3, device="cuda"), 4)
+    assert idx.shape == (0, 4)
+    tt.free()
+
+
+def test_knn_bad_arguments_raise(lk):
+    lkc, ctx = lk
+    t = lkc.lkc_build_target(ctx, dev(workloads.random_cloud(10, 1)), 1.0)
+    q = dev(workloads.random_cloud(4, 2))
+    for k, r in [(0, 1.0), (65, 1.0), (3, 0.0), (3, -1.0), (3, float("nan"))]:
+        with pytest.raises(lkc.LkcError) as e:
+            lkc.lkc_knn_query(ctx, t, q, k, r)
+        assert e.value.status == lkc.LKC_ERR_INVALID_ARG
+    for cfg in [dict(tile_queries=65), dict(waves_per_block=17), dict(merge_min=66)]:
+        with pytest.raises(lkc.LkcError):
+            lkc.lkc_knn_query(ctx, t, q, 3, 1.0, cfg=cfg)
+    with pytest.raises(lkc.LkcError):
+        lkc.lkc_build_target(ctx, dev(workloads.random_cloud(10, 1)), 0.0)
+    t.free()
+
+
+@pytest.mark.parametrize("cfg", [dict(tile_queries=1, waves_per_block=1, merge_min=1),
+                                 dict(tile_queries=16, waves_per_block=8, merge_min=65),
+                                 dict(tile_queries=64, waves_per_block=2, merge_min=4)])
+def test_knn_launch_shapes_agree(lk, cfg):
+    """Any launch shape gives the same bits (the result is order-independent)."""
+    p = workloads.plane_wall(3000, seed=4)
+    a = run_knn(lk, p, p, 20, 0.8, 1.0)
+    b = run_knn(lk, p, p, 20, 0.8, 1.0, cfg=cfg)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------ covariance --
+
+def test_cov_tiny_config_against_oracle(lk):
+    lkc, ctx = lk
+    p = workloads.plane_wall(2048, seed=0)
+    t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+    out = lkc.lkc_knn_cov(ctx, t, dev(p), 10, INF, 1e-3)
+    torch.cuda.synchronize()
+    o = {k: host(v) for k, v in out.items()}
+    parity.check_knn(p, p, 10, INF, o["idx"], o["d2"], o["count"])
+    parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"])
+    t.free()
+
+
+def test_cov_lattice_closed_form(lk):
+    lkc, ctx = lk
+    a = 0.5
+    lat = workloads.lattice_1d(64, a)
+    lat[:, 0] += 300.0   # map-frame offset: query-relative arithmetic keeps precision
+    t = lkc.lkc_build_target(ctx, dev(lat), 1.0)
+    for k in (3, 5, 9, 21):
+        out = lkc.lkc_knn_cov(ctx, t, dev(lat), k, INF, 1e-3)
+        o = {kk: host(v) for kk, v in out.items()}
+        m = k // 2
+        cxx = a * a * (k * k - 1) / 12.0
+        for i in range(m, 64 - m):
+            assert abs(o["mean"][i, 0] - (300.0 + a * i)) <= 1e-5 * (300.0 + a * i)
+            assert abs(o["cov"][i, 0, 0] - cxx) <= 1e-5 * cxx
+            assert np.all(o["cov"][i].ravel()[1:] == 0.0)
+    t.free()
+
+
+def test_cov_plain_equals_fused_bitwise(lk):
+    """lkc_covariances on lkc_knn_query's output == lkc_knn_cov, bit for bit."""
+    lkc, ctx = lk
+    p = workloads.single_scan(seed=7)[:30000]
+    t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+    qd = dev(p)
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, qd, 20, 2.0)
+    plain = lkc.lkc_covariances(ctx, t, idx, cnt, queries=qd)
+    fused = lkc.lkc_knn_cov(ctx, t, qd, 20, 2.0, 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(idx, fused["idx"]) and torch.equal(cnt, fused["count"])
+    assert torch.equal(d2, fused["d2"])
+    for key in ("mean", "cov", "reg", "valid"):
+        assert torch.equal(plain[key], fused[key]), key
+    t.free()
+
+
+def test_cov_null_queries_and_bad_indices(lk):
+    lkc, ctx = lk
+    p = workloads.random_cloud(500, 5, scale=2.0, offset=(50.0, 0.0, 0.0))
+    t = lkc.lkc_build_target(ctx, dev(p), 0.5)
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(p), 8)
+    out = lkc.lkc_covariances(ctx, t, idx, cnt, queries=None)
+    o = {k: host(v) for k, v in out.items()}
+    parity.check_cov(p, host(idx), host(cnt), o["mean"], o["cov"], o["reg"], o["valid"])
+    # an out-of-range index ends the list at that position
+    bad = idx.clone()
+    bad[0, 4] = 10_000
+    bad[1, 0] = -1
+    out = lkc.lkc_covariances(ctx, t, bad, cnt, queries=dev(p))
+    o = {k: host(v) for k, v in out.items()}
+    cut = host(cnt).copy()
+    cut[0], cut[1] = 4, 0
+    parity.check_cov(p, host(idx), cut, o["mean"], o["cov"], o["reg"], o["valid"], rows=[0, 1])
+    t.free()
+
+
+# ------------------------------------------------------- full-size configs --
+
+@pytest.fixture(scope="module")
+def scan_c2():
+    return workloads.single_scan(seed=1)
+
+
+def test_scan_config_sampled_parity(lk, scan_c2):
+    """One ~118k-point scan, self-query, k = 20, r = 2 m, cell 1 m."""
+    lkc, ctx = lk
+    p = scan_c2
+    t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+    out = lkc.lkc_knn_cov(ctx, t, dev(p), 20, 2.0, 1e-3)
+    torch.cuda.synchronize()
+    o = {k: host(v) for k, v in out.items()}
+    rows = np.sort(np.random.default_rng(11).choice(p.shape[0], 1500, replace=False))
+    rows = np.concatenate([rows, [0, p.shape[0] - 1]])
+    parity.check_knn(p, p, 20, 2.0, o["idx"], o["d2"], o["count"], rows=rows)
+    parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"],
+                     rows=rows)
+    # properties on every query: self first, ascending, within radius, in range
+    assert np.all(o["idx"][:, 0] == np.arange(p.shape[0]))
+    assert np.all(o["count"] >= 1) and np.all(o["count"] <= 20)
+    d = o["d2"]
+    fin = np.isfinite(d)
+    assert np.all(d[fin] <= 4.0)
+    dd = np.where(fin, d, np.inf)
+    assert np.all(np.diff(dd, axis=1)[fin[:, 1:]] >= 0)
+    t.free()
+
+
+@pytest.fixture(scope="module")
+def map_c3():
+    m, _ = workloads.build_map(2_000_000, seed=2)
+    s = workloads.source_scan(65_536, seed=3)
+    return m, s
+
+
+def test_scan_to_map_sampled_parity(lk, map_c3):
+    """65,536-point scan against the 2,000,000-point voxelised map."""
+    lkc, ctx = lk
+    m, s = map_c3
+    t = lkc.lkc_build_target(ctx, dev(m), 1.0)
+    out = lkc.lkc_knn_cov(ctx, t, dev(s), 20, 2.0, 1e-3)
+    torch.cuda.synchronize()
+    o = {k: host(v) for k, v in out.items()}
+    rows = np.sort(np.random.default_rng(12).choice(s.shape[0], 400, replace=False))
+    parity.check_knn(m, s, 20, 2.0, o["idx"], o["d2"], o["count"], rows=rows)
+    parity.check_cov(m, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"])
+    t.free()
+
+
+# ------------------------------------------------------------- batched --
+
+def test_batched_equals_per_scan_bitwise(lk, map_c3):
+    """Uneven scans against two targets in one persistent launch: every
+    scan's rows equal lkc_knn_cov on that scan alone, bit for bit."""
+    lkc, ctx = lk
+    m, s = map_c3
+    small = workloads.plane_wall(5000, seed=9)
+    tm = lkc.lkc_build_target(ctx, dev(m), 1.0)
+    ts = lkc.lkc_build_target(ctx, dev(small), 0.5)
+    rng = np.random.default_rng(3)
+    sizes = [int(rng.integers(1, 9000)) for _ in range(7)] + [0, 64, 65, 63]
+    scans, parts, off = [], [], 0
+    for i, n in enumerate(sizes):
+        tgt = i % 2
+        src = s if tgt == 0 else small
+        sel = rng.choice(src.shape[0], size=min(n, src.shape[0]), replace=False)
+        parts.append(src[np.sort(sel)])
+        scans.append((off, parts[-1].shape[0], tgt))
+        off += parts[-1].shape[0]
+    allq = np.concatenate(parts)
+    tset = lkc.TargetSet(ctx, [tm, ts], max_scans=32)
+    tset.stage(scans)
+    got = lkc.lkc_knn_cov_batched(ctx, tset, dev(allq), 20, 2.0, 1e-3)
+    got2 = lkc.lkc_knn_cov_batched(ctx, tset, dev(allq), 20, 2.0, 1e-3)   # counter reset
+    torch.cuda.synchronize()
+    for (o, n, tgt), part in zip(scans, parts):
+        alone = lkc.lkc_knn_cov(ctx, [tm, ts][tgt], dev(part), 20, 2.0, 1e-3)
+        torch.cuda.synchronize()
+        for key in alone:
+            assert torch.equal(alone[key], got[key][o:o + n]), key
+            assert torch.equal(alone[key], got2[key][o:o + n]), key
+    with pytest.raises(lkc.LkcError) as e:
+        tset.stage([(0, 1, 0)] * 33)
+    assert e.value.status == lkc.LKC_ERR_BUDGET
+    tset.free()
+    tm.free()
+    ts.free()
