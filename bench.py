@@ -1,0 +1,315 @@
+"""Benchmark: kNN (k = 20) + covariance query points/s on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scan|map|batched|tiny]
+
+Default workload ``scan``: one spinning-LiDAR scan (128 x 1024 rays, 10 %
+dropout, ~118k points, sensor frame) queried against itself, k = 20,
+r = 2 m, 1 m cells.  One step = rebuild the hashed grid from the scan +
+fused search + covariance of every point, i.e. the whole per-scan path; the
+step ends when the results are on the device (per-scan latency).
+
+Other workloads: ``map`` (65,536-point scan against the resident
+2,000,000-point voxelised map; a step is one fused launch), ``batched``
+(48 uneven scans against the map in one persistent launch; a step is one
+launch, and the plain one-launch-per-scan loop is timed beside it), ``tiny``
+(2,048-point plane + wall, k = 10, no cap).
+
+Prints ONE JSON line.  ``value`` = queries/s over the timed steps (inputs
+resident in HBM).  ``roofline`` is for the search kernel: algorithmic bytes
+per query ``20 k + 100`` (query read, k neighbour gathers of 12 B, idx + d2 +
+count, mean + cov + reg_cov writes) times the queries of one launch, divided
+by the launch's mean duration from HIP events on the stream the kernel runs
+on.  ``traffic`` comes from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+summary for the same kernel source, else null.  ``cpu_baseline`` is the FP64
+oracle (brute force) on the host's cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "kNN(k=20)+covariance query points/s and % HBM roofline; p99 scan latency"
+
+
+def b_alg(k: int) -> int:
+    return 20 * k + 100
+
+
+def kernel_src_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("search.hip", "lkc_device.h"):
+        with open(os.path.join(ROOT, "paper_2308_07173_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(workload: str):
+    """HBM bytes per launch from the committed PMC summary, if the search
+    kernel source is unchanged since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_search_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    return d.get("traffic_bytes")
+
+
+def cpu_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def oracle_baseline(target, queries, k, radius, sample_rows, label):
+    from oracle import oracle
+    q = queries[sample_rows]
+    th = cpu_threads()
+    t0 = time.perf_counter()
+    idx, d2, cnt = oracle.knn(target, q, k, radius, threads=th)
+    oracle.covariances(target, idx, cnt, eps=1e-3, threads=th)
+    dt = time.perf_counter() - t0
+    return {"value": q.shape[0] / dt, "unit": "queries/s", "cores": th, "kind": "oracle",
+            "sample": f"{q.shape[0]} of {queries.shape[0]} queries ({label}); "
+                      f"{dt:.2f} s FP64 brute-force kNN + covariance"}
+
+
+def pct(xs, p):
+    return float(np.percentile(np.asarray(xs), p)) if len(xs) else float("nan")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="scan", choices=["scan", "map", "batched", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cfg", default="", help="launch cfg, e.g. tile_queries=32,merge_min=8")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, launch one plain device copy of this many MiB "
+                         "(reference dispatch for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this path has no multi-GPU mode "
+              "(queries shard with no exchange; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2308_07173_amd import lkc, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    cfg = None
+    if args.cfg:
+        cfg = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.cfg.split(",")}
+    ctx = lkc.Context()
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+    extra = {}
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    if args.workload in ("scan", "tiny"):
+        if args.workload == "scan":
+            pts = workloads.single_scan(seed=1)
+            k, radius, cell = 20, 2.0, 1.0
+            config = {"workload": "one 128x1024 spinning-LiDAR scan, self-query",
+                      "n_points": int(pts.shape[0]), "k": k, "radius_m": radius,
+                      "cell_m": cell, "step": "grid rebuild + fused kNN+covariance"}
+        else:
+            pts = workloads.plane_wall(2048, seed=0)
+            k, radius, cell = 10, math.inf, 1.0
+            config = {"workload": "2048-point plane + wall, self-query", "n_points": 2048,
+                      "k": k, "radius_m": None, "cell_m": cell,
+                      "step": "grid rebuild + fused kNN+covariance"}
+        p = torch.from_numpy(pts).to(dev)
+        Q = p.shape[0]
+        tgt = lkc.lkc_build_target(ctx, p, cell)
+        out = lkc.lkc_knn_cov_self(ctx, tgt, k, radius, 1e-3, cfg=cfg)
+
+        def step(kstart=None, kend=None):
+            tgt.rebuild(p)
+            if kstart is not None:
+                kstart.record(stream)
+            lkc.lkc_knn_cov_self(ctx, tgt, k, radius, 1e-3, out=out, cfg=cfg)
+            if kend is not None:
+                kend.record(stream)
+
+        for _ in range(W):
+            step()
+        torch.cuda.synchronize()
+        ks = [(ev(), ev()) for _ in range(K)]
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(K):
+            s0 = time.perf_counter()
+            step(*ks[i])
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - s0)
+        t1 = time.perf_counter()
+        kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ks]))
+        total = t1 - t0
+        queries_per_launch = Q
+        extra["latency_ms"] = {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
+                               "max": max(lat) * 1e3}
+        extra["search_kernel_ms"] = kern_ms
+        extra["build_ms_mean"] = total / K * 1e3 - kern_ms
+        info = tgt.info()
+        extra["grid"] = {"cells": info["n_cells"], "hash_capacity": info["hash_capacity"],
+                         "sort_passes": info["sort_passes"]}
+        baseline_args = (pts, pts, k, radius, np.arange(Q), "the whole scan")
+    elif args.workload == "map":
+        m, _ = workloads.build_map(2_000_000, seed=2)
+        s = workloads.source_scan(65_536, seed=3)
+        k, radius, cell = 20, 2.0, 1.0
+        config = {"workload": "65,536-point scan vs 2,000,000-point voxelised map",
+                  "n_points": 65536, "map_points": 2_000_000, "k": k, "radius_m": radius,
+                  "cell_m": cell, "step": "fused kNN+covariance (map resident)"}
+        mp = torch.from_numpy(m).to(dev)
+        sq = torch.from_numpy(s).to(dev)
+        torch.cuda.synchronize()
+        b0 = time.perf_counter()
+        tgt = lkc.lkc_build_target(ctx, mp, cell)
+        torch.cuda.synchronize()
+        extra["map_build_ms"] = (time.perf_counter() - b0) * 1e3
+        out = lkc.lkc_knn_cov(ctx, tgt, sq, k, radius, 1e-3, cfg=cfg)
+        Q = sq.shape[0]
+
+        def step(kstart=None, kend=None):
+            if kstart is not None:
+                kstart.record(stream)
+            lkc.lkc_knn_cov(ctx, tgt, sq, k, radius, 1e-3, out=out, cfg=cfg)
+            if kend is not None:
+                kend.record(stream)
+
+        for _ in range(W):
+            step()
+        torch.cuda.synchronize()
+        ks = [(ev(), ev()) for _ in range(K)]
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(K):
+            s0 = time.perf_counter()
+            step(*ks[i])
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - s0)
+        t1 = time.perf_counter()
+        kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ks]))
+        total = t1 - t0
+        queries_per_launch = Q
+        extra["latency_ms"] = {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3}
+        extra["search_kernel_ms"] = kern_ms
+        rows = np.sort(np.random.default_rng(0).choice(Q, 4096, replace=False))
+        baseline_args = (m, s, k, radius, rows, "seeded subsample")
+    else:  # batched
+        m, _ = workloads.build_map(2_000_000, seed=2)
+        scans = workloads.batched_scans(16, seed=4)
+        k, radius, cell = 20, 2.0, 1.0
+        allq = np.concatenate(scans)
+        offs = np.cumsum([0] + [sc.shape[0] for sc in scans])
+        Q = allq.shape[0]
+        config = {"workload": "48 uneven scans (16 frames x 3 LiDARs) vs 2,000,000-point map",
+                  "n_points": int(Q), "scans": len(scans), "map_points": 2_000_000, "k": k,
+                  "radius_m": radius, "cell_m": cell,
+                  "step": "one persistent batched kNN+covariance launch"}
+        mp = torch.from_numpy(m).to(dev)
+        aq = torch.from_numpy(allq).to(dev)
+        tgt = lkc.lkc_build_target(ctx, mp, cell)
+        tset = lkc.TargetSet(ctx, [tgt], max_scans=len(scans))
+        tset.stage([(int(offs[i]), int(scans[i].shape[0]), 0) for i in range(len(scans))])
+        out = lkc.lkc_knn_cov_batched(ctx, tset, aq, k, radius, 1e-3, cfg=cfg)
+
+        def step(kstart=None, kend=None):
+            if kstart is not None:
+                kstart.record(stream)
+            lkc.lkc_knn_cov_batched(ctx, tset, aq, k, radius, 1e-3, out=out, cfg=cfg)
+            if kend is not None:
+                kend.record(stream)
+
+        for _ in range(W):
+            step()
+        torch.cuda.synchronize()
+        ks = [(ev(), ev()) for _ in range(K)]
+        t0 = time.perf_counter()
+        for i in range(K):
+            step(*ks[i])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ks]))
+        total = t1 - t0
+        queries_per_launch = Q
+        extra["search_kernel_ms"] = kern_ms
+        # the plain path: one fused launch per scan, same stream
+        views = [aq[offs[i]:offs[i + 1]] for i in range(len(scans))]
+        outs = [lkc.lkc_knn_cov(ctx, tgt, v, k, radius, 1e-3) for v in views]
+        torch.cuda.synchronize()
+        pe = (ev(), ev())
+        pe[0].record(stream)
+        for v, o in zip(views, outs):
+            lkc.lkc_knn_cov(ctx, tgt, v, k, radius, 1e-3, out=o)
+        pe[1].record(stream)
+        torch.cuda.synchronize()
+        plain_ms = pe[0].elapsed_time(pe[1])
+        extra["plain_per_scan_loop_ms"] = plain_ms
+        extra["plain_per_scan_loop_qps"] = Q / (plain_ms * 1e-3)
+        rows = np.sort(np.random.default_rng(0).choice(Q, Q // 256, replace=False))
+        baseline_args = (m, allq, k, radius, rows, "seeded 1/256 subsample")
+
+    value = queries_per_launch * K / total
+    achieved = queries_per_launch * b_alg(k) / (kern_ms * 1e-3) / 1e9
+    traffic = committed_traffic(args.workload)
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": total / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded ray-cast race-track LiDAR)",
+        "config": config,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "search (query sort + k_group + k_fallback)",
+                     "bytes_per_query": b_alg(k), "queries_per_launch": int(queries_per_launch),
+                     "kernel_ms": kern_ms},
+    }
+    res.update(extra)
+    if cfg:
+        res["launch_cfg"] = cfg
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = oracle_baseline(*baseline_args)
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = nb
+    print(json.dumps(res))
+    ctx.synchronize()
+
+
+if __name__ == "__main__":
+    main()

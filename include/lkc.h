@@ -73,22 +73,29 @@ typedef enum lkc_status {
     LKC_ERR_UNSUPPORTED = -6  /* no usable gfx950 device */
 } lkc_status;
 
-/* Launch shape of the search kernels.  Any field <= 0 takes the default.
- *  tile_queries      queries one wavefront handles back to back; their
- *                    covariances are then computed one query per lane
- *                    (1..64, default 64)
- *  waves_per_block   wavefronts per workgroup (1..16, default 4)
- *  merge_min         a batch of candidates with at least this many entries
- *                    below the current k-th distance is merged by a bitonic
- *                    network instead of one insertion per entry (1..65,
- *                    default 12; 65 disables the network)
- *  blocks_per_cu     persistent workgroups per compute unit for the batched
- *                    call (default 8) */
+/* Launch options of the search.  Zero-initialised means "all defaults".
+ *  algorithm        0 auto; 1 lane-per-query group search (queries sorted by
+ *                   cell, one wavefront per 64 queries, register top-k, a
+ *                   wavefront-per-query pass for the queries it cannot prove
+ *                   exact); 2 wavefront-per-query search for every query.
+ *                   Auto takes 1 for k <= 32 and 2 above.  Both give
+ *                   bit-identical results.
+ *  group_reach      cells the group search looks beyond its queries' cells
+ *                   (0 = auto: ceil(radius / cell) clamped to [1, 2]; 1..4)
+ *  waves_per_block  wavefronts per workgroup (0 = 4; 1..4)
+ *  merge_min        the wavefront search merges a candidate batch with at
+ *                   least this many entries below the k-th distance by a
+ *                   bitonic network instead of one insertion per entry
+ *                   (0 = 12; 1..65, 65 disables the network)
+ *  persistent       0: one wavefront per 64-query group; n > 0: n persistent
+ *                   workgroups per compute unit pull groups from per-XCD
+ *                   work counters (0..32) */
 typedef struct lkc_launch_cfg {
-    int32_t tile_queries;
+    int32_t algorithm;
+    int32_t group_reach;
     int32_t waves_per_block;
     int32_t merge_min;
-    int32_t blocks_per_cu;
+    int32_t persistent;
 } lkc_launch_cfg;
 
 /* Static description of a built target (host struct). */
@@ -161,7 +168,9 @@ lkc_status lkc_target_arrays(const lkc_target *target, const void **pts, const v
 /* k nearest neighbours of each query (device [q][3]) in `target`:
  * idx int32 [q][k] (original target indices, -1 padding), d2 float [q][k]
  * (+INFINITY padding), count int32 [q].  1 <= k <= LKC_MAX_K; radius > 0
- * (INFINITY = uncapped).  cfg may be NULL. */
+ * (INFINITY = uncapped).  cfg may be NULL.  Uses the context's search
+ * scratch, growing it (allocation + synchronisation) when q exceeds what it
+ * holds. */
 lkc_status lkc_knn_query(lkc_ctx *ctx, const lkc_target *target, const float *queries, int64_t q,
                          int32_t k, float radius, int32_t *idx, float *d2, int32_t *count,
                          const lkc_launch_cfg *cfg);
@@ -190,30 +199,50 @@ lkc_status lkc_knn_cov(lkc_ctx *ctx, const lkc_target *target, const float *quer
 /* A set of targets addressable by the batched call.  Creating a set uploads
  * one small descriptor per target and sizes the set's scan table for at
  * most `max_scans` scans (host array of target pointers).  The targets must
- * outlive the set and must not be rebuilt while the set is in use. */
+ * outlive the set and must not be rebuilt while the set is in use.
+ * Synchronises. */
 lkc_status lkc_target_set_create(lkc_ctx *ctx, const lkc_target *const *targets,
                                  int32_t n_targets, int32_t max_scans, lkc_target_set **out);
 lkc_status lkc_target_set_free(lkc_ctx *ctx, lkc_target_set *set);
 
-/* Stage a batch description: copy `n_scans` scan descriptors (host array)
- * into the set's device scan table (one stream-ordered copy from the set's
- * pinned staging buffer).  Fails with LKC_ERR_BUDGET when n_scans exceeds
- * max_scans.  Descriptors must not overlap and must lie inside the query
- * array passed to lkc_knn_cov_batched. */
+/* Stage a batch description: `n_scans` scan descriptors (host array) that
+ * tile the concatenated query array in order (scan 0 at offset 0, each scan
+ * starting where the previous one ends).  One stream-ordered copy from the
+ * set's pinned staging buffer to its device table; synchronises first so
+ * that buffer is free.  LKC_ERR_BUDGET when n_scans > max_scans. */
 lkc_status lkc_target_set_stage(lkc_ctx *ctx, lkc_target_set *set, const lkc_scan_desc *scans,
                                 int32_t n_scans);
 
-/* Search + covariance for every scan staged in `set`, in one persistent
- * launch that pulls 64-query tiles from a device work counter.  queries is
- * the concatenated query array; the outputs are concatenated in the same
- * query order, in the layouts of lkc_knn_cov.  The launch reads the staged
- * table from device memory and allocates nothing, so it may be captured
- * once in a HIP graph and replayed after each lkc_target_set_stage.  Per
- * query the results are bit-identical to lkc_knn_cov on that scan alone. */
+/* Search + covariance for every scan staged in `set`: the queries of all
+ * scans are keyed by (target, cell) and sorted together, then one group
+ * search launch (persistent with cfg->persistent > 0) and one
+ * wavefront-per-query launch cover them all.  total_q must equal the
+ * number of queries the staged scans cover; outputs are concatenated in
+ * query order in the layouts of lkc_knn_cov.  Scratch comes from the
+ * context (see lkc_ctx_reserve), so once reserved the call allocates
+ * nothing and can be captured in a HIP graph; a capture stays valid for
+ * any later stage with the same total_q.  Per query the results are
+ * bit-identical to lkc_knn_cov on that scan alone. */
 lkc_status lkc_knn_cov_batched(lkc_ctx *ctx, lkc_target_set *set, const float *queries,
                                int64_t total_q, int32_t k, float radius, float plane_eps,
                                int32_t *idx, float *d2, int32_t *count, float *mean, float *cov,
                                float *reg_cov, uint8_t *valid, const lkc_launch_cfg *cfg);
+
+/* Self-query: the k nearest neighbours (and, when `valid` is not NULL, the
+ * covariances) of every point of the target itself, each point being its
+ * own first neighbour at distance 0 -- the per-scan covariance GICP needs
+ * for its source cloud.  Rows are in the target's original point order;
+ * no query sort is needed because the target's points are already in cell
+ * order.  Output layouts as lkc_knn_cov with q = n_points. */
+lkc_status lkc_knn_cov_self(lkc_ctx *ctx, const lkc_target *target, int32_t k, float radius,
+                            float plane_eps, int32_t *idx, float *d2, int32_t *count, float *mean,
+                            float *cov, float *reg_cov, uint8_t *valid, const lkc_launch_cfg *cfg);
+
+/* Grow the context's search scratch (query sort buffers and the fallback
+ * list, about 36 bytes per query) to `max_queries` now, so that later
+ * searches of at most that many queries allocate nothing.  Synchronises
+ * when it has to grow. */
+lkc_status lkc_ctx_reserve(lkc_ctx *ctx, int64_t max_queries);
 
 #ifdef __cplusplus
 }

@@ -62,7 +62,8 @@ lkc_status check_k_radius(lkc_ctx* ctx, int32_t k, float radius) {
 
 lkc_status check_target(lkc_ctx* ctx, const lkc_target* t) {
     if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
-    if (!t->cell_mem) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is not built");
+    if (!t->cell_mem || !t->view_dev)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "target is not built");
     return LKC_OK;
 }
 
@@ -108,6 +109,7 @@ lkc_status lkc_ctx_destroy(lkc_ctx* ctx) {
     if (!ctx) return LKC_OK;
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->build_scratch) (void)hipFree(ctx->build_scratch);
+    if (ctx->search_scratch) (void)hipFree(ctx->search_scratch);
     if (ctx->meta_dev) (void)hipFree(ctx->meta_dev);
     if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
     delete ctx;
@@ -290,6 +292,13 @@ lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,
         return set_error(ctx, LKC_ERR_OOM, "host allocation");
     }
     for (int i = 0; i < n_targets; ++i) hv[i] = targets[i]->view;
+    set->host_views = new (std::nothrow) lkc::TargetView[n_targets];
+    if (!set->host_views) {
+        delete[] hv;
+        lkc_target_set_free(ctx, set);
+        return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    }
+    for (int i = 0; i < n_targets; ++i) set->host_views[i] = hv[i];
     e = hipMemcpyAsync(set->views_dev, hv, vb, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(set->header_dev, set->staging_host, set->table_bytes,
@@ -310,6 +319,7 @@ lkc_status lkc_target_set_free(lkc_ctx* ctx, lkc_target_set* set) {
     if (set->views_dev) (void)hipFree(set->views_dev);
     if (set->header_dev) (void)hipFree(set->header_dev);
     if (set->staging_host) (void)hipHostFree(set->staging_host);
+    delete[] set->host_views;
     delete set;
     return LKC_OK;
 }
@@ -324,39 +334,37 @@ lkc_status lkc_target_set_stage(lkc_ctx* ctx, lkc_target_set* set, const lkc_sca
     if (n_scans > set->max_scans)
         return set_error(ctx, LKC_ERR_BUDGET, "%d scans exceed the set's max_scans = %d", n_scans,
                          set->max_scans);
-    // validate everything before touching the staging buffer
-    int64_t tiles = 0, qend = 0;
+    // validate everything before touching the staging buffer: the scans must
+    // tile [0, total) in order
+    int64_t next = 0;
     for (int i = 0; i < n_scans; ++i) {
         const lkc_scan_desc& d = scans[i];
-        if (d.q_offset < 0 || d.q_count < 0 || d.target_index < 0 ||
-            d.target_index >= set->n_targets)
-            return set_error(ctx, LKC_ERR_INVALID_ARG, "scan %d: bad offset, count or target", i);
-        if (d.q_offset + d.q_count > 0x7fffffffLL)
-            return set_error(ctx, LKC_ERR_INVALID_ARG, "scan %d exceeds 2^31 queries", i);
-        tiles += (d.q_count + 63) / 64;
-        if (d.q_offset + d.q_count > qend) qend = d.q_offset + d.q_count;
+        if (d.q_count < 0 || d.target_index < 0 || d.target_index >= set->n_targets)
+            return set_error(ctx, LKC_ERR_INVALID_ARG, "scan %d: bad count or target", i);
+        if (d.q_offset != next)
+            return set_error(ctx, LKC_ERR_INVALID_ARG,
+                             "scan %d starts at %lld; scans must be contiguous from 0 (expected %lld)",
+                             i, (long long)d.q_offset, (long long)next);
+        next += d.q_count;
+        if (next > 0x7fffffffLL)
+            return set_error(ctx, LKC_ERR_INVALID_ARG, "scans exceed 2^31 queries");
     }
-    if (tiles > 0x7fffffffLL) return set_error(ctx, LKC_ERR_INVALID_ARG, "too many tiles");
     // the host buffer may still be read by a previous stage's copy
     LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     auto* h = (BatchHeader*)set->staging_host;
     auto* hs = (BatchScan*)(h + 1);
-    int64_t tb = 0;
     for (int i = 0; i < n_scans; ++i) {
         hs[i].q_offset = scans[i].q_offset;
         hs[i].q_count = scans[i].q_count;
         hs[i].target_index = scans[i].target_index;
-        hs[i].tile_begin = (int32_t)tb;
-        tb += (scans[i].q_count + 63) / 64;
+        hs[i].reserved = 0;
     }
     h->n_scans = n_scans;
-    h->n_tiles = (int32_t)tiles;
-    h->work_counter = 0;
-    h->waves_done = 0;
-    const size_t bytes = sizeof(BatchHeader) + sizeof(BatchScan) * (size_t)(n_scans > 0 ? n_scans : 0);
+    const size_t bytes = sizeof(BatchHeader) + sizeof(BatchScan) * (size_t)n_scans;
     LKC_HIP_TRY(ctx, hipMemcpyAsync(set->header_dev, set->staging_host, bytes,
                                     hipMemcpyHostToDevice, ctx->stream));
-    set->max_query_end = qend;
+    set->staged_scans = n_scans;
+    set->staged_total = next;
     return LKC_OK;
 }
 
@@ -372,10 +380,31 @@ lkc_status lkc_knn_cov_batched(lkc_ctx* ctx, lkc_target_set* set, const float* q
     if (total_q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "total_q < 0");
     if (total_q > 0 && (!queries || !idx || !d2 || !count || !valid))
         return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
-    lkc::LaunchCfg c = lkc::resolve_cfg(cfg);
-    if (!cfg || cfg->tile_queries <= 0) c.tile_queries = 64;
     return lkc::launch_batched(ctx, set, queries, total_q, k, radius, plane_eps, idx, d2, count,
-                               mean, cov, reg_cov, valid, c);
+                               mean, cov, reg_cov, valid, lkc::resolve_cfg(cfg));
+}
+
+lkc_status lkc_knn_cov_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float radius,
+                            float plane_eps, int32_t* idx, float* d2, int32_t* count, float* mean,
+                            float* cov, float* reg_cov, uint8_t* valid,
+                            const lkc_launch_cfg* cfg) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if ((s = check_k_radius(ctx, k, radius)) != LKC_OK) return s;
+    if (valid && (s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
+    if (t->view.n > 0 && (!idx || !d2 || !count))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL output pointer");
+    return lkc::launch_knn_self(ctx, t, k, radius, plane_eps, idx, d2, count, mean, cov, reg_cov,
+                                valid, lkc::resolve_cfg(cfg));
+}
+
+lkc_status lkc_ctx_reserve(lkc_ctx* ctx, int64_t max_queries) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (max_queries < 0 || max_queries > 0x7fffffffLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "max_queries outside [0, 2^31 - 1]");
+    return lkc::reserve_search(ctx, max_queries);
 }
 
 }  // extern "C"

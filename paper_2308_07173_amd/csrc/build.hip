@@ -350,10 +350,40 @@ lkc_status ensure_scratch(lkc_ctx* ctx, size_t bytes) {
 
 }  // namespace
 
+size_t sort_count_words(int64_t n) {
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    return (size_t)RADIX * (size_t)(nb > 0 ? nb : 1);
+}
+
+lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsigned long long* kb,
+                      uint32_t* vb, int64_t n, int bits, uint32_t* counts, bool* in_b) {
+    hipStream_t st = ctx->stream;
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    bool b = false;
+    for (int shift = 0; shift < bits && n > 1; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(BT), 0, st, ka, n, shift,
+                           counts, (int)nb);
+        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, counts,
+                           (int64_t)RADIX * nb, (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(BT), 0, st, ka, va, kb, vb,
+                           n, shift, counts, (int)nb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+        b = !b;
+    }
+    LKC_HIP_TRY(ctx, hipGetLastError());
+    *in_b = b;
+    return LKC_OK;
+}
+
 void free_target_memory(lkc_target* t) {
     if (t->point_mem) (void)hipFree(t->point_mem);
     if (t->cell_mem) (void)hipFree(t->cell_mem);
+    if (t->view_dev) (void)hipFree(t->view_dev);
+    if (t->view_host) (void)hipHostFree(t->view_host);
     t->point_mem = t->cell_mem = nullptr;
+    t->view_dev = nullptr;
+    t->view_host = nullptr;
     t->point_bytes = t->cell_bytes = 0;
 }
 
@@ -369,7 +399,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     t->sort_passes = 0;
 
     // ---- point storage (pts + orig), grow-only
-    const size_t pbytes = align256(sizeof(float4) * (size_t)(n > 0 ? n : 1));
+    // pts carries 16 spare records: the search streams candidates four at a
+    // time and may read up to three records past the last run
+    const size_t pbytes = align256(sizeof(float4) * ((size_t)(n > 0 ? n : 1) + 16));
     if (t->point_bytes < 2 * pbytes) {
         if (t->point_mem) {
             LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -518,7 +550,7 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n_cells, BT)), dim3(BT), 0, st, tkeys,
                            tstart, n_cells, n, ckeys, cstart, hash, hbits, (uint32_t)(cap - 1));
     } else {
-        LKC_HIP_TRY(ctx, hipMemsetAsync(cstart, 0, 4, st));
+        hipLaunchKernelGGL(k_iota, dim3(1), dim3(1), 0, st, cstart, (int64_t)1);
     }
     LKC_HIP_TRY(ctx, hipGetLastError());
 
@@ -532,6 +564,22 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     V.hash_bits = hbits;
     V.hash_mask = (uint32_t)(cap - 1);
     t->hash_capacity = cap;
+    if (!t->view_dev) {
+        hipError_t e = hipMalloc((void**)&t->view_dev, sizeof(TargetView));
+        if (e == hipSuccess) e = hipHostMalloc(&t->view_host, sizeof(TargetView), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            if (t->view_dev) (void)hipFree(t->view_dev);
+            t->view_dev = nullptr;
+            t->view_host = nullptr;
+            return set_error(ctx, LKC_ERR_OOM, "target view: %s", hipGetErrorString(e));
+        }
+    }
+    // the pinned copy is only rewritten by the next build, which has
+    // synchronised the stream by this point, so the previous copy is done
+    if (n == 0) LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+    *(TargetView*)t->view_host = V;
+    LKC_HIP_TRY(ctx, hipMemcpyAsync(t->view_dev, t->view_host, sizeof(TargetView),
+                                    hipMemcpyHostToDevice, st));
     return LKC_OK;
 }
 

@@ -103,6 +103,23 @@ __device__ __forceinline__ bool key_less(float da, int32_t ia, float db, int32_t
     return da < db || (da == db && ia < ib);
 }
 
+// Load a read-only object at a wavefront-uniform address through the
+// constant address space, so the compiler issues scalar loads (one request
+// for the whole wavefront, results in SGPRs).  Only for memory no kernel
+// writes while the reading kernel runs.
+typedef __attribute__((address_space(4))) const uint32_t const_u32;
+
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized objects only");
+    T out;
+    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+    const const_u32* s = (const const_u32*)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = s[i];
+    return out;
+}
+
 // --------------------------------------------------------------- wavefront --
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }

@@ -21,6 +21,9 @@ struct lkc_ctx {
     // small device/pinned words for build metadata read-back
     void* meta_dev = nullptr;
     void* meta_host = nullptr;
+    // grow-only device scratch for searches (query sort, fallback list)
+    void* search_scratch = nullptr;
+    size_t search_scratch_bytes = 0;
 };
 
 struct lkc_target {
@@ -34,6 +37,8 @@ struct lkc_target {
     size_t point_bytes = 0;
     void* cell_mem = nullptr;    // cell_keys + cell_start + hash
     size_t cell_bytes = 0;
+    lkc::TargetView* view_dev = nullptr;  // device copy of `view`
+    void* view_host = nullptr;            // pinned staging for that copy
 };
 
 // Device-side staged batch: header + scan table.
@@ -41,25 +46,25 @@ struct BatchScan {
     int64_t q_offset;
     int64_t q_count;
     int32_t target_index;
-    int32_t tile_begin;   // first tile of this scan (exclusive prefix)
+    int32_t reserved;
 };
 
 struct BatchHeader {
     int32_t n_scans;
-    int32_t n_tiles;
-    uint32_t work_counter;   // next tile to hand out
-    uint32_t waves_done;     // waves that found the queue empty
+    int32_t reserved[3];
 };
 
 struct lkc_target_set {
     int32_t n_targets = 0;
     int32_t max_scans = 0;
     lkc::TargetView* views_dev = nullptr;   // [n_targets]
+    lkc::TargetView* host_views = nullptr;  // host copy (sizes the query sort key)
     BatchHeader* header_dev = nullptr;      // header followed by BatchScan[max_scans]
     BatchScan* scans_dev = nullptr;
     void* staging_host = nullptr;           // pinned, same layout as header_dev
     size_t table_bytes = 0;
-    int64_t max_query_end = 0;              // largest q_offset + q_count staged
+    int32_t staged_scans = 0;
+    int64_t staged_total = 0;               // queries covered by the staged scans
 };
 
 namespace lkc {
@@ -70,18 +75,28 @@ lkc_status hip_error(lkc_ctx* ctx, hipError_t e, const char* what);
 // implemented in build.hip
 lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n);
 void free_target_memory(lkc_target* t);
+size_t sort_count_words(int64_t n);
+// stable LSD radix sort of (key, val) pairs on the low `bits` key bits;
+// *in_b tells whether the result ended in the b buffers
+lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsigned long long* kb,
+                      uint32_t* vb, int64_t n, int bits, uint32_t* counts, bool* in_b);
 
 // implemented in search.hip
 struct LaunchCfg {
-    int tile_queries;
+    int algorithm;        // 0 auto, 1 group (lane per query), 2 wavefront per query
+    int group_reach;      // block reach in cells (0 = auto)
     int waves_per_block;
     int merge_min;
-    int blocks_per_cu;
+    int persistent;       // 0 = one wave per group; n = n persistent workgroups per CU
 };
 LaunchCfg resolve_cfg(const lkc_launch_cfg* cfg);
 lkc_status launch_knn(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
                       int32_t k, float radius, int32_t* idx, float* d2, int32_t* count,
                       const LaunchCfg& cfg);
+lkc_status launch_knn_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float radius,
+                           float eps, int32_t* idx, float* d2, int32_t* count, float* mean,
+                           float* cov, float* reg, uint8_t* valid, const LaunchCfg& cfg);
+lkc_status reserve_search(lkc_ctx* ctx, int64_t max_queries);
 lkc_status launch_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries,
                       const int32_t* idx, const int32_t* count, int64_t q, int32_t k, float eps,
                       float* mean, float* cov, float* reg, uint8_t* valid);

@@ -447,110 +447,365 @@ struct KnnPtrs {
     int32_t* count;
 };
 
-// ------------------------------------------------------------------ tiles --
+// ---------------------------------------------------------- group search --
+//
+// Lane-per-query search over queries sorted by grid cell.  A wavefront takes
+// 64 consecutive sorted queries (a "group": they sit in one or a few
+// neighbouring cells), probes the cells of the group's block (its cells
+// grown by R on every side) in parallel, and streams every surviving cell's
+// point run once for the whole group: the candidate address is the same in
+// all lanes, so each load is one broadcast.  Each lane keeps its own sorted
+// top-k in registers as 64-bit keys ((bits(d2) + 1) << 32 | original index;
+// d2 >= 0, so the integer order of the keys is the (d2, index) order).  A
+// lane whose result the block cannot prove exact (the k-th distance, or the
+// radius, reaches past the block) is handed to the wavefront-per-query
+// search through a fallback list.
 
-// Search `nq` consecutive queries starting at q0, one after another with the
-// whole wavefront; with FUSED, keep the neighbour positions in LDS and then
-// compute the tile's covariances one query per lane.
-template <bool FUSED>
-__device__ __forceinline__ void run_tile(const TargetView& T, const float* __restrict__ queries,
-                                         int64_t q0, int nq, const SearchParams& sp,
-                                         const KnnPtrs& ko, const CovPtrs& co, float eps,
-                                         int32_t* lds_nb, int32_t* lds_cnt) {
+constexpr int GROUP_W = 2;   // lanes farther than this (cells) from the anchor fall back
+
+__device__ __forceinline__ unsigned long long lane_key(float d, int32_t idx) {
+    return ((unsigned long long)(__float_as_uint(d) + 1u) << 32) | (uint32_t)idx;
+}
+__device__ __forceinline__ float key_d2(unsigned long long key) {
+    return __uint_as_float((uint32_t)(key >> 32) - 1u);
+}
+
+// Insert x (known to be below kk[K-1]) into the ascending list kk.
+template <int K>
+__device__ __forceinline__ void lane_insert(unsigned long long (&kk)[K], unsigned long long x) {
+    bool c_hi = x < kk[K - 1];
+#pragma unroll
+    for (int j = K - 1; j >= 1; --j) {
+        const bool c_lo = x < kk[j - 1];
+        const unsigned long long t = c_hi ? x : kk[j];
+        kk[j] = c_lo ? kk[j - 1] : t;
+        c_hi = c_lo;
+    }
+    kk[0] = c_hi ? x : kk[0];
+}
+
+__device__ __forceinline__ float wave_minf(float v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = fminf(v, shfl_xor(v, s));
+    return v;
+}
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = fmaxf(v, shfl_xor(v, s));
+    return v;
+}
+
+struct GroupArgs {
+    const TargetView* views;          // device array, one per target
+    const float* queries;             // [q][3]; NULL: the queries are the target's own points
+    const uint32_t* order;            // sorted slot -> query index (NULL with self queries)
+    const unsigned long long* skeys;  // sorted keys, target index in bits >= tshift (NULL: one target)
+    int tshift;
+    int R;                            // block reach in cells
+    int64_t n_slots;
+    SearchParams sp;
+    KnnPtrs ko;
+    CovPtrs co;
+    float eps;
+    uint32_t* fb_list;                // slots handed to the fallback search
+    uint32_t* fb_count;
+    uint32_t* counters;               // per-XCD work counters (persistent mode) or NULL
+};
+
+struct SlotQuery {
+    int64_t qi;   // output row
+    float x, y, z;
+    int tgt;
+};
+
+__device__ __forceinline__ SlotQuery load_slot(const GroupArgs& a, const TargetView& T, int64_t slot) {
+    SlotQuery s;
+    s.tgt = a.skeys ? (int)(a.skeys[slot] >> a.tshift) : 0;
+    if (a.queries) {
+        s.qi = a.order ? (int64_t)a.order[slot] : slot;
+        s.x = a.queries[3 * s.qi];
+        s.y = a.queries[3 * s.qi + 1];
+        s.z = a.queries[3 * s.qi + 2];
+    } else {
+        const float4 p = T.pts[slot];
+        s.qi = __float_as_int(p.w);
+        s.x = p.x;
+        s.y = p.y;
+        s.z = p.z;
+    }
+    return s;
+}
+
+template <int K>
+__device__ __forceinline__ void visit(const float4& c, bool member, float qx, float qy, float qz,
+                                      float r2, unsigned long long (&kk)[K]) {
+    const float d = dist2(qx, qy, qz, c.x, c.y, c.z);
+    const unsigned long long key = lane_key(d, __float_as_int(c.w));
+    const bool pass = member && d <= r2 && key < kk[K - 1];
+    if (ballot(pass)) {
+        if (pass) lane_insert<K>(kk, key);
+    }
+}
+
+template <int K, bool FUSED>
+__device__ void group_body(const GroupArgs& a, int64_t group) {
     const int lane = lane_id();
-    const int k = sp.k;
-    for (int j = 0; j < nq; ++j) {
-        const int64_t qi = q0 + j;
-        const float qx = queries[3 * qi], qy = queries[3 * qi + 1], qz = queries[3 * qi + 2];
+    const int64_t slot = group * WAVE + lane;
+    const bool active = slot < a.n_slots;
+    int gt = a.skeys ? (int)(load_uniform(a.skeys + group * WAVE) >> a.tshift) : 0;
+    gt = __builtin_amdgcn_readfirstlane(gt);
+    const TargetView T = load_uniform(a.views + gt);
+    SlotQuery s{-1, 0.f, 0.f, 0.f, gt};
+    if (active) s = load_slot(a, T, slot);
+    const bool fin = active && finite3(s.x, s.y, s.z);
+    const int cx = fin ? cell_coord(s.x, T.inv_cell) : 0;
+    const int cy = fin ? cell_coord(s.y, T.inv_cell) : 0;
+    const int cz = fin ? cell_coord(s.z, T.inv_cell) : 0;
+    const bool same = fin && s.tgt == gt;
+    const unsigned long long sm = ballot(same);
+    bool member = false;
+    if (sm) {
+        const int L0 = __builtin_ffsll((long long)sm) - 1;
+        const int ax = readlane(cx, L0), ay = readlane(cy, L0), az = readlane(cz, L0);
+        member = same && abs(cx - ax) <= GROUP_W && abs(cy - ay) <= GROUP_W &&
+                 abs(cz - az) <= GROUP_W;
+    }
+    const float r2 = a.sp.r2;
+    const int k = a.sp.k;
+    const int pad = K - k;
+    unsigned long long kk[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) kk[j] = (j < pad) ? 0ull : ~0ull;
+    const unsigned long long mm = ballot(member);
+    bool ok = true;
+    if (mm && T.n_cells > 0) {
+        const float bx0 = wave_minf(member ? s.x : INF), bx1 = wave_maxf(member ? s.x : -INF);
+        const float by0 = wave_minf(member ? s.y : INF), by1 = wave_maxf(member ? s.y : -INF);
+        const float bz0 = wave_minf(member ? s.z : INF), bz1 = wave_maxf(member ? s.z : -INF);
+        const float b0[3] = {bx0, by0, bz0}, b1[3] = {bx1, by1, bz1};
+        int blo[3], bhi[3], lo[3], ext[3];
+        int64_t total = 1;
+        for (int d = 0; d < 3; ++d) {
+            blo[d] = cell_coord(b0[d], T.inv_cell) - a.R;
+            bhi[d] = cell_coord(b1[d], T.inv_cell) + a.R;
+            lo[d] = max(blo[d], T.cmin[d]);
+            const int hi = min(bhi[d], T.cmax[d]);
+            ext[d] = hi - lo[d] + 1;
+            total *= ext[d] > 0 ? ext[d] : 0;
+        }
+        const float qabs = fmaxf(fmaxf(fmaxf(fabsf(bx0), fabsf(bx1)), fmaxf(fabsf(by0), fabsf(by1))),
+                                 fmaxf(fabsf(bz0), fabsf(bz1)));
+        const float margin = (fmaxf(qabs, T.max_abs) + 2.0f * T.cell) * 1e-6f;
+        float gthr = INF;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int64_t base = 0; base < total; base += WAVE) {
+                if (pass == 1)
+                    gthr = wave_maxf(member ? (kk[K - 1] == ~0ull ? INF : key_d2(kk[K - 1]))
+                                            : -INF);
+                const int64_t t = base + lane;
+                bool want = false;
+                uint32_t st = 0, cn = 0;
+                if (t < total) {
+                    const int c3[3] = {lo[0] + (int)(t % ext[0]),
+                                       lo[1] + (int)((t / ext[0]) % ext[1]),
+                                       lo[2] + (int)(t / ((int64_t)ext[0] * ext[1]))};
+                    float bd = 0.0f;
+                    for (int d = 0; d < 3; ++d) {
+                        const float cl = (float)c3[d] * T.cell - margin;
+                        const float ch = (float)(c3[d] + 1) * T.cell + margin;
+                        const float g = fmaxf(fmaxf(cl - b1[d], b0[d] - ch), 0.0f);
+                        bd += g * g;
+                    }
+                    const bool inside = bd == 0.0f;
+                    if (inside == (pass == 0) && bd <= r2 && bd * (1.0f - 1e-6f) <= gthr)
+                        want = hash_find(T, pack_key(T, c3[0], c3[1], c3[2]), st, cn) && cn > 0;
+                }
+                unsigned long long wm = ballot(want);
+                while (wm) {
+                    const int cl = __builtin_ffsll((long long)wm) - 1;
+                    wm &= wm - 1;
+                    const int s0 = readlane((int)st, cl);
+                    const int e0 = s0 + readlane((int)cn, cl);
+                    // candidates stream through scalar loads, two records
+                    // ahead (the point array is padded past its end)
+                    const float4* pts = T.pts;
+                    float4 c0 = load_uniform(pts + s0), c1 = load_uniform(pts + s0 + 1);
+                    for (int i = s0; i < e0; i += 2) {
+                        const float4 n0 = load_uniform(pts + i + 2);
+                        const float4 n1 = load_uniform(pts + i + 3);
+                        visit<K>(c0, member, s.x, s.y, s.z, r2, kk);
+                        if (i + 1 < e0) visit<K>(c1, member, s.x, s.y, s.z, r2, kk);
+                        c0 = n0;
+                        c1 = n1;
+                    }
+                }
+            }
+        }
+        // exactness: every point outside the (unclamped) block is at least f away
+        if (member) {
+            bool covers = true;
+            float f = INF;
+            const float q3[3] = {s.x, s.y, s.z};
+            for (int d = 0; d < 3; ++d) {
+                covers = covers && blo[d] <= T.cmin[d] && bhi[d] >= T.cmax[d];
+                f = fminf(f, fminf(q3[d] - (float)blo[d] * T.cell,
+                                   (float)(bhi[d] + 1) * T.cell - q3[d]));
+            }
+            f -= margin;
+            const float f2 = f > 0.0f ? f * f * (1.0f - 1e-6f) : 0.0f;
+            const bool full = kk[K - 1] != ~0ull;
+            ok = covers || (full && f2 > key_d2(kk[K - 1])) || (a.sp.capped && f2 > r2);
+        }
+    }
+    const bool to_fb = (fin && !member) || (member && !ok);
+    const unsigned long long fm = ballot(to_fb);
+    if (fm) {
+        const int leader = __builtin_ffsll((long long)fm) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(a.fb_count, (uint32_t)__popcll(fm));
+        base = (uint32_t)__shfl((int)base, leader);
+        if (to_fb)
+            a.fb_list[base + __popcll(fm & ((1ull << lane) - 1ull))] = (uint32_t)slot;
+    }
+    if (!active || to_fb) return;
+    // results (also for non-finite queries: empty)
+    int cnt = 0;
+    int32_t* irow = a.ko.idx + s.qi * k;
+    float* drow = a.ko.d2 + s.qi * k;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (j >= pad) {
+            const unsigned long long key = kk[j];
+            const bool have = key != ~0ull;
+            irow[j - pad] = have ? (int32_t)(uint32_t)key : -1;
+            drow[j - pad] = have ? key_d2(key) : INF;
+            cnt += have ? 1 : 0;
+        }
+    }
+    a.ko.count[s.qi] = cnt;
+    if (FUSED) {
+        const float4* orig = T.orig;
+        CovOut c;
+        covariance(s.x, s.y, s.z, cnt, [&](int j) { return orig[irow[j]]; }, a.eps, c);
+        store_cov(a.co, s.qi, c);
+    }
+}
+
+template <int K, bool FUSED>
+__global__ void __launch_bounds__(256) k_group(GroupArgs a) {
+    const int wpb = blockDim.x / WAVE;
+    const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
+    if (!a.counters) {
+        const int64_t g = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * wpb + threadIdx.x / WAVE;
+        if (g < n_groups) group_body<K, FUSED>(a, g);
+        return;
+    }
+    // persistent: the groups are split into 8 contiguous ranges, one per XCD
+    // (workgroups are dealt round-robin over the XCDs); a wave drains its own
+    // XCD's range, then helps the others
+    const int lane = lane_id();
+    const int x0 = blockIdx.x % 8;
+    for (int s = 0; s < 8; ++s) {
+        const int x = (x0 + s) % 8;
+        const int64_t g_lo = n_groups * x / 8, g_hi = n_groups * (x + 1) / 8;
+        for (;;) {
+            uint32_t t = 0;
+            if (lane == 0) t = atomicAdd(&a.counters[x], 1u);
+            t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+            const int64_t g = g_lo + t;
+            if (g >= g_hi) break;
+            group_body<K, FUSED>(a, g);
+        }
+    }
+}
+
+// Wavefront-per-query search for the slots the group search handed over.
+// Persistent: waves stride over the list (its length is only known on the
+// device).
+template <bool FUSED>
+__global__ void __launch_bounds__(256) k_fallback(GroupArgs a) {
+    const int lane = lane_id();
+    const uint32_t nfb = *(volatile uint32_t*)a.fb_count;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int k = a.sp.k;
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; i < nfb;
+         i += nw) {
+        const int64_t slot = load_uniform(a.fb_list + i);
+        int tg = a.skeys ? (int)(load_uniform(a.skeys + slot) >> a.tshift) : 0;
+        tg = __builtin_amdgcn_readfirstlane(tg);
+        const TargetView T = load_uniform(a.views + tg);
+        const SlotQuery s = load_slot(a, T, slot);
         TopK L;
-        const int cnt = knn_query_wave(T, qx, qy, qz, sp, L);
+        const int cnt = knn_query_wave(T, s.x, s.y, s.z, a.sp, L);
         if (lane < k) {
             const bool have = lane < cnt;
-            ko.idx[qi * k + lane] = have ? L.i : -1;
-            ko.d2[qi * k + lane] = have ? L.d : INF;
-            if (FUSED) lds_nb[j * k + lane] = have ? L.p : 0;
+            a.ko.idx[s.qi * k + lane] = have ? L.i : -1;
+            a.ko.d2[s.qi * k + lane] = have ? L.d : INF;
         }
-        if (lane == 0) {
-            ko.count[qi] = cnt;
-            if (FUSED) lds_cnt[j] = cnt;
-        }
-    }
-    if (FUSED) {
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < nq) {
-            const int64_t qi = q0 + lane;
-            const float qx = queries[3 * qi], qy = queries[3 * qi + 1], qz = queries[3 * qi + 2];
-            const int n = lds_cnt[lane];
-            const int32_t* nb = lds_nb + lane * k;
+        if (lane == 0) a.ko.count[s.qi] = cnt;
+        if (FUSED) {
+            // all lanes run the same covariance (neighbour j's reordered
+            // position is read from lane j); lane 0 stores it
             const float4* pts = T.pts;
             CovOut c;
-            covariance(qx, qy, qz, n, [&](int jj) { return pts[nb[jj]]; }, eps, c);
-            store_cov(co, qi, c);
+            covariance(s.x, s.y, s.z, cnt, [&](int j) { return pts[readlane(L.p, j)]; }, a.eps, c);
+            if (lane == 0) store_cov(a.co, s.qi, c);
         }
     }
 }
 
-template <bool FUSED>
-__global__ void __launch_bounds__(1024) k_search(TargetView T, const float* __restrict__ queries,
-                                                 int64_t q, SearchParams sp, KnnPtrs ko,
-                                                 CovPtrs co, float eps, int tile_q) {
-    extern __shared__ int32_t lds[];
-    const int wpb = blockDim.x / WAVE;
-    const int w = threadIdx.x / WAVE;
-    const int64_t tile = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * wpb + w;
-    const int64_t q0 = tile * tile_q;
-    if (q0 >= q) return;
-    const int nq = (int)min((int64_t)tile_q, q - q0);
-    int32_t* lds_nb = lds + w * tile_q * (sp.k + 1);
-    int32_t* lds_cnt = lds_nb + tile_q * sp.k;
-    run_tile<FUSED>(T, queries, q0, nq, sp, ko, co, eps, lds_nb, lds_cnt);
-}
+// Sort keys of the queries: target index above the query's cell in the
+// target's grid (clamped to one cell around the occupied box, packed
+// x-fastest).  scans/n_scans map a query to its target (NULL: target 0).
+struct QueryKeyArgs {
+    const float* queries;
+    int64_t q;
+    const TargetView* views;
+    const BatchScan* scans;
+    const BatchHeader* hdr;
+    int tshift;
+    unsigned long long* keys;
+    uint32_t* vals;
+};
 
-// Persistent batched kernel: waves pull 64-query tiles from the staged
-// table's work counter; each tile lies inside one scan (one target).
-__global__ void __launch_bounds__(1024) k_batched(const TargetView* __restrict__ views,
-                                                  BatchHeader* __restrict__ hdr,
-                                                  const BatchScan* __restrict__ scans,
-                                                  const float* __restrict__ queries,
-                                                  SearchParams sp, KnnPtrs ko, CovPtrs co,
-                                                  float eps, int tile_q, uint32_t total_waves) {
-    extern __shared__ int32_t lds[];
-    const int w = threadIdx.x / WAVE;
-    const int lane = lane_id();
-    int32_t* lds_nb = lds + w * tile_q * (sp.k + 1);
-    int32_t* lds_cnt = lds_nb + tile_q * sp.k;
-    const int n_scans = hdr->n_scans;
-    const uint32_t n_tiles = (uint32_t)hdr->n_tiles;
-    for (;;) {
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(&hdr->work_counter, 1u);
-        t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
-        if (t >= n_tiles) break;
-        // scan s with tile_begin[s] <= t < tile_begin[s+1]
-        int lo = 0, hi = n_scans - 1;
-        while (lo < hi) {
+__global__ void __launch_bounds__(256) k_query_keys(QueryKeyArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.q) return;
+    int tg = 0;
+    if (a.scans) {
+        int lo = 0, hi = a.hdr->n_scans - 1;
+        while (lo < hi) {   // last scan with q_offset <= i
             const int mid = (lo + hi + 1) >> 1;
-            if ((uint32_t)scans[mid].tile_begin <= t)
+            if (a.scans[mid].q_offset <= i)
                 lo = mid;
             else
                 hi = mid - 1;
         }
-        const BatchScan s = scans[lo];
-        const int64_t q0 = s.q_offset + (int64_t)(t - (uint32_t)s.tile_begin) * tile_q;
-        const int nq = (int)min((int64_t)tile_q, s.q_offset + s.q_count - q0);
-        const TargetView T = views[s.target_index];
-        run_tile<true>(T, queries, q0, nq, sp, ko, co, eps, lds_nb, lds_cnt);
+        tg = a.scans[lo].target_index;
     }
-    // the last wave to find the queue empty resets it for the next launch
-    if (lane == 0) {
-        const uint32_t done = atomicAdd(&hdr->waves_done, 1u);
-        if (done == total_waves - 1) {
-            atomicExch(&hdr->work_counter, 0u);
-            atomicExch(&hdr->waves_done, 0u);
+    const TargetView& T = a.views[tg];
+    const float x = a.queries[3 * i], y = a.queries[3 * i + 1], z = a.queries[3 * i + 2];
+    unsigned long long key = 0;
+    if (finite3(x, y, z)) {
+        const int c[3] = {cell_coord(x, T.inv_cell), cell_coord(y, T.inv_cell),
+                          cell_coord(z, T.inv_cell)};
+        int sh = 0;
+        for (int d = 0; d < 3; ++d) {
+            const int range = max(T.cmax[d] - T.cmin[d], 0) + 2;
+            const int v = min(max(c[d] - (T.cmin[d] - 1), 0), range);
+            key |= (unsigned long long)(uint32_t)v << sh;
+            sh += 32 - __builtin_clz((uint32_t)range);
         }
+    } else {
+        key = (1ull << a.tshift) - 1ull;
     }
+    a.keys[i] = ((unsigned long long)tg << a.tshift) | key;
+    a.vals[i] = (uint32_t)i;
+}
+
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 // Plain covariance kernel: one thread per query, neighbours named by
@@ -598,70 +853,254 @@ SearchParams make_params(int k, float radius, int merge_min) {
     return sp;
 }
 
-size_t lds_bytes(int wpb, int tile_q, int k) {
-    return (size_t)wpb * tile_q * (k + 1) * sizeof(int32_t);
-}
-
 }  // namespace
 
-LaunchCfg resolve_cfg(const lkc_launch_cfg* c) {
-    LaunchCfg r{64, 4, 12, 8};
-    if (c) {
-        if (c->tile_queries > 0) r.tile_queries = c->tile_queries;
-        if (c->waves_per_block > 0) r.waves_per_block = c->waves_per_block;
-        if (c->merge_min > 0) r.merge_min = c->merge_min;
-        if (c->blocks_per_cu > 0) r.blocks_per_cu = c->blocks_per_cu;
-    }
-    return r;
+
+namespace {
+
+__global__ void k_fill_iota(uint32_t* __restrict__ v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = (uint32_t)i;
 }
 
-static lkc_status check_cfg(lkc_ctx* ctx, const LaunchCfg& c) {
-    if (c.tile_queries < 1 || c.tile_queries > 64)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "tile_queries must be in [1, 64]");
-    if (c.waves_per_block < 1 || c.waves_per_block > 16)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "waves_per_block must be in [1, 16]");
-    if (c.merge_min < 1 || c.merge_min > 65)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "merge_min must be in [1, 65]");
-    if (c.blocks_per_cu < 1 || c.blocks_per_cu > 32)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "blocks_per_cu must be in [1, 32]");
+__global__ void k_set_words(uint32_t* __restrict__ w, int n, uint32_t first) {
+    const int i = threadIdx.x;
+    if (i < n) w[i] = (i == 0) ? first : 0u;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int bitw(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
+
+struct Scratch {
+    unsigned long long *ka, *kb;
+    uint32_t *va, *vb, *counts, *words, *fb_list;
+};
+
+lkc_status search_scratch(lkc_ctx* ctx, int64_t n, Scratch& s) {
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    size_t off = 0;
+    auto carve = [&](size_t b) {
+        const size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    const size_t o_ka = carve(8 * nn), o_kb = carve(8 * nn), o_va = carve(4 * nn),
+                 o_vb = carve(4 * nn), o_c = carve(4 * sort_count_words(n)), o_w = carve(256),
+                 o_fb = carve(4 * nn);
+    if (ctx->search_scratch_bytes < off) {
+        if (ctx->search_scratch) {
+            LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            (void)hipFree(ctx->search_scratch);
+            ctx->search_scratch = nullptr;
+            ctx->search_scratch_bytes = 0;
+        }
+        const size_t bytes = off + off / 4;   // headroom for slightly larger calls
+        hipError_t e = hipMalloc(&ctx->search_scratch, bytes);
+        if (e != hipSuccess) {
+            ctx->search_scratch = nullptr;
+            return set_error(ctx, LKC_ERR_OOM, "search scratch of %zu bytes: %s", bytes,
+                             hipGetErrorString(e));
+        }
+        ctx->search_scratch_bytes = bytes;
+    }
+    char* b = (char*)ctx->search_scratch;
+    s.ka = (unsigned long long*)(b + o_ka);
+    s.kb = (unsigned long long*)(b + o_kb);
+    s.va = (uint32_t*)(b + o_va);
+    s.vb = (uint32_t*)(b + o_vb);
+    s.counts = (uint32_t*)(b + o_c);
+    s.words = (uint32_t*)(b + o_w);
+    s.fb_list = (uint32_t*)(b + o_fb);
     return LKC_OK;
 }
 
+int choose_k_tile(int k) {
+    if (k <= 8) return 8;
+    if (k <= 16) return 16;
+    if (k <= 20) return 20;
+    if (k <= 32) return 32;
+    return 0;
+}
+
 template <bool FUSED>
-static lkc_status launch_search(lkc_ctx* ctx, const lkc_target* t, const float* queries,
-                                int64_t q, int32_t k, float radius, float eps, KnnPtrs ko,
-                                CovPtrs co, const LaunchCfg& cfg) {
-    lkc_status s = check_cfg(ctx, cfg);
+void launch_group(int K, dim3 grid, dim3 block, hipStream_t st, const GroupArgs& a) {
+    switch (K) {
+        case 8: hipLaunchKernelGGL((k_group<8, FUSED>), grid, block, 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_group<16, FUSED>), grid, block, 0, st, a); break;
+        case 20: hipLaunchKernelGGL((k_group<20, FUSED>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_group<32, FUSED>), grid, block, 0, st, a); break;
+    }
+}
+
+struct SearchJob {
+    const TargetView* views_dev;
+    const TargetView* host_views;
+    int n_targets;
+    const float* queries;   // NULL: self queries over target 0's points
+    int64_t n_slots;
+    const BatchScan* scans_dev;
+    const BatchHeader* hdr_dev;
+    int32_t k;
+    float radius;
+    float eps;
+    bool fused;
+    KnnPtrs ko;
+    CovPtrs co;
+};
+
+lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
+    if (j.n_slots == 0) return LKC_OK;
+    hipStream_t st = ctx->stream;
+    Scratch sc;
+    lkc_status s = search_scratch(ctx, j.n_slots, sc);
     if (s != LKC_OK) return s;
-    if (q == 0) return LKC_OK;
-    const SearchParams sp = make_params(k, radius, cfg.merge_min);
-    const int64_t tiles = (q + cfg.tile_queries - 1) / cfg.tile_queries;
-    const int64_t blocks = (tiles + cfg.waves_per_block - 1) / cfg.waves_per_block;
-    if (blocks > 0x7fffffff) return set_error(ctx, LKC_ERR_INVALID_ARG, "too many queries");
-    const size_t lds = FUSED ? lds_bytes(cfg.waves_per_block, cfg.tile_queries, k) : 0;
-    if (lds > 160 * 1024)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "tile needs %zu bytes of LDS", lds);
-    hipLaunchKernelGGL(k_search<FUSED>, dim3((unsigned)blocks), dim3(cfg.waves_per_block * WAVE),
-                       lds, ctx->stream, t->view, queries, q, sp, ko, co, eps,
-                       cfg.tile_queries);
+    GroupArgs a{};
+    a.views = j.views_dev;
+    a.queries = j.queries;
+    a.order = nullptr;
+    a.skeys = nullptr;
+    a.tshift = 0;
+    a.n_slots = j.n_slots;
+    a.sp = make_params(j.k, j.radius, cfg.merge_min);
+    a.ko = j.ko;
+    a.co = j.co;
+    a.eps = j.eps;
+    a.fb_list = sc.fb_list;
+    a.fb_count = sc.words;
+    a.counters = nullptr;
+    const int K = choose_k_tile(j.k);
+    const bool group = K > 0 && cfg.algorithm != 2;
+    const unsigned wpb = (unsigned)cfg.waves_per_block;
+    if (group) {
+        hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, sc.words, 16, 0u);
+        if (j.queries) {
+            // sort the queries by their cell in the target grid
+            int tshift = 0;
+            for (int t = 0; t < j.n_targets; ++t) {
+                const TargetView& V = j.host_views[t];
+                int b = 0;
+                for (int d = 0; d < 3; ++d) b += bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2));
+                tshift = std::max(tshift, b);
+            }
+            const int tbits = j.n_targets > 1 ? bitw((uint32_t)(j.n_targets - 1)) : 0;
+            if (tshift + tbits > 63)
+                return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",
+                                 tshift + tbits);
+            QueryKeyArgs qa{j.queries, j.n_slots, j.views_dev, j.scans_dev, j.hdr_dev, tshift,
+                            sc.ka, sc.va};
+            hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256),
+                               0, st, qa);
+            bool in_b = false;
+            s = sort_pairs(ctx, sc.ka, sc.va, sc.kb, sc.vb, j.n_slots, tshift + tbits, sc.counts,
+                           &in_b);
+            if (s != LKC_OK) return s;
+            a.order = in_b ? sc.vb : sc.va;
+            a.skeys = j.n_targets > 1 ? (in_b ? sc.kb : sc.ka) : nullptr;
+            a.tshift = tshift;
+        }
+        int R = cfg.group_reach;
+        if (R <= 0) {
+            R = 1;
+            if (a.sp.capped)
+                for (int t = 0; t < j.n_targets; ++t) {
+                    const float c = j.host_views[t].cell;
+                    const int rt = (int)std::ceil(std::sqrt(a.sp.r2) / c);
+                    R = std::max(R, std::min(rt, 2));
+                }
+        }
+        a.R = R;
+        const int64_t n_groups = (j.n_slots + WAVE - 1) / WAVE;
+        unsigned blocks;
+        if (cfg.persistent > 0) {
+            a.counters = sc.words + 8;
+            blocks = (unsigned)(ctx->num_cus * cfg.persistent);
+        } else {
+            blocks = (unsigned)((n_groups + wpb - 1) / wpb);
+        }
+        if (j.fused)
+            launch_group<true>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+        else
+            launch_group<false>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+    } else {
+        // every query goes to the wavefront-per-query search
+        hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, sc.words, 16,
+                           (uint32_t)j.n_slots);
+        hipLaunchKernelGGL(k_fill_iota, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256), 0,
+                           st, sc.fb_list, j.n_slots);
+    }
+    const dim3 fgrid((unsigned)(ctx->num_cus * 4));
+    if (j.fused)
+        hipLaunchKernelGGL(k_fallback<true>, fgrid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fallback<false>, fgrid, dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(ctx, e, "search launch");
     return LKC_OK;
 }
 
+lkc_status check_cfg(lkc_ctx* ctx, const LaunchCfg& c) {
+    if (c.algorithm < 0 || c.algorithm > 2)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "algorithm must be 0 (auto), 1 or 2");
+    if (c.group_reach < 0 || c.group_reach > 4)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "group_reach must be in [0, 4]");
+    if (c.waves_per_block < 1 || c.waves_per_block > 4)   // kernels are built for <= 256 threads
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "waves_per_block must be in [1, 4]");
+    if (c.merge_min < 1 || c.merge_min > 65)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "merge_min must be in [1, 65]");
+    if (c.persistent < 0 || c.persistent > 32)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "persistent must be in [0, 32]");
+    return LKC_OK;
+}
+
+}  // namespace
+
+lkc_status reserve_search(lkc_ctx* ctx, int64_t max_queries) {
+    Scratch sc;
+    return search_scratch(ctx, max_queries, sc);
+}
+
+LaunchCfg resolve_cfg(const lkc_launch_cfg* c) {
+    LaunchCfg r{0, 0, 4, 12, 0};
+    if (c) {
+        r.algorithm = c->algorithm;
+        r.group_reach = c->group_reach;
+        if (c->waves_per_block != 0) r.waves_per_block = c->waves_per_block;
+        if (c->merge_min != 0) r.merge_min = c->merge_min;
+        r.persistent = c->persistent;
+    }
+    return r;
+}
+
 lkc_status launch_knn(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
                       int32_t k, float radius, int32_t* idx, float* d2, int32_t* count,
                       const LaunchCfg& cfg) {
-    return launch_search<false>(ctx, t, queries, q, k, radius, 0.0f, KnnPtrs{idx, d2, count},
-                                CovPtrs{nullptr, nullptr, nullptr, nullptr}, cfg);
+    lkc_status s = check_cfg(ctx, cfg);
+    if (s != LKC_OK) return s;
+    SearchJob j{t->view_dev, &t->view, 1, queries, q, nullptr, nullptr, k, radius, 0.0f, false,
+                KnnPtrs{idx, d2, count}, CovPtrs{nullptr, nullptr, nullptr, nullptr}};
+    return run_search(ctx, j, cfg);
 }
 
 lkc_status launch_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
                           int32_t k, float radius, float eps, int32_t* idx, float* d2,
                           int32_t* count, float* mean, float* cov, float* reg, uint8_t* valid,
                           const LaunchCfg& cfg) {
-    return launch_search<true>(ctx, t, queries, q, k, radius, eps, KnnPtrs{idx, d2, count},
-                               CovPtrs{mean, cov, reg, valid}, cfg);
+    lkc_status s = check_cfg(ctx, cfg);
+    if (s != LKC_OK) return s;
+    SearchJob j{t->view_dev, &t->view, 1, queries, q, nullptr, nullptr, k, radius, eps,
+                valid != nullptr, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
+    return run_search(ctx, j, cfg);
+}
+
+lkc_status launch_knn_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float radius,
+                           float eps, int32_t* idx, float* d2, int32_t* count, float* mean,
+                           float* cov, float* reg, uint8_t* valid, const LaunchCfg& cfg) {
+    lkc_status s = check_cfg(ctx, cfg);
+    if (s != LKC_OK) return s;
+    SearchJob j{t->view_dev, &t->view, 1, nullptr, t->view.n, nullptr, nullptr, k, radius, eps,
+                valid != nullptr, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
+    return run_search(ctx, j, cfg);
 }
 
 lkc_status launch_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries,
@@ -683,25 +1122,15 @@ lkc_status launch_batched(lkc_ctx* ctx, lkc_target_set* set, const float* querie
                           uint8_t* valid, const LaunchCfg& cfg) {
     lkc_status s = check_cfg(ctx, cfg);
     if (s != LKC_OK) return s;
-    if (set->max_query_end > total_q)
+    if (set->staged_total != total_q)
         return set_error(ctx, LKC_ERR_INVALID_ARG,
-                         "staged scans reach query %lld but total_q is %lld",
-                         (long long)set->max_query_end, (long long)total_q);
-    if (cfg.tile_queries != 64)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "the batched call uses 64-query tiles");
-    const SearchParams sp = make_params(k, radius, cfg.merge_min);
-    const size_t lds = lds_bytes(cfg.waves_per_block, cfg.tile_queries, k);
-    if (lds > 160 * 1024)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "tile needs %zu bytes of LDS", lds);
-    const unsigned blocks = (unsigned)(ctx->num_cus * cfg.blocks_per_cu);
-    const uint32_t total_waves = blocks * (uint32_t)cfg.waves_per_block;
-    hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(cfg.waves_per_block * WAVE), lds,
-                       ctx->stream, set->views_dev, set->header_dev, set->scans_dev, queries, sp,
-                       KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}, eps,
-                       cfg.tile_queries, total_waves);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_error(ctx, e, "batched launch");
-    return LKC_OK;
+                         "the staged scans cover %lld queries but total_q is %lld",
+                         (long long)set->staged_total, (long long)total_q);
+    if (set->staged_scans == 0) return LKC_OK;
+    SearchJob j{set->views_dev, set->host_views, set->n_targets, queries, total_q,
+                set->scans_dev, set->header_dev, k, radius, eps, true,
+                KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
+    return run_search(ctx, j, cfg);
 }
 
 }  // namespace lkc

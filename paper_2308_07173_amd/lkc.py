@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = (
     "lkc_synchronize", "lkc_build_target", "lkc_target_rebuild", "lkc_target_free",
     "lkc_target_get_info", "lkc_target_arrays", "lkc_knn_query", "lkc_covariances",
     "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
-    "lkc_knn_cov_batched",
+    "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve",
 )
 
 
@@ -51,8 +51,9 @@ class LkcError(RuntimeError):
 
 
 class LaunchCfg(ctypes.Structure):
-    _fields_ = [("tile_queries", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("merge_min", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+    _fields_ = [("algorithm", ctypes.c_int32), ("group_reach", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("merge_min", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -106,6 +107,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_target_set_free": ([P, P], I32),
             "lkc_target_set_stage": ([P, P, P, I32], I32),
             "lkc_knn_cov_batched": ([P, P, P, I64, I32, F, F, P, P, P, P, P, P, P, P], I32),
+            "lkc_knn_cov_self": ([P, P, I32, F, F, P, P, P, P, P, P, P, P], I32),
+            "lkc_ctx_reserve": ([P, I64], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -170,6 +173,10 @@ class Context:
     def check(self, st: int):
         if st != LKC_OK:
             raise LkcError(st, self.lib.lkc_last_error(self.handle).decode())
+
+    def reserve(self, max_queries: int):
+        self._bind()
+        self.check(self.lib.lkc_ctx_reserve(self.handle, int(max_queries)))
 
     def synchronize(self):
         self._bind()
@@ -330,6 +337,29 @@ def lkc_knn_cov(ctx: Context, target: Target, queries, k: int, radius: float = m
     return out
 
 
+def lkc_knn_cov_self(ctx: Context, target: Target, k: int, radius: float = math.inf,
+                     plane_eps: float = 1e-3, out: Optional[Dict] = None, cfg=None,
+                     with_cov: bool = True):
+    """k nearest neighbours (+ covariances) of every point of the target itself;
+    rows in the target's original point order."""
+    torch = _torch()
+    n = target.info()["n_points"] if out is None else out["count"].shape[0]
+    if out is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = _cov_out(n, dev) if with_cov else {}
+        out.update(idx=torch.empty(n, k, dtype=torch.int32, device=dev),
+                   d2=torch.empty(n, k, dtype=torch.float32, device=dev),
+                   count=torch.empty(n, dtype=torch.int32, device=dev))
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_knn_cov_self(
+        ctx.handle, target.handle, int(k), float(radius), float(plane_eps),
+        ctypes.c_void_p(_ptr(out["idx"])), ctypes.c_void_p(_ptr(out["d2"])),
+        ctypes.c_void_p(_ptr(out["count"])), ctypes.c_void_p(_ptr(out.get("mean"))),
+        ctypes.c_void_p(_ptr(out.get("cov"))), ctypes.c_void_p(_ptr(out.get("reg"))),
+        ctypes.c_void_p(_ptr(out.get("valid"))), _cfg_ptr(cfg)))
+    return out
+
+
 class TargetSet:
     """``lkc_target_set``: several targets + a staged scan table for batching."""
 
@@ -394,3 +424,4 @@ knn_query = lkc_knn_query
 covariances = lkc_covariances
 knn_cov = lkc_knn_cov
 knn_cov_batched = lkc_knn_cov_batched
+knn_cov_self = lkc_knn_cov_self

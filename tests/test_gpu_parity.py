@@ -165,7 +165,8 @@ def test_knn_bad_arguments_raise(lk):
         with pytest.raises(lkc.LkcError) as e:
             lkc.lkc_knn_query(ctx, t, q, k, r)
         assert e.value.status == lkc.LKC_ERR_INVALID_ARG
-    for cfg in [dict(tile_queries=65), dict(waves_per_block=17), dict(merge_min=66)]:
+    for cfg in [dict(algorithm=3), dict(waves_per_block=5), dict(merge_min=66),
+                dict(group_reach=5), dict(persistent=33)]:
         with pytest.raises(lkc.LkcError):
             lkc.lkc_knn_query(ctx, t, q, 3, 1.0, cfg=cfg)
     with pytest.raises(lkc.LkcError):
@@ -173,16 +174,44 @@ def test_knn_bad_arguments_raise(lk):
     t.free()
 
 
-@pytest.mark.parametrize("cfg", [dict(tile_queries=1, waves_per_block=1, merge_min=1),
-                                 dict(tile_queries=16, waves_per_block=8, merge_min=65),
-                                 dict(tile_queries=64, waves_per_block=2, merge_min=4)])
+@pytest.mark.parametrize("cfg", [dict(algorithm=2), dict(algorithm=2, merge_min=65),
+                                 dict(algorithm=2, merge_min=1, waves_per_block=1),
+                                 dict(group_reach=1), dict(group_reach=3, waves_per_block=2),
+                                 dict(persistent=2), dict(persistent=1, waves_per_block=2)])
 def test_knn_launch_shapes_agree(lk, cfg):
-    """Any launch shape gives the same bits (the result is order-independent)."""
+    """Both search algorithms and every launch shape give the same bits (the
+    result is independent of the order candidates are visited in)."""
     p = workloads.plane_wall(3000, seed=4)
-    a = run_knn(lk, p, p, 20, 0.8, 1.0)
-    b = run_knn(lk, p, p, 20, 0.8, 1.0, cfg=cfg)
-    for x, y in zip(a, b):
-        assert np.array_equal(x, y)
+    q = workloads.random_cloud(2500, 9, scale=10.0)
+    for radius in (0.8, INF):
+        a = run_knn(lk, p, q, 20, radius, 1.0)
+        b = run_knn(lk, p, q, 20, radius, 1.0, cfg=cfg)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_self_query_matches_plain_and_oracle(lk):
+    """lkc_knn_cov_self == lkc_knn_cov with the points as queries, bitwise,
+    and matches the oracle."""
+    lkc, ctx = lk
+    for pts, k, radius, cell in [(workloads.plane_wall(2048, seed=0), 10, INF, 1.0),
+                                 (workloads.single_scan(seed=3)[::4].copy(), 20, 2.0, 1.0),
+                                 (workloads.lattice_nd((9, 9, 3)), 7, INF, 0.8)]:
+        t = lkc.lkc_build_target(ctx, dev(pts), cell)
+        a = lkc.lkc_knn_cov_self(ctx, t, k, radius, 1e-3)
+        b = lkc.lkc_knn_cov(ctx, t, dev(pts), k, radius, 1e-3)
+        c = lkc.lkc_knn_cov_self(ctx, t, k, radius, 1e-3, with_cov=False)
+        torch.cuda.synchronize()
+        for key in b:
+            assert torch.equal(a[key], b[key]), key
+        for key in ("idx", "d2", "count"):
+            assert torch.equal(a[key], c[key]), key
+        o = {kk: host(v) for kk, v in a.items()}
+        rows = np.arange(pts.shape[0])[:: max(1, pts.shape[0] // 2000)]
+        parity.check_knn(pts, pts, k, radius, o["idx"], o["d2"], o["count"], rows=rows)
+        parity.check_cov(pts, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"],
+                         rows=rows)
+        t.free()
 
 
 # ------------------------------------------------------------ covariance --
@@ -317,7 +346,7 @@ def test_batched_equals_per_scan_bitwise(lk, map_c3):
     tm = lkc.lkc_build_target(ctx, dev(m), 1.0)
     ts = lkc.lkc_build_target(ctx, dev(small), 0.5)
     rng = np.random.default_rng(3)
-    sizes = [int(rng.integers(1, 9000)) for _ in range(7)] + [0, 64, 65, 63]
+    sizes = [int(rng.integers(1, 9000)) for _ in range(7)] + [0, 64, 65, 63, 1]
     scans, parts, off = [], [], 0
     for i, n in enumerate(sizes):
         tgt = i % 2
@@ -330,7 +359,8 @@ def test_batched_equals_per_scan_bitwise(lk, map_c3):
     tset = lkc.TargetSet(ctx, [tm, ts], max_scans=32)
     tset.stage(scans)
     got = lkc.lkc_knn_cov_batched(ctx, tset, dev(allq), 20, 2.0, 1e-3)
-    got2 = lkc.lkc_knn_cov_batched(ctx, tset, dev(allq), 20, 2.0, 1e-3)   # counter reset
+    got2 = lkc.lkc_knn_cov_batched(ctx, tset, dev(allq), 20, 2.0, 1e-3,
+                                   cfg=dict(persistent=2))
     torch.cuda.synchronize()
     for (o, n, tgt), part in zip(scans, parts):
         alone = lkc.lkc_knn_cov(ctx, [tm, ts][tgt], dev(part), 20, 2.0, 1e-3)
@@ -339,8 +369,14 @@ def test_batched_equals_per_scan_bitwise(lk, map_c3):
             assert torch.equal(alone[key], got[key][o:o + n]), key
             assert torch.equal(alone[key], got2[key][o:o + n]), key
     with pytest.raises(lkc.LkcError) as e:
-        tset.stage([(0, 1, 0)] * 33)
+        tset.stage([(i, 1, 0) for i in range(33)])
     assert e.value.status == lkc.LKC_ERR_BUDGET
+    with pytest.raises(lkc.LkcError) as e:     # scans must tile the query array
+        tset.stage([(0, 5, 0), (6, 5, 1)])
+    assert e.value.status == lkc.LKC_ERR_INVALID_ARG
+    tset.stage(scans)
+    with pytest.raises(lkc.LkcError):          # total_q must match the staged scans
+        lkc.lkc_knn_cov_batched(ctx, tset, dev(allq[:-1]), 20, 2.0, 1e-3)
     tset.free()
     tm.free()
     ts.free()
