@@ -208,8 +208,11 @@ lkc_status lkc_target_set_free(lkc_ctx *ctx, lkc_target_set *set);
 /* Stage a batch description: `n_scans` scan descriptors (host array) that
  * tile the concatenated query array in order (scan 0 at offset 0, each scan
  * starting where the previous one ends).  One stream-ordered copy from the
- * set's pinned staging buffer to its device table; synchronises first so
- * that buffer is free.  LKC_ERR_BUDGET when n_scans > max_scans. */
+ * set's pinned staging buffer to its device table; it first waits (host
+ * side) for this set's previous staging copy, so that buffer is free, but
+ * not for other work on the stream.  A launch that reads the previous
+ * staging must have been enqueued before the next stage.
+ * LKC_ERR_BUDGET when n_scans > max_scans. */
 lkc_status lkc_target_set_stage(lkc_ctx *ctx, lkc_target_set *set, const lkc_scan_desc *scans,
                                 int32_t n_scans);
 
@@ -237,6 +240,14 @@ lkc_status lkc_knn_cov_batched(lkc_ctx *ctx, lkc_target_set *set, const float *q
 lkc_status lkc_knn_cov_self(lkc_ctx *ctx, const lkc_target *target, int32_t k, float radius,
                             float plane_eps, int32_t *idx, float *d2, int32_t *count, float *mean,
                             float *cov, float *reg_cov, uint8_t *valid, const lkc_launch_cfg *cfg);
+
+/* Counters of the last search on the context (host struct).  Synchronises. */
+typedef struct lkc_search_stats {
+    int64_t queries;          /* queries of the last search */
+    int64_t fallback_queries; /* queries the group search handed to the
+                                 wavefront-per-query search */
+} lkc_search_stats;
+lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
 
 /* Grow the context's search scratch (query sort buffers and the fallback
  * list, about 36 bytes per query) to `max_queries` now, so that later

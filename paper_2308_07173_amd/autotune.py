@@ -1,0 +1,92 @@
+"""Autotuner for the search: grid cell size and launch shape.
+
+The hashed grid is an exact accelerator, so every cell size and launch shape
+gives the same results; only the time changes.  The tuner builds the target
+at each candidate cell size, times the fused search + covariance on a seeded
+calibration sample of the real queries (HIP events on the launch stream,
+median of a few repetitions after a warm-up) for each launch shape, and
+returns the fastest combination.  Results are cached in memory per
+(target fingerprint, sample fingerprint, k, radius).
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import math
+from typing import Dict, Iterable, Optional, Sequence, Tuple
+
+import numpy as np
+
+DEFAULT_CELLS = (0.5, 0.75, 1.0, 1.5, 2.0)
+DEFAULT_CFGS = (
+    dict(),                                   # group search, reach auto, 4 waves/WG
+    dict(group_reach=1),
+    dict(waves_per_block=2),
+    dict(waves_per_block=1),
+    dict(persistent=4),
+    dict(persistent=8, waves_per_block=2),
+)
+
+_cache: Dict[Tuple, Dict] = {}
+
+
+def _fingerprint(a: np.ndarray) -> str:
+    a = np.ascontiguousarray(a, np.float32)
+    h = hashlib.sha1()
+    h.update(str(a.shape).encode())
+    h.update(a[:: max(1, a.shape[0] // 4096)].tobytes())
+    return h.hexdigest()[:16]
+
+
+def autotune(target_points: np.ndarray, queries: np.ndarray, k: int, radius: float = math.inf,
+             cells: Sequence[float] = DEFAULT_CELLS, cfgs: Iterable[dict] = DEFAULT_CFGS,
+             sample: int = 131_072, reps: int = 3, seed: int = 0, ctx=None,
+             verbose: bool = False) -> Dict:
+    """Pick (cell size, launch cfg) minimising the fused search time.
+
+    Returns {"cell": c, "cfg": dict, "ms": best time on the sample,
+    "table": [(cell, cfg, ms), ...], "sample": n}."""
+    import torch
+    from paper_2308_07173_amd import lkc
+
+    rng = np.random.default_rng(seed)
+    q = np.ascontiguousarray(queries, np.float32)
+    if q.shape[0] > sample:
+        q = q[np.sort(rng.choice(q.shape[0], sample, replace=False))]
+    key = (_fingerprint(target_points), _fingerprint(q), int(k), float(radius),
+           tuple(cells), tuple(tuple(sorted(c.items())) for c in cfgs))
+    if key in _cache:
+        return _cache[key]
+    own_ctx = ctx is None
+    ctx = ctx or lkc.Context()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    tp = torch.from_numpy(np.ascontiguousarray(target_points, np.float32)).to(dev)
+    qd = torch.from_numpy(q).to(dev)
+    ctx.reserve(q.shape[0])
+    stream = torch.cuda.current_stream()
+    table = []
+    out = None
+    for cell in cells:
+        t = lkc.lkc_build_target(ctx, tp, cell)
+        for cfg in cfgs:
+            out = lkc.lkc_knn_cov(ctx, t, qd, k, radius, 1e-3, out=out, cfg=cfg)  # warm-up
+            times = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                lkc.lkc_knn_cov(ctx, t, qd, k, radius, 1e-3, out=out, cfg=cfg)
+                b.record(stream)
+                b.synchronize()
+                times.append(a.elapsed_time(b))
+            ms = float(np.median(times))
+            table.append((cell, dict(cfg), ms))
+            if verbose:
+                print(f"autotune cell={cell} cfg={cfg} {ms:.3f} ms")
+        t.free()
+    best = min(table, key=lambda r: r[2])
+    res = {"cell": best[0], "cfg": best[1], "ms": best[2], "table": table,
+           "sample": int(q.shape[0])}
+    _cache[key] = res
+    if own_ctx:
+        ctx.close()
+    return res

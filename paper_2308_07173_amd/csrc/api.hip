@@ -277,6 +277,7 @@ lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,
     hipError_t e = hipMalloc((void**)&set->views_dev, vb);
     if (e == hipSuccess) e = hipMalloc((void**)&set->header_dev, set->table_bytes);
     if (e == hipSuccess) e = hipHostMalloc(&set->staging_host, set->table_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&set->staged, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (set->views_dev) (void)hipFree(set->views_dev);
         if (set->header_dev) (void)hipFree(set->header_dev);
@@ -319,6 +320,7 @@ lkc_status lkc_target_set_free(lkc_ctx* ctx, lkc_target_set* set) {
     if (set->views_dev) (void)hipFree(set->views_dev);
     if (set->header_dev) (void)hipFree(set->header_dev);
     if (set->staging_host) (void)hipHostFree(set->staging_host);
+    if (set->staged) (void)hipEventDestroy(set->staged);
     delete[] set->host_views;
     delete set;
     return LKC_OK;
@@ -349,8 +351,8 @@ lkc_status lkc_target_set_stage(lkc_ctx* ctx, lkc_target_set* set, const lkc_sca
         if (next > 0x7fffffffLL)
             return set_error(ctx, LKC_ERR_INVALID_ARG, "scans exceed 2^31 queries");
     }
-    // the host buffer may still be read by a previous stage's copy
-    LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    // the pinned buffer may still be read by this set's previous staging copy
+    LKC_HIP_TRY(ctx, hipEventSynchronize(set->staged));
     auto* h = (BatchHeader*)set->staging_host;
     auto* hs = (BatchScan*)(h + 1);
     for (int i = 0; i < n_scans; ++i) {
@@ -363,6 +365,7 @@ lkc_status lkc_target_set_stage(lkc_ctx* ctx, lkc_target_set* set, const lkc_sca
     const size_t bytes = sizeof(BatchHeader) + sizeof(BatchScan) * (size_t)n_scans;
     LKC_HIP_TRY(ctx, hipMemcpyAsync(set->header_dev, set->staging_host, bytes,
                                     hipMemcpyHostToDevice, ctx->stream));
+    LKC_HIP_TRY(ctx, hipEventRecord(set->staged, ctx->stream));
     set->staged_scans = n_scans;
     set->staged_total = next;
     return LKC_OK;
@@ -397,6 +400,21 @@ lkc_status lkc_knn_cov_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float 
         return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL output pointer");
     return lkc::launch_knn_self(ctx, t, k, radius, plane_eps, idx, d2, count, mean, cov, reg_cov,
                                 valid, lkc::resolve_cfg(cfg));
+}
+
+lkc_status lkc_ctx_search_stats(lkc_ctx* ctx, lkc_search_stats* out) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!out) return set_error(ctx, LKC_ERR_INVALID_ARG, "out is NULL");
+    out->queries = ctx->last_queries;
+    out->fallback_queries = 0;
+    if (ctx->last_fallback_count) {
+        uint32_t v = 0;
+        LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        LKC_HIP_TRY(ctx, hipMemcpy(&v, ctx->last_fallback_count, 4, hipMemcpyDeviceToHost));
+        out->fallback_queries = v;
+    }
+    return LKC_OK;
 }
 
 lkc_status lkc_ctx_reserve(lkc_ctx* ctx, int64_t max_queries) {

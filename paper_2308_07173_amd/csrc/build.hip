@@ -7,15 +7,20 @@
 //
 //   1. scan_points   cell coordinates floor(p / cell), occupied-cell bounding
 //                    box, finiteness flag, copy of the points as float4
-//   2. make_keys     compact key (only the bits the bounding box needs)
+//   2. make_keys     Morton key of the cell (relative to the bounding box)
+//                    followed by the Morton key of the point's 4x4x4 sub-cell
 //   3. radix sort    stable LSD, 8-bit digits, only as many passes as the
-//                    key has bits (3 for a 400 m x 150 m track at 1 m cells)
-//   4. cell runs     run boundaries of the sorted keys -> occupied cells
-//   5. hash insert   open addressing, linear probing, capacity 2^ceil(log2 2C)
-//   6. reorder       points into cell order as float4 (x, y, z, original idx)
+//                    key has bits
+//   4. reorder       points into that order as float4 (x, y, z, original idx)
+//   5. cell runs     run boundaries of the cell part of the key
+//   6. hash insert   open addressing, linear probing, capacity 2^ceil(log2 2C);
+//                    the hash key is the row-major compact cell key
+//   7. run boxes     bounding box of every aligned 16-point run
 //
-// Within a cell the points keep their original order (the sort is stable),
-// so the layout is deterministic.
+// Morton order keeps neighbouring cells close in memory, and the sub-cell
+// order makes every 16-point run of a dense cell spatially compact, so a
+// search can skip runs by their boxes.  Equal keys keep their original
+// order (the sort is stable), so the layout is deterministic.
 #include <climits>
 #include <cstring>
 
@@ -29,6 +34,8 @@ constexpr int BT = 256;          // threads per block for the build kernels
 constexpr int RS_ITEMS = 8;      // radix items per thread per tile
 constexpr int RS_TILE = BT * RS_ITEMS;
 constexpr int RADIX = 256;
+constexpr int SUB_BITS = 6;      // Morton bits of the 4x4x4 sub-cell below the cell key
+constexpr int SCAN_TILE = 4096;  // entries per workgroup of the multi-block scan
 
 struct BuildMeta {
     int cmin[3];
@@ -125,8 +132,13 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
 struct KeyParams {
     float inv_cell;
     int cmin[3];
-    int sh_y, sh_z;
 };
+
+__device__ __forceinline__ uint32_t sub_cell(float x, float inv_cell) {
+    const float u = x * inv_cell;
+    const float f = u - floorf(u);
+    return (uint32_t)min(max((int)(f * 4.0f), 0), 3);
+}
 
 __global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ orig, int64_t n,
                                                   KeyParams kp, unsigned long long* __restrict__ keys,
@@ -134,11 +146,12 @@ __global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ ori
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n) return;
     const float4 p = orig[i];
-    const int cx = cell_coord(p.x, kp.inv_cell) - kp.cmin[0];
-    const int cy = cell_coord(p.y, kp.inv_cell) - kp.cmin[1];
-    const int cz = cell_coord(p.z, kp.inv_cell) - kp.cmin[2];
-    keys[i] = (unsigned long long)(uint32_t)cx | ((unsigned long long)(uint32_t)cy << kp.sh_y) |
-              ((unsigned long long)(uint32_t)cz << kp.sh_z);
+    const uint32_t cx = (uint32_t)(cell_coord(p.x, kp.inv_cell) - kp.cmin[0]);
+    const uint32_t cy = (uint32_t)(cell_coord(p.y, kp.inv_cell) - kp.cmin[1]);
+    const uint32_t cz = (uint32_t)(cell_coord(p.z, kp.inv_cell) - kp.cmin[2]);
+    const unsigned long long sub = morton3(sub_cell(p.x, kp.inv_cell), sub_cell(p.y, kp.inv_cell),
+                                           sub_cell(p.z, kp.inv_cell));
+    keys[i] = (morton3(cx, cy, cz) << SUB_BITS) | sub;
     vals[i] = (uint32_t)i;
 }
 
@@ -186,6 +199,38 @@ __global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t* __restrict__ 
         run += v;
     }
     if (total && threadIdx.x == T - 1) *total = run;
+}
+
+// Multi-block exclusive scan, step 1: every workgroup scans its 4096-entry
+// tile in place and records the tile total.
+__global__ void __launch_bounds__(BT) k_scan_tiles(uint32_t* __restrict__ data, int64_t m,
+                                                   uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s_w[BT / WAVE];
+    __shared__ uint32_t s_carry;
+    const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    if (threadIdx.x == 0) s_carry = 0;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    for (int it = 0; it < SCAN_TILE / BT; ++it) {
+        const int64_t i = base + it * BT + threadIdx.x;
+        const uint32_t v = i < m ? data[i] : 0u;
+        const int incl = wave_incl_scan((int)v);
+        if (l == WAVE - 1) s_w[w] = (uint32_t)incl;
+        __syncthreads();
+        uint32_t wo = s_carry;
+        for (int j = 0; j < w; ++j) wo += s_w[j];
+        if (i < m) data[i] = wo + (uint32_t)incl - v;
+        __syncthreads();
+        if (threadIdx.x == BT - 1) s_carry = wo + (uint32_t)incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = s_carry;
+}
+
+// step 3: add the scanned tile totals
+__global__ void __launch_bounds__(BT) k_scan_add(uint32_t* __restrict__ data, int64_t m,
+                                                 const uint32_t* __restrict__ totals) {
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (i < m) data[i] += totals[i / SCAN_TILE];
 }
 
 // Stable scatter of one 8-bit digit.  Items of a tile are visited in index
@@ -244,23 +289,33 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
     }
 }
 
-// Cell runs: flag(i) = key[i] != key[i-1].  Pass 1 counts flags per block.
+// Cell runs: flag(i) = cell part of key[i] differs from key[i-1]'s.  Pass 1
+// counts flags per block.
 __global__ void __launch_bounds__(BT) k_cell_count(const unsigned long long* __restrict__ keys,
                                                    int64_t n, uint32_t* __restrict__ bcount) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    const bool f = i < n && (i == 0 || keys[i] != keys[i - 1]);
+    const bool f = i < n && (i == 0 || (keys[i] >> SUB_BITS) != (keys[i - 1] >> SUB_BITS));
     const int c = __syncthreads_count(f);
     if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)c;
 }
 
+struct RowKey {
+    float inv_cell;
+    int cmin[3];
+    int sh_y, sh_z;
+};
+
+// Pass 2: each run start writes its cell's row-major key (recomputed from the
+// reordered point) and its first position.
 __global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __restrict__ keys,
-                                                   int64_t n, const uint32_t* __restrict__ boff,
+                                                   const float4* __restrict__ pts, int64_t n,
+                                                   const uint32_t* __restrict__ boff, RowKey rk,
                                                    unsigned long long* __restrict__ ckeys,
                                                    uint32_t* __restrict__ cstart,
                                                    BuildMeta* __restrict__ meta) {
     __shared__ uint32_t s_w[BT / WAVE];
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    const bool f = i < n && (i == 0 || keys[i] != keys[i - 1]);
+    const bool f = i < n && (i == 0 || (keys[i] >> SUB_BITS) != (keys[i - 1] >> SUB_BITS));
     const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     const unsigned long long bal = __ballot(f);
     const uint32_t pre = (uint32_t)__popcll(bal & ((1ull << l) - 1ull));
@@ -270,10 +325,39 @@ __global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __r
     for (int j = 0; j < w; ++j) wo += s_w[j];
     const uint32_t cid = boff[blockIdx.x] + wo + pre;
     if (f) {
-        ckeys[cid] = keys[i];
+        const float4 p = pts[i];
+        const uint32_t cx = (uint32_t)(cell_coord(p.x, rk.inv_cell) - rk.cmin[0]);
+        const uint32_t cy = (uint32_t)(cell_coord(p.y, rk.inv_cell) - rk.cmin[1]);
+        const uint32_t cz = (uint32_t)(cell_coord(p.z, rk.inv_cell) - rk.cmin[2]);
+        ckeys[cid] = (unsigned long long)cx | ((unsigned long long)cy << rk.sh_y) |
+                     ((unsigned long long)cz << rk.sh_z);
         cstart[cid] = (uint32_t)i;
     }
     if (i == n - 1) meta->n_cells = cid + (f ? 1u : 0u);
+}
+
+// Bounding box of every aligned 16-point run of the reordered points (one
+// 16-lane quarter of a wavefront per box).
+__global__ void __launch_bounds__(BT) k_chunk_boxes(const float4* __restrict__ pts, int64_t n,
+                                                    float4* __restrict__ boxes) {
+    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    const int64_t box = i / BOX_PTS;
+    const bool v = i < n;
+    const float4 p = v ? pts[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float lo[3] = {v ? p.x : INFINITY, v ? p.y : INFINITY, v ? p.z : INFINITY};
+    float hi[3] = {v ? p.x : -INFINITY, v ? p.y : -INFINITY, v ? p.z : -INFINITY};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int s = BOX_PTS / 2; s > 0; s >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], s));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], s));
+        }
+    }
+    if (i % BOX_PTS == 0 && box * BOX_PTS < n) {
+        boxes[2 * box] = make_float4(lo[0], lo[1], lo[2], 0.f);
+        boxes[2 * box + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+    }
 }
 
 __global__ void k_hash_clear(HashSlot* __restrict__ h, int64_t cap) {
@@ -350,21 +434,37 @@ lkc_status ensure_scratch(lkc_ctx* ctx, size_t bytes) {
 
 }  // namespace
 
+// Exclusive scan of m words in place; `tmp` holds ceil(m / 4096) + 1 words.
+static void scan_exclusive(hipStream_t st, uint32_t* data, int64_t m, uint32_t* tmp) {
+    if (m <= 4 * SCAN_TILE) {
+        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, data, m,
+                           (uint32_t*)nullptr);
+        return;
+    }
+    const int64_t nt = (m + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(BT), 0, st, data, m, tmp);
+    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, tmp, nt, (uint32_t*)nullptr);
+    hipLaunchKernelGGL(k_scan_add, dim3(grid_for(m, BT)), dim3(BT), 0, st, data, m,
+                       (const uint32_t*)tmp);
+}
+
 size_t sort_count_words(int64_t n) {
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
-    return (size_t)RADIX * (size_t)(nb > 0 ? nb : 1);
+    const size_t m = (size_t)RADIX * (size_t)(nb > 0 ? nb : 1);
+    return m + m / SCAN_TILE + 64;
 }
 
 lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsigned long long* kb,
                       uint32_t* vb, int64_t n, int bits, uint32_t* counts, bool* in_b) {
     hipStream_t st = ctx->stream;
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    const int64_t m = (int64_t)RADIX * nb;
+    uint32_t* tmp = counts + m;
     bool b = false;
     for (int shift = 0; shift < bits && n > 1; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(BT), 0, st, ka, n, shift,
                            counts, (int)nb);
-        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, counts,
-                           (int64_t)RADIX * nb, (uint32_t*)nullptr);
+        scan_exclusive(st, counts, m, tmp);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(BT), 0, st, ka, va, kb, vb,
                            n, shift, counts, (int)nb);
         std::swap(ka, kb);
@@ -399,9 +499,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     t->sort_passes = 0;
 
     // ---- point storage (pts + orig), grow-only
-    // pts carries 16 spare records: the search streams candidates four at a
-    // time and may read up to three records past the last run
-    const size_t pbytes = align256(sizeof(float4) * ((size_t)(n > 0 ? n : 1) + 16));
+    // pts carries 64 spare records: the search loads whole aligned 64-record
+    // chunks and may read up to 63 records past the last point
+    const size_t pbytes = align256(sizeof(float4) * ((size_t)(n > 0 ? n : 1) + 64));
     if (t->point_bytes < 2 * pbytes) {
         if (t->point_mem) {
             LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -421,7 +521,6 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     float4* orig = (float4*)((char*)t->point_mem + pbytes);
 
     // ---- scratch: keys a/b, vals a/b, radix counts, block counts, cell temps
-    const int64_t nb_rs = (n + RS_TILE - 1) / RS_TILE;
     const int64_t nb_bt = (n + BT - 1) / BT;
     size_t off = 0;
     auto carve = [&](size_t bytes) {
@@ -432,8 +531,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     const size_t nn = (size_t)(n > 0 ? n : 1);
     const size_t o_ka = carve(8 * nn), o_kb = carve(8 * nn);
     const size_t o_va = carve(4 * nn), o_vb = carve(4 * nn);
-    const size_t o_cnt = carve(4 * (size_t)RADIX * (size_t)(nb_rs > 0 ? nb_rs : 1));
+    const size_t o_cnt = carve(4 * sort_count_words(n));
     const size_t o_bc = carve(4 * (size_t)(nb_bt > 0 ? nb_bt : 1) + 4);
+    const size_t o_bt = carve(4 * (size_t)(nb_bt / SCAN_TILE + 2));
     const size_t o_tk = carve(8 * nn), o_ts = carve(4 * nn + 4);
     lkc_status s = ensure_scratch(ctx, off);
     if (s != LKC_OK) return s;
@@ -444,6 +544,7 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     auto* vals_b = (uint32_t*)(sb + o_vb);
     auto* rcounts = (uint32_t*)(sb + o_cnt);
     auto* bcounts = (uint32_t*)(sb + o_bc);
+    auto* btmp = (uint32_t*)(sb + o_bt);
     auto* tkeys = (unsigned long long*)(sb + o_tk);
     auto* tstart = (uint32_t*)(sb + o_ts);
     auto* meta = (BuildMeta*)ctx->meta_dev;
@@ -462,51 +563,49 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
             V.n = 0;
             return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
         }
-        int bits[3];
+        int bits[3], wmax = 0;
         for (int a = 0; a < 3; ++a) {
             V.cmin[a] = hmeta->cmin[a];
             V.cmax[a] = hmeta->cmax[a];
             bits[a] = bit_width((uint32_t)(hmeta->cmax[a] - hmeta->cmin[a]));
+            wmax = std::max(wmax, bits[a]);
         }
         V.max_abs = __builtin_bit_cast(float, hmeta->max_abs_bits);
         V.sh_y = bits[0];
         V.sh_z = bits[0] + bits[1];
-        t->key_bits = bits[0] + bits[1] + bits[2];
+        t->key_bits = 3 * wmax + SUB_BITS;
         t->sort_passes = (t->key_bits + 7) / 8;
 
         // ---- 2. keys
         KeyParams kp;
         kp.inv_cell = inv_cell;
         for (int a = 0; a < 3; ++a) kp.cmin[a] = V.cmin[a];
-        kp.sh_y = V.sh_y;
-        kp.sh_z = V.sh_z;
         hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, n, kp,
                            keys_a, vals_a);
 
         // ---- 3. LSD radix sort on the occupied key bits
-        for (int pass = 0; pass < t->sort_passes; ++pass) {
-            const int shift = 8 * pass;
-            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb_rs), dim3(BT), 0, st, keys_a, n,
-                               shift, rcounts, (int)nb_rs);
-            hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, rcounts,
-                               (int64_t)RADIX * nb_rs, (uint32_t*)nullptr);
-            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb_rs), dim3(BT), 0, st, keys_a,
-                               vals_a, keys_b, vals_b, n, shift, rcounts, (int)nb_rs);
+        bool in_b = false;
+        s = sort_pairs(ctx, keys_a, vals_a, keys_b, vals_b, n, t->key_bits, rcounts, &in_b);
+        if (s != LKC_OK) return s;
+        if (in_b) {
             std::swap(keys_a, keys_b);
             std::swap(vals_a, vals_b);
         }
-        LKC_HIP_TRY(ctx, hipGetLastError());
 
-        // ---- 4. cell runs
-        hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a, n,
-                           bcounts);
-        hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, st, bcounts, nb_bt,
-                           (uint32_t*)nullptr);
-        hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a, n,
-                           bcounts, tkeys, tstart, meta);
-        // ---- 6. reorder (independent of the cell count)
+        // ---- 4. reorder
         hipLaunchKernelGGL(k_reorder, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, vals_a, n,
                            pts);
+        // ---- 5. cell runs
+        RowKey rk;
+        rk.inv_cell = inv_cell;
+        for (int a = 0; a < 3; ++a) rk.cmin[a] = V.cmin[a];
+        rk.sh_y = V.sh_y;
+        rk.sh_z = V.sh_z;
+        hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a, n,
+                           bcounts);
+        scan_exclusive(st, bcounts, nb_bt, btmp);
+        hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a,
+                           (const float4*)pts, n, bcounts, rk, tkeys, tstart, meta);
         LKC_HIP_TRY(ctx, hipGetLastError());
         LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
         LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -518,14 +617,16 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         }
     }
 
-    // ---- 5. cell arrays + hash (sized by the cell count)
+    // ---- 6. cell arrays + hash (sized by the cell count), 7. chunk boxes
     int hbits = 6;
     while (((int64_t)1 << hbits) < 2 * n_cells) ++hbits;
     const int64_t cap = (int64_t)1 << hbits;
+    const int64_t n_chunks = (n + BOX_PTS - 1) / BOX_PTS;
     const size_t ck_b = align256(8 * (size_t)(n_cells > 0 ? n_cells : 1));
     const size_t cs_b = align256(4 * (size_t)(n_cells + 1));
     const size_t h_b = align256(sizeof(HashSlot) * (size_t)cap);
-    const size_t cbytes = ck_b + cs_b + h_b;
+    const size_t bx_b = align256(2 * sizeof(float4) * (size_t)(n_chunks > 0 ? n_chunks : 1));
+    const size_t cbytes = ck_b + cs_b + h_b + bx_b;
     if (t->cell_bytes < cbytes) {
         if (t->cell_mem) {
             LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -545,10 +646,13 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     auto* ckeys = (unsigned long long*)t->cell_mem;
     auto* cstart = (uint32_t*)((char*)t->cell_mem + ck_b);
     auto* hash = (HashSlot*)((char*)t->cell_mem + ck_b + cs_b);
+    auto* boxes = (float4*)((char*)t->cell_mem + ck_b + cs_b + h_b);
     hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap, BT)), dim3(BT), 0, st, hash, cap);
     if (n_cells > 0) {
         hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n_cells, BT)), dim3(BT), 0, st, tkeys,
                            tstart, n_cells, n, ckeys, cstart, hash, hbits, (uint32_t)(cap - 1));
+        hipLaunchKernelGGL(k_chunk_boxes, dim3(grid_for(n, BT)), dim3(BT), 0, st,
+                           (const float4*)pts, n, boxes);
     } else {
         hipLaunchKernelGGL(k_iota, dim3(1), dim3(1), 0, st, cstart, (int64_t)1);
     }
@@ -559,6 +663,7 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     V.hash = hash;
     V.cell_keys = ckeys;
     V.cell_start = cstart;
+    V.boxes = boxes;
     V.n = n;
     V.n_cells = (int32_t)n_cells;
     V.hash_bits = hbits;

@@ -2,9 +2,14 @@
 // HIP kernels of the nearest-points search and covariance library.
 //
 // Layout of a built target in HBM (all arrays 16-byte aligned):
-//   pts   float4[n]      points reordered by cell key; .w holds the original
-//                        index (bit-cast int32), so a cell's candidates are one
-//                        contiguous, coalesced run of 16-byte records
+//   pts   float4[n]      points reordered by the Morton order of their cells
+//                        and, inside a cell, of 4x4x4 sub-cells; .w holds the
+//                        original index (bit-cast int32), so a cell's
+//                        candidates are one contiguous run of 16-byte records
+//   boxes float4[2 ceil(n/16)]
+//                        bounding box of every aligned 16-record run of pts
+//                        (lets a search skip the parts of a dense cell that
+//                        lie far from its queries)
 //   orig  float4[n]      the caller's points in original order (.w = 0); the
 //                        gather source when neighbours are named by original
 //                        index
@@ -23,6 +28,7 @@ constexpr int WAVE = 64;
 constexpr unsigned long long EMPTY_KEY = ~0ull;
 constexpr int32_t IDX_SENTINEL = 0x7fffffff;
 constexpr int CELL_CLAMP = 1 << 20;  // integer cell coordinates live in [-2^20, 2^20)
+constexpr int BOX_PTS = 16;          // points per bounding box of the reordered array
 
 struct HashSlot {
     unsigned long long key;
@@ -48,6 +54,7 @@ struct TargetView {
     int32_t cmax[3];
     int32_t sh_y, sh_z;   // compact key = kx | ky << sh_y | kz << sh_z
     float max_abs;        // max |coordinate| over the target (for error margins)
+    const float4* boxes;  // per 16-point run of pts: lo (2b) and hi (2b+1) corners
 };
 
 // --------------------------------------------------------------- scalars --
@@ -103,6 +110,22 @@ __device__ __forceinline__ bool key_less(float da, int32_t ia, float db, int32_t
     return da < db || (da == db && ia < ib);
 }
 
+// Morton (Z-order) interleave of three non-negative integers below 2^21:
+// bit i of x, y, z lands on bits 3i, 3i+1, 3i+2.  Sorting by it keeps
+// neighbouring cells (and queries) close in memory order.
+__device__ __forceinline__ unsigned long long spread3(uint32_t v) {
+    unsigned long long x = v & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+__device__ __forceinline__ unsigned long long morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
 // Load a read-only object at a wavefront-uniform address through the
 // constant address space, so the compiler issues scalar loads (one request
 // for the whole wavefront, results in SGPRs).  Only for memory no kernel
@@ -152,6 +175,26 @@ __device__ __forceinline__ T shfl(T v, int src) {
     static_assert(sizeof(T) == 4, "32-bit only");
     return __builtin_bit_cast(T, __shfl(__builtin_bit_cast(int, v), src));
 }
+
+// Maximum / minimum over the wavefront with DPP row shifts and row
+// broadcasts (no LDS traffic); every lane receives the result.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                 __builtin_bit_cast(int, v), CTRL,
+                                                                 ROW_MASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    const float id = -__builtin_huge_valf();
+    v = fmaxf(v, dpp_f<0x111, 0xf>(id, v));  // row_shr:1
+    v = fmaxf(v, dpp_f<0x112, 0xf>(id, v));  // row_shr:2
+    v = fmaxf(v, dpp_f<0x114, 0xf>(id, v));  // row_shr:4
+    v = fmaxf(v, dpp_f<0x118, 0xf>(id, v));  // row_shr:8  (lane 15 of a row: row max)
+    v = fmaxf(v, dpp_f<0x142, 0xa>(id, v));  // row_bcast:15
+    v = fmaxf(v, dpp_f<0x143, 0xc>(id, v));  // row_bcast:31 (lane 63: wave max)
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ float wave_min_dpp(float v) { return -wave_max_dpp(-v); }
 
 // inclusive prefix sum across the wave (Hillis-Steele with shuffles)
 __device__ __forceinline__ int wave_incl_scan(int v) {

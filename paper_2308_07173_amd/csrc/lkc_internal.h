@@ -24,6 +24,8 @@ struct lkc_ctx {
     // grow-only device scratch for searches (query sort, fallback list)
     void* search_scratch = nullptr;
     size_t search_scratch_bytes = 0;
+    uint32_t* last_fallback_count = nullptr;  // device word of the last search
+    int64_t last_queries = 0;
 };
 
 struct lkc_target {
@@ -62,6 +64,7 @@ struct lkc_target_set {
     BatchHeader* header_dev = nullptr;      // header followed by BatchScan[max_scans]
     BatchScan* scans_dev = nullptr;
     void* staging_host = nullptr;           // pinned, same layout as header_dev
+    hipEvent_t staged = nullptr;            // recorded after the last staging copy
     size_t table_bytes = 0;
     int32_t staged_scans = 0;
     int64_t staged_total = 0;               // queries covered by the staged scans

@@ -536,14 +536,80 @@ __device__ __forceinline__ SlotQuery load_slot(const GroupArgs& a, const TargetV
     return s;
 }
 
+// Squared distance between two axis-aligned boxes (0 if they overlap),
+// shrunk by `margin`.
+__device__ __forceinline__ float box_box_dist2(const float (&a0)[3], const float (&a1)[3],
+                                               float b0x, float b0y, float b0z, float b1x,
+                                               float b1y, float b1z, float margin) {
+    const float gx = fmaxf(fmaxf(b0x - a1[0], a0[0] - b1x) - margin, 0.0f);
+    const float gy = fmaxf(fmaxf(b0y - a1[1], a0[1] - b1y) - margin, 0.0f);
+    const float gz = fmaxf(fmaxf(b0z - a1[2], a0[2] - b1z) - margin, 0.0f);
+    return gx * gx + gy * gy + gz * gz;
+}
+
+// Stream the reordered points [s0, e0) through every member lane's top-k.
+// The run is walked in aligned 64-point chunks made of four 16-point runs
+// with their own bounding boxes; mode 0 takes only the 16-point runs whose
+// box touches the group's query box, mode 1 only the others, mode 2 all of
+// them, and modes 1-2 skip a 16-point run whose box is farther from the
+// query box than the radius or the group's largest k-th distance.  A kept
+// chunk is loaded once (lane t holds point t, one coalesced read); each
+// candidate is broadcast from its lane and tested by every lane, which only
+// sets a bit per passing candidate; the insertions follow as "pops" in which
+// every lane inserts its own next passing candidate, so a chunk costs as
+// many insertion steps as its busiest lane needs rather than one per
+// candidate that any lane wants.
 template <int K>
-__device__ __forceinline__ void visit(const float4& c, bool member, float qx, float qy, float qz,
-                                      float r2, unsigned long long (&kk)[K]) {
-    const float d = dist2(qx, qy, qz, c.x, c.y, c.z);
-    const unsigned long long key = lane_key(d, __float_as_int(c.w));
-    const bool pass = member && d <= r2 && key < kk[K - 1];
-    if (ballot(pass)) {
-        if (pass) lane_insert<K>(kk, key);
+__device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bool member,
+                                         float qx, float qy, float qz, float r2,
+                                         const float (&b0)[3], const float (&b1)[3],
+                                         float margin, float& gthr,
+                                         unsigned long long (&kk)[K], int mode) {
+    const int lane = lane_id();
+#pragma unroll 1
+    for (int cb = s0 & ~(WAVE - 1); cb < e0; cb += WAVE) {
+        uint32_t keep = 0;
+#pragma unroll
+        for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
+            const int sb = cb + q4 * BOX_PTS;
+            if (sb + BOX_PTS <= s0 || sb >= e0) continue;
+            const float4 blo = load_uniform(T.boxes + 2 * (sb / BOX_PTS));
+            const float4 bhi = load_uniform(T.boxes + 2 * (sb / BOX_PTS) + 1);
+            const float bd =
+                box_box_dist2(b0, b1, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, margin);
+            const bool near = bd <= r2 && bd * (1.0f - 1e-6f) <= gthr;
+            const bool want = mode == 0 ? bd == 0.0f : (mode == 1 ? (bd > 0.0f && near) : near);
+            if (want) keep |= 1u << q4;
+        }
+        if (!keep) continue;
+        const float4 c = T.pts[cb + lane];   // padded: reads past n stay in bounds
+        unsigned long long bits = 0;
+        const int lo = max(s0, cb) - cb, hi = min(e0, cb + WAVE) - cb;
+#pragma unroll 1
+        for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
+            if (!((keep >> q4) & 1u)) continue;
+            const int t1 = min(hi, (q4 + 1) * BOX_PTS);
+#pragma unroll 2
+            for (int t = max(lo, q4 * BOX_PTS); t < t1; ++t) {
+                const float cx = readlane(c.x, t), cy = readlane(c.y, t), cz = readlane(c.z, t);
+                const int32_t ci = readlane(__float_as_int(c.w), t);
+                const float d = dist2(qx, qy, qz, cx, cy, cz);
+                const bool pass = member && d <= r2 && lane_key(d, ci) < kk[K - 1];
+                bits |= pass ? (1ull << t) : 0ull;
+            }
+        }
+        if (!ballot(bits != 0ull)) continue;
+        do {
+            const int j = bits ? __builtin_ffsll((long long)bits) - 1 : 0;
+            const float cx = shfl(c.x, j), cy = shfl(c.y, j), cz = shfl(c.z, j);
+            const int32_t ci = shfl(__float_as_int(c.w), j);
+            if (bits) {
+                bits &= bits - 1;
+                const unsigned long long key = lane_key(dist2(qx, qy, qz, cx, cy, cz), ci);
+                if (key < kk[K - 1]) lane_insert<K>(kk, key);
+            }
+        } while (ballot(bits != 0ull));
+        gthr = wave_max_dpp(member ? (kk[K - 1] == ~0ull ? INF : key_d2(kk[K - 1])) : -INF);
     }
 }
 
@@ -579,9 +645,9 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
     const unsigned long long mm = ballot(member);
     bool ok = true;
     if (mm && T.n_cells > 0) {
-        const float bx0 = wave_minf(member ? s.x : INF), bx1 = wave_maxf(member ? s.x : -INF);
-        const float by0 = wave_minf(member ? s.y : INF), by1 = wave_maxf(member ? s.y : -INF);
-        const float bz0 = wave_minf(member ? s.z : INF), bz1 = wave_maxf(member ? s.z : -INF);
+        const float bx0 = wave_min_dpp(member ? s.x : INF), bx1 = wave_max_dpp(member ? s.x : -INF);
+        const float by0 = wave_min_dpp(member ? s.y : INF), by1 = wave_max_dpp(member ? s.y : -INF);
+        const float bz0 = wave_min_dpp(member ? s.z : INF), bz1 = wave_max_dpp(member ? s.z : -INF);
         const float b0[3] = {bx0, by0, bz0}, b1[3] = {bx1, by1, bz1};
         int blo[3], bhi[3], lo[3], ext[3];
         int64_t total = 1;
@@ -599,9 +665,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
         float gthr = INF;
         for (int pass = 0; pass < 2; ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
-                if (pass == 1)
-                    gthr = wave_maxf(member ? (kk[K - 1] == ~0ull ? INF : key_d2(kk[K - 1]))
-                                            : -INF);
+
                 const int64_t t = base + lane;
                 bool want = false;
                 uint32_t st = 0, cn = 0;
@@ -620,23 +684,19 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
                     if (inside == (pass == 0) && bd <= r2 && bd * (1.0f - 1e-6f) <= gthr)
                         want = hash_find(T, pack_key(T, c3[0], c3[1], c3[2]), st, cn) && cn > 0;
                 }
-                unsigned long long wm = ballot(want);
-                while (wm) {
-                    const int cl = __builtin_ffsll((long long)wm) - 1;
-                    wm &= wm - 1;
-                    const int s0 = readlane((int)st, cl);
-                    const int e0 = s0 + readlane((int)cn, cl);
-                    // candidates stream through scalar loads, two records
-                    // ahead (the point array is padded past its end)
-                    const float4* pts = T.pts;
-                    float4 c0 = load_uniform(pts + s0), c1 = load_uniform(pts + s0 + 1);
-                    for (int i = s0; i < e0; i += 2) {
-                        const float4 n0 = load_uniform(pts + i + 2);
-                        const float4 n1 = load_uniform(pts + i + 3);
-                        visit<K>(c0, member, s.x, s.y, s.z, r2, kk);
-                        if (i + 1 < e0) visit<K>(c1, member, s.x, s.y, s.z, r2, kk);
-                        c0 = n0;
-                        c1 = n1;
+                // the cells holding the queries: first the 16-point runs that
+                // touch the query box (they set tight k-th distances), then
+                // the rest; the surrounding cells after that, pruned
+                const unsigned long long wm0 = ballot(want);
+                for (int mode = (pass == 0 ? 0 : 2); mode <= (pass == 0 ? 1 : 2); ++mode) {
+                    unsigned long long wm = wm0;
+                    while (wm) {
+                        const int cl = __builtin_ffsll((long long)wm) - 1;
+                        wm &= wm - 1;
+                        const int s0 = readlane((int)st, cl);
+                        const int e0 = s0 + readlane((int)cn, cl);
+                        scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, b0, b1, margin, gthr,
+                                    kk, mode);
                     }
                 }
             }
@@ -785,17 +845,16 @@ __global__ void __launch_bounds__(256) k_query_keys(QueryKeyArgs a) {
     }
     const TargetView& T = a.views[tg];
     const float x = a.queries[3 * i], y = a.queries[3 * i + 1], z = a.queries[3 * i + 2];
-    unsigned long long key = 0;
+    unsigned long long key;
     if (finite3(x, y, z)) {
-        const int c[3] = {cell_coord(x, T.inv_cell), cell_coord(y, T.inv_cell),
-                          cell_coord(z, T.inv_cell)};
-        int sh = 0;
+        uint32_t v[3];
+        const float p3[3] = {x, y, z};
         for (int d = 0; d < 3; ++d) {
+            const int c = cell_coord(p3[d], T.inv_cell);
             const int range = max(T.cmax[d] - T.cmin[d], 0) + 2;
-            const int v = min(max(c[d] - (T.cmin[d] - 1), 0), range);
-            key |= (unsigned long long)(uint32_t)v << sh;
-            sh += 32 - __builtin_clz((uint32_t)range);
+            v[d] = (uint32_t)min(max(c - (T.cmin[d] - 1), 0), range);
         }
+        key = morton3(v[0], v[1], v[2]);
     } else {
         key = (1ull << a.tshift) - 1ull;
     }
@@ -894,6 +953,7 @@ lkc_status search_scratch(lkc_ctx* ctx, int64_t n, Scratch& s) {
             (void)hipFree(ctx->search_scratch);
             ctx->search_scratch = nullptr;
             ctx->search_scratch_bytes = 0;
+            ctx->last_fallback_count = nullptr;
         }
         const size_t bytes = off + off / 4;   // headroom for slightly larger calls
         hipError_t e = hipMalloc(&ctx->search_scratch, bytes);
@@ -969,6 +1029,8 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     a.fb_list = sc.fb_list;
     a.fb_count = sc.words;
     a.counters = nullptr;
+    ctx->last_fallback_count = sc.words;
+    ctx->last_queries = j.n_slots;
     const int K = choose_k_tile(j.k);
     const bool group = K > 0 && cfg.algorithm != 2;
     const unsigned wpb = (unsigned)cfg.waves_per_block;
@@ -976,13 +1038,13 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
         hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, sc.words, 16, 0u);
         if (j.queries) {
             // sort the queries by their cell in the target grid
-            int tshift = 0;
+            int wmax = 1;
             for (int t = 0; t < j.n_targets; ++t) {
                 const TargetView& V = j.host_views[t];
-                int b = 0;
-                for (int d = 0; d < 3; ++d) b += bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2));
-                tshift = std::max(tshift, b);
+                for (int d = 0; d < 3; ++d)
+                    wmax = std::max(wmax, bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2)));
             }
+            const int tshift = 3 * wmax;   // Morton key of the (clamped) query cell
             const int tbits = j.n_targets > 1 ? bitw((uint32_t)(j.n_targets - 1)) : 0;
             if (tshift + tbits > 63)
                 return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",

@@ -40,7 +40,7 @@ EXPORTED_SYMBOLS = (
     "lkc_synchronize", "lkc_build_target", "lkc_target_rebuild", "lkc_target_free",
     "lkc_target_get_info", "lkc_target_arrays", "lkc_knn_query", "lkc_covariances",
     "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
-    "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve",
+    "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve", "lkc_ctx_search_stats",
 )
 
 
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_knn_cov_batched": ([P, P, P, I64, I32, F, F, P, P, P, P, P, P, P, P], I32),
             "lkc_knn_cov_self": ([P, P, I32, F, F, P, P, P, P, P, P, P, P], I32),
             "lkc_ctx_reserve": ([P, I64], I32),
+            "lkc_ctx_search_stats": ([P, P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -177,6 +178,13 @@ class Context:
     def reserve(self, max_queries: int):
         self._bind()
         self.check(self.lib.lkc_ctx_reserve(self.handle, int(max_queries)))
+
+    def search_stats(self) -> Dict:
+        """Queries and fallback queries of the last search (synchronises)."""
+        buf = (ctypes.c_int64 * 2)()
+        self._bind()
+        self.check(self.lib.lkc_ctx_search_stats(self.handle, buf))
+        return {"queries": buf[0], "fallback_queries": buf[1]}
 
     def synchronize(self):
         self._bind()

@@ -347,6 +347,35 @@ def served_schedule(duration: float = 60.0, rate_hz: float = 20.0, n_sensors: in
     return reqs
 
 
+def served_maps(sizes=SERVED_MAP_SIZES, seed: int = 50) -> List[np.ndarray]:
+    """The resident maps of the served stream: same builder, different
+    seeds; a size above 2,000,000 points is the union of two maps built
+    with different seeds (a denser map of the same track)."""
+    out = []
+    for i, n in enumerate(sizes):
+        parts, left, j = [], n, 0
+        while left > 0:
+            m = min(left, 2_000_000)
+            parts.append(build_map(m, seed=seed + 10 * i + j)[0])
+            left -= m
+            j += 1
+        out.append(np.ascontiguousarray(np.concatenate(parts)))
+    return out
+
+
+def served_scan_pool(n_poses: int = 16, seed: int = 6) -> List[np.ndarray]:
+    """Full 0 %-dropout sweeps (131,072 points, world frame) of three
+    sensors at n_poses random track poses; served requests take the first
+    n points of pool[rid % len(pool)]."""
+    rng = np.random.default_rng(seed)
+    pool = []
+    for _ in range(n_poses):
+        pose = track_pose(rng.uniform(0, PERIMETER), rng.uniform(-6.0, 6.0))
+        for off in (0.0, 2 * math.pi / 3, -2 * math.pi / 3):
+            pool.append(raycast_scan(pose, rng, dropout=0.0, yaw_offset=off).points_world)
+    return pool
+
+
 def request_points(req: Request, map_seed_base: int = 100) -> np.ndarray:
     """World-frame points for a served request (scan at a random track pose)."""
     rng = np.random.default_rng(req.scan_seed)

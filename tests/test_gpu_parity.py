@@ -78,10 +78,23 @@ def test_build_cells_partition_points(lk, n, cell, seed):
     by = int(info["cell_max"][1] - info["cell_min"][1]).bit_length()
     packed = key[:, 0] | (key[:, 1] << np.uint64(bx)) | (key[:, 2] << np.uint64(bx + by))
     assert np.array_equal(packed, ck.astype(np.uint64)[cell_of])
-    assert np.all(np.diff(ck.astype(np.uint64)) > 0)
-    for j in range(C):
-        seg = orig[cs[j]:cs[j + 1]]
-        assert np.all(np.diff(seg) > 0)
+    assert np.unique(ck).size == C                       # one run per cell
+    # cells follow the Morton order of their (relative) coordinates; inside
+    # a cell the 4x4x4 sub-cells follow Morton order and ties keep the
+    # original order (stable sort)
+    def spread(v):
+        out = np.zeros_like(v, dtype=np.uint64)
+        for b in range(21):
+            out |= ((v.astype(np.uint64) >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b)
+        return out
+    rel = (c - np.array(info["cell_min"])).astype(np.uint64)
+    u = p[orig].astype(np.float32) * inv
+    sub = np.clip(((u - np.floor(u)) * np.float32(4.0)).astype(np.int64), 0, 3).astype(np.uint64)
+    mort = ((spread(rel[:, 0]) | spread(rel[:, 1]) << np.uint64(1) | spread(rel[:, 2]) << np.uint64(2))
+            << np.uint64(6)) | spread(sub[:, 0]) | spread(sub[:, 1]) << np.uint64(1) | \
+        spread(sub[:, 2]) << np.uint64(2)
+    order = np.lexsort((orig, mort))
+    assert np.array_equal(order, np.arange(n))
     assert info["hash_capacity"] >= 2 * C
     t.free()
 
