@@ -48,22 +48,26 @@ def build(force: bool = False) -> str:
     return _LIB_PATH
 
 
+def configure(lib):
+    """Declare the C signatures on a loaded oracle library."""
+    P = ctypes.c_void_p
+    lib.oracle_knn.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32,
+                               ctypes.c_double, ctypes.c_int32, P, P, P]
+    lib.oracle_knn.restype = ctypes.c_int
+    lib.oracle_covariances.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                       P, P, P, P, P, P]
+    lib.oracle_covariances.restype = ctypes.c_int
+    lib.oracle_sym3_eig.argtypes = [P, P, P]
+    lib.oracle_sym3_eig.restype = None
+    return lib
+
+
 def _load():
     global _lib
     with _lock:
         if _lib is None:
-            lib = ctypes.CDLL(build())
-            P = ctypes.c_void_p
-            lib.oracle_knn.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int32,
-                                       ctypes.c_double, ctypes.c_int32, P, P, P]
-            lib.oracle_knn.restype = ctypes.c_int
-            lib.oracle_covariances.argtypes = [P, ctypes.c_int64, P, P, ctypes.c_int64,
-                                               ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
-                                               P, P, P, P, P, P]
-            lib.oracle_covariances.restype = ctypes.c_int
-            lib.oracle_sym3_eig.argtypes = [P, P, P]
-            lib.oracle_sym3_eig.restype = None
-            _lib = lib
+            _lib = configure(ctypes.CDLL(build()))
     return _lib
 
 

@@ -314,3 +314,24 @@ def test_noisy_plane_and_wall_normals():
     R = out["reg"][plane]
     assert (np.abs(R[:, 2, 2] - 1e-3) < 0.01).mean() >= 0.95
     assert (np.abs(R[:, 0, 0] - 1.0) < 0.01).mean() >= 0.95
+
+
+def test_oracle_reproduces_golden_fixture():
+    """Regression pin: tests/golden/plane_wall_k10.json (written by
+    tests/golden/make_golden.py from the oracle alone)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "plane_wall_k10.json")
+    g = json.load(open(path))
+    p = workloads.plane_wall(2048, seed=0)
+    rows = g["rows"]
+    idx, d2, cnt = oracle.knn(p, p[rows], 10)
+    assert idx.tolist() == g["idx"] and cnt.tolist() == g["count"]
+    np.testing.assert_array_equal(d2, np.array(g["d2"]))
+    cov = oracle.covariances(p, idx, cnt)
+    np.testing.assert_allclose(cov["mean"], np.array(g["mean"]), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(cov["cov"].reshape(-1, 9), np.array(g["cov"]), rtol=1e-12,
+                               atol=1e-16)
+    np.testing.assert_allclose(cov["reg"].reshape(-1, 9), np.array(g["reg"]), rtol=1e-10,
+                               atol=1e-12)
+    assert cov["valid"].tolist() == g["valid"]
