@@ -241,13 +241,24 @@ lkc_status lkc_knn_cov_self(lkc_ctx *ctx, const lkc_target *target, int32_t k, f
                             float plane_eps, int32_t *idx, float *d2, int32_t *count, float *mean,
                             float *cov, float *reg_cov, uint8_t *valid, const lkc_launch_cfg *cfg);
 
-/* Counters of the last search on the context (host struct).  Synchronises. */
+/* Counters of the last search on the context (host struct).  Synchronises.
+ * The three phase times are GPU times (HIP events on the context's stream)
+ * of the last search when timing is on (lkc_ctx_set_timing), else -1:
+ * query sort (with its key kernel), group kernel, fallback kernel. */
 typedef struct lkc_search_stats {
     int64_t queries;          /* queries of the last search */
     int64_t fallback_queries; /* queries the group search handed to the
                                  wavefront-per-query search */
+    float sort_ms;
+    float group_ms;
+    float fallback_ms;
+    int32_t reserved;
 } lkc_search_stats;
 lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
+/* Record HIP events between the phases of every following search on this
+ * context (on = 1) or stop (on = 0).  Creates the events on first use; the
+ * events are not captured-graph safe, so keep timing off under capture. */
+lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
 
 /* Grow the context's search scratch (query sort buffers and the fallback
  * list, about 36 bytes per query) to `max_queries` now, so that later

@@ -112,6 +112,8 @@ lkc_status lkc_ctx_destroy(lkc_ctx* ctx) {
     if (ctx->search_scratch) (void)hipFree(ctx->search_scratch);
     if (ctx->meta_dev) (void)hipFree(ctx->meta_dev);
     if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
+    for (int i = 0; i < 4; ++i)
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     delete ctx;
     return LKC_OK;
 }
@@ -402,12 +404,30 @@ lkc_status lkc_knn_cov_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float 
                                 valid, lkc::resolve_cfg(cfg));
 }
 
+lkc_status lkc_ctx_set_timing(lkc_ctx* ctx, int32_t on) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (on && !ctx->ev[0]) {
+        for (int i = 0; i < 4; ++i) LKC_HIP_TRY(ctx, hipEventCreate(&ctx->ev[i]));
+    }
+    ctx->timing = on != 0;
+    ctx->ev_valid = false;
+    return LKC_OK;
+}
+
 lkc_status lkc_ctx_search_stats(lkc_ctx* ctx, lkc_search_stats* out) {
     lkc_status s = check_ctx(ctx);
     if (s != LKC_OK) return s;
     if (!out) return set_error(ctx, LKC_ERR_INVALID_ARG, "out is NULL");
     out->queries = ctx->last_queries;
     out->fallback_queries = 0;
+    out->sort_ms = out->group_ms = out->fallback_ms = -1.0f;
+    if (ctx->ev_valid) {
+        LKC_HIP_TRY(ctx, hipEventSynchronize(ctx->ev[3]));
+        LKC_HIP_TRY(ctx, hipEventElapsedTime(&out->sort_ms, ctx->ev[0], ctx->ev[1]));
+        LKC_HIP_TRY(ctx, hipEventElapsedTime(&out->group_ms, ctx->ev[1], ctx->ev[2]));
+        LKC_HIP_TRY(ctx, hipEventElapsedTime(&out->fallback_ms, ctx->ev[2], ctx->ev[3]));
+    }
     if (ctx->last_fallback_count) {
         uint32_t v = 0;
         LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -8,7 +8,7 @@
 //   1. scan_points   cell coordinates floor(p / cell), occupied-cell bounding
 //                    box, finiteness flag, copy of the points as float4
 //   2. make_keys     Morton key of the cell (relative to the bounding box)
-//                    followed by the Morton key of the point's 4x4x4 sub-cell
+//                    followed by the Morton key of the point's 16x16x16 sub-cell
 //   3. radix sort    stable LSD, 8-bit digits, only as many passes as the
 //                    key has bits
 //   4. reorder       points into that order as float4 (x, y, z, original idx)
@@ -34,7 +34,6 @@ constexpr int BT = 256;          // threads per block for the build kernels
 constexpr int RS_ITEMS = 8;      // radix items per thread per tile
 constexpr int RS_TILE = BT * RS_ITEMS;
 constexpr int RADIX = 256;
-constexpr int SUB_BITS = 6;      // Morton bits of the 4x4x4 sub-cell below the cell key
 constexpr int SCAN_TILE = 4096;  // entries per workgroup of the multi-block scan
 
 struct BuildMeta {
@@ -132,13 +131,8 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
 struct KeyParams {
     float inv_cell;
     int cmin[3];
+    int sub_bits;    // Morton bits per axis of the sub-cell below the cell key
 };
-
-__device__ __forceinline__ uint32_t sub_cell(float x, float inv_cell) {
-    const float u = x * inv_cell;
-    const float f = u - floorf(u);
-    return (uint32_t)min(max((int)(f * 4.0f), 0), 3);
-}
 
 __global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ orig, int64_t n,
                                                   KeyParams kp, unsigned long long* __restrict__ keys,
@@ -149,9 +143,11 @@ __global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ ori
     const uint32_t cx = (uint32_t)(cell_coord(p.x, kp.inv_cell) - kp.cmin[0]);
     const uint32_t cy = (uint32_t)(cell_coord(p.y, kp.inv_cell) - kp.cmin[1]);
     const uint32_t cz = (uint32_t)(cell_coord(p.z, kp.inv_cell) - kp.cmin[2]);
-    const unsigned long long sub = morton3(sub_cell(p.x, kp.inv_cell), sub_cell(p.y, kp.inv_cell),
-                                           sub_cell(p.z, kp.inv_cell));
-    keys[i] = (morton3(cx, cy, cz) << SUB_BITS) | sub;
+    const int sb = kp.sub_bits;
+    const unsigned long long sub =
+        morton3(sub_cell(p.x, kp.inv_cell, sb), sub_cell(p.y, kp.inv_cell, sb),
+                sub_cell(p.z, kp.inv_cell, sb));
+    keys[i] = (morton3(cx, cy, cz) << (3 * sb)) | sub;
     vals[i] = (uint32_t)i;
 }
 
@@ -292,9 +288,10 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
 // Cell runs: flag(i) = cell part of key[i] differs from key[i-1]'s.  Pass 1
 // counts flags per block.
 __global__ void __launch_bounds__(BT) k_cell_count(const unsigned long long* __restrict__ keys,
-                                                   int64_t n, uint32_t* __restrict__ bcount) {
+                                                   int64_t n, int sub_shift,
+                                                   uint32_t* __restrict__ bcount) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    const bool f = i < n && (i == 0 || (keys[i] >> SUB_BITS) != (keys[i - 1] >> SUB_BITS));
+    const bool f = i < n && (i == 0 || (keys[i] >> sub_shift) != (keys[i - 1] >> sub_shift));
     const int c = __syncthreads_count(f);
     if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)c;
 }
@@ -309,13 +306,14 @@ struct RowKey {
 // reordered point) and its first position.
 __global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __restrict__ keys,
                                                    const float4* __restrict__ pts, int64_t n,
+                                                   int sub_shift,
                                                    const uint32_t* __restrict__ boff, RowKey rk,
                                                    unsigned long long* __restrict__ ckeys,
                                                    uint32_t* __restrict__ cstart,
                                                    BuildMeta* __restrict__ meta) {
     __shared__ uint32_t s_w[BT / WAVE];
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    const bool f = i < n && (i == 0 || (keys[i] >> SUB_BITS) != (keys[i - 1] >> SUB_BITS));
+    const bool f = i < n && (i == 0 || (keys[i] >> sub_shift) != (keys[i - 1] >> sub_shift));
     const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     const unsigned long long bal = __ballot(f);
     const uint32_t pre = (uint32_t)__popcll(bal & ((1ull << l) - 1ull));
@@ -573,13 +571,15 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         V.max_abs = __builtin_bit_cast(float, hmeta->max_abs_bits);
         V.sh_y = bits[0];
         V.sh_z = bits[0] + bits[1];
-        t->key_bits = 3 * wmax + SUB_BITS;
+        const int sub_bits = std::max(0, std::min(4, (63 - 3 * wmax) / 3));
+        t->key_bits = 3 * wmax + 3 * sub_bits;
         t->sort_passes = (t->key_bits + 7) / 8;
 
         // ---- 2. keys
         KeyParams kp;
         kp.inv_cell = inv_cell;
         for (int a = 0; a < 3; ++a) kp.cmin[a] = V.cmin[a];
+        kp.sub_bits = sub_bits;
         hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, n, kp,
                            keys_a, vals_a);
 
@@ -602,10 +602,10 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         rk.sh_y = V.sh_y;
         rk.sh_z = V.sh_z;
         hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a, n,
-                           bcounts);
+                           3 * sub_bits, bcounts);
         scan_exclusive(st, bcounts, nb_bt, btmp);
         hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a,
-                           (const float4*)pts, n, bcounts, rk, tkeys, tstart, meta);
+                           (const float4*)pts, n, 3 * sub_bits, bcounts, rk, tkeys, tstart, meta);
         LKC_HIP_TRY(ctx, hipGetLastError());
         LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
         LKC_HIP_TRY(ctx, hipStreamSynchronize(st));

@@ -3,7 +3,7 @@
 //
 // Layout of a built target in HBM (all arrays 16-byte aligned):
 //   pts   float4[n]      points reordered by the Morton order of their cells
-//                        and, inside a cell, of 4x4x4 sub-cells; .w holds the
+//                        and, inside a cell, of 16x16x16 sub-cells; .w holds the
 //                        original index (bit-cast int32), so a cell's
 //                        candidates are one contiguous run of 16-byte records
 //   boxes float4[2 ceil(n/16)]
@@ -124,6 +124,15 @@ __device__ __forceinline__ unsigned long long spread3(uint32_t v) {
 }
 __device__ __forceinline__ unsigned long long morton3(uint32_t x, uint32_t y, uint32_t z) {
     return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+// Sub-cell index of a coordinate: which of 2^bits equal slices of its cell
+// it falls in (bits <= 4).
+__device__ __forceinline__ uint32_t sub_cell(float x, float inv_cell, int bits) {
+    const float u = x * inv_cell;
+    const float f = u - floorf(u);
+    const int m = (1 << bits) - 1;
+    return (uint32_t)min(max((int)(f * (float)(1 << bits)), 0), m);
 }
 
 // Load a read-only object at a wavefront-uniform address through the

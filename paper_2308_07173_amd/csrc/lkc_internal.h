@@ -26,6 +26,11 @@ struct lkc_ctx {
     size_t search_scratch_bytes = 0;
     uint32_t* last_fallback_count = nullptr;  // device word of the last search
     int64_t last_queries = 0;
+    // optional phase timing of searches: events before the query sort, the
+    // group kernel and the fallback kernel, and after the fallback kernel
+    bool timing = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool ev_valid = false;
 };
 
 struct lkc_target {

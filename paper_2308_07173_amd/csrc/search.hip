@@ -824,6 +824,7 @@ struct QueryKeyArgs {
     const BatchScan* scans;
     const BatchHeader* hdr;
     int tshift;
+    int sub_bits;
     unsigned long long* keys;
     uint32_t* vals;
 };
@@ -854,7 +855,10 @@ __global__ void __launch_bounds__(256) k_query_keys(QueryKeyArgs a) {
             const int range = max(T.cmax[d] - T.cmin[d], 0) + 2;
             v[d] = (uint32_t)min(max(c - (T.cmin[d] - 1), 0), range);
         }
-        key = morton3(v[0], v[1], v[2]);
+        const int sb = a.sub_bits;
+        key = (morton3(v[0], v[1], v[2]) << (3 * sb)) |
+              morton3(sub_cell(x, T.inv_cell, sb), sub_cell(y, T.inv_cell, sb),
+                      sub_cell(z, T.inv_cell, sb));
     } else {
         key = (1ull << a.tshift) - 1ull;
     }
@@ -1031,6 +1035,8 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     a.counters = nullptr;
     ctx->last_fallback_count = sc.words;
     ctx->last_queries = j.n_slots;
+    ctx->ev_valid = ctx->timing;
+    if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[0], st));
     const int K = choose_k_tile(j.k);
     const bool group = K > 0 && cfg.algorithm != 2;
     const unsigned wpb = (unsigned)cfg.waves_per_block;
@@ -1044,13 +1050,15 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
                 for (int d = 0; d < 3; ++d)
                     wmax = std::max(wmax, bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2)));
             }
-            const int tshift = 3 * wmax;   // Morton key of the (clamped) query cell
+            // Morton key of the (clamped) query cell, then of its sub-cell
             const int tbits = j.n_targets > 1 ? bitw((uint32_t)(j.n_targets - 1)) : 0;
+            const int sub_bits = std::max(0, std::min(4, (63 - tbits - 3 * wmax) / 3));
+            const int tshift = 3 * wmax + 3 * sub_bits;
             if (tshift + tbits > 63)
                 return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",
                                  tshift + tbits);
             QueryKeyArgs qa{j.queries, j.n_slots, j.views_dev, j.scans_dev, j.hdr_dev, tshift,
-                            sc.ka, sc.va};
+                            sub_bits, sc.ka, sc.va};
             hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256),
                                0, st, qa);
             bool in_b = false;
@@ -1072,6 +1080,7 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
                 }
         }
         a.R = R;
+        if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
         const int64_t n_groups = (j.n_slots + WAVE - 1) / WAVE;
         unsigned blocks;
         if (cfg.persistent > 0) {
@@ -1090,7 +1099,9 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
                            (uint32_t)j.n_slots);
         hipLaunchKernelGGL(k_fill_iota, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256), 0,
                            st, sc.fb_list, j.n_slots);
+        if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     }
+    if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     const dim3 fgrid((unsigned)(ctx->num_cus * 4));
     if (j.fused)
         hipLaunchKernelGGL(k_fallback<true>, fgrid, dim3(256), 0, st, a);
@@ -1098,6 +1109,7 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
         hipLaunchKernelGGL(k_fallback<false>, fgrid, dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(ctx, e, "search launch");
+    if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
     return LKC_OK;
 }
 

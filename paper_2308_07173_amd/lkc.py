@@ -41,6 +41,7 @@ EXPORTED_SYMBOLS = (
     "lkc_target_get_info", "lkc_target_arrays", "lkc_knn_query", "lkc_covariances",
     "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
     "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve", "lkc_ctx_search_stats",
+    "lkc_ctx_set_timing",
 )
 
 
@@ -65,6 +66,12 @@ class TargetInfo(ctypes.Structure):
                 ("cell_max", ctypes.c_int32 * 3), ("key_bits", ctypes.c_int32),
                 ("sort_passes", ctypes.c_int32), ("cell_size", ctypes.c_float),
                 ("device_bytes", ctypes.c_int64)]
+
+
+class SearchStats(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_int64), ("fallback_queries", ctypes.c_int64),
+                ("sort_ms", ctypes.c_float), ("group_ms", ctypes.c_float),
+                ("fallback_ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
 
 
 class ScanDesc(ctypes.Structure):
@@ -110,6 +117,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_knn_cov_self": ([P, P, I32, F, F, P, P, P, P, P, P, P, P], I32),
             "lkc_ctx_reserve": ([P, I64], I32),
             "lkc_ctx_search_stats": ([P, P], I32),
+            "lkc_ctx_set_timing": ([P, I32], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -180,11 +188,16 @@ class Context:
         self.check(self.lib.lkc_ctx_reserve(self.handle, int(max_queries)))
 
     def search_stats(self) -> Dict:
-        """Queries and fallback queries of the last search (synchronises)."""
-        buf = (ctypes.c_int64 * 2)()
+        """Queries, fallback queries and (with timing on) phase GPU times of
+        the last search (synchronises)."""
+        st = SearchStats()
         self._bind()
-        self.check(self.lib.lkc_ctx_search_stats(self.handle, buf))
-        return {"queries": buf[0], "fallback_queries": buf[1]}
+        self.check(self.lib.lkc_ctx_search_stats(self.handle, ctypes.byref(st)))
+        return {"queries": st.queries, "fallback_queries": st.fallback_queries,
+                "sort_ms": st.sort_ms, "group_ms": st.group_ms, "fallback_ms": st.fallback_ms}
+
+    def set_timing(self, on: bool):
+        self.check(self.lib.lkc_ctx_set_timing(self.handle, 1 if on else 0))
 
     def synchronize(self):
         self._bind()

@@ -80,7 +80,7 @@ def test_build_cells_partition_points(lk, n, cell, seed):
     assert np.array_equal(packed, ck.astype(np.uint64)[cell_of])
     assert np.unique(ck).size == C                       # one run per cell
     # cells follow the Morton order of their (relative) coordinates; inside
-    # a cell the 4x4x4 sub-cells follow Morton order and ties keep the
+    # a cell the 16x16x16 sub-cells follow Morton order and ties keep the
     # original order (stable sort)
     def spread(v):
         out = np.zeros_like(v, dtype=np.uint64)
@@ -89,9 +89,12 @@ def test_build_cells_partition_points(lk, n, cell, seed):
         return out
     rel = (c - np.array(info["cell_min"])).astype(np.uint64)
     u = p[orig].astype(np.float32) * inv
-    sub = np.clip(((u - np.floor(u)) * np.float32(4.0)).astype(np.int64), 0, 3).astype(np.uint64)
+    wmax = max(int(info["cell_max"][a] - info["cell_min"][a]).bit_length() for a in range(3))
+    sb = max(0, min(4, (63 - 3 * wmax) // 3))
+    sub = np.clip(((u - np.floor(u)) * np.float32(2 ** sb)).astype(np.int64), 0,
+                  2 ** sb - 1).astype(np.uint64)
     mort = ((spread(rel[:, 0]) | spread(rel[:, 1]) << np.uint64(1) | spread(rel[:, 2]) << np.uint64(2))
-            << np.uint64(6)) | spread(sub[:, 0]) | spread(sub[:, 1]) << np.uint64(1) | \
+            << np.uint64(3 * sb)) | spread(sub[:, 0]) | spread(sub[:, 1]) << np.uint64(1) | \
         spread(sub[:, 2]) << np.uint64(2)
     order = np.lexsort((orig, mort))
     assert np.array_equal(order, np.arange(n))
