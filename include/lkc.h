@@ -260,6 +260,14 @@ lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
  * events are not captured-graph safe, so keep timing off under capture. */
 lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
 
+/* Diagnostics: when `buffer` (device, 8 uint32 per group) holds at least
+ * the number of 64-query groups of a search, the group search writes per
+ * group: clock cycles, probe rounds, cells streamed, 64-point chunks
+ * loaded, candidates tested, insertion steps, member lanes and lanes handed
+ * to the fallback search.  n_groups = 0 turns it off.  The caller owns the
+ * buffer. */
+lkc_status lkc_ctx_set_profile(lkc_ctx *ctx, void *buffer, int64_t n_groups);
+
 /* Grow the context's search scratch (query sort buffers and the fallback
  * list, about 36 bytes per query) to `max_queries` now, so that later
  * searches of at most that many queries allocate nothing.  Synchronises

@@ -404,6 +404,16 @@ lkc_status lkc_knn_cov_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float 
                                 valid, lkc::resolve_cfg(cfg));
 }
 
+lkc_status lkc_ctx_set_profile(lkc_ctx* ctx, void* buffer, int64_t n_groups) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (n_groups < 0 || (n_groups > 0 && !buffer))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "bad profile buffer");
+    ctx->prof_buf = n_groups > 0 ? buffer : nullptr;
+    ctx->prof_groups = n_groups;
+    return LKC_OK;
+}
+
 lkc_status lkc_ctx_set_timing(lkc_ctx* ctx, int32_t on) {
     lkc_status s = check_ctx(ctx);
     if (s != LKC_OK) return s;

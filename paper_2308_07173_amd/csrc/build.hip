@@ -46,18 +46,6 @@ struct BuildMeta {
 };
 static_assert(sizeof(BuildMeta) == 64, "BuildMeta layout");
 
-__global__ void k_meta_init(BuildMeta* m) {
-    if (threadIdx.x == 0) {
-        for (int a = 0; a < 3; ++a) {
-            m->cmin[a] = INT_MAX;
-            m->cmax[a] = INT_MIN;
-        }
-        m->nonfinite = 0;
-        m->n_cells = 0;
-        m->max_abs_bits = 0;
-    }
-}
-
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) v = min(v, __shfl_xor(v, s));
@@ -74,19 +62,29 @@ __device__ __forceinline__ uint32_t wave_maxu(uint32_t v) {
     return v;
 }
 
+// Per-block partial of the occupied-cell box, the finiteness flag and the
+// largest |coordinate|; one record per block, combined by k_meta_reduce
+// (no contended atomics).
+struct MetaPart {
+    int cmin[3];
+    int cmax[3];
+    int bad;
+    uint32_t abs_bits;
+};
+
 __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p, int64_t n,
                                                     float inv_cell, float4* __restrict__ orig,
-                                                    BuildMeta* __restrict__ meta) {
+                                                    MetaPart* __restrict__ parts) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX};
     int mx[3] = {INT_MIN, INT_MIN, INT_MIN};
     uint32_t mabs = 0;
-    bool bad = false;
+    int bad = 0;
     if (i < n) {
         const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
         orig[i] = make_float4(x, y, z, 0.0f);
         if (!finite3(x, y, z)) {
-            bad = true;
+            bad = 1;
         } else {
             const int c[3] = {cell_coord(x, inv_cell), cell_coord(y, inv_cell),
                               cell_coord(z, inv_cell)};
@@ -94,12 +92,8 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
             mabs = __float_as_uint(fmaxf(fabsf(x), fmaxf(fabsf(y), fabsf(z))));
         }
     }
-    __shared__ int s_mn[3][BT / WAVE], s_mx[3][BT / WAVE];
+    __shared__ int s_mn[3][BT / WAVE], s_mx[3][BT / WAVE], s_bad[BT / WAVE];
     __shared__ uint32_t s_abs[BT / WAVE];
-    __shared__ int s_bad;
-    if (threadIdx.x == 0) s_bad = 0;
-    __syncthreads();
-    if (bad) s_bad = 1;
     const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
     for (int a = 0; a < 3; ++a) {
         const int vmn = wave_min(mn[a]), vmx = wave_max(mx[a]);
@@ -109,22 +103,83 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
         }
     }
     const uint32_t vab = wave_maxu(mabs);
-    if (l == 0) s_abs[w] = vab;
+    const int vbad = wave_max(bad);
+    if (l == 0) {
+        s_abs[w] = vab;
+        s_bad[w] = vbad;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
+        MetaPart m;
+        for (int a = 0; a < 3; ++a) {
+            m.cmin[a] = INT_MAX;
+            m.cmax[a] = INT_MIN;
+            for (int j = 0; j < BT / WAVE; ++j) {
+                m.cmin[a] = min(m.cmin[a], s_mn[a][j]);
+                m.cmax[a] = max(m.cmax[a], s_mx[a][j]);
+            }
+        }
+        m.bad = 0;
+        m.abs_bits = 0;
+        for (int j = 0; j < BT / WAVE; ++j) {
+            m.bad |= s_bad[j];
+            m.abs_bits = max(m.abs_bits, s_abs[j]);
+        }
+        parts[blockIdx.x] = m;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_meta_reduce(const MetaPart* __restrict__ parts,
+                                                      int64_t np, BuildMeta* __restrict__ meta) {
+    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+    int bad = 0;
+    uint32_t ab = 0;
+    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
+        const MetaPart m = parts[i];
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = min(mn[a], m.cmin[a]);
+            mx[a] = max(mx[a], m.cmax[a]);
+        }
+        bad |= m.bad;
+        ab = max(ab, m.abs_bits);
+    }
+    __shared__ int s_mn[3][16], s_mx[3][16], s_bad[16];
+    __shared__ uint32_t s_ab[16];
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    for (int a = 0; a < 3; ++a) {
+        const int vmn = wave_min(mn[a]), vmx = wave_max(mx[a]);
+        if (l == 0) {
+            s_mn[a][w] = vmn;
+            s_mx[a][w] = vmx;
+        }
+    }
+    const uint32_t vab = wave_maxu(ab);
+    const int vbad = wave_max(bad);
+    if (l == 0) {
+        s_ab[w] = vab;
+        s_bad[w] = vbad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / WAVE;
         for (int a = 0; a < 3; ++a) {
             int vmn = INT_MAX, vmx = INT_MIN;
-            for (int j = 0; j < BT / WAVE; ++j) {
+            for (int j = 0; j < nw; ++j) {
                 vmn = min(vmn, s_mn[a][j]);
                 vmx = max(vmx, s_mx[a][j]);
             }
-            if (vmn != INT_MAX) atomicMin(&meta->cmin[a], vmn);
-            if (vmx != INT_MIN) atomicMax(&meta->cmax[a], vmx);
+            meta->cmin[a] = vmn;
+            meta->cmax[a] = vmx;
         }
-        uint32_t ab = 0;
-        for (int j = 0; j < BT / WAVE; ++j) ab = max(ab, s_abs[j]);
-        if (ab) atomicMax(&meta->max_abs_bits, ab);
-        if (s_bad) atomicOr(&meta->nonfinite, 1);
+        int vb = 0;
+        uint32_t va = 0;
+        for (int j = 0; j < nw; ++j) {
+            vb |= s_bad[j];
+            va = max(va, s_ab[j]);
+        }
+        meta->nonfinite = vb;
+        meta->max_abs_bits = va;
+        meta->n_cells = 0;
     }
 }
 
@@ -533,6 +588,7 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     const size_t o_bc = carve(4 * (size_t)(nb_bt > 0 ? nb_bt : 1) + 4);
     const size_t o_bt = carve(4 * (size_t)(nb_bt / SCAN_TILE + 2));
     const size_t o_tk = carve(8 * nn), o_ts = carve(4 * nn + 4);
+    const size_t o_mp = carve(sizeof(MetaPart) * (size_t)(nb_bt > 0 ? nb_bt : 1));
     lkc_status s = ensure_scratch(ctx, off);
     if (s != LKC_OK) return s;
     char* sb = (char*)ctx->build_scratch;
@@ -545,15 +601,17 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     auto* btmp = (uint32_t*)(sb + o_bt);
     auto* tkeys = (unsigned long long*)(sb + o_tk);
     auto* tstart = (uint32_t*)(sb + o_ts);
+    auto* mparts = (MetaPart*)(sb + o_mp);
     auto* meta = (BuildMeta*)ctx->meta_dev;
     auto* hmeta = (BuildMeta*)ctx->meta_host;
 
     int64_t n_cells = 0;
     if (n > 0) {
         // ---- 1. cell coordinates, bounding box, finiteness
-        hipLaunchKernelGGL(k_meta_init, dim3(1), dim3(1), 0, st, meta);
         hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
-                           inv_cell, orig, meta);
+                           inv_cell, orig, mparts);
+        hipLaunchKernelGGL(k_meta_reduce, dim3(1), dim3(1024), 0, st, (const MetaPart*)mparts,
+                           nb_bt, meta);
         LKC_HIP_TRY(ctx, hipGetLastError());
         LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
         LKC_HIP_TRY(ctx, hipStreamSynchronize(st));

@@ -28,6 +28,8 @@ struct lkc_ctx {
     int64_t last_queries = 0;
     // optional phase timing of searches: events before the query sort, the
     // group kernel and the fallback kernel, and after the fallback kernel
+    void* prof_buf = nullptr;    // optional device buffer for per-group counters
+    int64_t prof_groups = 0;
     bool timing = false;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool ev_valid = false;

@@ -510,6 +510,15 @@ struct GroupArgs {
     uint32_t* fb_list;                // slots handed to the fallback search
     uint32_t* fb_count;
     uint32_t* counters;               // per-XCD work counters (persistent mode) or NULL
+    uint32_t* prof;                   // optional per-group counters (PROF_WORDS each) or NULL
+};
+
+// per-group profile words: clock cycles, probe rounds, cells streamed,
+// 64-point chunks loaded, candidates tested, insertion pops, member lanes,
+// fallback lanes
+constexpr int PROF_WORDS = 8;
+struct GroupProf {
+    uint32_t probes, cells, chunks, cands, pops;
 };
 
 struct SlotQuery {
@@ -564,11 +573,14 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                                          float qx, float qy, float qz, float r2,
                                          const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr,
-                                         unsigned long long (&kk)[K], int mode) {
+                                         unsigned long long (&kk)[K], int mode,
+                                         GroupProf& gp) {
     const int lane = lane_id();
 #pragma unroll 1
     for (int cb = s0 & ~(WAVE - 1); cb < e0; cb += WAVE) {
         uint32_t keep = 0;
+        // this lane's current k-th distance (radius while its list is not full)
+        const float lthr = kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2);
 #pragma unroll
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
             const int sb = cb + q4 * BOX_PTS;
@@ -579,9 +591,17 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                 box_box_dist2(b0, b1, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, margin);
             const bool near = bd <= r2 && bd * (1.0f - 1e-6f) <= gthr;
             const bool want = mode == 0 ? bd == 0.0f : (mode == 1 ? (bd > 0.0f && near) : near);
-            if (want) keep |= 1u << q4;
+            if (!want) continue;
+            // and some lane needs it: the run's box is within that lane's own
+            // k-th distance (or radius)
+            const float gx = fmaxf(fmaxf(blo.x - qx, qx - bhi.x) - margin, 0.0f);
+            const float gy = fmaxf(fmaxf(blo.y - qy, qy - bhi.y) - margin, 0.0f);
+            const float gz = fmaxf(fmaxf(blo.z - qz, qz - bhi.z) - margin, 0.0f);
+            const float ld = gx * gx + gy * gy + gz * gz;
+            if (ballot(member && ld * (1.0f - 1e-6f) <= lthr)) keep |= 1u << q4;
         }
         if (!keep) continue;
+        gp.chunks++;
         const float4 c = T.pts[cb + lane];   // padded: reads past n stay in bounds
         unsigned long long bits = 0;
         const int lo = max(s0, cb) - cb, hi = min(e0, cb + WAVE) - cb;
@@ -589,6 +609,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
             if (!((keep >> q4) & 1u)) continue;
             const int t1 = min(hi, (q4 + 1) * BOX_PTS);
+            gp.cands += (uint32_t)max(0, t1 - max(lo, q4 * BOX_PTS));
 #pragma unroll 2
             for (int t = max(lo, q4 * BOX_PTS); t < t1; ++t) {
                 const float cx = readlane(c.x, t), cy = readlane(c.y, t), cz = readlane(c.z, t);
@@ -600,6 +621,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         }
         if (!ballot(bits != 0ull)) continue;
         do {
+            gp.pops++;
             const int j = bits ? __builtin_ffsll((long long)bits) - 1 : 0;
             const float cx = shfl(c.x, j), cy = shfl(c.y, j), cz = shfl(c.z, j);
             const int32_t ci = shfl(__float_as_int(c.w), j);
@@ -609,7 +631,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                 if (key < kk[K - 1]) lane_insert<K>(kk, key);
             }
         } while (ballot(bits != 0ull));
-        gthr = wave_max_dpp(member ? (kk[K - 1] == ~0ull ? INF : key_d2(kk[K - 1])) : -INF);
+        gthr = wave_max_dpp(member ? (kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1])) : -INF);
     }
 }
 
@@ -644,6 +666,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
     for (int j = 0; j < K; ++j) kk[j] = (j < pad) ? 0ull : ~0ull;
     const unsigned long long mm = ballot(member);
     bool ok = true;
+    GroupProf gp{0, 0, 0, 0, 0};
+    const unsigned long long t_start = a.prof ? __builtin_amdgcn_s_memtime() : 0ull;
     if (mm && T.n_cells > 0) {
         const float bx0 = wave_min_dpp(member ? s.x : INF), bx1 = wave_max_dpp(member ? s.x : -INF);
         const float by0 = wave_min_dpp(member ? s.y : INF), by1 = wave_max_dpp(member ? s.y : -INF);
@@ -662,10 +686,10 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
         const float qabs = fmaxf(fmaxf(fmaxf(fabsf(bx0), fabsf(bx1)), fmaxf(fabsf(by0), fabsf(by1))),
                                  fmaxf(fabsf(bz0), fabsf(bz1)));
         const float margin = (fmaxf(qabs, T.max_abs) + 2.0f * T.cell) * 1e-6f;
-        float gthr = INF;
+        float gthr = r2;   // largest k-th distance over the members (radius while unfilled)
         for (int pass = 0; pass < 2; ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
-
+                gp.probes++;
                 const int64_t t = base + lane;
                 bool want = false;
                 uint32_t st = 0, cn = 0;
@@ -695,8 +719,9 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
                         wm &= wm - 1;
                         const int s0 = readlane((int)st, cl);
                         const int e0 = s0 + readlane((int)cn, cl);
+                        gp.cells++;
                         scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, b0, b1, margin, gthr,
-                                    kk, mode);
+                                    kk, mode, gp);
                     }
                 }
             }
@@ -719,6 +744,17 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
     }
     const bool to_fb = (fin && !member) || (member && !ok);
     const unsigned long long fm = ballot(to_fb);
+    if (a.prof && lane == 0) {
+        uint32_t* pw = a.prof + group * PROF_WORDS;
+        pw[0] = (uint32_t)(__builtin_amdgcn_s_memtime() - t_start);
+        pw[1] = gp.probes;
+        pw[2] = gp.cells;
+        pw[3] = gp.chunks;
+        pw[4] = gp.cands;
+        pw[5] = gp.pops;
+        pw[6] = (uint32_t)__popcll(mm);
+        pw[7] = (uint32_t)__popcll(fm);
+    }
     if (fm) {
         const int leader = __builtin_ffsll((long long)fm) - 1;
         uint32_t base = 0;
@@ -1033,6 +1069,8 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     a.fb_list = sc.fb_list;
     a.fb_count = sc.words;
     a.counters = nullptr;
+    a.prof = (ctx->prof_buf && (j.n_slots + WAVE - 1) / WAVE <= ctx->prof_groups)
+                 ? (uint32_t*)ctx->prof_buf : nullptr;
     ctx->last_fallback_count = sc.words;
     ctx->last_queries = j.n_slots;
     ctx->ev_valid = ctx->timing;

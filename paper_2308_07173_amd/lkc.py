@@ -41,7 +41,7 @@ EXPORTED_SYMBOLS = (
     "lkc_target_get_info", "lkc_target_arrays", "lkc_knn_query", "lkc_covariances",
     "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
     "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve", "lkc_ctx_search_stats",
-    "lkc_ctx_set_timing",
+    "lkc_ctx_set_timing", "lkc_ctx_set_profile",
 )
 
 
@@ -118,6 +118,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_ctx_reserve": ([P, I64], I32),
             "lkc_ctx_search_stats": ([P, P], I32),
             "lkc_ctx_set_timing": ([P, I32], I32),
+            "lkc_ctx_set_profile": ([P, P, I64], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -195,6 +196,15 @@ class Context:
         self.check(self.lib.lkc_ctx_search_stats(self.handle, ctypes.byref(st)))
         return {"queries": st.queries, "fallback_queries": st.fallback_queries,
                 "sort_ms": st.sort_ms, "group_ms": st.group_ms, "fallback_ms": st.fallback_ms}
+
+    def set_profile(self, buf=None):
+        """Per-group counters of the group search into `buf` (device int32
+        tensor [groups, 8]) or off (None)."""
+        if buf is None:
+            self.check(self.lib.lkc_ctx_set_profile(self.handle, None, 0))
+        else:
+            self.check(self.lib.lkc_ctx_set_profile(self.handle, ctypes.c_void_p(buf.data_ptr()),
+                                                    buf.shape[0]))
 
     def set_timing(self, on: bool):
         self.check(self.lib.lkc_ctx_set_timing(self.handle, 1 if on else 0))
