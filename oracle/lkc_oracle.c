@@ -330,3 +330,88 @@ int oracle_covariances(const float *target, int64_t n, const int32_t *idx, const
     free(th);
     return bad ? -1 : 0;
 }
+
+/* -------------------------------------------- kernel-weighted covariance --- */
+
+/* Kernel descriptors of the paper's Table `tab:kernel_descriptors` (Sec.
+ * III-C.1) as neighbour weights: with D = |q - t|^2 the exponent is
+ *   1 RBF        D * sigma
+ *   2 Gaussian   D / (2 sigma^2)
+ *   3 Laplacian  sqrt(D) / sigma
+ * and the weight is exp(-(e_j - min_j e_j)) -- the kernel value divided by
+ * the largest one among the neighbours, which leaves the normalised weights
+ * unchanged and keeps them from underflowing.  Weighted mean
+ * mu = sum w t / sum w and covariance C = sum w (t - mu)(t - mu)^T / sum w;
+ * the regulariser and validity (n >= 3) are those of the unweighted case.
+ * The reference point q is the query (queries != NULL) or the first
+ * neighbour. */
+int oracle_covariances_weighted(const float *target, int64_t n, const float *queries,
+                                const int32_t *idx, const int32_t *count, int64_t q, int32_t k,
+                                int32_t kind, double sigma, double eps, double *mean, double *cov,
+                                double *reg, uint8_t *valid)
+{
+    if (k < 1 || n < 0 || q < 0 || kind < 1 || kind > 3 || !(sigma > 0.0))
+        return -1;
+    for (int64_t qi = 0; qi < q; ++qi) {
+        const int32_t m = count[qi];
+        const int32_t *nb = idx + qi * k;
+        if (m < 0 || m > k)
+            return -1;
+        for (int32_t j = 0; j < m; ++j)
+            if (nb[j] < 0 || nb[j] >= n)
+                return -1;
+        double mu[3] = {0.0, 0.0, 0.0}, c[9] = {0.0};
+        if (m > 0) {
+            double ref[3];
+            for (int a = 0; a < 3; ++a)
+                ref[a] = queries ? (double)queries[3 * qi + a] : (double)target[3 * (int64_t)nb[0] + a];
+            double *e = (double *)malloc(sizeof(double) * (size_t)m);
+            double emin = INFINITY;
+            for (int32_t j = 0; j < m; ++j) {
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    const double dd = ref[a] - (double)target[3 * (int64_t)nb[j] + a];
+                    d2 += dd * dd;
+                }
+                e[j] = kind == 1 ? d2 * sigma : kind == 2 ? d2 / (2.0 * sigma * sigma) : sqrt(d2) / sigma;
+                if (e[j] < emin)
+                    emin = e[j];
+            }
+            double sw = 0.0;
+            for (int32_t j = 0; j < m; ++j) {
+                const double w = exp(-(e[j] - emin));
+                sw += w;
+                for (int a = 0; a < 3; ++a)
+                    mu[a] += w * (double)target[3 * (int64_t)nb[j] + a];
+            }
+            for (int a = 0; a < 3; ++a)
+                mu[a] /= sw;
+            for (int32_t j = 0; j < m; ++j) {
+                const double w = exp(-(e[j] - emin));
+                double d[3];
+                for (int a = 0; a < 3; ++a)
+                    d[a] = (double)target[3 * (int64_t)nb[j] + a] - mu[a];
+                for (int r = 0; r < 3; ++r)
+                    for (int cc = 0; cc < 3; ++cc)
+                        c[3 * r + cc] += w * d[r] * d[cc];
+            }
+            for (int i = 0; i < 9; ++i)
+                c[i] /= sw;
+            free(e);
+        }
+        double ev[3], V[9];
+        oracle_sym3_eig(c, ev, V);
+        const int ok = (m >= 3);
+        for (int a = 0; a < 3; ++a)
+            mean[3 * qi + a] = mu[a];
+        for (int i = 0; i < 9; ++i)
+            cov[9 * qi + i] = c[i];
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc) {
+                const double eye = (r == cc) ? 1.0 : 0.0;
+                reg[9 * qi + 3 * r + cc] = ok ? eye - (1.0 - eps) * V[3 * r] * V[3 * cc] : eye;
+            }
+        valid[qi] = (uint8_t)ok;
+    }
+    return 0;
+}

@@ -60,6 +60,12 @@ def configure(lib):
     lib.oracle_covariances.restype = ctypes.c_int
     lib.oracle_sym3_eig.argtypes = [P, P, P]
     lib.oracle_sym3_eig.restype = None
+    if hasattr(lib, "oracle_covariances_weighted"):
+        lib.oracle_covariances_weighted.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_int64,
+                                                    ctypes.c_int32, ctypes.c_int32,
+                                                    ctypes.c_double, ctypes.c_double,
+                                                    P, P, P, P]
+        lib.oracle_covariances_weighted.restype = ctypes.c_int
     return lib
 
 
@@ -129,6 +135,30 @@ def covariances(target, idx, count, eps: float = 1e-3, threads: int | None = Non
     if with_eig:
         out.update(evals=evals, evec0=evec0)
     return out
+
+
+WEIGHT_KINDS = {"rbf": 1, "gaussian": 2, "laplacian": 3}
+
+
+def covariances_weighted(target, idx, count, kind: str, sigma: float, queries=None,
+                         eps: float = 1e-3):
+    """Kernel-descriptor weighted mean / covariance (FP64); see lkc_oracle.c."""
+    t = _f32(target)
+    idx = np.ascontiguousarray(idx, np.int32)
+    count = np.ascontiguousarray(count, np.int32)
+    nq, k = idx.shape
+    qa = None if queries is None else _f32(queries)
+    mean = np.empty((nq, 3))
+    cov = np.empty((nq, 3, 3))
+    reg = np.empty((nq, 3, 3))
+    valid = np.empty(nq, np.uint8)
+    rc = _load().oracle_covariances_weighted(
+        _ptr(t), t.shape[0], None if qa is None else _ptr(qa), _ptr(idx), _ptr(count), nq, int(k),
+        WEIGHT_KINDS[kind], float(sigma), float(eps), _ptr(mean), _ptr(cov), _ptr(reg),
+        _ptr(valid))
+    if rc != 0:
+        raise ValueError("oracle_covariances_weighted: invalid arguments")
+    return dict(mean=mean, cov=cov, reg=reg, valid=valid)
 
 
 def sym3_eig(a):

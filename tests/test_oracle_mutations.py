@@ -3,7 +3,9 @@
 Each case plants one mistake in a copy of the oracle's C source (a dropped
 coordinate term, a reversed tie-break, an exclusive radius, 1/(n-1), a
 wrong mean divisor, the largest eigenvector, a flipped regulariser sign, a
-wrong Jacobi rotation sign, a wrong validity threshold), compiles it on the
+wrong Jacobi rotation sign, a wrong validity threshold; in the weighted
+covariance a wrong kernel exponent, a flipped weight sign, an unnormalised
+mean, an unweighted sum, a wrong reference point), compiles it on the
 CPU, swaps it in for the real oracle and runs the pin tests: at least one
 must fail.  The real oracle is restored afterwards.
 """
@@ -15,6 +17,7 @@ import pytest
 
 from oracle import oracle
 from tests import test_oracle as pins
+from tests import test_oracle_weighted as wpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lkc_oracle.c")
 
@@ -46,14 +49,42 @@ PINS = [
 ]
 
 
+# planted mistakes in the kernel-descriptor weighted covariance
+WEIGHTED_MUTATIONS = {
+    "rbf_divides": ("kind == 1 ? d2 * sigma", "kind == 1 ? d2 / sigma"),
+    "gauss_no_half": ("d2 / (2.0 * sigma * sigma)", "d2 / (sigma * sigma)"),
+    "laplacian_squared": (": sqrt(d2) / sigma", ": d2 / sigma"),
+    "weight_sign": ("const double w = exp(-(e[j] - emin));\n                sw += w;",
+                    "const double w = exp(+(e[j] - emin));\n                sw += w;"),
+    "mean_unnormalised": ("mu[a] /= sw;", "mu[a] /= (double)m;"),
+    "cov_unweighted": ("c[3 * r + cc] += w * d[r] * d[cc];", "c[3 * r + cc] += d[r] * d[cc];"),
+    "reference_first_neighbour": ("ref[a] = queries ? (double)queries[3 * qi + a]",
+                                  "ref[a] = 0 ? (double)queries[3 * qi + a]"),
+    "weighted_valid": ("const int ok = (m >= 3);", "const int ok = (m >= 1);"),
+}
+
+WEIGHTED_PINS = [getattr(wpins, n) for n in dir(wpins) if n.startswith("test_")]
+
+
+def _call(pin):
+    marks = getattr(pin, "pytestmark", [])
+    params = [m for m in marks if m.name == "parametrize"]
+    if not params:
+        return pin()
+    names = [a.strip() for a in params[0].args[0].split(",")]
+    for vals in params[0].args[1]:
+        pin(**dict(zip(names, vals if len(names) > 1 else (vals,))))
+
+
 def test_unmutated_source_passes_the_pins():
-    for pin in PINS:
-        pin()
+    for pin in PINS + WEIGHTED_PINS:
+        _call(pin)
 
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
+@pytest.mark.parametrize("name", sorted(MUTATIONS) + sorted(WEIGHTED_MUTATIONS))
 def test_pins_catch_planted_mistake(name, tmp_path):
-    old, new = MUTATIONS[name]
+    old, new = MUTATIONS.get(name) or WEIGHTED_MUTATIONS[name]
+    pins_for = PINS if name in MUTATIONS else WEIGHTED_PINS
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor for {name} not unique"
     mut = tmp_path / "mut.c"
@@ -65,9 +96,9 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     oracle._lib = oracle.configure(ctypes.CDLL(str(so)))
     failed = []
     try:
-        for pin in PINS:
+        for pin in pins_for:
             try:
-                pin()
+                _call(pin)
             except (AssertionError, ValueError):
                 failed.append(pin)
     finally:
