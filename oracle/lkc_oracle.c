@@ -415,3 +415,192 @@ int oracle_covariances_weighted(const float *target, int64_t n, const float *que
     }
     return 0;
 }
+
+/* --------------------------------------------------- GICP linearisation --- */
+
+/* One Gauss-Newton linearisation of the GICP cost the covariances feed (Sec.
+ * III-C.1, Eqs. eq_trans_err .. eq_trans_likelihood).  The printed combined
+ * covariance is garbled; it is read as in generalized ICP (Segal et al.):
+ *   d_i = q_j - (R p_i + t),   W_i = (C^q_j + R C^p_i R^T)^{-1},
+ *   E   = sum_i d_i^T W_i d_i
+ * over the source points p_i whose correspondence j (the nearest target point
+ * of T p_i) exists.  The increment delta = (omega, v) acts on the left,
+ * T <- exp(delta^) T, so to first order T p_i moves by omega x p'_i + v with
+ * p'_i = R p_i + t, and
+ *   J_i = d d_i / d delta = [ [p'_i]_x , -I ]        (3 x 6),
+ *   H = sum J_i^T W_i J_i,   b = sum J_i^T W_i d_i   (W_i held fixed),
+ * whose step is delta = -H^{-1} b.  T is a 4x4 row-major rigid transform. */
+
+typedef struct {
+    const float *src, *tgt;
+    int64_t m, q_begin, q_end;
+    const double *T;
+    double r2;
+    int32_t *corr;
+    double *d2;
+} corr_job;
+
+static void *corr_worker(void *arg)
+{
+    corr_job *jb = (corr_job *)arg;
+    const double *T = jb->T;
+    for (int64_t i = jb->q_begin; i < jb->q_end; ++i) {
+        const double px = jb->src[3 * i], py = jb->src[3 * i + 1], pz = jb->src[3 * i + 2];
+        double x[3];
+        for (int r = 0; r < 3; ++r)
+            x[r] = T[4 * r] * px + T[4 * r + 1] * py + T[4 * r + 2] * pz + T[4 * r + 3];
+        int64_t best = -1;
+        double bd = INFINITY;
+        if (isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))
+            for (int64_t j = 0; j < jb->m; ++j) {
+                const double dx = x[0] - (double)jb->tgt[3 * j];
+                const double dy = x[1] - (double)jb->tgt[3 * j + 1];
+                const double dz = x[2] - (double)jb->tgt[3 * j + 2];
+                const double d = dx * dx + dy * dy + dz * dz;
+                if (d <= jb->r2 && (d < bd || (d == bd && j < best))) {
+                    bd = d;
+                    best = j;
+                }
+            }
+        jb->corr[i] = (int32_t)best;
+        jb->d2[i] = bd;
+    }
+    return NULL;
+}
+
+/* Correspondences: for each source point, the nearest target point of
+ * T p_i (p_i transformed in FP64), by brute force, key (D, j) ascending,
+ * D <= max_dist^2 inclusive; -1 / +inf when none. */
+int oracle_gicp_correspond(const float *src, int64_t n, const float *tgt, int64_t m,
+                           const double *T, double max_dist, int32_t nthreads, int32_t *corr,
+                           double *d2)
+{
+    if (n < 0 || m < 0 || !(max_dist > 0.0))
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if ((int64_t)nthreads > n)
+        nthreads = (int32_t)(n > 0 ? n : 1);
+    corr_job *jobs = (corr_job *)calloc((size_t)nthreads, sizeof(corr_job));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    const double r2 = isinf(max_dist) ? INFINITY : max_dist * max_dist;
+    for (int32_t w = 0; w < nthreads; ++w) {
+        corr_job *jb = &jobs[w];
+        jb->src = src;
+        jb->tgt = tgt;
+        jb->m = m;
+        jb->q_begin = n * w / nthreads;
+        jb->q_end = n * (w + 1) / nthreads;
+        jb->T = T;
+        jb->r2 = r2;
+        jb->corr = corr;
+        jb->d2 = d2;
+        pthread_create(&th[w], NULL, corr_worker, jb);
+    }
+    for (int32_t w = 0; w < nthreads; ++w)
+        pthread_join(th[w], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}
+
+/* Inverse of a 3x3 by the adjugate: inv = adj(M) / det(M).  Returns 0 when
+ * det(M) is not a positive finite number (M is SPD here). */
+static int inv3_adjugate(const double *M, double *inv)
+{
+    const double c00 = M[4] * M[8] - M[5] * M[7];
+    const double c01 = M[5] * M[6] - M[3] * M[8];
+    const double c02 = M[3] * M[7] - M[4] * M[6];
+    const double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    if (!(det > 0.0) || !isfinite(det))
+        return 0;
+    inv[0] = c00 / det;
+    inv[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+    inv[2] = (M[1] * M[5] - M[2] * M[4]) / det;
+    inv[3] = c01 / det;
+    inv[4] = (M[0] * M[8] - M[2] * M[6]) / det;
+    inv[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+    inv[6] = c02 / det;
+    inv[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+    inv[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+    return 1;
+}
+
+/* H [6][6], b [6], E, count for the given correspondences (corr[i] < 0: no
+ * correspondence).  src/tgt float32 [.][3]; src_cov/tgt_cov float32
+ * [.][3][3] row-major.  Returns -1 on an index out of range or a combined
+ * covariance that is not positive definite. */
+int oracle_gicp_linearize(const float *src, const float *src_cov, int64_t n, const float *tgt,
+                          const float *tgt_cov, int64_t m, const double *T, const int32_t *corr,
+                          double *H, double *b, double *E, int64_t *count)
+{
+    if (n < 0 || m < 0)
+        return -1;
+    double R[9], t[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            R[3 * r + c] = T[4 * r + c];
+        t[r] = T[4 * r + 3];
+    }
+    for (int e = 0; e < 36; ++e)
+        H[e] = 0.0;
+    for (int e = 0; e < 6; ++e)
+        b[e] = 0.0;
+    double err = 0.0;
+    int64_t used = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t j = corr[i];
+        if (j < 0)
+            continue;
+        if ((int64_t)j >= m)
+            return -1;
+        double p[3], d[3];
+        for (int r = 0; r < 3; ++r)
+            p[r] = R[3 * r] * src[3 * i] + R[3 * r + 1] * src[3 * i + 1] +
+                   R[3 * r + 2] * src[3 * i + 2] + t[r];
+        for (int r = 0; r < 3; ++r)
+            d[r] = (double)tgt[3 * (int64_t)j + r] - p[r];
+        /* M = C^q + R C^p R^T */
+        double RC[9], M[9], W[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    s += R[3 * r + a] * (double)src_cov[9 * i + 3 * a + c];
+                RC[3 * r + c] = s;
+            }
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    s += RC[3 * r + a] * R[3 * c + a];
+                M[3 * r + c] = (double)tgt_cov[9 * (int64_t)j + 3 * r + c] + s;
+            }
+        if (!inv3_adjugate(M, W))
+            return -1;
+        /* J = [ [p]_x , -I ];  [p]_x = [[0,-z,y],[z,0,-x],[-y,x,0]] */
+        double J[3][6] = {{0.0, -p[2], p[1], -1.0, 0.0, 0.0},
+                          {p[2], 0.0, -p[0], 0.0, -1.0, 0.0},
+                          {-p[1], p[0], 0.0, 0.0, 0.0, -1.0}};
+        double WJ[3][6], Wd[3];
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 6; ++c) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    s += W[3 * r + a] * J[a][c];
+                WJ[r][c] = s;
+            }
+            Wd[r] = W[3 * r] * d[0] + W[3 * r + 1] * d[1] + W[3 * r + 2] * d[2];
+        }
+        for (int r = 0; r < 6; ++r) {
+            for (int c = 0; c < 6; ++c)
+                H[6 * r + c] += J[0][r] * WJ[0][c] + J[1][r] * WJ[1][c] + J[2][r] * WJ[2][c];
+            b[r] += J[0][r] * Wd[0] + J[1][r] * Wd[1] + J[2][r] * Wd[2];
+        }
+        err += d[0] * Wd[0] + d[1] * Wd[1] + d[2] * Wd[2];
+        ++used;
+    }
+    *E = err;
+    *count = used;
+    return 0;
+}

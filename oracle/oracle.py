@@ -66,6 +66,13 @@ def configure(lib):
                                                     ctypes.c_double, ctypes.c_double,
                                                     P, P, P, P]
         lib.oracle_covariances_weighted.restype = ctypes.c_int
+    if hasattr(lib, "oracle_gicp_linearize"):
+        lib.oracle_gicp_correspond.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P,
+                                               ctypes.c_double, ctypes.c_int32, P, P]
+        lib.oracle_gicp_correspond.restype = ctypes.c_int
+        lib.oracle_gicp_linearize.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, P, P,
+                                              P, P, P, P]
+        lib.oracle_gicp_linearize.restype = ctypes.c_int
     return lib
 
 
@@ -159,6 +166,46 @@ def covariances_weighted(target, idx, count, kind: str, sigma: float, queries=No
     if rc != 0:
         raise ValueError("oracle_covariances_weighted: invalid arguments")
     return dict(mean=mean, cov=cov, reg=reg, valid=valid)
+
+
+def _T(T):
+    T = np.ascontiguousarray(T, np.float64)
+    assert T.shape == (4, 4)
+    return T
+
+
+def gicp_correspond(source, target, T, max_dist: float = float("inf"),
+                    threads: int | None = None):
+    """Nearest target point of T p_i (FP64 brute force).  Returns (corr int32, d2 float64)."""
+    s, t, T = _f32(source), _f32(target), _T(T)
+    n = s.shape[0]
+    corr = np.empty(n, np.int32)
+    d2 = np.empty(n)
+    rc = _load().oracle_gicp_correspond(_ptr(s), n, _ptr(t), t.shape[0], _ptr(T),
+                                        float(max_dist), int(threads or default_threads()),
+                                        _ptr(corr), _ptr(d2))
+    if rc != 0:
+        raise ValueError("oracle_gicp_correspond: invalid arguments")
+    return corr, d2
+
+
+def gicp_linearize(source, source_cov, target, target_cov, T, corr):
+    """Gauss-Newton system of the GICP cost at T.  Returns dict H [6,6], b [6],
+    E, count."""
+    s, t, T = _f32(source), _f32(target), _T(T)
+    sc = np.ascontiguousarray(np.asarray(source_cov, np.float32).reshape(-1, 9))
+    tc = np.ascontiguousarray(np.asarray(target_cov, np.float32).reshape(-1, 9))
+    corr = np.ascontiguousarray(corr, np.int32)
+    H = np.empty((6, 6))
+    b = np.empty(6)
+    E = np.empty(1)
+    cnt = np.empty(1, np.int64)
+    rc = _load().oracle_gicp_linearize(_ptr(s), _ptr(sc), s.shape[0], _ptr(t), _ptr(tc),
+                                       t.shape[0], _ptr(T), _ptr(corr), _ptr(H), _ptr(b),
+                                       _ptr(E), _ptr(cnt))
+    if rc != 0:
+        raise ValueError("oracle_gicp_linearize: bad correspondence or covariance")
+    return dict(H=H, b=b, E=float(E[0]), count=int(cnt[0]))
 
 
 def sym3_eig(a):

@@ -5,7 +5,9 @@ coordinate term, a reversed tie-break, an exclusive radius, 1/(n-1), a
 wrong mean divisor, the largest eigenvector, a flipped regulariser sign, a
 wrong Jacobi rotation sign, a wrong validity threshold; in the weighted
 covariance a wrong kernel exponent, a flipped weight sign, an unnormalised
-mean, an unweighted sum, a wrong reference point), compiles it on the
+mean, an unweighted sum, a wrong reference point; in the GICP system a
+Jacobian or residual sign, a missing inverse or transpose, a dropped
+covariance, a tie or radius slip in the correspondences), compiles it on the
 CPU, swaps it in for the real oracle and runs the pin tests: at least one
 must fail.  The real oracle is restored afterwards.
 """
@@ -18,11 +20,13 @@ import pytest
 from oracle import oracle
 from tests import test_oracle as pins
 from tests import test_oracle_weighted as wpins
+from tests import test_oracle_gicp as gpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lkc_oracle.c")
 
 MUTATIONS = {
-    "dropped_dz": ("dx * dx + dy * dy + dz * dz", "dx * dx + dy * dy"),
+    "dropped_dz": ("dx * dx + dy * dy + dz * dz;\n            if (!(d <= jb->r2))",
+                   "dx * dx + dy * dy;\n            if (!(d <= jb->r2))"),
     "tiebreak_reversed": ("(da == db && ia < ib)", "(da == db && ia > ib)"),
     "radius_exclusive": ("if (!(d <= jb->r2))", "if (!(d < jb->r2))"),
     "cov_n_minus_1": ("c[e] /= (double)n;", "c[e] /= (double)(n - 1);"),
@@ -65,6 +69,26 @@ WEIGHTED_MUTATIONS = {
 
 WEIGHTED_PINS = [getattr(wpins, n) for n in dir(wpins) if n.startswith("test_")]
 
+# planted mistakes in the GICP correspondence search and Gauss-Newton system
+GICP_MUTATIONS = {
+    "jacobian_skew_sign": ("{0.0, -p[2], p[1], -1.0, 0.0, 0.0}",
+                           "{0.0, p[2], -p[1], -1.0, 0.0, 0.0}"),
+    "residual_sign": ("d[r] = (double)tgt[3 * (int64_t)j + r] - p[r];",
+                      "d[r] = p[r] - (double)tgt[3 * (int64_t)j + r];"),
+    "no_inverse": ("if (!inv3_adjugate(M, W))", "if (!inv3_adjugate(M, W) || !memcpy(W, M, sizeof W))"),
+    "rotation_not_transposed": ("s += RC[3 * r + a] * R[3 * c + a];",
+                                "s += RC[3 * r + a] * R[3 * a + c];"),
+    "target_cov_dropped": ("M[3 * r + c] = (double)tgt_cov[9 * (int64_t)j + 3 * r + c] + s;",
+                           "M[3 * r + c] = s;"),
+    "corr_later_tie": ("(d < bd || (d == bd && j < best))", "(d <= bd)"),
+    "corr_radius_exclusive": ("if (d <= jb->r2 && (d < bd", "if (d < jb->r2 && (d < bd"),
+    "b_sign": ("b[r] += J[0][r] * Wd[0]", "b[r] -= J[0][r] * Wd[0]"),
+    "adjugate_entry": ("inv[5] = (M[2] * M[3] - M[0] * M[5]) / det;",
+                       "inv[5] = (M[0] * M[5] - M[2] * M[3]) / det;"),
+}
+
+GICP_PINS = [getattr(gpins, n) for n in dir(gpins) if n.startswith("test_")]
+
 
 def _call(pin):
     marks = getattr(pin, "pytestmark", [])
@@ -77,14 +101,17 @@ def _call(pin):
 
 
 def test_unmutated_source_passes_the_pins():
-    for pin in PINS + WEIGHTED_PINS:
+    for pin in PINS + WEIGHTED_PINS + GICP_PINS:
         _call(pin)
 
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS) + sorted(WEIGHTED_MUTATIONS))
+GROUPS = [(MUTATIONS, PINS), (WEIGHTED_MUTATIONS, WEIGHTED_PINS), (GICP_MUTATIONS, GICP_PINS)]
+
+
+@pytest.mark.parametrize("name", [n for muts, _ in GROUPS for n in sorted(muts)])
 def test_pins_catch_planted_mistake(name, tmp_path):
-    old, new = MUTATIONS.get(name) or WEIGHTED_MUTATIONS[name]
-    pins_for = PINS if name in MUTATIONS else WEIGHTED_PINS
+    muts, pins_for = next((m, p) for m, p in GROUPS if name in m)
+    old, new = muts[name]
     src = open(SRC).read()
     assert src.count(old) == 1, f"mutation anchor for {name} not unique"
     mut = tmp_path / "mut.c"
