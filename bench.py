@@ -46,6 +46,16 @@ def b_alg(k: int) -> int:
     return 20 * k + 100
 
 
+# GICP reduction: source point (12) + its covariance (36) + correspondence
+# (4) + the target point (16, float4 record) + its covariance (36)
+B_GICP_REDUCE = 104
+
+
+def b_knn(k: int) -> int:
+    """kNN without covariance: query read, k gathers, idx + d2, count."""
+    return 12 + 12 * k + 8 * k + 4
+
+
 def kernel_src_sha() -> str:
     h = hashlib.sha256()
     for f in ("search.hip", "lkc_device.h"):
@@ -74,13 +84,16 @@ def cpu_threads() -> int:
         return os.cpu_count() or 1
 
 
-def oracle_baseline(target, queries, k, radius, sample_rows, label):
+def oracle_baseline(target, queries, k, radius, sample_rows, label, weight=None):
     from oracle import oracle
     q = queries[sample_rows]
     th = cpu_threads()
     t0 = time.perf_counter()
     idx, d2, cnt = oracle.knn(target, q, k, radius, threads=th)
-    oracle.covariances(target, idx, cnt, eps=1e-3, threads=th)
+    if weight is None:
+        oracle.covariances(target, idx, cnt, eps=1e-3, threads=th)
+    else:
+        oracle.covariances_weighted(target, idx, cnt, weight[0], weight[1], queries=q, eps=1e-3)
     dt = time.perf_counter() - t0
     return {"value": q.shape[0] / dt, "unit": "queries/s", "cores": th, "kind": "oracle",
             "sample": f"{q.shape[0]} of {queries.shape[0]} queries ({label}); "
@@ -128,13 +141,106 @@ def served(args, lkc, workloads, torch):
     print(json.dumps(out))
 
 
+def gicp(args, lkc, workloads, torch, ctx, cfg):
+    """GICP linearisation of a 65,536-point scan against the resident
+    2,000,000-point map: float32 transform, k = 1 correspondence search
+    (1 m radius), FP64 per-point system and fixed-order reduction.  One step
+    is one lkc_gicp_linearize; the covariances of both clouds are computed
+    once beforehand (lkc_knn_cov_self, k = 20, r = 2 m)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    m, _ = workloads.build_map(2_000_000, seed=2)
+    s = workloads.source_scan(65_536, seed=3)
+    cell, max_d = 1.0, 1.0
+    mp, sp = torch.from_numpy(m).to(dev), torch.from_numpy(s).to(dev)
+    tgt = lkc.lkc_build_target(ctx, mp, cell)
+    src_t = lkc.lkc_build_target(ctx, sp, cell)
+    tcov = lkc.lkc_knn_cov_self(ctx, tgt, 20, 2.0, 1e-3)["reg"]
+    scov = lkc.lkc_knn_cov_self(ctx, src_t, 20, 2.0, 1e-3)["reg"]
+    src_t.free()
+    th = 0.002
+    T = np.eye(4)
+    T[:3, :3] = [[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]]
+    T[:3, 3] = [0.05, -0.03, 0.01]
+    system, corr = lkc.lkc_gicp_linearize(ctx, tgt, tcov, sp, scov, T, max_d, cfg=cfg)
+    K, W = args.steps, args.warmup
+    for _ in range(W):
+        lkc.lkc_gicp_linearize(ctx, tgt, tcov, sp, scov, T, max_d, corr=corr, system=system,
+                               cfg=cfg)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(K)]
+    phases = []
+    t0 = time.perf_counter()
+    for i in range(K):
+        evs[i][0].record(stream)
+        lkc.lkc_gicp_linearize(ctx, tgt, tcov, sp, scov, T, max_d, corr=corr, system=system,
+                               cfg=cfg)
+        evs[i][1].record(stream)
+        torch.cuda.synchronize()
+        st = ctx.search_stats()
+        phases.append((st["sort_ms"], st["group_ms"], st["fallback_ms"], st["reduce_ms"],
+                       st["fallback_queries"]))
+    total = time.perf_counter() - t0
+    n = s.shape[0]
+    call_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ph = np.array(phases)
+    sort_ms, group_ms, fb_ms, red_ms = (float(ph[:, i].mean()) for i in range(4))
+    fb_q = int(ph[-1, 4])
+    sysd = lkc.split_system(system)
+    red_gbs = n * B_GICP_REDUCE / (red_ms * 1e-3) / 1e9
+    grp_gbs = (n - fb_q) * b_knn(1) / (group_ms * 1e-3) / 1e9
+    if red_ms >= group_ms:
+        roof = {"kernel": "k_gicp_reduce", "achieved": red_gbs, "bytes_per_query": B_GICP_REDUCE,
+                "queries_per_launch": n, "kernel_ms": red_ms}
+    else:
+        roof = {"kernel": "k_group (k=1)", "achieved": grp_gbs, "bytes_per_query": b_knn(1),
+                "queries_per_launch": n - fb_q, "kernel_ms": group_ms}
+    roof.update(bound="hbm", peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=roof["achieved"] / HBM_PEAK_GBS, traffic=None)
+    res = {
+        "metric": "GICP linearisation source points/s (correspondence + FP64 system)",
+        "value": n * K / total, "unit": "points/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": total / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 search, f64 system",
+        "data": "synthetic (seeded ray-cast race-track LiDAR)",
+        "config": {"workload": "GICP step: 65,536-point scan vs 2,000,000-point voxelised map",
+                   "n_points": n, "map_points": int(m.shape[0]), "max_corr_dist_m": max_d,
+                   "cell_m": cell, "step": "transform + k=1 search + FP64 system reduction"},
+        "roofline": roof,
+        "phases_ms": {"query_sort": sort_ms, "k_group": group_ms, "k_fallback": fb_ms,
+                      "reduce": red_ms, "call": call_ms},
+        "fallback_queries": fb_q,
+        "system": {"correspondences": sysd["count"], "rejected": sysd["rejected"],
+                   "error": sysd["E"]},
+        "other_kernel_GBs": {"k_gicp_reduce": red_gbs, "k_group": grp_gbs},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        rows = np.sort(np.random.default_rng(0).choice(n, 1024, replace=False))
+        tc, sc = tcov.cpu().numpy(), scov.cpu().numpy()
+        c0 = time.perf_counter()
+        oc, _ = oracle.gicp_correspond(s[rows], m, T, max_d, threads=cpu_threads())
+        oracle.gicp_linearize(s[rows], sc[rows], m, tc, T, oc)
+        dt = time.perf_counter() - c0
+        res["cpu_baseline"] = {"value": len(rows) / dt, "unit": "points/s",
+                               "cores": cpu_threads(), "kind": "oracle",
+                               "sample": f"{len(rows)} of {n} source points; {dt:.2f} s FP64 "
+                                         "brute-force correspondences + system"}
+    tgt.free()
+    print(json.dumps(res))
+    ctx.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scan",
-                    choices=["scan", "map", "batched", "tiny", "served"])
+                    choices=["scan", "map", "weighted", "gicp", "batched", "tiny", "served"])
+    ap.add_argument("--sigma", type=float, default=0.2,
+                    help="weighted: Laplacian kernel width in metres")
     ap.add_argument("--time-scale", type=float, default=10.0,
                     help="served: schedule compression (inf = open loop)")
     ap.add_argument("--duration", type=float, default=60.0, help="served: stream seconds")
@@ -150,7 +256,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this path has no multi-GPU mode "
-              "(queries shard with no exchange; see the design notes).", file=sys.stderr)
+              "(queries are independent and would shard across GPUs with no exchange).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -178,6 +285,8 @@ def main():
 
     if args.workload == "served":
         return served(args, lkc, workloads, torch)
+    if args.workload == "gicp":
+        return gicp(args, lkc, workloads, torch, ctx, cfg)
     if args.workload in ("scan", "tiny"):
         if args.workload == "scan":
             pts = workloads.single_scan(seed=1)
@@ -228,13 +337,17 @@ def main():
         extra["grid"] = {"cells": info["n_cells"], "hash_capacity": info["hash_capacity"],
                          "sort_passes": info["sort_passes"]}
         baseline_args = (pts, pts, k, radius, np.arange(Q), "the whole scan")
-    elif args.workload == "map":
+    elif args.workload in ("map", "weighted"):
         m, _ = workloads.build_map(2_000_000, seed=2)
         s = workloads.source_scan(65_536, seed=3)
         k, radius, cell = 20, 2.0, 1.0
         config = {"workload": "65,536-point scan vs 2,000,000-point voxelised map",
                   "n_points": 65536, "map_points": 2_000_000, "k": k, "radius_m": radius,
                   "cell_m": cell, "step": "fused kNN+covariance (map resident)"}
+        weighted = args.workload == "weighted"
+        if weighted:
+            config["step"] = "fused kNN + Laplacian-weighted covariance (map resident)"
+            config["kernel"] = {"kind": "laplacian", "sigma_m": args.sigma}
         mp = torch.from_numpy(m).to(dev)
         sq = torch.from_numpy(s).to(dev)
         torch.cuda.synchronize()
@@ -242,13 +355,21 @@ def main():
         tgt = lkc.lkc_build_target(ctx, mp, cell)
         torch.cuda.synchronize()
         extra["map_build_ms"] = (time.perf_counter() - b0) * 1e3
-        out = lkc.lkc_knn_cov(ctx, tgt, sq, k, radius, 1e-3, cfg=cfg)
+        if weighted:
+            out = lkc.lkc_knn_cov_weighted(ctx, tgt, sq, k, "laplacian", args.sigma, radius,
+                                           1e-3, cfg=cfg)
+        else:
+            out = lkc.lkc_knn_cov(ctx, tgt, sq, k, radius, 1e-3, cfg=cfg)
         Q = sq.shape[0]
 
         def step(kstart=None, kend=None):
             if kstart is not None:
                 kstart.record(stream)
-            lkc.lkc_knn_cov(ctx, tgt, sq, k, radius, 1e-3, out=out, cfg=cfg)
+            if weighted:
+                lkc.lkc_knn_cov_weighted(ctx, tgt, sq, k, "laplacian", args.sigma, radius,
+                                         1e-3, out=out, cfg=cfg)
+            else:
+                lkc.lkc_knn_cov(ctx, tgt, sq, k, radius, 1e-3, out=out, cfg=cfg)
             if kend is not None:
                 kend.record(stream)
 
@@ -272,6 +393,8 @@ def main():
         extra["search_kernel_ms"] = kern_ms
         rows = np.sort(np.random.default_rng(0).choice(Q, 4096, replace=False))
         baseline_args = (m, s, k, radius, rows, "seeded subsample")
+        if weighted:
+            baseline_args = baseline_args + (("laplacian", args.sigma),)
     else:  # batched
         m, _ = workloads.build_map(2_000_000, seed=2)
         scans = workloads.batched_scans(16, seed=4)
@@ -349,6 +472,8 @@ def main():
     extra["search_call"] = {"ms": kern_ms, "achieved_GBs": path_achieved,
                             "frac": path_achieved / HBM_PEAK_GBS}
     traffic = committed_traffic(args.workload)
+    if args.workload == "weighted":
+        config["note"] = "roofline bytes as the plain path: the weights add no HBM traffic"
     res = {
         "metric": METRIC,
         "value": value,

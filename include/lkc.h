@@ -13,6 +13,10 @@
  *   lkc_knn_query       queries -> k nearest target points (within a radius)
  *   lkc_covariances     neighbour lists -> mean, covariance, regularised cov
  *   lkc_knn_cov         the two steps above fused in one launch
+ *   lkc_covariances_weighted / lkc_knn_cov_weighted
+ *                       the same with kernel-descriptor neighbour weights
+ *   lkc_gicp_linearize / lkc_gicp_align
+ *                       GICP correspondences, Gauss-Newton system, iterations
  *   lkc_knn_cov_batched many scans against several targets in one persistent
  *                       launch (graph-capturable)
  *
@@ -70,7 +74,8 @@ typedef enum lkc_status {
     LKC_ERR_HIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
     LKC_ERR_BUDGET = -4,      /* request exceeds a size limit fixed at creation */
     LKC_ERR_NONFINITE = -5,   /* a target point has a NaN/Inf coordinate */
-    LKC_ERR_UNSUPPORTED = -6  /* no usable gfx950 device */
+    LKC_ERR_UNSUPPORTED = -6, /* no usable gfx950 device */
+    LKC_ERR_DEGENERATE = -7   /* registration system not positive definite */
 } lkc_status;
 
 /* Launch options of the search.  Zero-initialised means "all defaults".
@@ -196,6 +201,91 @@ lkc_status lkc_knn_cov(lkc_ctx *ctx, const lkc_target *target, const float *quer
                        int32_t *count, float *mean, float *cov, float *reg_cov, uint8_t *valid,
                        const lkc_launch_cfg *cfg);
 
+/* Kernel-descriptor weighted covariance (the paper's table of kernel
+ * descriptors, Sec. III-C.1, which uses them as similarity measures in the
+ * GPU covariance estimate and finds the Laplacian best).  Neighbour j of a
+ * query at origin o (the query, or its first neighbour when queries is NULL)
+ * gets weight w_j = K(o, t_j) with, for D = |o - t_j|^2,
+ *   LKC_WEIGHT_RBF        K = exp(-D * sigma)
+ *   LKC_WEIGHT_GAUSSIAN   K = exp(-D / (2 sigma^2))
+ *   LKC_WEIGHT_LAPLACIAN  K = exp(-sqrt(D) / sigma)
+ * and mean = sum w t / sum w, C = sum w (t - mean)(t - mean)^T / sum w.  The
+ * weights are evaluated relative to the largest one (exp(-(e_j - min e))),
+ * which leaves the result unchanged and cannot underflow to a zero sum.
+ * valid and reg_cov follow the plain estimate (n >= 3; eigenvector of C).
+ * LKC_WEIGHT_NONE gives the plain estimate, bit-identical to
+ * lkc_covariances.  sigma > 0 and finite; LKC_ERR_INVALID_ARG when the
+ * kernel's scale (sigma, 1/(2 sigma^2) or 1/sigma) is not a positive finite
+ * float.  Everything else as lkc_covariances. */
+enum {
+    LKC_WEIGHT_NONE = 0,
+    LKC_WEIGHT_RBF = 1,
+    LKC_WEIGHT_GAUSSIAN = 2,
+    LKC_WEIGHT_LAPLACIAN = 3
+};
+lkc_status lkc_covariances_weighted(lkc_ctx *ctx, const lkc_target *target, const float *queries,
+                                    const int32_t *idx, const int32_t *count, int64_t q,
+                                    int32_t k, int32_t kernel, float sigma, float plane_eps,
+                                    float *mean, float *cov, float *reg_cov, uint8_t *valid);
+
+/* lkc_knn_query followed by lkc_covariances_weighted (queries as origin) in
+ * one launch; bit-identical to the two calls. */
+lkc_status lkc_knn_cov_weighted(lkc_ctx *ctx, const lkc_target *target, const float *queries,
+                                int64_t q, int32_t k, float radius, int32_t kernel, float sigma,
+                                float plane_eps, int32_t *idx, float *d2, int32_t *count,
+                                float *mean, float *cov, float *reg_cov, uint8_t *valid,
+                                const lkc_launch_cfg *cfg);
+
+/* ---- GICP registration on the covariances (paper Sec. III-C.1,
+ * Eqs. eq_trans_err .. eq_trans_likelihood).  The printed combined
+ * covariance is garbled; it is read as in generalized ICP (Segal et al.):
+ *   d_i = q_j - (R p_i + t),  W_i = (C^q_j + R C^p_i R^T)^{-1},
+ *   E = sum_i d_i^T W_i d_i
+ * over the source points whose correspondence j -- the nearest target point
+ * of T p_i within max_corr_dist (lkc_knn_query rules with k = 1, on p_i
+ * transformed in float32) -- exists.  The increment delta = (omega, v) acts
+ * on the left, T <- exp(delta^) T, so J_i = [ [p'_i]_x , -I ] with
+ * p'_i = R p_i + t, and the Gauss-Newton system is H = sum J^T W J,
+ * b = sum J^T W d (W held fixed), step delta = -H^{-1} b.  Per point the
+ * arithmetic is FP64 on the float32 inputs; sums are FP64 in a fixed order
+ * (deterministic for a given n). */
+#define LKC_GICP_SYSTEM_WORDS 45
+
+/* One linearisation at T (host double [4][4], row-major rigid transform).
+ * target_cov: device float [n_target][3][3] by original target index (the
+ * reg_cov lkc_knn_cov_self writes for the target); source [n][3] and
+ * source_cov [n][3][3] device.  Outputs (device): corr int32 [n] (-1 = none;
+ * may be NULL) and system double [LKC_GICP_SYSTEM_WORDS] =
+ *   H [6][6] row-major, b [6], E, correspondences, rejected
+ * where rejected counts correspondences whose combined covariance is not
+ * positive definite (they are left out).  max_corr_dist > 0 (INFINITY =
+ * uncapped).  Stream-ordered; grows the context's registration scratch. */
+lkc_status lkc_gicp_linearize(lkc_ctx *ctx, const lkc_target *target, const float *target_cov,
+                              const float *source, const float *source_cov, int64_t n,
+                              const double *T, float max_corr_dist, int32_t *corr,
+                              double *system, const lkc_launch_cfg *cfg);
+
+typedef struct lkc_gicp_stats {
+    int32_t iterations;       /* linearisations done */
+    int32_t converged;        /* 1 when the last step was below tol */
+    int64_t correspondences;  /* of the last linearisation */
+    int64_t rejected;
+    double error;             /* E at the last linearisation */
+    double last_step;         /* max |delta| of the last step */
+} lkc_gicp_stats;
+
+/* Gauss-Newton iterations from T_init (host double [4][4]): each one
+ * re-finds the correspondences, linearises, solves H delta = -b (Cholesky,
+ * host FP64) and applies T <- exp(delta^) T; stops after max_iters or when
+ * max |delta| < tol.  T_out (host [4][4]) receives the last transform, also
+ * on LKC_ERR_DEGENERATE (fewer than 6 independent constraints).
+ * Synchronises once per iteration.  stats (host) may be NULL. */
+lkc_status lkc_gicp_align(lkc_ctx *ctx, const lkc_target *target, const float *target_cov,
+                          const float *source, const float *source_cov, int64_t n,
+                          const double *T_init, float max_corr_dist, int32_t max_iters,
+                          double tol, double *T_out, lkc_gicp_stats *stats,
+                          const lkc_launch_cfg *cfg);
+
 /* A set of targets addressable by the batched call.  Creating a set uploads
  * one small descriptor per target and sizes the set's scan table for at
  * most `max_scans` scans (host array of target pointers).  The targets must
@@ -242,9 +332,10 @@ lkc_status lkc_knn_cov_self(lkc_ctx *ctx, const lkc_target *target, int32_t k, f
                             float *cov, float *reg_cov, uint8_t *valid, const lkc_launch_cfg *cfg);
 
 /* Counters of the last search on the context (host struct).  Synchronises.
- * The three phase times are GPU times (HIP events on the context's stream)
- * of the last search when timing is on (lkc_ctx_set_timing), else -1:
- * query sort (with its key kernel), group kernel, fallback kernel. */
+ * The phase times are GPU times (HIP events on the context's stream) when
+ * timing is on (lkc_ctx_set_timing), else -1: query sort (with its key
+ * kernel), group kernel and fallback kernel of the last search, and the
+ * reduction (partial and final sums) of the last lkc_gicp_linearize. */
 typedef struct lkc_search_stats {
     int64_t queries;          /* queries of the last search */
     int64_t fallback_queries; /* queries the group search handed to the
@@ -252,7 +343,7 @@ typedef struct lkc_search_stats {
     float sort_ms;
     float group_ms;
     float fallback_ms;
-    int32_t reserved;
+    float reduce_ms;
 } lkc_search_stats;
 lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
 /* Record HIP events between the phases of every following search on this

@@ -110,9 +110,11 @@ lkc_status lkc_ctx_destroy(lkc_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->build_scratch) (void)hipFree(ctx->build_scratch);
     if (ctx->search_scratch) (void)hipFree(ctx->search_scratch);
+    if (ctx->gicp_scratch) (void)hipFree(ctx->gicp_scratch);
+    if (ctx->gicp_host) (void)hipHostFree(ctx->gicp_host);
     if (ctx->meta_dev) (void)hipFree(ctx->meta_dev);
     if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 6; ++i)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     delete ctx;
     return LKC_OK;
@@ -256,6 +258,120 @@ lkc_status lkc_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries, 
         return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
     return lkc::launch_knn_cov(ctx, t, queries, q, k, radius, plane_eps, idx, d2, count, mean,
                                cov, reg_cov, valid, lkc::resolve_cfg(cfg));
+}
+
+namespace {
+
+lkc_status make_weight(lkc_ctx* ctx, int32_t kernel, float sigma, lkc::CovWeight* w) {
+    w->kind = kernel;
+    w->scale = 0.0f;
+    if (kernel == LKC_WEIGHT_NONE) return LKC_OK;
+    if (kernel < LKC_WEIGHT_NONE || kernel > LKC_WEIGHT_LAPLACIAN)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "unknown weight kernel %d", kernel);
+    if (!(sigma > 0.0f) || !std::isfinite(sigma))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "sigma must be positive and finite");
+    const double sg = sigma;
+    const double sc = kernel == LKC_WEIGHT_RBF ? sg
+                    : kernel == LKC_WEIGHT_GAUSSIAN ? 1.0 / (2.0 * sg * sg) : 1.0 / sg;
+    const float f = (float)sc;
+    if (!(f > 0.0f) || !std::isfinite(f))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "sigma %g gives a kernel scale outside float",
+                         (double)sigma);
+    w->scale = f;
+    return LKC_OK;
+}
+
+}  // namespace
+
+lkc_status lkc_covariances_weighted(lkc_ctx* ctx, const lkc_target* t, const float* queries,
+                                    const int32_t* idx, const int32_t* count, int64_t q,
+                                    int32_t k, int32_t kernel, float sigma, float plane_eps,
+                                    float* mean, float* cov, float* reg_cov, uint8_t* valid) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if (k < 1 || k > LKC_MAX_K)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "k = %d outside [1, %d]", k, LKC_MAX_K);
+    if ((s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
+    lkc::CovWeight w;
+    if ((s = make_weight(ctx, kernel, sigma, &w)) != LKC_OK) return s;
+    if (q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "q < 0");
+    if (q > 0 && (!idx || !count || !valid))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL idx, count or valid pointer");
+    return lkc::launch_cov(ctx, t, queries, idx, count, q, k, plane_eps, mean, cov, reg_cov,
+                           valid, w);
+}
+
+lkc_status lkc_knn_cov_weighted(lkc_ctx* ctx, const lkc_target* t, const float* queries,
+                                int64_t q, int32_t k, float radius, int32_t kernel, float sigma,
+                                float plane_eps, int32_t* idx, float* d2, int32_t* count,
+                                float* mean, float* cov, float* reg_cov, uint8_t* valid,
+                                const lkc_launch_cfg* cfg) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if ((s = check_k_radius(ctx, k, radius)) != LKC_OK) return s;
+    if ((s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
+    lkc::CovWeight w;
+    if ((s = make_weight(ctx, kernel, sigma, &w)) != LKC_OK) return s;
+    if (q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "q < 0");
+    if (q > 0 && (!queries || !idx || !d2 || !count || !valid))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
+    return lkc::launch_knn_cov(ctx, t, queries, q, k, radius, plane_eps, idx, d2, count, mean,
+                               cov, reg_cov, valid, lkc::resolve_cfg(cfg), w);
+}
+
+namespace {
+
+lkc_status check_gicp(lkc_ctx* ctx, const lkc_target* t, const float* tcov, const float* src,
+                      const float* scov, int64_t n, const double* T, float max_dist) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if (n < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "n < 0");
+    if (n > INT32_MAX) return set_error(ctx, LKC_ERR_INVALID_ARG, "n above 2^31 - 1");
+    if (!T) return set_error(ctx, LKC_ERR_INVALID_ARG, "T is NULL");
+    for (int i = 0; i < 16; ++i)
+        if (!std::isfinite(T[i])) return set_error(ctx, LKC_ERR_INVALID_ARG, "T is not finite");
+    if (T[12] != 0.0 || T[13] != 0.0 || T[14] != 0.0 || T[15] != 1.0)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "T's last row is not (0, 0, 0, 1)");
+    if (!(max_dist > 0.0f))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "max_corr_dist must be > 0");
+    if (n > 0 && (!src || !scov || (t->view.n > 0 && !tcov)))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL source or covariance pointer");
+    return LKC_OK;
+}
+
+}  // namespace
+
+lkc_status lkc_gicp_linearize(lkc_ctx* ctx, const lkc_target* t, const float* tcov,
+                              const float* src, const float* scov, int64_t n, const double* T,
+                              float max_corr_dist, int32_t* corr, double* system,
+                              const lkc_launch_cfg* cfg) {
+    lkc_status s = check_gicp(ctx, t, tcov, src, scov, n, T, max_corr_dist);
+    if (s != LKC_OK) return s;
+    if (!system) return set_error(ctx, LKC_ERR_INVALID_ARG, "system is NULL");
+    const lkc::LaunchCfg c = lkc::resolve_cfg(cfg);
+    if ((s = lkc::check_launch_cfg(ctx, c)) != LKC_OK) return s;
+    return lkc::launch_gicp_linearize(ctx, t, tcov, src, scov, n, T, max_corr_dist, corr, system,
+                                      c);
+}
+
+lkc_status lkc_gicp_align(lkc_ctx* ctx, const lkc_target* t, const float* tcov,
+                          const float* src, const float* scov, int64_t n, const double* T_init,
+                          float max_corr_dist, int32_t max_iters, double tol, double* T_out,
+                          lkc_gicp_stats* stats, const lkc_launch_cfg* cfg) {
+    lkc_status s = check_gicp(ctx, t, tcov, src, scov, n, T_init, max_corr_dist);
+    if (s != LKC_OK) return s;
+    if (!T_out) return set_error(ctx, LKC_ERR_INVALID_ARG, "T_out is NULL");
+    if (max_iters < 1 || max_iters > 1000)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "max_iters outside [1, 1000]");
+    if (!(tol >= 0.0) || !std::isfinite(tol))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "tol must be finite and >= 0");
+    const lkc::LaunchCfg c = lkc::resolve_cfg(cfg);
+    if ((s = lkc::check_launch_cfg(ctx, c)) != LKC_OK) return s;
+    return lkc::gicp_align(ctx, t, tcov, src, scov, n, T_init, max_corr_dist, max_iters, tol,
+                           T_out, stats, c);
 }
 
 lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,
@@ -418,10 +534,11 @@ lkc_status lkc_ctx_set_timing(lkc_ctx* ctx, int32_t on) {
     lkc_status s = check_ctx(ctx);
     if (s != LKC_OK) return s;
     if (on && !ctx->ev[0]) {
-        for (int i = 0; i < 4; ++i) LKC_HIP_TRY(ctx, hipEventCreate(&ctx->ev[i]));
+        for (int i = 0; i < 6; ++i) LKC_HIP_TRY(ctx, hipEventCreate(&ctx->ev[i]));
     }
     ctx->timing = on != 0;
     ctx->ev_valid = false;
+    ctx->ev_reduce_valid = false;
     return LKC_OK;
 }
 
@@ -431,12 +548,16 @@ lkc_status lkc_ctx_search_stats(lkc_ctx* ctx, lkc_search_stats* out) {
     if (!out) return set_error(ctx, LKC_ERR_INVALID_ARG, "out is NULL");
     out->queries = ctx->last_queries;
     out->fallback_queries = 0;
-    out->sort_ms = out->group_ms = out->fallback_ms = -1.0f;
+    out->sort_ms = out->group_ms = out->fallback_ms = out->reduce_ms = -1.0f;
     if (ctx->ev_valid) {
         LKC_HIP_TRY(ctx, hipEventSynchronize(ctx->ev[3]));
         LKC_HIP_TRY(ctx, hipEventElapsedTime(&out->sort_ms, ctx->ev[0], ctx->ev[1]));
         LKC_HIP_TRY(ctx, hipEventElapsedTime(&out->group_ms, ctx->ev[1], ctx->ev[2]));
         LKC_HIP_TRY(ctx, hipEventElapsedTime(&out->fallback_ms, ctx->ev[2], ctx->ev[3]));
+    }
+    if (ctx->ev_reduce_valid) {
+        LKC_HIP_TRY(ctx, hipEventSynchronize(ctx->ev[5]));
+        LKC_HIP_TRY(ctx, hipEventElapsedTime(&out->reduce_ms, ctx->ev[4], ctx->ev[5]));
     }
     if (ctx->last_fallback_count) {
         uint32_t v = 0;

@@ -31,8 +31,14 @@ struct lkc_ctx {
     void* prof_buf = nullptr;    // optional device buffer for per-group counters
     int64_t prof_groups = 0;
     bool timing = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool ev_valid = false;
+    bool ev_reduce_valid = false;   // ev[4], ev[5] bracket the last registration reduction
+    // grow-only device scratch for registration (transformed source,
+    // correspondences, partial sums) and a pinned read-back of the system
+    void* gicp_scratch = nullptr;
+    size_t gicp_scratch_bytes = 0;
+    void* gicp_host = nullptr;
 };
 
 struct lkc_target {
@@ -100,6 +106,14 @@ struct LaunchCfg {
     int persistent;       // 0 = one wave per group; n = n persistent workgroups per CU
 };
 LaunchCfg resolve_cfg(const lkc_launch_cfg* cfg);
+lkc_status check_launch_cfg(lkc_ctx* ctx, const LaunchCfg& c);
+// Neighbour weights of the kernel-descriptor covariance: kind 0 is the plain
+// (unweighted) estimate; otherwise w_j = exp(-(e_j - min e)) with
+// e_j = scale * d2_j (RBF, Gaussian) or scale * sqrt(d2_j) (Laplacian).
+struct CovWeight {
+    int kind;     // LKC_WEIGHT_*
+    float scale;  // RBF sigma; Gaussian 1 / (2 sigma^2); Laplacian 1 / sigma
+};
 lkc_status launch_knn(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
                       int32_t k, float radius, int32_t* idx, float* d2, int32_t* count,
                       const LaunchCfg& cfg);
@@ -109,11 +123,30 @@ lkc_status launch_knn_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float r
 lkc_status reserve_search(lkc_ctx* ctx, int64_t max_queries);
 lkc_status launch_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries,
                       const int32_t* idx, const int32_t* count, int64_t q, int32_t k, float eps,
-                      float* mean, float* cov, float* reg, uint8_t* valid);
+                      float* mean, float* cov, float* reg, uint8_t* valid,
+                      const CovWeight& wt = CovWeight{0, 0.0f});
 lkc_status launch_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
                           int32_t k, float radius, float eps, int32_t* idx, float* d2,
                           int32_t* count, float* mean, float* cov, float* reg, uint8_t* valid,
-                          const LaunchCfg& cfg);
+                          const LaunchCfg& cfg, const CovWeight& wt = CovWeight{0, 0.0f});
+// implemented in gicp.hip
+struct GicpScratch {
+    float* queries;
+    int32_t* idx;
+    float* d2;
+    int32_t* count;
+    double* partials;
+    double* system;
+};
+lkc_status gicp_scratch(lkc_ctx* ctx, int64_t n, GicpScratch& g);
+lkc_status launch_gicp_linearize(lkc_ctx* ctx, const lkc_target* t, const float* tcov,
+                                 const float* src, const float* scov, int64_t n, const double* T,
+                                 float max_dist, int32_t* corr, double* system,
+                                 const LaunchCfg& cfg);
+lkc_status gicp_align(lkc_ctx* ctx, const lkc_target* t, const float* tcov, const float* src,
+                      const float* scov, int64_t n, const double* T0, float max_dist,
+                      int32_t max_iters, double tol, double* T_out, lkc_gicp_stats* stats,
+                      const LaunchCfg& cfg);
 lkc_status launch_batched(lkc_ctx* ctx, lkc_target_set* set, const float* queries,
                           int64_t total_q, int32_t k, float radius, float eps, int32_t* idx,
                           float* d2, int32_t* count, float* mean, float* cov, float* reg,

@@ -356,6 +356,34 @@ __device__ __forceinline__ void smallest_eigvec(const float (&c)[6], float (&v0)
     v0[2] = z;
 }
 
+__device__ __forceinline__ void cov_empty(CovOut& out) {
+    for (int a = 0; a < 3; ++a) out.mean[a] = 0.0f;
+    for (int e = 0; e < 6; ++e) out.cov[e] = 0.0f;
+    out.reg[0] = 1.f; out.reg[1] = 0.f; out.reg[2] = 0.f;
+    out.reg[3] = 1.f; out.reg[4] = 0.f; out.reg[5] = 1.f;
+    out.valid = false;
+}
+
+// GICP plane regulariser I - (1 - eps) v0 v0^T (v0: smallest eigenvector
+// of out.cov) for n >= 3 neighbours, else I.
+__device__ __forceinline__ void cov_regularise(int n, float eps, CovOut& out) {
+    out.valid = n >= 3;
+    if (out.valid) {
+        float v0[3];
+        smallest_eigvec(out.cov, v0);
+        const float w = 1.0f - eps;
+        out.reg[0] = 1.0f - w * v0[0] * v0[0];
+        out.reg[1] = -w * v0[0] * v0[1];
+        out.reg[2] = -w * v0[0] * v0[2];
+        out.reg[3] = 1.0f - w * v0[1] * v0[1];
+        out.reg[4] = -w * v0[1] * v0[2];
+        out.reg[5] = 1.0f - w * v0[2] * v0[2];
+    } else {
+        out.reg[0] = 1.f; out.reg[1] = 0.f; out.reg[2] = 0.f;
+        out.reg[3] = 1.f; out.reg[4] = 0.f; out.reg[5] = 1.f;
+    }
+}
+
 // Two-pass centred covariance of n neighbours relative to origin o.
 // fetch(j) returns neighbour j as float4.  Identical arithmetic in every
 // kernel that calls it (plain, fused, batched), so their results agree
@@ -364,11 +392,7 @@ template <typename Fetch>
 __device__ __forceinline__ void covariance(float ox, float oy, float oz, int n, Fetch fetch,
                                            float eps, CovOut& out) {
     if (n <= 0) {
-        for (int a = 0; a < 3; ++a) out.mean[a] = 0.0f;
-        for (int e = 0; e < 6; ++e) out.cov[e] = 0.0f;
-        out.reg[0] = 1.f; out.reg[1] = 0.f; out.reg[2] = 0.f;
-        out.reg[3] = 1.f; out.reg[4] = 0.f; out.reg[5] = 1.f;
-        out.valid = false;
+        cov_empty(out);
         return;
     }
     float sx = 0.f, sy = 0.f, sz = 0.f;
@@ -400,21 +424,79 @@ __device__ __forceinline__ void covariance(float ox, float oy, float oz, int n, 
     out.mean[0] = ox + mx;
     out.mean[1] = oy + my;
     out.mean[2] = oz + mz;
-    out.valid = n >= 3;
-    if (out.valid) {
-        float v0[3];
-        smallest_eigvec(out.cov, v0);
-        const float w = 1.0f - eps;
-        out.reg[0] = 1.0f - w * v0[0] * v0[0];
-        out.reg[1] = -w * v0[0] * v0[1];
-        out.reg[2] = -w * v0[0] * v0[2];
-        out.reg[3] = 1.0f - w * v0[1] * v0[1];
-        out.reg[4] = -w * v0[1] * v0[2];
-        out.reg[5] = 1.0f - w * v0[2] * v0[2];
-    } else {
-        out.reg[0] = 1.f; out.reg[1] = 0.f; out.reg[2] = 0.f;
-        out.reg[3] = 1.f; out.reg[4] = 0.f; out.reg[5] = 1.f;
+    cov_regularise(n, eps, out);
+}
+
+// Exponent of the kernel descriptor for squared distance d2.
+__device__ __forceinline__ float weight_exponent(const CovWeight& W, float d2) {
+    return W.kind == LKC_WEIGHT_LAPLACIAN ? sqrtf(d2) * W.scale : d2 * W.scale;
+}
+
+// Kernel-descriptor weighted covariance (the paper's table of kernel
+// descriptors, Sec. III-C.1): neighbour j of the query at o gets
+// w_j = K(o, t_j) / max_j K(o, t_j) = exp(-(e_j - min e)); the rescaling
+// leaves the normalised estimate unchanged, keeps the weights in (0, 1] and
+// makes the sum >= 1.  Three passes relative to o: the smallest exponent,
+// the weighted mean, the weighted centred second moment; both divided by
+// the weight sum.  Validity and the regulariser are those of the plain
+// estimate.  Shared by every kernel that computes it, so the standalone and
+// fused results agree bit for bit.
+template <typename Fetch>
+__device__ __forceinline__ void covariance_weighted(float ox, float oy, float oz, int n,
+                                                    Fetch fetch, const CovWeight& W, float eps,
+                                                    CovOut& out) {
+    if (n <= 0) {
+        cov_empty(out);
+        return;
     }
+    float emin = INF;
+    for (int j = 0; j < n; ++j) {
+        const float4 t = fetch(j);
+        emin = fminf(emin, weight_exponent(W, dist2(ox, oy, oz, t.x, t.y, t.z)));
+    }
+    float sw = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+    for (int j = 0; j < n; ++j) {
+        const float4 t = fetch(j);
+        const float w = expf(emin - weight_exponent(W, dist2(ox, oy, oz, t.x, t.y, t.z)));
+        sw += w;
+        sx = fmaf(w, t.x - ox, sx);
+        sy = fmaf(w, t.y - oy, sy);
+        sz = fmaf(w, t.z - oz, sz);
+    }
+    const float mx = sx / sw, my = sy / sw, mz = sz / sw;
+    float cxx = 0.f, cxy = 0.f, cxz = 0.f, cyy = 0.f, cyz = 0.f, czz = 0.f;
+    for (int j = 0; j < n; ++j) {
+        const float4 t = fetch(j);
+        const float w = expf(emin - weight_exponent(W, dist2(ox, oy, oz, t.x, t.y, t.z)));
+        const float dx = (t.x - ox) - mx, dy = (t.y - oy) - my, dz = (t.z - oz) - mz;
+        const float wx = w * dx, wy = w * dy, wz = w * dz;
+        cxx = fmaf(wx, dx, cxx);
+        cxy = fmaf(wx, dy, cxy);
+        cxz = fmaf(wx, dz, cxz);
+        cyy = fmaf(wy, dy, cyy);
+        cyz = fmaf(wy, dz, cyz);
+        czz = fmaf(wz, dz, czz);
+    }
+    out.cov[0] = cxx / sw;
+    out.cov[1] = cxy / sw;
+    out.cov[2] = cxz / sw;
+    out.cov[3] = cyy / sw;
+    out.cov[4] = cyz / sw;
+    out.cov[5] = czz / sw;
+    out.mean[0] = ox + mx;
+    out.mean[1] = oy + my;
+    out.mean[2] = oz + mz;
+    cov_regularise(n, eps, out);
+}
+
+// The plain or the weighted estimate, as W asks.
+template <typename Fetch>
+__device__ __forceinline__ void covariance_any(float ox, float oy, float oz, int n, Fetch fetch,
+                                               const CovWeight& W, float eps, CovOut& out) {
+    if (W.kind == LKC_WEIGHT_NONE)
+        covariance(ox, oy, oz, n, fetch, eps, out);
+    else
+        covariance_weighted(ox, oy, oz, n, fetch, W, eps, out);
 }
 
 struct CovPtrs {
@@ -507,6 +589,7 @@ struct GroupArgs {
     KnnPtrs ko;
     CovPtrs co;
     float eps;
+    CovWeight wt;                     // covariance weights (fused mode 2)
     uint32_t* fb_list;                // slots handed to the fallback search
     uint32_t* fb_count;
     uint32_t* counters;               // per-XCD work counters (persistent mode) or NULL
@@ -635,7 +718,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
     }
 }
 
-template <int K, bool FUSED>
+template <int K, int FUSED>
 __device__ void group_body(const GroupArgs& a, int64_t group) {
     const int lane = lane_id();
     const int64_t slot = group * WAVE + lane;
@@ -782,12 +865,16 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
     if (FUSED) {
         const float4* orig = T.orig;
         CovOut c;
-        covariance(s.x, s.y, s.z, cnt, [&](int j) { return orig[irow[j]]; }, a.eps, c);
+        if (FUSED == 1)
+            covariance(s.x, s.y, s.z, cnt, [&](int j) { return orig[irow[j]]; }, a.eps, c);
+        else
+            covariance_weighted(s.x, s.y, s.z, cnt, [&](int j) { return orig[irow[j]]; }, a.wt,
+                                a.eps, c);
         store_cov(a.co, s.qi, c);
     }
 }
 
-template <int K, bool FUSED>
+template <int K, int FUSED>
 __global__ void __launch_bounds__(256) k_group(GroupArgs a) {
     const int wpb = blockDim.x / WAVE;
     const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
@@ -818,7 +905,7 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs a) {
 // Wavefront-per-query search for the slots the group search handed over.
 // Persistent: waves stride over the list (its length is only known on the
 // device).
-template <bool FUSED>
+template <int FUSED>
 __global__ void __launch_bounds__(256) k_fallback(GroupArgs a) {
     const int lane = lane_id();
     const uint32_t nfb = *(volatile uint32_t*)a.fb_count;
@@ -844,7 +931,11 @@ __global__ void __launch_bounds__(256) k_fallback(GroupArgs a) {
             // position is read from lane j); lane 0 stores it
             const float4* pts = T.pts;
             CovOut c;
-            covariance(s.x, s.y, s.z, cnt, [&](int j) { return pts[readlane(L.p, j)]; }, a.eps, c);
+            const auto fetch = [&](int j) { return pts[readlane(L.p, j)]; };
+            if (FUSED == 1)
+                covariance(s.x, s.y, s.z, cnt, fetch, a.eps, c);
+            else
+                covariance_weighted(s.x, s.y, s.z, cnt, fetch, a.wt, a.eps, c);
             if (lane == 0) store_cov(a.co, s.qi, c);
         }
     }
@@ -912,7 +1003,7 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 __global__ void __launch_bounds__(256) k_cov(TargetView T, const float* __restrict__ queries,
                                              const int32_t* __restrict__ idx,
                                              const int32_t* __restrict__ count, int64_t q, int k,
-                                             float eps, CovPtrs co) {
+                                             float eps, CovWeight wt, CovPtrs co) {
     const int64_t qi = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (qi >= q) return;
     const int32_t* nb = idx + qi * k;
@@ -939,7 +1030,7 @@ __global__ void __launch_bounds__(256) k_cov(TargetView T, const float* __restri
     }
     const float4* orig = T.orig;
     CovOut c;
-    covariance(ox, oy, oz, n, [&](int j) { return orig[nb[j]]; }, eps, c);
+    covariance_any(ox, oy, oz, n, [&](int j) { return orig[nb[j]]; }, wt, eps, c);
     store_cov(co, qi, c);
 }
 
@@ -1023,7 +1114,7 @@ int choose_k_tile(int k) {
     return 0;
 }
 
-template <bool FUSED>
+template <int FUSED>
 void launch_group(int K, dim3 grid, dim3 block, hipStream_t st, const GroupArgs& a) {
     switch (K) {
         case 8: hipLaunchKernelGGL((k_group<8, FUSED>), grid, block, 0, st, a); break;
@@ -1044,9 +1135,10 @@ struct SearchJob {
     int32_t k;
     float radius;
     float eps;
-    bool fused;
+    int fused;      // 0 search only, 1 plain covariance, 2 weighted covariance
     KnnPtrs ko;
     CovPtrs co;
+    CovWeight wt;
 };
 
 lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
@@ -1066,6 +1158,7 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     a.ko = j.ko;
     a.co = j.co;
     a.eps = j.eps;
+    a.wt = j.wt;
     a.fb_list = sc.fb_list;
     a.fb_count = sc.words;
     a.counters = nullptr;
@@ -1127,10 +1220,12 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
         } else {
             blocks = (unsigned)((n_groups + wpb - 1) / wpb);
         }
-        if (j.fused)
-            launch_group<true>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+        if (j.fused == 2)
+            launch_group<2>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+        else if (j.fused == 1)
+            launch_group<1>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
         else
-            launch_group<false>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+            launch_group<0>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
     } else {
         // every query goes to the wavefront-per-query search
         hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, sc.words, 16,
@@ -1141,10 +1236,12 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     }
     if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
     const dim3 fgrid((unsigned)(ctx->num_cus * 4));
-    if (j.fused)
-        hipLaunchKernelGGL(k_fallback<true>, fgrid, dim3(256), 0, st, a);
+    if (j.fused == 2)
+        hipLaunchKernelGGL(k_fallback<2>, fgrid, dim3(256), 0, st, a);
+    else if (j.fused == 1)
+        hipLaunchKernelGGL(k_fallback<1>, fgrid, dim3(256), 0, st, a);
     else
-        hipLaunchKernelGGL(k_fallback<false>, fgrid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_fallback<0>, fgrid, dim3(256), 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(ctx, e, "search launch");
     if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[3], st));
@@ -1166,6 +1263,8 @@ lkc_status check_cfg(lkc_ctx* ctx, const LaunchCfg& c) {
 }
 
 }  // namespace
+
+lkc_status check_launch_cfg(lkc_ctx* ctx, const LaunchCfg& c) { return check_cfg(ctx, c); }
 
 lkc_status reserve_search(lkc_ctx* ctx, int64_t max_queries) {
     Scratch sc;
@@ -1189,7 +1288,7 @@ lkc_status launch_knn(lkc_ctx* ctx, const lkc_target* t, const float* queries, i
                       const LaunchCfg& cfg) {
     lkc_status s = check_cfg(ctx, cfg);
     if (s != LKC_OK) return s;
-    SearchJob j{t->view_dev, &t->view, 1, queries, q, nullptr, nullptr, k, radius, 0.0f, false,
+    SearchJob j{t->view_dev, &t->view, 1, queries, q, nullptr, nullptr, k, radius, 0.0f, 0,
                 KnnPtrs{idx, d2, count}, CovPtrs{nullptr, nullptr, nullptr, nullptr}};
     return run_search(ctx, j, cfg);
 }
@@ -1197,11 +1296,12 @@ lkc_status launch_knn(lkc_ctx* ctx, const lkc_target* t, const float* queries, i
 lkc_status launch_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries, int64_t q,
                           int32_t k, float radius, float eps, int32_t* idx, float* d2,
                           int32_t* count, float* mean, float* cov, float* reg, uint8_t* valid,
-                          const LaunchCfg& cfg) {
+                          const LaunchCfg& cfg, const CovWeight& wt) {
     lkc_status s = check_cfg(ctx, cfg);
     if (s != LKC_OK) return s;
+    const int mode = valid == nullptr ? 0 : wt.kind == LKC_WEIGHT_NONE ? 1 : 2;
     SearchJob j{t->view_dev, &t->view, 1, queries, q, nullptr, nullptr, k, radius, eps,
-                valid != nullptr, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
+                mode, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}, wt};
     return run_search(ctx, j, cfg);
 }
 
@@ -1211,18 +1311,18 @@ lkc_status launch_knn_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float r
     lkc_status s = check_cfg(ctx, cfg);
     if (s != LKC_OK) return s;
     SearchJob j{t->view_dev, &t->view, 1, nullptr, t->view.n, nullptr, nullptr, k, radius, eps,
-                valid != nullptr, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
+                valid != nullptr ? 1 : 0, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
     return run_search(ctx, j, cfg);
 }
 
 lkc_status launch_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries,
                       const int32_t* idx, const int32_t* count, int64_t q, int32_t k, float eps,
-                      float* mean, float* cov, float* reg, uint8_t* valid) {
+                      float* mean, float* cov, float* reg, uint8_t* valid, const CovWeight& wt) {
     if (q == 0) return LKC_OK;
     const int64_t blocks = (q + 255) / 256;
     if (blocks > 0x7fffffff) return set_error(ctx, LKC_ERR_INVALID_ARG, "too many queries");
     hipLaunchKernelGGL(k_cov, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, t->view,
-                       queries, idx, count, q, k, eps, CovPtrs{mean, cov, reg, valid});
+                       queries, idx, count, q, k, eps, wt, CovPtrs{mean, cov, reg, valid});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_error(ctx, e, "covariance launch");
     return LKC_OK;
@@ -1240,7 +1340,7 @@ lkc_status launch_batched(lkc_ctx* ctx, lkc_target_set* set, const float* querie
                          (long long)set->staged_total, (long long)total_q);
     if (set->staged_scans == 0) return LKC_OK;
     SearchJob j{set->views_dev, set->host_views, set->n_targets, queries, total_q,
-                set->scans_dev, set->header_dev, k, radius, eps, true,
+                set->scans_dev, set->header_dev, k, radius, eps, 1,
                 KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
     return run_search(ctx, j, cfg);
 }

@@ -32,7 +32,8 @@ LKC_ERR_UNSUPPORTED = -6
 LKC_MAX_K = 64
 
 _STATUS_NAMES = {0: "LKC_OK", -1: "LKC_ERR_INVALID_ARG", -2: "LKC_ERR_OOM", -3: "LKC_ERR_HIP",
-                 -4: "LKC_ERR_BUDGET", -5: "LKC_ERR_NONFINITE", -6: "LKC_ERR_UNSUPPORTED"}
+                 -4: "LKC_ERR_BUDGET", -5: "LKC_ERR_NONFINITE", -6: "LKC_ERR_UNSUPPORTED",
+                 -7: "LKC_ERR_DEGENERATE"}
 
 # every symbol include/lkc.h declares
 EXPORTED_SYMBOLS = (
@@ -41,8 +42,12 @@ EXPORTED_SYMBOLS = (
     "lkc_target_get_info", "lkc_target_arrays", "lkc_knn_query", "lkc_covariances",
     "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
     "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve", "lkc_ctx_search_stats",
-    "lkc_ctx_set_timing", "lkc_ctx_set_profile",
+    "lkc_ctx_set_timing", "lkc_ctx_set_profile", "lkc_covariances_weighted",
+    "lkc_knn_cov_weighted", "lkc_gicp_linearize", "lkc_gicp_align",
 )
+
+# neighbour weight kernels of lkc_covariances_weighted / lkc_knn_cov_weighted
+WEIGHT_KERNELS = {"none": 0, "rbf": 1, "gaussian": 2, "laplacian": 3}
 
 
 class LkcError(RuntimeError):
@@ -71,13 +76,24 @@ class TargetInfo(ctypes.Structure):
 class SearchStats(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_int64), ("fallback_queries", ctypes.c_int64),
                 ("sort_ms", ctypes.c_float), ("group_ms", ctypes.c_float),
-                ("fallback_ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("fallback_ms", ctypes.c_float), ("reduce_ms", ctypes.c_float)]
 
 
 class ScanDesc(ctypes.Structure):
     _fields_ = [("q_offset", ctypes.c_int64), ("q_count", ctypes.c_int64),
                 ("target_index", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
+
+class GicpStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("correspondences", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("error", ctypes.c_double), ("last_step", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+GICP_SYSTEM_WORDS = 45
 
 _lib = None
 _lib_lock = threading.Lock()
@@ -119,6 +135,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_ctx_search_stats": ([P, P], I32),
             "lkc_ctx_set_timing": ([P, I32], I32),
             "lkc_ctx_set_profile": ([P, P, I64], I32),
+            "lkc_covariances_weighted": ([P, P, P, P, P, I64, I32, I32, F, F, P, P, P, P], I32),
+            "lkc_knn_cov_weighted": ([P, P, P, I64, I32, F, I32, F, F, P, P, P, P, P, P, P, P],
+                                     I32),
+            "lkc_gicp_linearize": ([P, P, P, P, P, I64, P, F, P, P, P], I32),
+            "lkc_gicp_align": ([P, P, P, P, P, I64, P, F, I32, ctypes.c_double, P,
+                                ctypes.POINTER(GicpStats), P], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -195,7 +217,8 @@ class Context:
         self._bind()
         self.check(self.lib.lkc_ctx_search_stats(self.handle, ctypes.byref(st)))
         return {"queries": st.queries, "fallback_queries": st.fallback_queries,
-                "sort_ms": st.sort_ms, "group_ms": st.group_ms, "fallback_ms": st.fallback_ms}
+                "sort_ms": st.sort_ms, "group_ms": st.group_ms, "fallback_ms": st.fallback_ms,
+                "reduce_ms": st.reduce_ms}
 
     def set_profile(self, buf=None):
         """Per-group counters of the group search into `buf` (device int32
@@ -366,6 +389,125 @@ def lkc_knn_cov(ctx: Context, target: Target, queries, k: int, radius: float = m
         ctypes.c_void_p(_ptr(out.get("cov"))), ctypes.c_void_p(_ptr(out.get("reg"))),
         ctypes.c_void_p(_ptr(out["valid"])), _cfg_ptr(cfg)))
     return out
+
+
+def _weight_kernel(kernel) -> int:
+    if isinstance(kernel, str):
+        return WEIGHT_KERNELS[kernel]
+    return int(kernel)
+
+
+def lkc_covariances_weighted(ctx: Context, target: Target, idx, count, kernel, sigma: float,
+                             queries=None, plane_eps: float = 1e-3, out: Optional[Dict] = None):
+    """Kernel-descriptor weighted mean / covariance; ``kernel`` is a name of
+    ``WEIGHT_KERNELS`` or its code."""
+    torch = _torch()
+    _check_dev(idx, "idx", torch.int32)
+    _check_dev(count, "count", torch.int32)
+    _check_dev(queries, "queries", torch.float32, (3,))
+    q, k = idx.shape
+    out = out or _cov_out(q, idx.device)
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_covariances_weighted(
+        ctx.handle, target.handle, ctypes.c_void_p(_ptr(queries)), ctypes.c_void_p(_ptr(idx)),
+        ctypes.c_void_p(_ptr(count)), q, int(k), _weight_kernel(kernel), float(sigma),
+        float(plane_eps), ctypes.c_void_p(_ptr(out.get("mean"))),
+        ctypes.c_void_p(_ptr(out.get("cov"))), ctypes.c_void_p(_ptr(out.get("reg"))),
+        ctypes.c_void_p(_ptr(out["valid"]))))
+    return out
+
+
+def lkc_knn_cov_weighted(ctx: Context, target: Target, queries, k: int, kernel, sigma: float,
+                         radius: float = math.inf, plane_eps: float = 1e-3,
+                         out: Optional[Dict] = None, cfg=None):
+    torch = _torch()
+    _check_dev(queries, "queries", torch.float32, (3,))
+    q = queries.shape[0]
+    if out is None:
+        out = _cov_out(q, queries.device)
+        out.update(idx=torch.empty(q, k, dtype=torch.int32, device=queries.device),
+                   d2=torch.empty(q, k, dtype=torch.float32, device=queries.device),
+                   count=torch.empty(q, dtype=torch.int32, device=queries.device))
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_knn_cov_weighted(
+        ctx.handle, target.handle, ctypes.c_void_p(_ptr(queries)), q, int(k), float(radius),
+        _weight_kernel(kernel), float(sigma), float(plane_eps),
+        ctypes.c_void_p(_ptr(out["idx"])), ctypes.c_void_p(_ptr(out["d2"])),
+        ctypes.c_void_p(_ptr(out["count"])), ctypes.c_void_p(_ptr(out.get("mean"))),
+        ctypes.c_void_p(_ptr(out.get("cov"))), ctypes.c_void_p(_ptr(out.get("reg"))),
+        ctypes.c_void_p(_ptr(out["valid"])), _cfg_ptr(cfg)))
+    return out
+
+
+def _host_T(T):
+    import numpy as np
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.float64))
+    if T.shape != (4, 4):
+        raise ValueError("T must be a 4x4 transform")
+    return T
+
+
+def lkc_gicp_linearize(ctx: Context, target: Target, target_cov, source, source_cov, T,
+                       max_corr_dist: float = math.inf, corr=None, system=None, cfg=None):
+    """One GICP linearisation at T (host 4x4).  Returns (system, corr) device
+    tensors: system float64 [45] = H (36, row-major), b (6), E, count, rejected."""
+    torch = _torch()
+    _check_dev(target_cov, "target_cov", torch.float32, (3, 3))
+    _check_dev(source, "source", torch.float32, (3,))
+    _check_dev(source_cov, "source_cov", torch.float32, (3, 3))
+    n = source.shape[0]
+    if source_cov.shape[0] != n:
+        raise ValueError("source_cov must have one row per source point")
+    if target_cov.shape[0] != target.info()["n_points"]:
+        raise ValueError("target_cov must have one row per target point")
+    if corr is None:
+        corr = torch.empty(n, dtype=torch.int32, device=source.device)
+    if system is None:
+        system = torch.empty(GICP_SYSTEM_WORDS, dtype=torch.float64, device=source.device)
+    _check_dev(corr, "corr", torch.int32)
+    _check_dev(system, "system", torch.float64)
+    Th = _host_T(T)
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_gicp_linearize(
+        ctx.handle, target.handle, ctypes.c_void_p(_ptr(target_cov)),
+        ctypes.c_void_p(_ptr(source)), ctypes.c_void_p(_ptr(source_cov)), n,
+        Th.ctypes.data_as(ctypes.c_void_p), float(max_corr_dist),
+        ctypes.c_void_p(_ptr(corr)), ctypes.c_void_p(_ptr(system)), _cfg_ptr(cfg)))
+    return system, corr
+
+
+def split_system(system):
+    """Host view of a system vector: dict H [6,6], b [6], E, count, rejected."""
+    import numpy as np
+    v = np.asarray(system.cpu().numpy() if hasattr(system, "cpu") else system, np.float64)
+    return dict(H=v[:36].reshape(6, 6), b=v[36:42], E=float(v[42]), count=int(v[43]),
+                rejected=int(v[44]))
+
+
+def lkc_gicp_align(ctx: Context, target: Target, target_cov, source, source_cov, T_init,
+                   max_corr_dist: float = math.inf, max_iters: int = 30, tol: float = 1e-6,
+                   cfg=None):
+    """Gauss-Newton GICP iterations; returns (T 4x4 numpy, stats dict)."""
+    import numpy as np
+    torch = _torch()
+    _check_dev(target_cov, "target_cov", torch.float32, (3, 3))
+    _check_dev(source, "source", torch.float32, (3,))
+    _check_dev(source_cov, "source_cov", torch.float32, (3, 3))
+    n = source.shape[0]
+    if source_cov.shape[0] != n:
+        raise ValueError("source_cov must have one row per source point")
+    if target_cov.shape[0] != target.info()["n_points"]:
+        raise ValueError("target_cov must have one row per target point")
+    T0 = _host_T(T_init)
+    Tout = np.empty((4, 4))
+    st = GicpStats()
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_gicp_align(
+        ctx.handle, target.handle, ctypes.c_void_p(_ptr(target_cov)),
+        ctypes.c_void_p(_ptr(source)), ctypes.c_void_p(_ptr(source_cov)), n,
+        T0.ctypes.data_as(ctypes.c_void_p), float(max_corr_dist), int(max_iters), float(tol),
+        Tout.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), _cfg_ptr(cfg)))
+    return Tout, st.as_dict()
 
 
 def lkc_knn_cov_self(ctx: Context, target: Target, k: int, radius: float = math.inf,

@@ -9,8 +9,11 @@ counts may differ only by points within ``1e-5 * r^2`` of the radius.
 Where every distance is exact in float32 (integer lattices) the match must be
 exact.
 
-Covariance is compared on the GPU's own neighbour sets (the oracle is run on
-the GPU's idx/count), so kNN near-ties do not leak into it:
+Covariance after a search is compared with the oracle's covariance of the
+oracle's own neighbour set; where the GPU returned a different set (a
+validated float32 near-tie), with the oracle's covariance of the GPU's set.
+Where the neighbour lists are an input of the call they are produced on the
+host (by the oracle) and both sides use them.  Tolerances:
 ``|C_gpu - C_or|_F <= 1e-4 max(|C_or|_F, 1e-10)``,
 ``|mu_gpu - mu_or| <= 1e-5 max(|mu_or|, 1 m)``; the regularised covariance is
 compared at 1e-4 relative Frobenius where the oracle's eigen-gap
@@ -80,10 +83,49 @@ def check_knn(target, queries, k, radius, g_idx, g_d2, g_cnt, rows=None, exact=F
     return near
 
 
-def check_cov(target, g_idx, g_cnt, mean, cov, reg, valid, eps=1e-3, rows=None):
-    """Compare GPU covariance outputs with the oracle run on the GPU's neighbours."""
+def reference_sets(target, g_idx, g_cnt, rows, search):
+    """Neighbour sets the expected covariances are computed on.
+
+    ``search = (queries, k, radius)``: the oracle's own kNN of those rows,
+    except where the GPU returned a different set -- a float32 near-tie that
+    ``check_knn`` has validated -- where the GPU's set is used, so the
+    covariance of the set it did return is still checked.  ``search = None``:
+    the given lists (the neighbour lists were an input of the call, produced
+    on the host)."""
+    if search is None:
+        return g_idx[rows], g_cnt[rows]
+    queries, k, radius = search
+    qs = np.asarray(queries, np.float32).reshape(-1, 3)[rows]
+    o_idx, _, o_cnt = oracle.knn(target, qs, k, radius)
+    gi, gc = g_idx[rows], g_cnt[rows]
+    for r in range(len(rows)):
+        a, b = int(gc[r]), int(o_cnt[r])
+        if a != b or not np.array_equal(np.sort(gi[r, :a]), np.sort(o_idx[r, :b])):
+            o_idx[r], o_cnt[r] = gi[r], gc[r]
+    return o_idx, o_cnt
+
+
+def check_cov_weighted(target, g_idx, g_cnt, mean, cov, reg, valid, kind, sigma, queries=None,
+                       eps=1e-3, rows=None, search=None):
+    """Compare the GPU's kernel-weighted covariance with the oracle's (same
+    tolerances as the plain estimate).  ``queries`` is the origin (None: the
+    first neighbour); ``search`` as in ``reference_sets``."""
     rows = np.arange(g_idx.shape[0]) if rows is None else np.asarray(rows)
-    ref = oracle.covariances(target, g_idx[rows], g_cnt[rows], eps=eps, with_eig=True)
+    q = None if queries is None else np.asarray(queries, np.float32).reshape(-1, 3)[rows]
+    r_idx, r_cnt = reference_sets(target, g_idx, g_cnt, rows, search)
+    ref = oracle.covariances_weighted(target, r_idx, r_cnt, kind, sigma, queries=q, eps=eps)
+    ref["evals"] = np.linalg.eigvalsh(ref["cov"])
+    return check_cov(target, g_idx, g_cnt, mean, cov, reg, valid, eps=eps, rows=rows, ref=ref)
+
+
+def check_cov(target, g_idx, g_cnt, mean, cov, reg, valid, eps=1e-3, rows=None, ref=None,
+              search=None):
+    """Compare GPU covariance outputs with the oracle's on the sets
+    ``reference_sets`` names."""
+    rows = np.arange(g_idx.shape[0]) if rows is None else np.asarray(rows)
+    if ref is None:
+        r_idx, r_cnt = reference_sets(target, g_idx, g_cnt, rows, search)
+        ref = oracle.covariances(target, r_idx, r_cnt, eps=eps, with_eig=True)
     assert np.array_equal(valid[rows], ref["valid"]), "valid differs"
     C = cov[rows].astype(np.float64)
     err = np.linalg.norm(C - ref["cov"], axis=(1, 2))

@@ -10,6 +10,7 @@ import math
 import numpy as np
 import pytest
 
+from oracle import oracle
 from paper_2308_07173_amd import workloads
 from tests import parity
 
@@ -226,7 +227,7 @@ def test_self_query_matches_plain_and_oracle(lk):
         rows = np.arange(pts.shape[0])[:: max(1, pts.shape[0] // 2000)]
         parity.check_knn(pts, pts, k, radius, o["idx"], o["d2"], o["count"], rows=rows)
         parity.check_cov(pts, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"],
-                         rows=rows)
+                         rows=rows, search=(pts, k, radius))
         t.free()
 
 
@@ -240,7 +241,8 @@ def test_cov_tiny_config_against_oracle(lk):
     torch.cuda.synchronize()
     o = {k: host(v) for k, v in out.items()}
     parity.check_knn(p, p, 10, INF, o["idx"], o["d2"], o["count"])
-    parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"])
+    parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"],
+                     search=(p, 10, INF))
     t.free()
 
 
@@ -283,10 +285,12 @@ def test_cov_null_queries_and_bad_indices(lk):
     lkc, ctx = lk
     p = workloads.random_cloud(500, 5, scale=2.0, offset=(50.0, 0.0, 0.0))
     t = lkc.lkc_build_target(ctx, dev(p), 0.5)
-    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(p), 8)
+    # neighbour lists produced on the host are the input of the call
+    o_idx, _, o_cnt = oracle.knn(p, p, 8)
+    idx, cnt = dev(o_idx), dev(o_cnt)
     out = lkc.lkc_covariances(ctx, t, idx, cnt, queries=None)
     o = {k: host(v) for k, v in out.items()}
-    parity.check_cov(p, host(idx), host(cnt), o["mean"], o["cov"], o["reg"], o["valid"])
+    parity.check_cov(p, o_idx, o_cnt, o["mean"], o["cov"], o["reg"], o["valid"])
     # an out-of-range index ends the list at that position
     bad = idx.clone()
     bad[0, 4] = 10_000
@@ -295,7 +299,7 @@ def test_cov_null_queries_and_bad_indices(lk):
     o = {k: host(v) for k, v in out.items()}
     cut = host(cnt).copy()
     cut[0], cut[1] = 4, 0
-    parity.check_cov(p, host(idx), cut, o["mean"], o["cov"], o["reg"], o["valid"], rows=[0, 1])
+    parity.check_cov(p, o_idx, cut, o["mean"], o["cov"], o["reg"], o["valid"], rows=[0, 1])
     t.free()
 
 
@@ -318,7 +322,7 @@ def test_scan_config_sampled_parity(lk, scan_c2):
     rows = np.concatenate([rows, [0, p.shape[0] - 1]])
     parity.check_knn(p, p, 20, 2.0, o["idx"], o["d2"], o["count"], rows=rows)
     parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"],
-                     rows=rows)
+                     rows=rows, search=(p, 20, 2.0))
     # properties on every query: self first, ascending, within radius, in range
     assert np.all(o["idx"][:, 0] == np.arange(p.shape[0]))
     assert np.all(o["count"] >= 1) and np.all(o["count"] <= 20)
@@ -347,7 +351,8 @@ def test_scan_to_map_sampled_parity(lk, map_c3):
     o = {k: host(v) for k, v in out.items()}
     rows = np.sort(np.random.default_rng(12).choice(s.shape[0], 400, replace=False))
     parity.check_knn(m, s, 20, 2.0, o["idx"], o["d2"], o["count"], rows=rows)
-    parity.check_cov(m, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"])
+    parity.check_cov(m, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"],
+                     rows=rows, search=(s, 20, 2.0))
     t.free()
 
 
