@@ -604,3 +604,97 @@ int oracle_gicp_linearize(const float *src, const float *src_cov, int64_t n, con
     *count = used;
     return 0;
 }
+
+/* ------------------------------------------ voxel filter and submap window --- */
+
+/* Voxel downsampling, as the paper applies to the map and to the scans
+ * (Sec. III-D.1 "voxel-filtered LiDAR points"; leaf sizes in Sec. IV).  The
+ * voxel of p is floor((p - o) / leaf) per axis, evaluated in float32 (IEEE
+ * subtraction, correctly rounded division): the integer decision is taken
+ * in the kernel's precision.  Each occupied voxel yields one point, the
+ * FP64 mean of its points; voxels are listed by (vz, vy, vx) ascending.
+ * Points with a non-finite coordinate are dropped.  Returns the number of
+ * voxels, or -1 when a voxel coordinate falls outside [-2^20, 2^20). */
+typedef struct {
+    int64_t v[3];
+    int64_t i;
+} vox_rec;
+
+static int vox_cmp(const void *a, const void *b)
+{
+    const vox_rec *x = (const vox_rec *)a, *y = (const vox_rec *)b;
+    for (int d = 2; d >= 0; --d) {
+        if (x->v[d] != y->v[d])
+            return x->v[d] < y->v[d] ? -1 : 1;
+    }
+    return x->i < y->i ? -1 : (x->i > y->i);
+}
+
+int64_t oracle_voxel_filter(const float *pts, int64_t n, const float *origin, float leaf,
+                            int64_t *vox, double *centroid, int32_t *count)
+{
+    if (n < 0 || !(leaf > 0.0f))
+        return -1;
+    vox_rec *r = (vox_rec *)malloc(sizeof(vox_rec) * (size_t)(n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const float *p = pts + 3 * i;
+        if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2]))
+            continue;
+        for (int d = 0; d < 3; ++d) {
+            const float q = (p[d] - origin[d]) / leaf;   /* float32 IEEE */
+            const double f = floor((double)q);
+            if (!(f >= -1048576.0 && f < 1048576.0)) {
+                free(r);
+                return -1;
+            }
+            r[m].v[d] = (int64_t)f;
+        }
+        r[m].i = i;
+        ++m;
+    }
+    qsort(r, (size_t)m, sizeof(vox_rec), vox_cmp);
+    int64_t out = 0;
+    for (int64_t a = 0; a < m;) {
+        int64_t b = a;
+        double s[3] = {0.0, 0.0, 0.0};
+        while (b < m && r[b].v[0] == r[a].v[0] && r[b].v[1] == r[a].v[1] &&
+               r[b].v[2] == r[a].v[2]) {
+            for (int d = 0; d < 3; ++d)
+                s[d] += (double)pts[3 * r[b].i + d];
+            ++b;
+        }
+        for (int d = 0; d < 3; ++d) {
+            vox[3 * out + d] = r[a].v[d];
+            centroid[3 * out + d] = s[d] / (double)(b - a);
+        }
+        count[out] = (int32_t)(b - a);
+        ++out;
+        a = b;
+    }
+    free(r);
+    return out;
+}
+
+/* Sliding-window submap (Sec. III-C.3: only the map points near the current
+ * race-line pose are queried): the indices of the points within `radius` of
+ * `center`, inclusive, ascending.  The decision d2 <= radius^2 is taken in
+ * float32 in the kernel's order, d2 = fma(dz, dz, fma(dy, dy, dx * dx)) with
+ * d = p - center.  Returns the count. */
+int64_t oracle_submap(const float *pts, int64_t n, const float *center, float radius,
+                      int32_t *out)
+{
+    if (n < 0 || !(radius > 0.0f))
+        return -1;
+    const float r2 = radius * radius;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const float dx = pts[3 * i] - center[0];
+        const float dy = pts[3 * i + 1] - center[1];
+        const float dz = pts[3 * i + 2] - center[2];
+        const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if (d2 <= r2)
+            out[m++] = (int32_t)i;
+    }
+    return m;
+}

@@ -66,6 +66,11 @@ def configure(lib):
                                                     ctypes.c_double, ctypes.c_double,
                                                     P, P, P, P]
         lib.oracle_covariances_weighted.restype = ctypes.c_int
+    if hasattr(lib, "oracle_voxel_filter"):
+        lib.oracle_voxel_filter.argtypes = [P, ctypes.c_int64, P, ctypes.c_float, P, P, P]
+        lib.oracle_voxel_filter.restype = ctypes.c_int64
+        lib.oracle_submap.argtypes = [P, ctypes.c_int64, P, ctypes.c_float, P]
+        lib.oracle_submap.restype = ctypes.c_int64
     if hasattr(lib, "oracle_gicp_linearize"):
         lib.oracle_gicp_correspond.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P,
                                                ctypes.c_double, ctypes.c_int32, P, P]
@@ -206,6 +211,34 @@ def gicp_linearize(source, source_cov, target, target_cov, T, corr):
     if rc != 0:
         raise ValueError("oracle_gicp_linearize: bad correspondence or covariance")
     return dict(H=H, b=b, E=float(E[0]), count=int(cnt[0]))
+
+
+def voxel_filter(points, leaf: float, origin=(0.0, 0.0, 0.0)):
+    """Voxel centroids (FP64), voxel coordinates (int64) and counts, voxels
+    ordered by (vz, vy, vx)."""
+    p = _f32(points)
+    n = p.shape[0]
+    o = np.ascontiguousarray(origin, np.float32)
+    vox = np.empty((max(n, 1), 3), np.int64)
+    cen = np.empty((max(n, 1), 3))
+    cnt = np.empty(max(n, 1), np.int32)
+    m = _load().oracle_voxel_filter(_ptr(p), n, _ptr(o), float(np.float32(leaf)), _ptr(vox),
+                                    _ptr(cen), _ptr(cnt))
+    if m < 0:
+        raise ValueError("oracle_voxel_filter: invalid leaf or voxel coordinate out of range")
+    return dict(voxel=vox[:m], centroid=cen[:m], count=cnt[:m])
+
+
+def submap(points, center, radius: float):
+    """Ascending indices of the points within radius of center (float32 decision)."""
+    p = _f32(points)
+    c = np.ascontiguousarray(center, np.float32)
+    out = np.empty(max(p.shape[0], 1), np.int32)
+    m = _load().oracle_submap(_ptr(p), p.shape[0], _ptr(c), float(np.float32(radius)),
+                              _ptr(out))
+    if m < 0:
+        raise ValueError("oracle_submap: invalid radius")
+    return out[:m]
 
 
 def sym3_eig(a):

@@ -21,6 +21,7 @@ from oracle import oracle
 from tests import test_oracle as pins
 from tests import test_oracle_weighted as wpins
 from tests import test_oracle_gicp as gpins
+from tests import test_oracle_voxel as vpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lkc_oracle.c")
 
@@ -89,6 +90,21 @@ GICP_MUTATIONS = {
 
 GICP_PINS = [getattr(gpins, n) for n in dir(gpins) if n.startswith("test_")]
 
+# planted mistakes in the voxel filter and the submap window
+VOXEL_MUTATIONS = {
+    "voxel_order_x_first": ("for (int d = 2; d >= 0; --d) {\n        if (x->v[d] != y->v[d])",
+                            "for (int d = 0; d < 3; ++d) {\n        if (x->v[d] != y->v[d])"),
+    "voxel_trunc": ("const double f = floor((double)q);", "const double f = trunc((double)q);"),
+    "voxel_mean_divisor": ("s[d] / (double)(b - a);", "s[d] / (double)(b - a + 1);"),
+    "voxel_reciprocal": ("const float q = (p[d] - origin[d]) / leaf;",
+                         "const float q = (p[d] - origin[d]) * (1.0f / leaf);"),
+    "submap_exclusive": ("if (d2 <= r2)\n            out[m++]", "if (d2 < r2)\n            out[m++]"),
+    "submap_dropped_z": ("const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));",
+                         "const float d2 = fmaf(dy, dy, dx * dx);"),
+}
+
+VOXEL_PINS = [getattr(vpins, n) for n in dir(vpins) if n.startswith("test_")]
+
 
 def _call(pin):
     marks = getattr(pin, "pytestmark", [])
@@ -101,11 +117,12 @@ def _call(pin):
 
 
 def test_unmutated_source_passes_the_pins():
-    for pin in PINS + WEIGHTED_PINS + GICP_PINS:
+    for pin in PINS + WEIGHTED_PINS + GICP_PINS + VOXEL_PINS:
         _call(pin)
 
 
-GROUPS = [(MUTATIONS, PINS), (WEIGHTED_MUTATIONS, WEIGHTED_PINS), (GICP_MUTATIONS, GICP_PINS)]
+GROUPS = [(MUTATIONS, PINS), (WEIGHTED_MUTATIONS, WEIGHTED_PINS), (GICP_MUTATIONS, GICP_PINS),
+          (VOXEL_MUTATIONS, VOXEL_PINS)]
 
 
 @pytest.mark.parametrize("name", [n for muts, _ in GROUPS for n in sorted(muts)])
