@@ -17,6 +17,9 @@
  *                       the same with kernel-descriptor neighbour weights
  *   lkc_gicp_linearize / lkc_gicp_align
  *                       GICP correspondences, Gauss-Newton system, iterations
+ *   lkc_voxel_filter    voxel centroids of a cloud
+ *   lkc_submap_extract / lkc_submap_build
+ *                       the map points within a radius of a pose
  *   lkc_knn_cov_batched many scans against several targets in one persistent
  *                       launch (graph-capturable)
  *
@@ -286,6 +289,41 @@ lkc_status lkc_gicp_align(lkc_ctx *ctx, const lkc_target *target, const float *t
                           double tol, double *T_out, lkc_gicp_stats *stats,
                           const lkc_launch_cfg *cfg);
 
+/* ---- Voxel filter and sliding-window submap (the steps before the path).
+ *
+ * Voxel filter (the paper voxel-filters scans and maps, Sec. III-D.1 and
+ * Sec. IV): voxel(p) = floor((p - origin) / leaf) per axis, evaluated in
+ * float32 (IEEE subtraction, correctly rounded division).  One output point
+ * per occupied voxel: the mean of its points (summed in FP64 in ascending
+ * point order, rounded to float32).  Voxels are listed in (vz, vy, vx)
+ * ascending order.  Points with a non-finite coordinate are dropped.
+ * points: device float [n][3]; origin: host float [3] (NULL = 0).
+ * Outputs (device, capacity rows): centroid float [.][3], count int32 [.]
+ * (may be NULL), voxel int32 [.][3] (may be NULL); *n_out (host) receives
+ * the number of voxels.  LKC_ERR_BUDGET (nothing written) when it exceeds
+ * capacity; LKC_ERR_INVALID_ARG when a voxel coordinate falls outside
+ * [-2^20, 2^20).  Synchronises twice (key width, voxel count). */
+lkc_status lkc_voxel_filter(lkc_ctx *ctx, const float *points, int64_t n, const float *origin,
+                            float leaf, float *centroid, int32_t *count, int32_t *voxel,
+                            int64_t capacity, int64_t *n_out);
+
+/* Sliding-window submap (Sec. III-C.3: only the map points near the
+ * current race-line pose are queried): the original indices of the points
+ * of `map` within `radius` of `center` (host float [3]), inclusive, with
+ * d2 = fma(dz, dz, fma(dy, dy, dx * dx)) in float32, ascending.  idx:
+ * device int32 [capacity]; *n_out (host) receives the count;
+ * LKC_ERR_BUDGET when it exceeds capacity.  Synchronises once. */
+lkc_status lkc_submap_extract(lkc_ctx *ctx, const lkc_target *map, const float *center,
+                              float radius, int32_t *idx, int64_t capacity, int64_t *n_out);
+
+/* The window's points (in ascending map order) built into a new target
+ * with the map's cell size; target index j is the window's j-th point, and
+ * idx (device int32 [capacity], may be NULL) receives its map index.
+ * Synchronises. */
+lkc_status lkc_submap_build(lkc_ctx *ctx, const lkc_target *map, const float *center,
+                            float radius, int32_t *idx, int64_t capacity, int64_t *n_out,
+                            lkc_target **out);
+
 /* A set of targets addressable by the batched call.  Creating a set uploads
  * one small descriptor per target and sizes the set's scan table for at
  * most `max_scans` scans (host array of target pointers).  The targets must
@@ -351,12 +389,13 @@ lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
  * events are not captured-graph safe, so keep timing off under capture. */
 lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
 
-/* Diagnostics: when `buffer` (device, 8 uint32 per group) holds at least
+/* Diagnostics: when `buffer` (device, 10 uint32 per group) holds at least
  * the number of 64-query groups of a search, the group search writes per
  * group: clock cycles, probe rounds, cells streamed, 64-point chunks
- * loaded, candidates tested, insertion steps, member lanes and lanes handed
- * to the fallback search.  n_groups = 0 turns it off.  The caller owns the
- * buffer. */
+ * loaded, candidates tested, insertion steps, member lanes, lanes handed
+ * to the fallback search, insertions summed over the lanes, and insertion
+ * steps in which no lane inserted.  n_groups = 0 turns it off.  The caller
+ * owns the buffer. */
 lkc_status lkc_ctx_set_profile(lkc_ctx *ctx, void *buffer, int64_t n_groups);
 
 /* Grow the context's search scratch (query sort buffers and the fallback

@@ -111,6 +111,7 @@ lkc_status lkc_ctx_destroy(lkc_ctx* ctx) {
     if (ctx->build_scratch) (void)hipFree(ctx->build_scratch);
     if (ctx->search_scratch) (void)hipFree(ctx->search_scratch);
     if (ctx->gicp_scratch) (void)hipFree(ctx->gicp_scratch);
+    if (ctx->aux_scratch) (void)hipFree(ctx->aux_scratch);
     if (ctx->gicp_host) (void)hipHostFree(ctx->gicp_host);
     if (ctx->meta_dev) (void)hipFree(ctx->meta_dev);
     if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
@@ -372,6 +373,77 @@ lkc_status lkc_gicp_align(lkc_ctx* ctx, const lkc_target* t, const float* tcov,
     if ((s = lkc::check_launch_cfg(ctx, c)) != LKC_OK) return s;
     return lkc::gicp_align(ctx, t, tcov, src, scov, n, T_init, max_corr_dist, max_iters, tol,
                            T_out, stats, c);
+}
+
+lkc_status lkc_voxel_filter(lkc_ctx* ctx, const float* points, int64_t n, const float* origin,
+                            float leaf, float* centroid, int32_t* count, int32_t* voxel,
+                            int64_t capacity, int64_t* n_out) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!n_out) return set_error(ctx, LKC_ERR_INVALID_ARG, "n_out is NULL");
+    *n_out = 0;
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (!(leaf > 0.0f) || !std::isfinite(leaf))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "leaf must be finite and > 0");
+    const float zero[3] = {0.0f, 0.0f, 0.0f};
+    const float* o = origin ? origin : zero;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(o[d])) return set_error(ctx, LKC_ERR_INVALID_ARG, "origin not finite");
+    if (capacity < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "capacity < 0");
+    if (n > 0 && (!points || (capacity > 0 && !centroid)))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL points or centroid pointer");
+    return lkc::voxel_filter(ctx, points, n, o, leaf, centroid, count, voxel, capacity, n_out);
+}
+
+namespace {
+
+lkc_status check_window(lkc_ctx* ctx, const lkc_target* map, const float* center, float radius,
+                        int64_t capacity, int64_t* n_out) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, map)) != LKC_OK) return s;
+    if (!n_out) return set_error(ctx, LKC_ERR_INVALID_ARG, "n_out is NULL");
+    *n_out = 0;
+    if (!center) return set_error(ctx, LKC_ERR_INVALID_ARG, "center is NULL");
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(center[d]))
+            return set_error(ctx, LKC_ERR_INVALID_ARG, "center not finite");
+    if (!(radius > 0.0f) || !std::isfinite(radius * radius))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "radius must be finite and > 0");
+    if (capacity < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "capacity < 0");
+    return LKC_OK;
+}
+
+}  // namespace
+
+lkc_status lkc_submap_extract(lkc_ctx* ctx, const lkc_target* map, const float* center,
+                              float radius, int32_t* idx, int64_t capacity, int64_t* n_out) {
+    lkc_status s = check_window(ctx, map, center, radius, capacity, n_out);
+    if (s != LKC_OK) return s;
+    if (capacity > 0 && !idx) return set_error(ctx, LKC_ERR_INVALID_ARG, "idx is NULL");
+    return lkc::submap_extract(ctx, map, center, radius, idx, nullptr, capacity, n_out);
+}
+
+lkc_status lkc_submap_build(lkc_ctx* ctx, const lkc_target* map, const float* center,
+                            float radius, int32_t* idx, int64_t capacity, int64_t* n_out,
+                            lkc_target** out) {
+    lkc_status s = check_window(ctx, map, center, radius, capacity, n_out);
+    if (s != LKC_OK) return s;
+    if (!out) return set_error(ctx, LKC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    lkc_target* t = new (std::nothrow) lkc_target();
+    if (!t) return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    t->cell_size = map->cell_size;
+    s = lkc::submap_build(ctx, map, center, radius, idx, idx ? capacity : 0, n_out, t);
+    if (s != LKC_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        lkc::free_target_memory(t);
+        delete t;
+        return s;
+    }
+    *out = t;
+    return LKC_OK;
 }
 
 lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,

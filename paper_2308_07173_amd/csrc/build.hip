@@ -501,6 +501,10 @@ static void scan_exclusive(hipStream_t st, uint32_t* data, int64_t m, uint32_t* 
                        (const uint32_t*)tmp);
 }
 
+void scan_words(hipStream_t st, uint32_t* data, int64_t m, uint32_t* tmp) {
+    scan_exclusive(st, data, m, tmp);
+}
+
 size_t sort_count_words(int64_t n) {
     const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
     const size_t m = (size_t)RADIX * (size_t)(nb > 0 ? nb : 1);

@@ -39,6 +39,9 @@ struct lkc_ctx {
     void* gicp_scratch = nullptr;
     size_t gicp_scratch_bytes = 0;
     void* gicp_host = nullptr;
+    // grow-only device scratch of the voxel filter and the submap window
+    void* aux_scratch = nullptr;
+    size_t aux_scratch_bytes = 0;
 };
 
 struct lkc_target {
@@ -96,6 +99,18 @@ size_t sort_count_words(int64_t n);
 // *in_b tells whether the result ended in the b buffers
 lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsigned long long* kb,
                       uint32_t* vb, int64_t n, int bits, uint32_t* counts, bool* in_b);
+
+// exclusive prefix sum of m words in place; tmp holds ceil(m / 4096) + 1 words
+void scan_words(hipStream_t st, uint32_t* data, int64_t m, uint32_t* tmp);
+
+// implemented in voxel.hip
+lkc_status voxel_filter(lkc_ctx* ctx, const float* pts, int64_t n, const float* origin,
+                        float leaf, float* centroid, int32_t* count, int32_t* voxel, int64_t cap,
+                        int64_t* n_out);
+lkc_status submap_extract(lkc_ctx* ctx, const lkc_target* t, const float* center, float radius,
+                          int32_t* idx, float* gathered, int64_t cap, int64_t* n_out);
+lkc_status submap_build(lkc_ctx* ctx, const lkc_target* map, const float* center, float radius,
+                        int32_t* idx, int64_t cap, int64_t* n_out, lkc_target* out);
 
 // implemented in search.hip
 struct LaunchCfg {

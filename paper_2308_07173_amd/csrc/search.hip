@@ -598,10 +598,10 @@ struct GroupArgs {
 
 // per-group profile words: clock cycles, probe rounds, cells streamed,
 // 64-point chunks loaded, candidates tested, insertion pops, member lanes,
-// fallback lanes
-constexpr int PROF_WORDS = 8;
+// fallback lanes, insertions (over all lanes), pops in which no lane inserted
+constexpr int PROF_WORDS = 10;
 struct GroupProf {
-    uint32_t probes, cells, chunks, cands, pops;
+    uint32_t probes, cells, chunks, cands, pops, inserts, dead;
 };
 
 struct SlotQuery {
@@ -650,7 +650,9 @@ __device__ __forceinline__ float box_box_dist2(const float (&a0)[3], const float
 // sets a bit per passing candidate; the insertions follow as "pops" in which
 // every lane inserts its own next passing candidate, so a chunk costs as
 // many insertion steps as its busiest lane needs rather than one per
-// candidate that any lane wants.
+// candidate that any lane wants.  The test compares float d2 with the
+// lane's k-th distance (the radius while its list is not full), so exact
+// ties pass it; the pop makes the exact (d2, index) comparison.
 template <int K>
 __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bool member,
                                          float qx, float qy, float qz, float r2,
@@ -686,33 +688,44 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         if (!keep) continue;
         gp.chunks++;
         const float4 c = T.pts[cb + lane];   // padded: reads past n stay in bounds
-        unsigned long long bits = 0;
+        // non-members never pass (d2 >= 0)
+        const float tthr = member ? lthr : -1.0f;
+        uint32_t blo = 0, bhi = 0;
         const int lo = max(s0, cb) - cb, hi = min(e0, cb + WAVE) - cb;
 #pragma unroll 1
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
             if (!((keep >> q4) & 1u)) continue;
             const int t1 = min(hi, (q4 + 1) * BOX_PTS);
             gp.cands += (uint32_t)max(0, t1 - max(lo, q4 * BOX_PTS));
+            uint32_t b = 0;
 #pragma unroll 2
             for (int t = max(lo, q4 * BOX_PTS); t < t1; ++t) {
                 const float cx = readlane(c.x, t), cy = readlane(c.y, t), cz = readlane(c.z, t);
-                const int32_t ci = readlane(__float_as_int(c.w), t);
                 const float d = dist2(qx, qy, qz, cx, cy, cz);
-                const bool pass = member && d <= r2 && lane_key(d, ci) < kk[K - 1];
-                bits |= pass ? (1ull << t) : 0ull;
+                b |= d <= tthr ? (1u << (t & 31)) : 0u;
             }
+            if (q4 < 2)
+                blo |= b;
+            else
+                bhi |= b;
         }
+        unsigned long long bits = ((unsigned long long)bhi << 32) | blo;
         if (!ballot(bits != 0ull)) continue;
         do {
             gp.pops++;
             const int j = bits ? __builtin_ffsll((long long)bits) - 1 : 0;
             const float cx = shfl(c.x, j), cy = shfl(c.y, j), cz = shfl(c.z, j);
             const int32_t ci = shfl(__float_as_int(c.w), j);
+            bool ins = false;
             if (bits) {
                 bits &= bits - 1;
                 const unsigned long long key = lane_key(dist2(qx, qy, qz, cx, cy, cz), ci);
-                if (key < kk[K - 1]) lane_insert<K>(kk, key);
+                ins = key < kk[K - 1];
+                if (ins) lane_insert<K>(kk, key);
             }
+            const unsigned long long im = ballot(ins);
+            gp.inserts += (uint32_t)__popcll(im);
+            gp.dead += im ? 0u : 1u;
         } while (ballot(bits != 0ull));
         gthr = wave_max_dpp(member ? (kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1])) : -INF);
     }
@@ -749,7 +762,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
     for (int j = 0; j < K; ++j) kk[j] = (j < pad) ? 0ull : ~0ull;
     const unsigned long long mm = ballot(member);
     bool ok = true;
-    GroupProf gp{0, 0, 0, 0, 0};
+    GroupProf gp{0, 0, 0, 0, 0, 0, 0};
     const unsigned long long t_start = a.prof ? __builtin_amdgcn_s_memtime() : 0ull;
     if (mm && T.n_cells > 0) {
         const float bx0 = wave_min_dpp(member ? s.x : INF), bx1 = wave_max_dpp(member ? s.x : -INF);
@@ -837,6 +850,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
         pw[5] = gp.pops;
         pw[6] = (uint32_t)__popcll(mm);
         pw[7] = (uint32_t)__popcll(fm);
+        pw[8] = gp.inserts;
+        pw[9] = gp.dead;
     }
     if (fm) {
         const int leader = __builtin_ffsll((long long)fm) - 1;

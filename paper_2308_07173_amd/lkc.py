@@ -43,7 +43,8 @@ EXPORTED_SYMBOLS = (
     "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
     "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve", "lkc_ctx_search_stats",
     "lkc_ctx_set_timing", "lkc_ctx_set_profile", "lkc_covariances_weighted",
-    "lkc_knn_cov_weighted", "lkc_gicp_linearize", "lkc_gicp_align",
+    "lkc_knn_cov_weighted", "lkc_gicp_linearize", "lkc_gicp_align", "lkc_voxel_filter",
+    "lkc_submap_extract", "lkc_submap_build",
 )
 
 # neighbour weight kernels of lkc_covariances_weighted / lkc_knn_cov_weighted
@@ -141,6 +142,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_gicp_linearize": ([P, P, P, P, P, I64, P, F, P, P, P], I32),
             "lkc_gicp_align": ([P, P, P, P, P, I64, P, F, I32, ctypes.c_double, P,
                                 ctypes.POINTER(GicpStats), P], I32),
+            "lkc_voxel_filter": ([P, P, I64, P, F, P, P, P, I64, ctypes.POINTER(ctypes.c_int64)],
+                                 I32),
+            "lkc_submap_extract": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64)], I32),
+            "lkc_submap_build": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64), PP], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -222,7 +227,7 @@ class Context:
 
     def set_profile(self, buf=None):
         """Per-group counters of the group search into `buf` (device int32
-        tensor [groups, 8]) or off (None)."""
+        tensor [groups, 10]) or off (None)."""
         if buf is None:
             self.check(self.lib.lkc_ctx_set_profile(self.handle, None, 0))
         else:
@@ -508,6 +513,65 @@ def lkc_gicp_align(ctx: Context, target: Target, target_cov, source, source_cov,
         T0.ctypes.data_as(ctypes.c_void_p), float(max_corr_dist), int(max_iters), float(tol),
         Tout.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), _cfg_ptr(cfg)))
     return Tout, st.as_dict()
+
+
+def lkc_voxel_filter(ctx: Context, points, leaf: float, origin=None, capacity=None):
+    """Voxel centroids of a device cloud.  Returns dict centroid float32
+    [m, 3], count int32 [m], voxel int32 [m, 3] (device tensors)."""
+    import numpy as np
+    torch = _torch()
+    _check_dev(points, "points", torch.float32, (3,))
+    n = points.shape[0]
+    cap = n if capacity is None else int(capacity)
+    dev = points.device
+    cen = torch.empty(max(cap, 1), 3, dtype=torch.float32, device=dev)
+    cnt = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    vox = torch.empty(max(cap, 1), 3, dtype=torch.int32, device=dev)
+    o = None if origin is None else np.ascontiguousarray(origin, np.float32)
+    m = ctypes.c_int64(0)
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_voxel_filter(
+        ctx.handle, ctypes.c_void_p(_ptr(points)), n,
+        None if o is None else o.ctypes.data_as(ctypes.c_void_p), float(leaf),
+        ctypes.c_void_p(_ptr(cen)), ctypes.c_void_p(_ptr(cnt)), ctypes.c_void_p(_ptr(vox)), cap,
+        ctypes.byref(m)))
+    k = m.value
+    return dict(centroid=cen[:k], count=cnt[:k], voxel=vox[:k])
+
+
+def lkc_submap_extract(ctx: Context, target: Target, center, radius: float, capacity=None):
+    """Ascending indices (device int32) of the target points within radius of center."""
+    import numpy as np
+    torch = _torch()
+    n = target.info()["n_points"]
+    cap = n if capacity is None else int(capacity)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    c = np.ascontiguousarray(center, np.float32)
+    m = ctypes.c_int64(0)
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_submap_extract(ctx.handle, target.handle,
+                                         c.ctypes.data_as(ctypes.c_void_p), float(radius),
+                                         ctypes.c_void_p(_ptr(idx)), cap, ctypes.byref(m)))
+    return idx[:m.value]
+
+
+def lkc_submap_build(ctx: Context, target: Target, center, radius: float, with_idx: bool = True):
+    """Build the window around center into a new Target; returns (Target, idx)."""
+    import numpy as np
+    torch = _torch()
+    n = target.info()["n_points"]
+    dev = torch.device("cuda", torch.cuda.current_device())
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if with_idx else None
+    c = np.ascontiguousarray(center, np.float32)
+    m = ctypes.c_int64(0)
+    h = ctypes.c_void_p()
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_submap_build(ctx.handle, target.handle,
+                                       c.ctypes.data_as(ctypes.c_void_p), float(radius),
+                                       ctypes.c_void_p(_ptr(idx)), n if with_idx else 0,
+                                       ctypes.byref(m), ctypes.byref(h)))
+    return Target(ctx, h), (idx[:m.value] if with_idx else None)
 
 
 def lkc_knn_cov_self(ctx: Context, target: Target, k: int, radius: float = math.inf,

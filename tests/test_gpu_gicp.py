@@ -132,8 +132,9 @@ def test_linearize_is_deterministic_and_corr_optional(lk):
     sc, tc = random_spd(50_000, 7), random_spd(30_000, 8)
     t = lkc.lkc_build_target(ctx, dev(tgt), 1.0)
     T = rigid(0.05, 0.02, -0.1, [0.3, 0.2, -0.1])
-    a, ca = lkc.lkc_gicp_linearize(ctx, t, dev(tc), dev(src), dev(sc), T, 1.0)
-    b, cb = lkc.lkc_gicp_linearize(ctx, t, dev(tc), dev(src), dev(sc), T, 1.0)
+    tc_d, src_d, sc_d = dev(tc), dev(src), dev(sc)     # kept alive across the raw call
+    a, ca = lkc.lkc_gicp_linearize(ctx, t, tc_d, src_d, sc_d, T, 1.0)
+    b, cb = lkc.lkc_gicp_linearize(ctx, t, tc_d, src_d, sc_d, T, 1.0)
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(ca, cb)
     # without a corr output the library uses its own scratch
@@ -142,8 +143,8 @@ def test_linearize_is_deterministic_and_corr_optional(lk):
     tch = np.ascontiguousarray(T)
     import ctypes
     ctx.check(ctx.lib.lkc_gicp_linearize(
-        ctx.handle, t.handle, ctypes.c_void_p(dev(tc).data_ptr()), ctypes.c_void_p(
-            dev(src).data_ptr()), ctypes.c_void_p(dev(sc).data_ptr()), 50_000,
+        ctx.handle, t.handle, ctypes.c_void_p(tc_d.data_ptr()), ctypes.c_void_p(
+            src_d.data_ptr()), ctypes.c_void_p(sc_d.data_ptr()), 50_000,
         tch.ctypes.data_as(ctypes.c_void_p), 1.0, None, ctypes.c_void_p(system.data_ptr()),
         None))
     torch.cuda.synchronize()

@@ -1,0 +1,134 @@
+"""GPU parity of the voxel filter and the sliding-window submap, through the
+C ABI.
+
+Voxel filter: the voxel decision is taken in float32 on both sides, so the
+voxel set, order and counts must match the oracle exactly; the GPU sums
+each voxel in FP64 in the oracle's order, so every centroid must equal the
+float32 rounding of the oracle's FP64 mean, bit for bit.  Submap: the
+decision is float32 in the same operation order on both sides, so the index
+list must match exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2308_07173_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_07173_amd import lkc
+    ctx = lkc.Context()
+    yield lkc, ctx
+    ctx.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def check_voxels(p, leaf, origin, out):
+    ref = oracle.voxel_filter(p, leaf, origin=origin if origin is not None else (0, 0, 0))
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    assert g["count"].shape[0] == ref["count"].shape[0]
+    np.testing.assert_array_equal(g["voxel"], ref["voxel"])
+    np.testing.assert_array_equal(g["count"], ref["count"])
+    np.testing.assert_array_equal(g["centroid"], ref["centroid"].astype(np.float32))
+
+
+@pytest.mark.parametrize("n,leaf,seed", [(1, 0.5, 0), (777, 0.25, 1), (100_003, 0.2, 2),
+                                         (300_000, 1.0, 3)])
+def test_voxel_filter_random(lk, n, leaf, seed):
+    lkc, ctx = lk
+    p = workloads.random_cloud(n, seed, scale=15.0, offset=(120.0, -40.0, 3.0))
+    out = lkc.lkc_voxel_filter(ctx, dev(p), leaf)
+    check_voxels(p, leaf, None, out)
+
+
+def test_voxel_filter_scan_origin_and_nonfinite(lk):
+    lkc, ctx = lk
+    p = workloads.single_scan(seed=5).copy()
+    p[::101, 2] = np.inf
+    p[::103, 0] = np.nan
+    origin = (0.05, -0.1, 0.02)
+    out = lkc.lkc_voxel_filter(ctx, dev(p), 0.2, origin=origin)
+    check_voxels(p, 0.2, origin, out)
+
+
+def test_voxel_filter_boundaries_exact(lk):
+    """Points on voxel faces and one ulp below them."""
+    lkc, ctx = lk
+    g = np.arange(-20, 20, dtype=np.float32) * np.float32(0.25)
+    below = np.nextafter(g, np.float32(-np.inf))
+    x = np.concatenate([g, below])
+    p = np.stack(np.meshgrid(x, x[:17], x[:9], indexing="ij"), -1).reshape(-1, 3)
+    out = lkc.lkc_voxel_filter(ctx, dev(p), 0.25)
+    check_voxels(p, 0.25, None, out)
+
+
+def test_voxel_filter_budget_and_errors(lk):
+    lkc, ctx = lk
+    p = workloads.random_cloud(5000, 6, scale=3.0)
+    n_vox = oracle.voxel_filter(p, 0.5)["count"].shape[0]
+    with pytest.raises(lkc.LkcError, match="BUDGET"):
+        lkc.lkc_voxel_filter(ctx, dev(p), 0.5, capacity=n_vox - 1)
+    out = lkc.lkc_voxel_filter(ctx, dev(p), 0.5, capacity=n_vox)
+    assert out["count"].shape[0] == n_vox
+    with pytest.raises(lkc.LkcError):
+        lkc.lkc_voxel_filter(ctx, dev(p), 0.0)
+    with pytest.raises(lkc.LkcError):
+        lkc.lkc_voxel_filter(ctx, dev(p * np.float32(1e6)), 0.01)   # voxel out of range
+    empty = lkc.lkc_voxel_filter(ctx, dev(np.full((10, 3), np.nan, np.float32)), 0.5)
+    assert empty["count"].shape[0] == 0
+
+
+@pytest.mark.parametrize("radius", [0.5, 12.5, 60.0])
+def test_submap_extract_exact(lk, radius):
+    lkc, ctx = lk
+    m, _ = workloads.build_map(300_000, seed=21, n_even=40)
+    t = lkc.lkc_build_target(ctx, dev(m), 1.0)
+    rng = np.random.default_rng(7)
+    for c in m[rng.choice(len(m), 3, replace=False)]:
+        idx = lkc.lkc_submap_extract(ctx, t, c, radius).cpu().numpy()
+        np.testing.assert_array_equal(idx, oracle.submap(m, c, radius))
+    t.free()
+
+
+def test_submap_lattice_inclusive_and_budget(lk):
+    lkc, ctx = lk
+    g = np.stack(np.meshgrid(*[np.arange(-3, 4)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    p = g.astype(np.float32) + np.float32(100.0)
+    t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+    c = np.array([100.0, 100.0, 100.0], np.float32)
+    idx = lkc.lkc_submap_extract(ctx, t, c, 2.0).cpu().numpy()
+    np.testing.assert_array_equal(idx, oracle.submap(p, c, 2.0))
+    assert len(idx) == 33
+    with pytest.raises(lkc.LkcError, match="BUDGET"):
+        lkc.lkc_submap_extract(ctx, t, c, 2.0, capacity=32)
+    t.free()
+
+
+def test_submap_build_queries_like_the_window(lk):
+    """A target built from the window answers kNN exactly as the oracle on
+    the window's points, and its indices map back to the map."""
+    from tests import parity
+    lkc, ctx = lk
+    m, _ = workloads.build_map(300_000, seed=22, n_even=40)
+    t = lkc.lkc_build_target(ctx, dev(m), 1.0)
+    c = m[12345]
+    sub, idx = lkc.lkc_submap_build(ctx, t, c, 15.0)
+    idx = idx.cpu().numpy()
+    np.testing.assert_array_equal(idx, oracle.submap(m, c, 15.0))
+    assert sub.info()["n_points"] == len(idx)
+    w = m[idx]
+    q = w[:: max(1, len(w) // 500)]
+    i, d2, cnt = lkc.lkc_knn_query(ctx, sub, dev(q), 10, 1.0)
+    parity.check_knn(w, q, 10, 1.0, i.cpu().numpy(), d2.cpu().numpy(), cnt.cpu().numpy())
+    sub.free()
+    t.free()
