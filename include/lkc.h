@@ -389,13 +389,17 @@ lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
  * events are not captured-graph safe, so keep timing off under capture. */
 lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
 
-/* Diagnostics: when `buffer` (device, 10 uint32 per group) holds at least
+/* Diagnostics: when `buffer` (device, 17 uint32 per group) holds at least
  * the number of 64-query groups of a search, the group search writes per
  * group: clock cycles, probe rounds, cells streamed, 64-point chunks
  * loaded, candidates tested, insertion steps, member lanes, lanes handed
- * to the fallback search, insertions summed over the lanes, and insertion
- * steps in which no lane inserted.  n_groups = 0 turns it off.  The caller
- * owns the buffer. */
+ * to the fallback search, insertions summed over the lanes, insertion
+ * steps in which no lane inserted, then insertions (3 words) and
+ * candidates (3 words) in the three streaming phases: runs of the queries'
+ * own cells touching the query box, the rest of those cells, the other
+ * cells, and insertions from the group's own chunk (self queries).
+ * n_groups = 0 turns it off.
+ * The caller owns the buffer. */
 lkc_status lkc_ctx_set_profile(lkc_ctx *ctx, void *buffer, int64_t n_groups);
 
 /* Grow the context's search scratch (query sort buffers and the fallback

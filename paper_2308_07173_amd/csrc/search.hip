@@ -598,10 +598,14 @@ struct GroupArgs {
 
 // per-group profile words: clock cycles, probe rounds, cells streamed,
 // 64-point chunks loaded, candidates tested, insertion pops, member lanes,
-// fallback lanes, insertions (over all lanes), pops in which no lane inserted
-constexpr int PROF_WORDS = 10;
+// fallback lanes, insertions (over all lanes), pops in which no lane
+// inserted; then insertions and candidates split by phase: the query cells'
+// runs touching the query box, the rest of the query cells, the other cells;
+// then insertions from the group's own chunk (self queries)
+constexpr int PROF_WORDS = 17;
 struct GroupProf {
     uint32_t probes, cells, chunks, cands, pops, inserts, dead;
+    uint32_t ins0, ins1, ins2, cand0, cand1, cand2, own;
 };
 
 struct SlotQuery {
@@ -659,10 +663,11 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                                          const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr,
                                          unsigned long long (&kk)[K], int mode,
-                                         GroupProf& gp) {
+                                         GroupProf& gp, int skip_cb) {
     const int lane = lane_id();
 #pragma unroll 1
     for (int cb = s0 & ~(WAVE - 1); cb < e0; cb += WAVE) {
+        if (cb == skip_cb) continue;   // streamed first, as the group's own chunk
         uint32_t keep = 0;
         // this lane's current k-th distance (radius while its list is not full)
         const float lthr = kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2);
@@ -762,7 +767,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
     for (int j = 0; j < K; ++j) kk[j] = (j < pad) ? 0ull : ~0ull;
     const unsigned long long mm = ballot(member);
     bool ok = true;
-    GroupProf gp{0, 0, 0, 0, 0, 0, 0};
+    GroupProf gp{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const unsigned long long t_start = a.prof ? __builtin_amdgcn_s_memtime() : 0ull;
     if (mm && T.n_cells > 0) {
         const float bx0 = wave_min_dpp(member ? s.x : INF), bx1 = wave_max_dpp(member ? s.x : -INF);
@@ -783,6 +788,18 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
                                  fmaxf(fabsf(bz0), fabsf(bz1)));
         const float margin = (fmaxf(qabs, T.max_abs) + 2.0f * T.cell) * 1e-6f;
         float gthr = r2;   // largest k-th distance over the members (radius while unfilled)
+        // Self queries: the group's 64 slots are 64 consecutive points of
+        // the target's Morton order, i.e. the queries themselves and each
+        // other's nearest points; streaming that chunk first fills every
+        // list with near neighbours, so later candidates rarely pass.
+        int own_cb = -1;
+        if (!a.queries) {
+            own_cb = (int)(group * WAVE);
+            const uint32_t i0 = gp.inserts;
+            scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
+                        s.z, r2, b0, b1, margin, gthr, kk, 2, gp, -1);
+            gp.own += gp.inserts - i0;
+        }
         for (int pass = 0; pass < 2; ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
                 gp.probes++;
@@ -810,6 +827,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
                 const unsigned long long wm0 = ballot(want);
                 for (int mode = (pass == 0 ? 0 : 2); mode <= (pass == 0 ? 1 : 2); ++mode) {
                     unsigned long long wm = wm0;
+                    const uint32_t i0 = gp.inserts, c0 = gp.cands;
                     while (wm) {
                         const int cl = __builtin_ffsll((long long)wm) - 1;
                         wm &= wm - 1;
@@ -817,7 +835,18 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
                         const int e0 = s0 + readlane((int)cn, cl);
                         gp.cells++;
                         scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, b0, b1, margin, gthr,
-                                    kk, mode, gp);
+                                    kk, mode, gp, own_cb);
+                    }
+                    const uint32_t di = gp.inserts - i0, dc = gp.cands - c0;
+                    if (mode == 0) {
+                        gp.ins0 += di;
+                        gp.cand0 += dc;
+                    } else if (mode == 1) {
+                        gp.ins1 += di;
+                        gp.cand1 += dc;
+                    } else {
+                        gp.ins2 += di;
+                        gp.cand2 += dc;
                     }
                 }
             }
@@ -852,6 +881,13 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
         pw[7] = (uint32_t)__popcll(fm);
         pw[8] = gp.inserts;
         pw[9] = gp.dead;
+        pw[10] = gp.ins0;
+        pw[11] = gp.ins1;
+        pw[12] = gp.ins2;
+        pw[13] = gp.cand0;
+        pw[14] = gp.cand1;
+        pw[15] = gp.cand2;
+        pw[16] = gp.own;
     }
     if (fm) {
         const int leader = __builtin_ffsll((long long)fm) - 1;
