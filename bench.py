@@ -232,13 +232,97 @@ def gicp(args, lkc, workloads, torch, ctx, cfg):
     ctx.synchronize()
 
 
+def timed_calls(torch, fn, K, W):
+    """Run fn W times untimed, then K times between HIP events on torch's
+    current stream; returns (mean event ms, wall seconds of the K calls)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(W):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(K)]
+    t0 = time.perf_counter()
+    for i in range(K):
+        evs[i][0].record(stream)
+        fn()
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return float(np.mean([a.elapsed_time(b) for a, b in evs])), wall
+
+
+def voxel_and_submap(args, lkc, workloads, torch, ctx):
+    """The steps before the path.  voxel: the 48 uneven scans of the batched
+    workload (3,757,703 points, world frame) voxel-filtered at 0.2 m in one
+    call.  submap: the map points within 50 m of a track pose, from the
+    resident 2,000,000-point map, in one call."""
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    if args.workload == "voxel":
+        pts = np.concatenate(workloads.batched_scans(16, seed=4))
+        n = pts.shape[0]
+        p = torch.from_numpy(pts).to(dev)
+        leaf = 0.2
+        out = lkc.lkc_voxel_filter(ctx, p, leaf)
+        m = int(out["count"].shape[0])
+        ms, wall = timed_calls(torch, lambda: lkc.lkc_voxel_filter(ctx, p, leaf), K, W)
+        alg = 12 * n + 28 * m      # points in; centroid + count + voxel out
+        config = {"workload": "voxel filter of 48 uneven LiDAR scans (16 frames x 3 sensors)",
+                  "n_points": n, "leaf_m": leaf, "voxels": m,
+                  "step": "one lkc_voxel_filter call (bounds, key sort, runs, FP64 means)"}
+        metric = "voxel filter input points/s"
+        if not args.no_cpu_baseline:
+            from oracle import oracle
+            c0 = time.perf_counter()
+            oracle.voxel_filter(pts, leaf)
+            dt = time.perf_counter() - c0
+            cpu = {"value": n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+                   "sample": f"all {n} points; {dt:.2f} s (qsort + FP64 sums, one thread)"}
+    else:
+        m_pts, _ = workloads.build_map(2_000_000, seed=2)
+        n = m_pts.shape[0]
+        t = lkc.lkc_build_target(ctx, torch.from_numpy(m_pts).to(dev), 1.0)
+        center = m_pts[777_777].copy()
+        radius = 50.0
+        idx = lkc.lkc_submap_extract(ctx, t, center, radius)
+        m = int(idx.shape[0])
+        ms, wall = timed_calls(torch, lambda: lkc.lkc_submap_extract(ctx, t, center, radius),
+                               K, W)
+        alg = 16 * n + 4 * m       # float4 map records in; indices out
+        config = {"workload": "sliding-window submap: points within 50 m of a track pose",
+                  "map_points": n, "radius_m": radius, "window_points": m,
+                  "step": "one lkc_submap_extract call (flags, scan, compaction)"}
+        metric = "submap map points scanned/s"
+        if not args.no_cpu_baseline:
+            from oracle import oracle
+            c0 = time.perf_counter()
+            oracle.submap(m_pts, center, radius)
+            dt = time.perf_counter() - c0
+            cpu = {"value": n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+                   "sample": f"all {n} map points; {dt:.3f} s (one thread)"}
+        t.free()
+    achieved = alg / (ms * 1e-3) / 1e9
+    res = {"metric": metric, "value": n * K / wall, "unit": "points/s", "n_gpus": 1, "steps": K,
+           "warmup": W, "ms_per_step": wall / K * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded ray-cast race-track LiDAR)", "config": config,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "whole call", "bytes_per_call": alg, "call_ms": ms}}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu
+    print(json.dumps(res))
+    ctx.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scan",
-                    choices=["scan", "map", "weighted", "gicp", "batched", "tiny", "served"])
+                    choices=["scan", "map", "weighted", "gicp", "batched", "tiny", "served",
+                             "voxel", "submap"])
     ap.add_argument("--sigma", type=float, default=0.2,
                     help="weighted: Laplacian kernel width in metres")
     ap.add_argument("--time-scale", type=float, default=10.0,
@@ -287,6 +371,8 @@ def main():
         return served(args, lkc, workloads, torch)
     if args.workload == "gicp":
         return gicp(args, lkc, workloads, torch, ctx, cfg)
+    if args.workload in ("voxel", "submap"):
+        return voxel_and_submap(args, lkc, workloads, torch, ctx)
     if args.workload in ("scan", "tiny"):
         if args.workload == "scan":
             pts = workloads.single_scan(seed=1)

@@ -698,3 +698,111 @@ int64_t oracle_submap(const float *pts, int64_t n, const float *center, float ra
     }
     return m;
 }
+
+/* ------------------------------------------------ z-vote and clustering --- */
+
+/* Vertical-feature extraction by z-axis voting (Sec. III-D.1, Eq.
+ * eq_hash_table, Fig. z_vote): every (voxel-filtered) point votes for its
+ * 2-D grid cell (u, v) = (floor(x / g), floor(y / g)), evaluated in float32
+ * (correctly rounded division: the integer decision is taken in the kernel's
+ * precision); votes[i] is the number of points in point i's cell and point
+ * i is a vertical feature (keep[i] = 1) when votes[i] >= tau.  The count of
+ * a cell is the size of the set of points mapping to it, computed here by
+ * sorting the cell pairs (a library sort as a step).  Non-finite points get
+ * 0 votes and are not kept.  Returns -1 on invalid arguments. */
+typedef struct {
+    int64_t u, v, i;
+} uv_rec;
+
+static int uv_cmp(const void *a, const void *b)
+{
+    const uv_rec *x = (const uv_rec *)a, *y = (const uv_rec *)b;
+    if (x->v != y->v)
+        return x->v < y->v ? -1 : 1;
+    if (x->u != y->u)
+        return x->u < y->u ? -1 : 1;
+    return x->i < y->i ? -1 : (x->i > y->i);
+}
+
+int oracle_zvote(const float *pts, int64_t n, float g, int32_t tau, uint8_t *keep,
+                 int32_t *votes)
+{
+    if (n < 0 || !(g > 0.0f) || tau < 1)
+        return -1;
+    uv_rec *r = (uv_rec *)malloc(sizeof(uv_rec) * (size_t)(n > 0 ? n : 1));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        keep[i] = 0;
+        votes[i] = 0;
+        const float *p = pts + 3 * i;
+        if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2]))
+            continue;
+        r[m].u = (int64_t)floor((double)(p[0] / g));
+        r[m].v = (int64_t)floor((double)(p[1] / g));
+        r[m].i = i;
+        ++m;
+    }
+    qsort(r, (size_t)m, sizeof(uv_rec), uv_cmp);
+    for (int64_t a = 0; a < m;) {
+        int64_t b = a;
+        while (b < m && r[b].u == r[a].u && r[b].v == r[a].v)
+            ++b;
+        for (int64_t c = a; c < b; ++c) {
+            votes[r[c].i] = (int32_t)(b - a);
+            keep[r[c].i] = (uint8_t)((b - a) >= tau);
+        }
+        a = b;
+    }
+    free(r);
+    return 0;
+}
+
+/* Euclidean-distance clustering (Sec. III-D.2): the clusters are the
+ * connected components of the graph joining points i and j when
+ * d2(i, j) <= eps^2, with d2 = fma(dz, dz, fma(dy, dy, dx * dx)) in float32
+ * (the kernel's decision precision).  The paper's Eq. eq_clustering is
+ * printed in k-means notation; the text and citations describe region
+ * growing by distance, which is this definition.  label[i] = the smallest
+ * index in i's component.  Brute force over all pairs with a union-find
+ * (union by smaller index, path compression).  Points with a non-finite
+ * coordinate are their own component.  Returns the number of components. */
+static int64_t uf_find(int64_t *par, int64_t x)
+{
+    while (par[x] != x) {
+        par[x] = par[par[x]];
+        x = par[x];
+    }
+    return x;
+}
+
+int64_t oracle_euclid_cluster(const float *pts, int64_t n, float eps, int32_t *label)
+{
+    if (n < 0 || !(eps > 0.0f))
+        return -1;
+    const float e2 = eps * eps;
+    int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i)
+        par[i] = i;
+    for (int64_t i = 0; i < n; ++i) {
+        const float *p = pts + 3 * i;
+        if (!isfinite(p[0]) || !isfinite(p[1]) || !isfinite(p[2]))
+            continue;
+        for (int64_t j = i + 1; j < n; ++j) {
+            const float *q = pts + 3 * j;
+            const float dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+            const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            if (d2 <= e2) {
+                const int64_t a = uf_find(par, i), b = uf_find(par, j);
+                if (a != b)
+                    par[a > b ? a : b] = a < b ? a : b;
+            }
+        }
+    }
+    int64_t k = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        label[i] = (int32_t)uf_find(par, i);
+        k += label[i] == i;
+    }
+    free(par);
+    return k;
+}

@@ -71,6 +71,11 @@ def configure(lib):
         lib.oracle_voxel_filter.restype = ctypes.c_int64
         lib.oracle_submap.argtypes = [P, ctypes.c_int64, P, ctypes.c_float, P]
         lib.oracle_submap.restype = ctypes.c_int64
+    if hasattr(lib, "oracle_zvote"):
+        lib.oracle_zvote.argtypes = [P, ctypes.c_int64, ctypes.c_float, ctypes.c_int32, P, P]
+        lib.oracle_zvote.restype = ctypes.c_int
+        lib.oracle_euclid_cluster.argtypes = [P, ctypes.c_int64, ctypes.c_float, P]
+        lib.oracle_euclid_cluster.restype = ctypes.c_int64
     if hasattr(lib, "oracle_gicp_linearize"):
         lib.oracle_gicp_correspond.argtypes = [P, ctypes.c_int64, P, ctypes.c_int64, P,
                                                ctypes.c_double, ctypes.c_int32, P, P]
@@ -239,6 +244,30 @@ def submap(points, center, radius: float):
     if m < 0:
         raise ValueError("oracle_submap: invalid radius")
     return out[:m]
+
+
+def zvote(points, cell: float, tau: int):
+    """z-axis voting: (keep uint8 [n], votes int32 [n])."""
+    p = _f32(points)
+    n = p.shape[0]
+    keep = np.empty(max(n, 1), np.uint8)
+    votes = np.empty(max(n, 1), np.int32)
+    rc = _load().oracle_zvote(_ptr(p), n, float(np.float32(cell)), int(tau), _ptr(keep),
+                              _ptr(votes))
+    if rc != 0:
+        raise ValueError("oracle_zvote: invalid arguments")
+    return keep[:n], votes[:n]
+
+
+def euclid_cluster(points, eps: float):
+    """Connected components under d2 <= eps^2: (label int32 [n], n_clusters)."""
+    p = _f32(points)
+    n = p.shape[0]
+    label = np.empty(max(n, 1), np.int32)
+    k = _load().oracle_euclid_cluster(_ptr(p), n, float(np.float32(eps)), _ptr(label))
+    if k < 0:
+        raise ValueError("oracle_euclid_cluster: invalid arguments")
+    return label[:n], int(k)
 
 
 def sym3_eig(a):

@@ -22,6 +22,7 @@ from tests import test_oracle as pins
 from tests import test_oracle_weighted as wpins
 from tests import test_oracle_gicp as gpins
 from tests import test_oracle_voxel as vpins
+from tests import test_oracle_walls as wlpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lkc_oracle.c")
 
@@ -99,11 +100,28 @@ VOXEL_MUTATIONS = {
     "voxel_reciprocal": ("const float q = (p[d] - origin[d]) / leaf;",
                          "const float q = (p[d] - origin[d]) * (1.0f / leaf);"),
     "submap_exclusive": ("if (d2 <= r2)\n            out[m++]", "if (d2 < r2)\n            out[m++]"),
-    "submap_dropped_z": ("const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));",
-                         "const float d2 = fmaf(dy, dy, dx * dx);"),
+    "submap_dropped_z": ("const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));\n        if (d2 <= r2)",
+                         "const float d2 = fmaf(dy, dy, dx * dx);\n        if (d2 <= r2)"),
 }
 
 VOXEL_PINS = [getattr(vpins, n) for n in dir(vpins) if n.startswith("test_")]
+
+# planted mistakes in the z-vote filter and the clustering
+WALL_MUTATIONS = {
+    "zvote_trunc": ("r[m].u = (int64_t)floor((double)(p[0] / g));",
+                    "r[m].u = (int64_t)trunc((double)(p[0] / g));"),
+    "zvote_v_from_x": ("r[m].v = (int64_t)floor((double)(p[1] / g));",
+                       "r[m].v = (int64_t)floor((double)(p[0] / g));"),
+    "zvote_strict": ("keep[r[c].i] = (uint8_t)((b - a) >= tau);",
+                     "keep[r[c].i] = (uint8_t)((b - a) > tau);"),
+    "cluster_exclusive": ("if (d2 <= e2) {", "if (d2 < e2) {"),
+    "cluster_max_label": ("par[a > b ? a : b] = a < b ? a : b;",
+                          "par[a < b ? a : b] = a > b ? a : b;"),
+    "cluster_dropped_dz": ("const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));\n            if (d2 <= e2)",
+                           "const float d2 = fmaf(dy, dy, dx * dx);\n            if (d2 <= e2)"),
+}
+
+WALL_PINS = [getattr(wlpins, n) for n in dir(wlpins) if n.startswith("test_")]
 
 
 def _call(pin):
@@ -117,12 +135,12 @@ def _call(pin):
 
 
 def test_unmutated_source_passes_the_pins():
-    for pin in PINS + WEIGHTED_PINS + GICP_PINS + VOXEL_PINS:
+    for pin in PINS + WEIGHTED_PINS + GICP_PINS + VOXEL_PINS + WALL_PINS:
         _call(pin)
 
 
 GROUPS = [(MUTATIONS, PINS), (WEIGHTED_MUTATIONS, WEIGHTED_PINS), (GICP_MUTATIONS, GICP_PINS),
-          (VOXEL_MUTATIONS, VOXEL_PINS)]
+          (VOXEL_MUTATIONS, VOXEL_PINS), (WALL_MUTATIONS, WALL_PINS)]
 
 
 @pytest.mark.parametrize("name", [n for muts, _ in GROUPS for n in sorted(muts)])
