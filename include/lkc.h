@@ -20,6 +20,8 @@
  *   lkc_voxel_filter    voxel centroids of a cloud
  *   lkc_submap_extract / lkc_submap_build
  *                       the map points within a radius of a pose
+ *   lkc_zvote / lkc_euclid_cluster
+ *                       vertical-feature filter and distance clustering
  *   lkc_knn_cov_batched many scans against several targets in one persistent
  *                       launch (graph-capturable)
  *
@@ -323,6 +325,29 @@ lkc_status lkc_submap_extract(lkc_ctx *ctx, const lkc_target *map, const float *
 lkc_status lkc_submap_build(lkc_ctx *ctx, const lkc_target *map, const float *center,
                             float radius, int32_t *idx, int64_t capacity, int64_t *n_out,
                             lkc_target **out);
+
+/* ---- Wall-detection front end (paper Sec. III-D).
+ *
+ * z-vote vertical-feature filter (Sec. III-D.1, Eq. eq_hash_table, Fig.
+ * z_vote): every point votes for its 2-D cell (floor(x / cell),
+ * floor(y / cell)), evaluated in float32 with correctly rounded division;
+ * votes[i] = the number of points in point i's cell, keep[i] = (votes[i] >=
+ * tau).  Non-finite points get 0 votes and keep 0.  points device float
+ * [n][3]; keep device uint8 [n]; votes device int32 [n] or NULL.
+ * LKC_ERR_BUDGET when the occupied 2-D box exceeds 2^28 cells.
+ * Synchronises once (box size). */
+lkc_status lkc_zvote(lkc_ctx *ctx, const float *points, int64_t n, float cell, int32_t tau,
+                     uint8_t *keep, int32_t *votes);
+
+/* Euclidean-distance clustering (Sec. III-D.2): connected components of the
+ * graph joining points i, j with d2 <= eps^2, d2 = fma(dz, dz, fma(dy, dy,
+ * dx * dx)) in float32.  labels device int32 [n]: the smallest index of the
+ * point's component; *n_clusters (host) the number of components.  All
+ * points must be finite (LKC_ERR_NONFINITE); LKC_ERR_INVALID_ARG when eps
+ * is below the cloud's extent / 2^20.  Builds (and keeps, for the next
+ * call) a grid of 1.25 eps cells in the context.  Synchronises. */
+lkc_status lkc_euclid_cluster(lkc_ctx *ctx, const float *points, int64_t n, float eps,
+                              int32_t *labels, int64_t *n_clusters);
 
 /* A set of targets addressable by the batched call.  Creating a set uploads
  * one small descriptor per target and sizes the set's scan table for at

@@ -112,6 +112,10 @@ lkc_status lkc_ctx_destroy(lkc_ctx* ctx) {
     if (ctx->search_scratch) (void)hipFree(ctx->search_scratch);
     if (ctx->gicp_scratch) (void)hipFree(ctx->gicp_scratch);
     if (ctx->aux_scratch) (void)hipFree(ctx->aux_scratch);
+    if (ctx->cluster_grid) {
+        lkc::free_target_memory(ctx->cluster_grid);
+        delete ctx->cluster_grid;
+    }
     if (ctx->gicp_host) (void)hipHostFree(ctx->gicp_host);
     if (ctx->meta_dev) (void)hipFree(ctx->meta_dev);
     if (ctx->meta_host) (void)hipHostFree(ctx->meta_host);
@@ -444,6 +448,35 @@ lkc_status lkc_submap_build(lkc_ctx* ctx, const lkc_target* map, const float* ce
     }
     *out = t;
     return LKC_OK;
+}
+
+lkc_status lkc_zvote(lkc_ctx* ctx, const float* points, int64_t n, float cell, int32_t tau,
+                     uint8_t* keep, int32_t* votes) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (!(cell > 0.0f) || !std::isfinite(cell))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "cell must be finite and > 0");
+    if (tau < 1) return set_error(ctx, LKC_ERR_INVALID_ARG, "tau must be >= 1");
+    if (n > 0 && (!points || !keep))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL points or keep pointer");
+    return lkc::zvote(ctx, points, n, cell, tau, keep, votes);
+}
+
+lkc_status lkc_euclid_cluster(lkc_ctx* ctx, const float* points, int64_t n, float eps,
+                              int32_t* labels, int64_t* n_clusters) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!n_clusters) return set_error(ctx, LKC_ERR_INVALID_ARG, "n_clusters is NULL");
+    *n_clusters = 0;
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (!(eps > 0.0f) || !std::isfinite(eps * eps) || !std::isfinite(1.0f / (1.25f * eps)))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "eps must be finite and > 0");
+    if (n > 0 && (!points || !labels))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL points or labels pointer");
+    return lkc::euclid_cluster(ctx, points, n, eps, labels, n_clusters);
 }
 
 lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,

@@ -42,6 +42,8 @@ struct lkc_ctx {
     // grow-only device scratch of the voxel filter and the submap window
     void* aux_scratch = nullptr;
     size_t aux_scratch_bytes = 0;
+    // grid reused by the clustering calls (built with 1.25 eps cells)
+    struct lkc_target* cluster_grid = nullptr;
 };
 
 struct lkc_target {
@@ -104,6 +106,9 @@ lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsign
 void scan_words(hipStream_t st, uint32_t* data, int64_t m, uint32_t* tmp);
 
 // implemented in voxel.hip
+// grow-only device scratch of the context shared by the voxel filter, the
+// submap window, the z-vote and the clustering (NULL and *st set on error)
+void* aux_scratch(lkc_ctx* ctx, size_t bytes, lkc_status* st);
 lkc_status voxel_filter(lkc_ctx* ctx, const float* pts, int64_t n, const float* origin,
                         float leaf, float* centroid, int32_t* count, int32_t* voxel, int64_t cap,
                         int64_t* n_out);
@@ -111,6 +116,12 @@ lkc_status submap_extract(lkc_ctx* ctx, const lkc_target* t, const float* center
                           int32_t* idx, float* gathered, int64_t cap, int64_t* n_out);
 lkc_status submap_build(lkc_ctx* ctx, const lkc_target* map, const float* center, float radius,
                         int32_t* idx, int64_t cap, int64_t* n_out, lkc_target* out);
+
+// implemented in walls.hip
+lkc_status zvote(lkc_ctx* ctx, const float* pts, int64_t n, float g, int32_t tau,
+                 uint8_t* keep, int32_t* votes);
+lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
+                          int32_t* labels, int64_t* n_clusters);
 
 // implemented in search.hip
 struct LaunchCfg {

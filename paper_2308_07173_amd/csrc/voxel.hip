@@ -285,6 +285,8 @@ __global__ void __launch_bounds__(VT) k_submap_compact(const float4* __restrict_
     if (i == n - 1) *total = o + (in ? 1u : 0u);
 }
 
+}  // namespace
+
 // grow-only auxiliary scratch of the context
 void* aux_scratch(lkc_ctx* ctx, size_t bytes, lkc_status* st) {
     *st = LKC_OK;
@@ -308,6 +310,8 @@ void* aux_scratch(lkc_ctx* ctx, size_t bytes, lkc_status* st) {
     }
     return ctx->aux_scratch;
 }
+
+namespace {
 
 VoxMeta* vox_meta_dev(lkc_ctx* ctx) { return (VoxMeta*)((char*)ctx->meta_dev + 128); }
 VoxMeta* vox_meta_host(lkc_ctx* ctx) { return (VoxMeta*)((char*)ctx->meta_host + 128); }

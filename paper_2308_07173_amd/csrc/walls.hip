@@ -1,0 +1,316 @@
+// walls.hip -- z-vote vertical-feature filter and Euclidean clustering on
+// gfx950 (the wall-detection front end, paper Sec. III-D).
+//
+// z-vote (Sec. III-D.1, Eq. eq_hash_table, Fig. z_vote): every point votes
+// for its 2-D cell (floor(x / g), floor(y / g)) in float32; a point is a
+// vertical feature when its cell holds at least tau points.  The paper hashes
+// the cells for sparsity; here the counts live in a direct-mapped table over
+// the occupied 2-D box (one 32-bit counter per cell, at most 2^28 cells), so
+// the vote is one atomic add per point and the read-back one load.
+//
+// Clustering (Sec. III-D.2): connected components of the graph joining
+// points closer than eps (d2 <= eps^2, float32, the search's fma order).
+// The points are bucketed in a grid of 1.25 eps cells (built with the target
+// build, so every pair within eps lies in adjacent cells even after float32
+// rounding of the cell coordinates); one thread per point tests the points
+// of the 27 surrounding cells with a smaller original index and joins the
+// two components in a lock-free union-find (the larger root is hooked under
+// the smaller with a compare-and-swap, parent reads bypass the per-CU cache).
+// Roots are therefore the smallest index of their component; a final pass
+// writes every point's root as its label.
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "lkc_internal.h"
+
+namespace lkc {
+
+namespace {
+
+constexpr int WT = 256;
+constexpr int UV_CLAMP = 1 << 30;
+constexpr uint64_t ZVOTE_MAX_CELLS = 1ull << 28;
+constexpr int UNION_SPIN_LIMIT = 1 << 20;
+
+inline unsigned grid_of(int64_t n, int bt) { return (unsigned)((n + bt - 1) / bt); }
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct UvMeta {      // 64 bytes, at offset 192 of the context's metadata words
+    int umin, umax, vmin, vmax;
+    uint32_t bad;    // a 2-D cell coordinate outside [-2^30, 2^30)
+    uint32_t spins;  // union-find retries that hit the limit
+    uint32_t n_clusters;
+    uint32_t pad[9];
+};
+static_assert(sizeof(UvMeta) == 64, "UvMeta layout");
+
+__device__ __forceinline__ bool uv_of(const float* p, float g, int& u, int& v, bool& bad) {
+    bad = false;
+    if (!finite3(p[0], p[1], p[2])) return false;
+    const float fu = floorf(p[0] / g), fv = floorf(p[1] / g);
+    const bool ok = fu >= -(float)UV_CLAMP && fu < (float)UV_CLAMP && fv >= -(float)UV_CLAMP &&
+                    fv < (float)UV_CLAMP;
+    bad = !ok;
+    u = ok ? (int)fu : 0;
+    v = ok ? (int)fv : 0;
+    return true;
+}
+
+__global__ void k_uv_init(UvMeta* m) {
+    if (threadIdx.x == 0) {
+        m->umin = m->vmin = INT32_MAX;
+        m->umax = m->vmax = INT32_MIN;
+        m->bad = 0;
+        m->spins = 0;
+        m->n_clusters = 0;
+    }
+}
+
+__global__ void __launch_bounds__(WT) k_uv_bounds(const float* __restrict__ pts, int64_t n,
+                                                  float g, UvMeta* __restrict__ m) {
+    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+    int u = 0, v = 0;
+    bool bad = false, fin = false;
+    if (i < n) fin = uv_of(pts + 3 * i, g, u, v, bad);
+    const bool use = fin && !bad;
+    int a = use ? u : INT32_MAX, b = use ? u : INT32_MIN, c = use ? v : INT32_MAX,
+        d = use ? v : INT32_MIN;
+    int nb = fin && bad ? 1 : 0;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+        a = min(a, __shfl_xor(a, s));
+        b = max(b, __shfl_xor(b, s));
+        c = min(c, __shfl_xor(c, s));
+        d = max(d, __shfl_xor(d, s));
+        nb += __shfl_xor(nb, s);
+    }
+    if (threadIdx.x % WAVE == 0) {
+        if (a != INT32_MAX) {
+            atomicMin(&m->umin, a);
+            atomicMax(&m->umax, b);
+            atomicMin(&m->vmin, c);
+            atomicMax(&m->vmax, d);
+        }
+        if (nb) atomicAdd(&m->bad, (uint32_t)nb);
+    }
+}
+
+__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t m) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) p[i] = 0u;
+}
+
+struct VoteArgs {
+    const float* pts;
+    int64_t n;
+    float g;
+    int umin, vmin;
+    uint32_t wu;
+    uint32_t* table;
+    int32_t tau;
+    uint8_t* keep;
+    int32_t* votes;
+};
+
+__device__ __forceinline__ int64_t vote_slot(const VoteArgs& a, int64_t i) {
+    int u, v;
+    bool bad;
+    if (!uv_of(a.pts + 3 * i, a.g, u, v, bad) || bad) return -1;
+    return (int64_t)(uint32_t)(u - a.umin) + (int64_t)a.wu * (int64_t)(uint32_t)(v - a.vmin);
+}
+
+__global__ void __launch_bounds__(WT) k_vote(VoteArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t s = vote_slot(a, i);
+    if (s >= 0) atomicAdd(&a.table[s], 1u);
+}
+
+__global__ void __launch_bounds__(WT) k_vote_read(VoteArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t s = vote_slot(a, i);
+    const int32_t c = s >= 0 ? (int32_t)a.table[s] : 0;
+    if (a.votes) a.votes[i] = c;
+    a.keep[i] = (s >= 0 && c >= a.tau) ? 1 : 0;
+}
+
+// ---------------------------------------------------------- clustering --
+
+__device__ __forceinline__ int32_t parent_load(const int32_t* par, int32_t x) {
+    return __hip_atomic_load(par + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x, reading the parents coherently (the union phase runs
+// concurrently with other hooks).  Parents only ever point to smaller
+// indices, so the walk ends.
+__device__ __forceinline__ int32_t uf_root(int32_t* par, int32_t x) {
+    for (;;) {
+        const int32_t p = parent_load(par, x);
+        if (p == x) return x;
+        x = p;
+    }
+}
+
+// Join the components of a and b: hook the larger root under the smaller.
+// A failed compare-and-swap means another thread hooked that root first (so
+// the structure progressed); the loop retries with fresh roots.  Bounded: a
+// retry count past the limit is reported and the join abandoned.
+__device__ __forceinline__ void uf_union(int32_t* par, int32_t a, int32_t b, UvMeta* m) {
+    for (int it = 0; it < UNION_SPIN_LIMIT; ++it) {
+        a = uf_root(par, a);
+        b = uf_root(par, b);
+        if (a == b) return;
+        const int32_t hi = max(a, b), lo = min(a, b);
+        if (atomicCAS(par + hi, hi, lo) == hi) return;
+        a = hi;
+        b = lo;
+    }
+    atomicAdd(&m->spins, 1u);
+}
+
+__global__ void k_parent_init(int32_t* __restrict__ par, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) par[i] = (int32_t)i;
+}
+
+// One thread per reordered point: join it with every point of the 27
+// surrounding cells that has a smaller original index and lies within eps.
+__global__ void __launch_bounds__(WT) k_cluster_union(const TargetView* __restrict__ Tp,
+                                                      float e2, int32_t* __restrict__ par,
+                                                      UvMeta* __restrict__ m) {
+    const TargetView T = load_uniform(Tp);
+    const int64_t s = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * WT + threadIdx.x;
+    if (s >= T.n) return;
+    const float4 p = T.pts[s];
+    const int32_t i = __float_as_int(p.w);
+    const int cx = cell_coord(p.x, T.inv_cell), cy = cell_coord(p.y, T.inv_cell),
+              cz = cell_coord(p.z, T.inv_cell);
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int x = cx + dx, y = cy + dy, z = cz + dz;
+                if (x < T.cmin[0] || x > T.cmax[0] || y < T.cmin[1] || y > T.cmax[1] ||
+                    z < T.cmin[2] || z > T.cmax[2])
+                    continue;
+                uint32_t st, cn;
+                if (!hash_find(T, pack_key(T, x, y, z), st, cn)) continue;
+                for (uint32_t t = st; t < st + cn; ++t) {
+                    const float4 q = T.pts[t];
+                    const int32_t j = __float_as_int(q.w);
+                    if (j < i && dist2(p.x, p.y, p.z, q.x, q.y, q.z) <= e2)
+                        uf_union(par, i, j, m);
+                }
+            }
+}
+
+// labels: every point's root (full path compression), roots counted
+__global__ void __launch_bounds__(WT) k_cluster_labels(int32_t* __restrict__ par, int64_t n,
+                                                       int32_t* __restrict__ label,
+                                                       UvMeta* __restrict__ m) {
+    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+    bool root = false;
+    if (i < n) {
+        int32_t x = (int32_t)i;
+        while (par[x] != x) x = par[x];
+        label[i] = x;
+        root = x == (int32_t)i;
+    }
+    const unsigned long long b = ballot(root);
+    if (threadIdx.x % WAVE == 0 && b) atomicAdd(&m->n_clusters, (uint32_t)__popcll(b));
+}
+
+UvMeta* uv_meta_dev(lkc_ctx* ctx) { return (UvMeta*)((char*)ctx->meta_dev + 192); }
+UvMeta* uv_meta_host(lkc_ctx* ctx) { return (UvMeta*)((char*)ctx->meta_host + 192); }
+
+}  // namespace
+
+lkc_status zvote(lkc_ctx* ctx, const float* pts, int64_t n, float g, int32_t tau,
+                 uint8_t* keep, int32_t* votes) {
+    if (n == 0) return LKC_OK;
+    hipStream_t st = ctx->stream;
+    UvMeta* md = uv_meta_dev(ctx);
+    UvMeta* mh = uv_meta_host(ctx);
+    hipLaunchKernelGGL(k_uv_init, dim3(1), dim3(64), 0, st, md);
+    hipLaunchKernelGGL(k_uv_bounds, dim3(grid_of(n, WT)), dim3(WT), 0, st, pts, n, g, md);
+    LKC_HIP_TRY(ctx, hipGetLastError());
+    LKC_HIP_TRY(ctx, hipMemcpyAsync(mh, md, sizeof(UvMeta), hipMemcpyDeviceToHost, st));
+    LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (mh->bad)
+        return set_error(ctx, LKC_ERR_INVALID_ARG,
+                         "%u points fall in a 2-D cell outside [-2^30, 2^30)", mh->bad);
+    VoteArgs a{pts, n, g, 0, 0, 1u, nullptr, tau, keep, votes};
+    uint64_t cells = 0;
+    if (mh->umin <= mh->umax) {
+        const uint64_t wu = (uint64_t)((int64_t)mh->umax - mh->umin) + 1;
+        const uint64_t wv = (uint64_t)((int64_t)mh->vmax - mh->vmin) + 1;
+        if (wu > ZVOTE_MAX_CELLS || wv > ZVOTE_MAX_CELLS || wu * wv > ZVOTE_MAX_CELLS)
+            return set_error(ctx, LKC_ERR_BUDGET,
+                             "the occupied 2-D box has %llu x %llu cells (limit 2^28)",
+                             (unsigned long long)wu, (unsigned long long)wv);
+        cells = wu * wv;
+        a.umin = mh->umin;
+        a.vmin = mh->vmin;
+        a.wu = (uint32_t)wu;
+    }
+    lkc_status s;
+    a.table = (uint32_t*)aux_scratch(ctx, 4 * (size_t)std::max<uint64_t>(cells, 1), &s);
+    if (!a.table) return s;
+    if (cells)
+        hipLaunchKernelGGL(k_zero_words, dim3(grid_of((int64_t)cells, WT)), dim3(WT), 0, st,
+                           a.table, (int64_t)cells);
+    hipLaunchKernelGGL(k_vote, dim3(grid_of(n, WT)), dim3(WT), 0, st, a);
+    hipLaunchKernelGGL(k_vote_read, dim3(grid_of(n, WT)), dim3(WT), 0, st, a);
+    LKC_HIP_TRY(ctx, hipGetLastError());
+    return LKC_OK;
+}
+
+lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
+                          int32_t* labels, int64_t* n_clusters) {
+    *n_clusters = 0;
+    if (n == 0) return LKC_OK;
+    hipStream_t st = ctx->stream;
+    if (!ctx->cluster_grid) {
+        ctx->cluster_grid = new (std::nothrow) lkc_target();
+        if (!ctx->cluster_grid) return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    }
+    lkc_target& grid = *ctx->cluster_grid;
+    grid.cell_size = 1.25f * eps;
+    lkc_status s = build_into(ctx, &grid, pts, n);
+    if (s == LKC_OK) {
+        const float reach = grid.view.max_abs * grid.view.inv_cell;
+        if (!(reach < (float)((1 << 20) - 4)))
+            s = set_error(ctx, LKC_ERR_INVALID_ARG,
+                          "eps %g is too small for the cloud's extent (|p| up to %g)",
+                          (double)eps, (double)grid.view.max_abs);
+    }
+    int32_t* par = nullptr;
+    if (s == LKC_OK) {
+        par = (int32_t*)aux_scratch(ctx, 4 * (size_t)n, &s);
+    }
+    if (s == LKC_OK) {
+        UvMeta* md = uv_meta_dev(ctx);
+        UvMeta* mh = uv_meta_host(ctx);
+        hipLaunchKernelGGL(k_uv_init, dim3(1), dim3(64), 0, st, md);
+        hipLaunchKernelGGL(k_parent_init, dim3(grid_of(n, WT)), dim3(WT), 0, st, par, n);
+        hipLaunchKernelGGL(k_cluster_union, dim3(grid_of(n, WT)), dim3(WT), 0, st,
+                           (const TargetView*)grid.view_dev, eps * eps, par, md);
+        hipLaunchKernelGGL(k_cluster_labels, dim3(grid_of(n, WT)), dim3(WT), 0, st, par, n,
+                           labels, md);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(mh, md, sizeof(UvMeta), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            s = hip_error(ctx, e, "clustering");
+        } else if (mh->spins) {
+            s = set_error(ctx, LKC_ERR_HIP, "%u union-find joins exceeded the retry limit",
+                          mh->spins);
+        } else {
+            *n_clusters = mh->n_clusters;
+        }
+    }
+    return s;
+}
+
+}  // namespace lkc

@@ -44,7 +44,7 @@ EXPORTED_SYMBOLS = (
     "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve", "lkc_ctx_search_stats",
     "lkc_ctx_set_timing", "lkc_ctx_set_profile", "lkc_covariances_weighted",
     "lkc_knn_cov_weighted", "lkc_gicp_linearize", "lkc_gicp_align", "lkc_voxel_filter",
-    "lkc_submap_extract", "lkc_submap_build",
+    "lkc_submap_extract", "lkc_submap_build", "lkc_zvote", "lkc_euclid_cluster",
 )
 
 # neighbour weight kernels of lkc_covariances_weighted / lkc_knn_cov_weighted
@@ -146,6 +146,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                  I32),
             "lkc_submap_extract": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64)], I32),
             "lkc_submap_build": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64), PP], I32),
+            "lkc_zvote": ([P, P, I64, F, I32, P, P], I32),
+            "lkc_euclid_cluster": ([P, P, I64, F, P, ctypes.POINTER(ctypes.c_int64)], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -572,6 +574,34 @@ def lkc_submap_build(ctx: Context, target: Target, center, radius: float, with_i
                                        ctypes.c_void_p(_ptr(idx)), n if with_idx else 0,
                                        ctypes.byref(m), ctypes.byref(h)))
     return Target(ctx, h), (idx[:m.value] if with_idx else None)
+
+
+def lkc_zvote(ctx: Context, points, cell: float, tau: int, with_votes: bool = True):
+    """z-vote filter: (keep uint8 [n], votes int32 [n] or None), device tensors."""
+    torch = _torch()
+    _check_dev(points, "points", torch.float32, (3,))
+    n = points.shape[0]
+    keep = torch.empty(n, dtype=torch.uint8, device=points.device)
+    votes = torch.empty(n, dtype=torch.int32, device=points.device) if with_votes else None
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_zvote(ctx.handle, ctypes.c_void_p(_ptr(points)), n, float(cell),
+                                int(tau), ctypes.c_void_p(_ptr(keep)),
+                                ctypes.c_void_p(_ptr(votes))))
+    return keep, votes
+
+
+def lkc_euclid_cluster(ctx: Context, points, eps: float):
+    """Distance clustering: (labels int32 [n] device, number of clusters)."""
+    torch = _torch()
+    _check_dev(points, "points", torch.float32, (3,))
+    n = points.shape[0]
+    labels = torch.empty(n, dtype=torch.int32, device=points.device)
+    k = ctypes.c_int64(0)
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_euclid_cluster(ctx.handle, ctypes.c_void_p(_ptr(points)), n,
+                                         float(eps), ctypes.c_void_p(_ptr(labels)),
+                                         ctypes.byref(k)))
+    return labels, k.value
 
 
 def lkc_knn_cov_self(ctx: Context, target: Target, k: int, radius: float = math.inf,

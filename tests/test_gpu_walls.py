@@ -1,0 +1,129 @@
+"""GPU parity of the z-vote filter and the Euclidean clustering, through the
+C ABI.
+
+Both decide integers from float32 arithmetic that the oracle takes in the
+same precision and operation order (the 2-D cell by correctly rounded
+division, the edge by the fma-ordered d2), so the votes, the keep mask and
+the cluster labels (smallest index per component) must match exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle
+from paper_2308_07173_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_07173_amd import lkc
+    ctx = lkc.Context()
+    yield lkc, ctx
+    ctx.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("n,cell,tau,seed", [(1, 0.5, 1, 0), (999, 0.25, 3, 1),
+                                             (200_001, 0.2, 6, 2)])
+def test_zvote_random(lk, n, cell, tau, seed):
+    lkc, ctx = lk
+    p = workloads.random_cloud(n, seed, scale=20.0, offset=(-80.0, 30.0, 1.0))
+    keep, votes = lkc.lkc_zvote(ctx, dev(p), cell, tau)
+    ok, ov = oracle.zvote(p, cell, tau)
+    np.testing.assert_array_equal(votes.cpu().numpy(), ov)
+    np.testing.assert_array_equal(keep.cpu().numpy(), ok)
+
+
+def test_zvote_voxelised_scan_boundaries_nonfinite(lk):
+    lkc, ctx = lk
+    scan = workloads.single_scan(seed=6)
+    v = oracle.voxel_filter(scan, 0.2)["centroid"].astype(np.float32)
+    g = np.arange(-40, 40, dtype=np.float32) * np.float32(0.5)
+    edge = np.stack([np.concatenate([g, np.nextafter(g, np.float32(-np.inf))]),
+                     np.full(160, 0.25, np.float32), np.zeros(160, np.float32)], 1)
+    p = np.concatenate([v, edge, np.array([[np.nan, 0, 0], [0, np.inf, 0]], np.float32)])
+    keep, votes = lkc.lkc_zvote(ctx, dev(p), 0.5, 12)
+    ok, ov = oracle.zvote(p, 0.5, 12)
+    np.testing.assert_array_equal(votes.cpu().numpy(), ov)
+    np.testing.assert_array_equal(keep.cpu().numpy(), ok)
+    assert ok.sum() > 100 and (1 - ok).sum() > 100
+
+
+def test_zvote_errors(lk):
+    lkc, ctx = lk
+    p = workloads.random_cloud(100, 3)
+    for cell, tau in ((0.0, 1), (0.5, 0), (float("nan"), 1)):
+        with pytest.raises(lkc.LkcError):
+            lkc.lkc_zvote(ctx, dev(p), cell, tau)
+    far = np.array([[0, 0, 0], [1e5, 1e5, 0]], np.float32)
+    with pytest.raises(lkc.LkcError, match="BUDGET"):
+        lkc.lkc_zvote(ctx, dev(far), 1e-3, 1)
+
+
+@pytest.mark.parametrize("n,eps,seed", [(1, 0.5, 0), (2_000, 0.4, 1), (15_000, 0.3, 2)])
+def test_cluster_random(lk, n, eps, seed):
+    lkc, ctx = lk
+    p = workloads.random_cloud(n, seed, scale=6.0, offset=(100.0, -50.0, 0.0))
+    labels, k = lkc.lkc_euclid_cluster(ctx, dev(p), eps)
+    ol, ok = oracle.euclid_cluster(p, eps)
+    assert k == ok
+    np.testing.assert_array_equal(labels.cpu().numpy(), ol)
+
+
+def test_cluster_inclusive_lattice(lk):
+    lkc, ctx = lk
+    t = np.arange(40, dtype=np.float32) * np.float32(0.5)
+    p = np.stack(np.meshgrid(t, t[:10], t[:3], indexing="ij"), -1).reshape(-1, 3)
+    p = p[np.random.default_rng(3).permutation(len(p))].copy()
+    labels, k = lkc.lkc_euclid_cluster(ctx, dev(p), 0.5)        # spacing == eps: one cluster
+    assert k == 1 and np.all(labels.cpu().numpy() == 0)
+    below = float(np.nextafter(np.float32(0.5), np.float32(0)))
+    labels, k = lkc.lkc_euclid_cluster(ctx, dev(p), below)      # just below: singletons
+    assert k == len(p)
+    np.testing.assert_array_equal(labels.cpu().numpy(), np.arange(len(p)))
+
+
+def test_wall_pipeline_plane_wall(lk):
+    """voxel filter -> z-vote -> clustering on the plane + wall: the kept
+    points form one wall cluster, matching the oracle end to end."""
+    lkc, ctx = lk
+    p = workloads.plane_wall(20_000, seed=1)
+    vox = lkc.lkc_voxel_filter(ctx, dev(p), 0.2)["centroid"]
+    keep, _ = lkc.lkc_zvote(ctx, vox, 0.5, 14)
+    kept = vox[keep.bool()].contiguous()
+    labels, k = lkc.lkc_euclid_cluster(ctx, kept, 0.5)
+    v = oracle.voxel_filter(p, 0.2)["centroid"].astype(np.float32)
+    ok, _ = oracle.zvote(v, 0.5, 14)
+    ol, oc = oracle.euclid_cluster(v[ok == 1], 0.5)
+    assert k == oc
+    np.testing.assert_array_equal(labels.cpu().numpy(), ol)
+    sizes = np.bincount(ol)
+    assert sizes.max() > 0.9 * len(ol)          # the wall is one cluster
+
+
+def test_cluster_errors_and_grid_reuse(lk):
+    lkc, ctx = lk
+    p = workloads.random_cloud(3000, 4, scale=3.0)
+    a, ka = lkc.lkc_euclid_cluster(ctx, dev(p), 0.3)
+    b, kb = lkc.lkc_euclid_cluster(ctx, dev(p[:1000]), 0.6)     # smaller input, other eps
+    c, kc = lkc.lkc_euclid_cluster(ctx, dev(p), 0.3)
+    assert torch.equal(a, c) and ka == kc
+    ol, ok = oracle.euclid_cluster(p[:1000], 0.6)
+    assert kb == ok
+    np.testing.assert_array_equal(b.cpu().numpy(), ol)
+    q = p.copy()
+    q[5, 0] = np.nan
+    with pytest.raises(lkc.LkcError, match="NONFINITE"):
+        lkc.lkc_euclid_cluster(ctx, dev(q), 0.3)
+    with pytest.raises(lkc.LkcError):
+        lkc.lkc_euclid_cluster(ctx, dev(p * np.float32(1e4)), 1e-3)   # eps below extent / 2^20
+    with pytest.raises(lkc.LkcError):
+        lkc.lkc_euclid_cluster(ctx, dev(p), 0.0)
