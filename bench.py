@@ -315,6 +315,51 @@ def voxel_and_submap(args, lkc, workloads, torch, ctx):
     ctx.synchronize()
 
 
+def walls(args, lkc, workloads, torch, ctx):
+    """Wall-detection front end on one 118k-point scan (sensor frame): voxel
+    filter (0.2 m), z-vote (0.2 m cells, 3 votes), clustering of the kept
+    voxels (0.5 m).  One step is the three calls."""
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    pts = workloads.single_scan(seed=1)
+    n = pts.shape[0]
+    p = torch.from_numpy(pts).to(dev)
+    state = {}
+
+    def step():
+        vox = lkc.lkc_voxel_filter(ctx, p, 0.2)["centroid"]
+        keep, _ = lkc.lkc_zvote(ctx, vox, 0.2, 3, with_votes=False)
+        labels, k = lkc.lkc_euclid_cluster(ctx, vox, 0.5, mask=keep)
+        state.update(voxels=int(vox.shape[0]), kept=int(keep.sum().item()), clusters=k)
+
+    ms, wall = timed_calls(torch, step, K, W)
+    res = {"metric": "wall-detection front end: scan points/s (voxel filter + z-vote + "
+                     "clustering)",
+           "value": n * K / wall, "unit": "points/s", "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": wall / K * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded ray-cast race-track LiDAR)",
+           "config": {"workload": "one 128x1024 spinning-LiDAR scan, sensor frame",
+                      "n_points": n, "leaf_m": 0.2, "vote_cell_m": 0.2, "tau": 3,
+                      "eps_m": 0.5, **state,
+                      "step": "lkc_voxel_filter + lkc_zvote + lkc_euclid_cluster (masked)"},
+           "step_event_ms": ms,
+           "roofline": None}
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        c0 = time.perf_counter()
+        v = oracle.voxel_filter(pts, 0.2)["centroid"].astype(np.float32)
+        keep, _ = oracle.zvote(v, 0.2, 3)
+        oracle.euclid_cluster(v[keep == 1], 0.5)
+        dt = time.perf_counter() - c0
+        res["cpu_baseline"] = {"value": n / dt, "unit": "points/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"the whole scan; {dt:.2f} s (sort-based voxel filter "
+                                         "and vote, all-pairs clustering, one thread)"}
+    print(json.dumps(res))
+    ctx.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,7 +367,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="scan",
                     choices=["scan", "map", "weighted", "gicp", "batched", "tiny", "served",
-                             "voxel", "submap"])
+                             "voxel", "submap", "walls"])
     ap.add_argument("--sigma", type=float, default=0.2,
                     help="weighted: Laplacian kernel width in metres")
     ap.add_argument("--time-scale", type=float, default=10.0,
@@ -373,6 +418,8 @@ def main():
         return gicp(args, lkc, workloads, torch, ctx, cfg)
     if args.workload in ("voxel", "submap"):
         return voxel_and_submap(args, lkc, workloads, torch, ctx)
+    if args.workload == "walls":
+        return walls(args, lkc, workloads, torch, ctx)
     if args.workload in ("scan", "tiny"):
         if args.workload == "scan":
             pts = workloads.single_scan(seed=1)

@@ -341,13 +341,16 @@ lkc_status lkc_zvote(lkc_ctx *ctx, const float *points, int64_t n, float cell, i
 
 /* Euclidean-distance clustering (Sec. III-D.2): connected components of the
  * graph joining points i, j with d2 <= eps^2, d2 = fma(dz, dz, fma(dy, dy,
- * dx * dx)) in float32.  labels device int32 [n]: the smallest index of the
- * point's component; *n_clusters (host) the number of components.  All
- * points must be finite (LKC_ERR_NONFINITE); LKC_ERR_INVALID_ARG when eps
- * is below the cloud's extent / 2^20.  Builds (and keeps, for the next
- * call) a grid of 1.25 eps cells in the context.  Synchronises. */
+ * dx * dx)) in float32.  mask (device uint8 [n], or NULL for all points)
+ * selects the points taking part, e.g. the keep output of lkc_zvote.
+ * labels device int32 [n]: the smallest index of the point's component, -1
+ * for points the mask leaves out; *n_clusters (host) the number of
+ * components.  The selected points must be finite (LKC_ERR_NONFINITE);
+ * LKC_ERR_INVALID_ARG when eps is below their extent / 2^20.  Builds (and
+ * keeps, for the next call) a grid of 1.25 eps cells in the context.
+ * Synchronises. */
 lkc_status lkc_euclid_cluster(lkc_ctx *ctx, const float *points, int64_t n, float eps,
-                              int32_t *labels, int64_t *n_clusters);
+                              const uint8_t *mask, int32_t *labels, int64_t *n_clusters);
 
 /* A set of targets addressable by the batched call.  Creating a set uploads
  * one small descriptor per target and sizes the set's scan table for at

@@ -465,7 +465,7 @@ lkc_status lkc_zvote(lkc_ctx* ctx, const float* points, int64_t n, float cell, i
 }
 
 lkc_status lkc_euclid_cluster(lkc_ctx* ctx, const float* points, int64_t n, float eps,
-                              int32_t* labels, int64_t* n_clusters) {
+                              const uint8_t* mask, int32_t* labels, int64_t* n_clusters) {
     lkc_status s = check_ctx(ctx);
     if (s != LKC_OK) return s;
     if (!n_clusters) return set_error(ctx, LKC_ERR_INVALID_ARG, "n_clusters is NULL");
@@ -476,7 +476,7 @@ lkc_status lkc_euclid_cluster(lkc_ctx* ctx, const float* points, int64_t n, floa
         return set_error(ctx, LKC_ERR_INVALID_ARG, "eps must be finite and > 0");
     if (n > 0 && (!points || !labels))
         return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL points or labels pointer");
-    return lkc::euclid_cluster(ctx, points, n, eps, labels, n_clusters);
+    return lkc::euclid_cluster(ctx, points, n, eps, mask, labels, n_clusters);
 }
 
 lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,

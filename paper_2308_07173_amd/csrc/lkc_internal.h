@@ -121,7 +121,7 @@ lkc_status submap_build(lkc_ctx* ctx, const lkc_target* map, const float* center
 lkc_status zvote(lkc_ctx* ctx, const float* pts, int64_t n, float g, int32_t tau,
                  uint8_t* keep, int32_t* votes);
 lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
-                          int32_t* labels, int64_t* n_clusters);
+                          const uint8_t* mask, int32_t* labels, int64_t* n_clusters);
 
 // implemented in search.hip
 struct LaunchCfg {

@@ -41,7 +41,8 @@ struct UvMeta {      // 64 bytes, at offset 192 of the context's metadata words
     uint32_t bad;    // a 2-D cell coordinate outside [-2^30, 2^30)
     uint32_t spins;  // union-find retries that hit the limit
     uint32_t n_clusters;
-    uint32_t pad[9];
+    uint32_t kept;   // points selected by the clustering mask
+    uint32_t pad[8];
 };
 static_assert(sizeof(UvMeta) == 64, "UvMeta layout");
 
@@ -205,8 +206,44 @@ __global__ void __launch_bounds__(WT) k_cluster_union(const TargetView* __restri
             }
 }
 
-// labels: every point's root (full path compression), roots counted
+// mask compaction: flags, then (after the exclusive scan) the kept points
+// and their indices in ascending order
+__global__ void __launch_bounds__(WT) k_mask_flags(const uint8_t* __restrict__ mask, int64_t n,
+                                                   uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+    if (i < n) flags[i] = mask[i] ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(WT) k_mask_compact(const float* __restrict__ pts,
+                                                     const uint8_t* __restrict__ mask, int64_t n,
+                                                     const uint32_t* __restrict__ offs,
+                                                     float* __restrict__ cpts,
+                                                     int32_t* __restrict__ cidx,
+                                                     UvMeta* __restrict__ m) {
+    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+    if (i >= n) return;
+    const bool in = mask[i] != 0;
+    const uint32_t o = offs[i];
+    if (in) {
+        cpts[3 * (int64_t)o] = pts[3 * i];
+        cpts[3 * (int64_t)o + 1] = pts[3 * i + 1];
+        cpts[3 * (int64_t)o + 2] = pts[3 * i + 2];
+        cidx[o] = (int32_t)i;
+    }
+    if (i == n - 1) m->kept = o + (in ? 1u : 0u);
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// labels: every point's root (full path compression), roots counted; with
+// a mask, compacted point c labels its original index cidx[c] with the
+// original index of its root (compaction keeps the order, so that is the
+// smallest original index of the component)
 __global__ void __launch_bounds__(WT) k_cluster_labels(int32_t* __restrict__ par, int64_t n,
+                                                       const int32_t* __restrict__ cidx,
                                                        int32_t* __restrict__ label,
                                                        UvMeta* __restrict__ m) {
     const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
@@ -214,7 +251,10 @@ __global__ void __launch_bounds__(WT) k_cluster_labels(int32_t* __restrict__ par
     if (i < n) {
         int32_t x = (int32_t)i;
         while (par[x] != x) x = par[x];
-        label[i] = x;
+        if (cidx)
+            label[cidx[i]] = cidx[x];
+        else
+            label[i] = x;
         root = x == (int32_t)i;
     }
     const unsigned long long b = ballot(root);
@@ -267,7 +307,7 @@ lkc_status zvote(lkc_ctx* ctx, const float* pts, int64_t n, float g, int32_t tau
 }
 
 lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
-                          int32_t* labels, int64_t* n_clusters) {
+                          const uint8_t* mask, int32_t* labels, int64_t* n_clusters) {
     *n_clusters = 0;
     if (n == 0) return LKC_OK;
     hipStream_t st = ctx->stream;
@@ -275,9 +315,46 @@ lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
         ctx->cluster_grid = new (std::nothrow) lkc_target();
         if (!ctx->cluster_grid) return set_error(ctx, LKC_ERR_OOM, "host allocation");
     }
+    size_t off = 0;
+    auto carve = [&](size_t b) {
+        const size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    const size_t o_par = carve(4 * (size_t)n), o_fl = carve(mask ? 4 * (size_t)n : 0),
+                 o_tmp = carve(mask ? 4 * ((size_t)n / 4096 + 2) : 0),
+                 o_cp = carve(mask ? 12 * (size_t)n : 0), o_ci = carve(mask ? 4 * (size_t)n : 0);
+    lkc_status s;
+    char* sb = (char*)aux_scratch(ctx, off, &s);
+    if (!sb) return s;
+    auto* par = (int32_t*)(sb + o_par);
+    UvMeta* md = uv_meta_dev(ctx);
+    UvMeta* mh = uv_meta_host(ctx);
+    hipLaunchKernelGGL(k_uv_init, dim3(1), dim3(64), 0, st, md);
+    const float* cp = pts;
+    const int32_t* cidx = nullptr;
+    int64_t m = n;
+    if (mask) {
+        // the kept points, compacted in ascending order
+        auto* flags = (uint32_t*)(sb + o_fl);
+        auto* cpts = (float*)(sb + o_cp);
+        auto* ci = (int32_t*)(sb + o_ci);
+        hipLaunchKernelGGL(k_mask_flags, dim3(grid_of(n, WT)), dim3(WT), 0, st, mask, n, flags);
+        scan_words(st, flags, n, (uint32_t*)(sb + o_tmp));
+        hipLaunchKernelGGL(k_mask_compact, dim3(grid_of(n, WT)), dim3(WT), 0, st, pts, mask, n,
+                           (const uint32_t*)flags, cpts, ci, md);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(n, WT)), dim3(WT), 0, st, labels, n, -1);
+        LKC_HIP_TRY(ctx, hipGetLastError());
+        LKC_HIP_TRY(ctx, hipMemcpyAsync(mh, md, sizeof(UvMeta), hipMemcpyDeviceToHost, st));
+        LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+        m = mh->kept;
+        cp = cpts;
+        cidx = ci;
+        if (m == 0) return LKC_OK;
+    }
     lkc_target& grid = *ctx->cluster_grid;
     grid.cell_size = 1.25f * eps;
-    lkc_status s = build_into(ctx, &grid, pts, n);
+    s = build_into(ctx, &grid, cp, m);
     if (s == LKC_OK) {
         const float reach = grid.view.max_abs * grid.view.inv_cell;
         if (!(reach < (float)((1 << 20) - 4)))
@@ -285,19 +362,12 @@ lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
                           "eps %g is too small for the cloud's extent (|p| up to %g)",
                           (double)eps, (double)grid.view.max_abs);
     }
-    int32_t* par = nullptr;
     if (s == LKC_OK) {
-        par = (int32_t*)aux_scratch(ctx, 4 * (size_t)n, &s);
-    }
-    if (s == LKC_OK) {
-        UvMeta* md = uv_meta_dev(ctx);
-        UvMeta* mh = uv_meta_host(ctx);
-        hipLaunchKernelGGL(k_uv_init, dim3(1), dim3(64), 0, st, md);
-        hipLaunchKernelGGL(k_parent_init, dim3(grid_of(n, WT)), dim3(WT), 0, st, par, n);
-        hipLaunchKernelGGL(k_cluster_union, dim3(grid_of(n, WT)), dim3(WT), 0, st,
+        hipLaunchKernelGGL(k_parent_init, dim3(grid_of(m, WT)), dim3(WT), 0, st, par, m);
+        hipLaunchKernelGGL(k_cluster_union, dim3(grid_of(m, WT)), dim3(WT), 0, st,
                            (const TargetView*)grid.view_dev, eps * eps, par, md);
-        hipLaunchKernelGGL(k_cluster_labels, dim3(grid_of(n, WT)), dim3(WT), 0, st, par, n,
-                           labels, md);
+        hipLaunchKernelGGL(k_cluster_labels, dim3(grid_of(m, WT)), dim3(WT), 0, st, par, m,
+                           cidx, labels, md);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(mh, md, sizeof(UvMeta), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

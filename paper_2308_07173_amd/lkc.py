@@ -147,7 +147,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_submap_extract": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64)], I32),
             "lkc_submap_build": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64), PP], I32),
             "lkc_zvote": ([P, P, I64, F, I32, P, P], I32),
-            "lkc_euclid_cluster": ([P, P, I64, F, P, ctypes.POINTER(ctypes.c_int64)], I32),
+            "lkc_euclid_cluster": ([P, P, I64, F, P, P, ctypes.POINTER(ctypes.c_int64)], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -590,17 +590,21 @@ def lkc_zvote(ctx: Context, points, cell: float, tau: int, with_votes: bool = Tr
     return keep, votes
 
 
-def lkc_euclid_cluster(ctx: Context, points, eps: float):
-    """Distance clustering: (labels int32 [n] device, number of clusters)."""
+def lkc_euclid_cluster(ctx: Context, points, eps: float, mask=None):
+    """Distance clustering: (labels int32 [n] device, number of clusters);
+    ``mask`` (device uint8 [n]) selects the points, the others get -1."""
     torch = _torch()
     _check_dev(points, "points", torch.float32, (3,))
+    _check_dev(mask, "mask", torch.uint8)
     n = points.shape[0]
+    if mask is not None and mask.shape[0] != n:
+        raise ValueError("mask must have one entry per point")
     labels = torch.empty(n, dtype=torch.int32, device=points.device)
     k = ctypes.c_int64(0)
     ctx._bind()
     ctx.check(ctx.lib.lkc_euclid_cluster(ctx.handle, ctypes.c_void_p(_ptr(points)), n,
-                                         float(eps), ctypes.c_void_p(_ptr(labels)),
-                                         ctypes.byref(k)))
+                                         float(eps), ctypes.c_void_p(_ptr(mask)),
+                                         ctypes.c_void_p(_ptr(labels)), ctypes.byref(k)))
     return labels, k.value
 
 

@@ -91,22 +91,53 @@ def test_cluster_inclusive_lattice(lk):
     np.testing.assert_array_equal(labels.cpu().numpy(), np.arange(len(p)))
 
 
-def test_wall_pipeline_plane_wall(lk):
-    """voxel filter -> z-vote -> clustering on the plane + wall: the kept
-    points form one wall cluster, matching the oracle end to end."""
+def masked_oracle(v, keep, eps):
+    """Oracle labels of the kept points, mapped back to the full index space."""
+    idx = np.flatnonzero(keep)
+    ol, oc = oracle.euclid_cluster(v[idx], eps)
+    full = np.full(len(v), -1, np.int32)
+    full[idx] = idx[ol]
+    return full, oc
+
+
+@pytest.mark.parametrize("cloud,cell,tau", [("plane_wall", 0.5, 14), ("scan", 0.2, 3)])
+def test_wall_pipeline(lk, cloud, cell, tau):
+    """voxel filter -> z-vote -> masked clustering, all on the device, equals
+    the oracle end to end; on the plane + wall the wall is one cluster, on a
+    scan the two track walls are the two largest clusters."""
     lkc, ctx = lk
-    p = workloads.plane_wall(20_000, seed=1)
+    p = workloads.plane_wall(20_000, seed=1) if cloud == "plane_wall" else \
+        workloads.single_scan(seed=1)
     vox = lkc.lkc_voxel_filter(ctx, dev(p), 0.2)["centroid"]
-    keep, _ = lkc.lkc_zvote(ctx, vox, 0.5, 14)
-    kept = vox[keep.bool()].contiguous()
-    labels, k = lkc.lkc_euclid_cluster(ctx, kept, 0.5)
+    keep, _ = lkc.lkc_zvote(ctx, vox, cell, tau, with_votes=False)
+    labels, k = lkc.lkc_euclid_cluster(ctx, vox, 0.5, mask=keep)
     v = oracle.voxel_filter(p, 0.2)["centroid"].astype(np.float32)
-    ok, _ = oracle.zvote(v, 0.5, 14)
-    ol, oc = oracle.euclid_cluster(v[ok == 1], 0.5)
+    ok, _ = oracle.zvote(v, cell, tau)
+    np.testing.assert_array_equal(keep.cpu().numpy(), ok)
+    full, oc = masked_oracle(v, ok, 0.5)
     assert k == oc
-    np.testing.assert_array_equal(labels.cpu().numpy(), ol)
-    sizes = np.bincount(ol)
-    assert sizes.max() > 0.9 * len(ol)          # the wall is one cluster
+    np.testing.assert_array_equal(labels.cpu().numpy(), full)
+    sizes = np.sort(np.bincount(full[full >= 0]))[::-1]
+    if cloud == "plane_wall":
+        assert sizes[0] > 0.9 * (full >= 0).sum()           # the wall is one cluster
+    else:
+        assert sizes[1] > 5 * sizes[2]                       # two walls dominate
+
+
+def test_cluster_mask_edge_cases(lk):
+    lkc, ctx = lk
+    p = workloads.random_cloud(4000, 8, scale=4.0)
+    p[::50] = np.nan                                         # masked out: allowed
+    mask = np.ones(4000, np.uint8)
+    mask[::50] = 0
+    mask[7::9] = 0
+    labels, k = lkc.lkc_euclid_cluster(ctx, dev(p), 0.35, mask=dev(mask))
+    full, oc = masked_oracle(p, mask, 0.35)
+    assert k == oc
+    np.testing.assert_array_equal(labels.cpu().numpy(), full)
+    none = np.zeros(4000, np.uint8)
+    labels, k = lkc.lkc_euclid_cluster(ctx, dev(p), 0.35, mask=dev(none))
+    assert k == 0 and np.all(labels.cpu().numpy() == -1)
 
 
 def test_cluster_errors_and_grid_reuse(lk):
