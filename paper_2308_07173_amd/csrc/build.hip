@@ -35,6 +35,7 @@ constexpr int RS_ITEMS = 8;      // radix items per thread per tile
 constexpr int RS_TILE = BT * RS_ITEMS;
 constexpr int RADIX = 256;
 constexpr int SCAN_TILE = 4096;  // entries per workgroup of the multi-block scan
+constexpr int RAW_OFFSET_TILES = 96;  // sorts of up to this many tiles skip the scan launch
 
 struct BuildMeta {
     int cmin[3];
@@ -288,16 +289,39 @@ __global__ void __launch_bounds__(BT) k_scan_add(uint32_t* __restrict__ data, in
 // order (256 consecutive items per step); within a step the rank of an item
 // among equal digits is (items of that digit in earlier steps) + (in earlier
 // wavefronts of this step) + (in lower lanes of its wavefront).
+//
+// With `raw` set, `offsets` holds the unscanned per-tile histograms and each
+// workgroup derives its own offsets (digit totals scanned across the
+// workgroup, plus the counts of the earlier tiles); used when there are few
+// tiles, so the separate scan launch is saved.
 __global__ void __launch_bounds__(BT) k_radix_scatter(
     const unsigned long long* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n,
-    int shift, const uint32_t* __restrict__ offsets, int nblocks) {
+    int shift, const uint32_t* __restrict__ offsets, int nblocks, int raw) {
     constexpr int NW = BT / WAVE;
     __shared__ uint32_t goff[RADIX];
     __shared__ uint32_t run[RADIX];
     __shared__ uint32_t wcnt[NW][RADIX];
     const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
-    goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+    if (raw) {
+        const uint32_t* row = offsets + (int64_t)tid * nblocks;
+        uint32_t tot = 0, pre = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            const uint32_t c = row[b];
+            pre += b < (int)blockIdx.x ? c : 0u;
+            tot += c;
+        }
+        // exclusive scan of the digit totals across the workgroup
+        const int incl = wave_incl_scan((int)tot);
+        if (l == WAVE - 1) run[w] = (uint32_t)incl;
+        __syncthreads();
+        uint32_t wo = 0;
+        for (int j = 0; j < w; ++j) wo += run[j];
+        goff[tid] = wo + (uint32_t)incl - tot + pre;
+        __syncthreads();
+    } else {
+        goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+    }
     run[tid] = 0;
     const unsigned long long lt_mask = (1ull << l) - 1ull;
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
@@ -518,12 +542,13 @@ lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsign
     const int64_t m = (int64_t)RADIX * nb;
     uint32_t* tmp = counts + m;
     bool b = false;
+    const int raw = nb <= RAW_OFFSET_TILES ? 1 : 0;
     for (int shift = 0; shift < bits && n > 1; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(BT), 0, st, ka, n, shift,
                            counts, (int)nb);
-        scan_exclusive(st, counts, m, tmp);
+        if (!raw) scan_exclusive(st, counts, m, tmp);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(BT), 0, st, ka, va, kb, vb,
-                           n, shift, counts, (int)nb);
+                           n, shift, counts, (int)nb, raw);
         std::swap(ka, kb);
         std::swap(va, vb);
         b = !b;
