@@ -99,13 +99,21 @@ typedef enum lkc_status {
  *                   (0 = 12; 1..65, 65 disables the network)
  *  persistent       0: one wavefront per 64-query group; n > 0: n persistent
  *                   workgroups per compute unit pull groups from per-XCD
- *                   work counters (0..32) */
+ *                   work counters (0..32)
+ *  group_split      0 auto; 1 one wavefront per group; 2 two wavefronts per
+ *                   group, each streaming half of the candidate chunks (they
+ *                   share their k-th distances through LDS and merge their
+ *                   lists at the end).  Auto splits when the launch has at
+ *                   most 8 groups per compute unit, where the slowest group
+ *                   sets the kernel time.  Not with persistent > 0.  Results
+ *                   are bit-identical either way. */
 typedef struct lkc_launch_cfg {
     int32_t algorithm;
     int32_t group_reach;
     int32_t waves_per_block;
     int32_t merge_min;
     int32_t persistent;
+    int32_t group_split;
 } lkc_launch_cfg;
 
 /* Static description of a built target (host struct). */

@@ -130,6 +130,7 @@ struct LaunchCfg {
     int waves_per_block;
     int merge_min;
     int persistent;       // 0 = one wave per group; n = n persistent workgroups per CU
+    int group_split;      // 0 auto, 1 off, 2 two waves per group
 };
 LaunchCfg resolve_cfg(const lkc_launch_cfg* cfg);
 lkc_status check_launch_cfg(lkc_ctx* ctx, const LaunchCfg& c);

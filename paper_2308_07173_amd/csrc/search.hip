@@ -594,6 +594,17 @@ struct GroupArgs {
     uint32_t* fb_count;
     uint32_t* counters;               // per-XCD work counters (persistent mode) or NULL
     uint32_t* prof;                   // optional per-group counters (PROF_WORDS each) or NULL
+    int split;                        // waves per group (1 or 2)
+};
+
+// Two waves sharing a group: each streams the chunks it owns (chunk index
+// parity) and publishes its lanes' k-th distances here; the other wave
+// prunes with the smaller of the two, which is still an upper bound of the
+// final k-th distance (each list holds k distinct candidates).
+struct SplitShare {
+    volatile float* thr;   // [2][64]
+    int sub;               // this wave's index in the group
+    int split_mask;        // split - 1
 };
 
 // per-group profile words: clock cycles, probe rounds, cells streamed,
@@ -663,14 +674,16 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                                          const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr,
                                          unsigned long long (&kk)[K], int mode,
-                                         GroupProf& gp, int skip_cb) {
+                                         GroupProf& gp, int skip_cb, const SplitShare& sh) {
     const int lane = lane_id();
 #pragma unroll 1
     for (int cb = s0 & ~(WAVE - 1); cb < e0; cb += WAVE) {
         if (cb == skip_cb) continue;   // streamed first, as the group's own chunk
+        if (((cb / WAVE) & sh.split_mask) != sh.sub) continue;   // the other wave's chunk
         uint32_t keep = 0;
         // this lane's current k-th distance (radius while its list is not full)
-        const float lthr = kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2);
+        float lthr = kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2);
+        if (sh.split_mask) lthr = fminf(lthr, sh.thr[(sh.sub ^ 1) * WAVE + lane]);
 #pragma unroll
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
             const int sb = cb + q4 * BOX_PTS;
@@ -732,12 +745,18 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             gp.inserts += (uint32_t)__popcll(im);
             gp.dead += im ? 0u : 1u;
         } while (ballot(bits != 0ull));
-        gthr = wave_max_dpp(member ? (kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1])) : -INF);
+        float own = kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1]);
+        if (sh.split_mask) {
+            sh.thr[sh.sub * WAVE + lane] = own;
+            own = fminf(own, sh.thr[(sh.sub ^ 1) * WAVE + lane]);
+        }
+        gthr = wave_max_dpp(member ? own : -INF);
     }
 }
 
 template <int K, int FUSED>
-__device__ void group_body(const GroupArgs& a, int64_t group) {
+__device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& sh,
+                           unsigned long long* s_kk) {
     const int lane = lane_id();
     const int64_t slot = group * WAVE + lane;
     const bool active = slot < a.n_slots;
@@ -797,7 +816,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
             own_cb = (int)(group * WAVE);
             const uint32_t i0 = gp.inserts;
             scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
-                        s.z, r2, b0, b1, margin, gthr, kk, 2, gp, -1);
+                        s.z, r2, b0, b1, margin, gthr, kk, 2, gp, -1, sh);
             gp.own += gp.inserts - i0;
         }
         for (int pass = 0; pass < 2; ++pass) {
@@ -835,7 +854,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
                         const int e0 = s0 + readlane((int)cn, cl);
                         gp.cells++;
                         scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, b0, b1, margin, gthr,
-                                    kk, mode, gp, own_cb);
+                                    kk, mode, gp, own_cb, sh);
                     }
                     const uint32_t di = gp.inserts - i0, dc = gp.cands - c0;
                     if (mode == 0) {
@@ -848,6 +867,26 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
                         gp.ins2 += di;
                         gp.cand2 += dc;
                     }
+                }
+            }
+        }
+        if (sh.split_mask) {
+            // both waves have streamed their chunks: wave 1 hands its lists to
+            // wave 0 through LDS, wave 0 inserts the entries below its k-th
+            // key (each list is ascending, so a lane stops at its first miss)
+            __syncthreads();
+            if (sh.sub == 1) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) s_kk[j * WAVE + lane] = kk[j];
+            }
+            __syncthreads();
+            if (sh.sub == 0) {
+#pragma unroll 1
+                for (int j = pad; j < K; ++j) {
+                    const unsigned long long x = s_kk[j * WAVE + lane];
+                    const bool ins = member && x < kk[K - 1];
+                    if (!ballot(ins)) break;
+                    if (ins) lane_insert<K>(kk, x);
                 }
             }
         }
@@ -867,6 +906,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group) {
             ok = covers || (full && f2 > key_d2(kk[K - 1])) || (a.sp.capped && f2 > r2);
         }
     }
+    if (sh.sub) return;   // the second wave of a split group is done
     const bool to_fb = (fin && !member) || (member && !ok);
     const unsigned long long fm = ballot(to_fb);
     if (a.prof && lane == 0) {
@@ -929,9 +969,21 @@ template <int K, int FUSED>
 __global__ void __launch_bounds__(256) k_group(GroupArgs a) {
     const int wpb = blockDim.x / WAVE;
     const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
+    const SplitShare none{nullptr, 0, 0};
+    if (a.split > 1) {
+        // one group per workgroup of two waves
+        __shared__ float s_thr[2 * WAVE];
+        __shared__ unsigned long long s_kk[K * WAVE];
+        s_thr[threadIdx.x] = a.sp.r2;
+        __syncthreads();
+        const SplitShare sh{s_thr, (int)(threadIdx.x / WAVE), 1};
+        const int64_t g = (int64_t)xcd_tile(blockIdx.x, gridDim.x);
+        if (g < n_groups) group_body<K, FUSED>(a, g, sh, s_kk);
+        return;
+    }
     if (!a.counters) {
         const int64_t g = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * wpb + threadIdx.x / WAVE;
-        if (g < n_groups) group_body<K, FUSED>(a, g);
+        if (g < n_groups) group_body<K, FUSED>(a, g, none, nullptr);
         return;
     }
     // persistent: the groups are split into 8 contiguous ranges, one per XCD
@@ -948,7 +1000,7 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs a) {
             t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             const int64_t g = g_lo + t;
             if (g >= g_hi) break;
-            group_body<K, FUSED>(a, g);
+            group_body<K, FUSED>(a, g, none, nullptr);
         }
     }
 }
@@ -1264,19 +1316,27 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
         a.R = R;
         if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
         const int64_t n_groups = (j.n_slots + WAVE - 1) / WAVE;
-        unsigned blocks;
+        unsigned blocks, threads = wpb * WAVE;
+        a.split = 1;
         if (cfg.persistent > 0) {
             a.counters = sc.words + 8;
             blocks = (unsigned)(ctx->num_cus * cfg.persistent);
+        } else if (cfg.group_split == 2 ||
+                   (cfg.group_split == 0 && n_groups <= 8 * (int64_t)ctx->num_cus)) {
+            // few groups: the slowest one sets the kernel time, so two waves
+            // share each group
+            a.split = 2;
+            blocks = (unsigned)n_groups;
+            threads = 2 * WAVE;
         } else {
             blocks = (unsigned)((n_groups + wpb - 1) / wpb);
         }
         if (j.fused == 2)
-            launch_group<2>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+            launch_group<2>(K, dim3(blocks), dim3(threads), st, a);
         else if (j.fused == 1)
-            launch_group<1>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+            launch_group<1>(K, dim3(blocks), dim3(threads), st, a);
         else
-            launch_group<0>(K, dim3(blocks), dim3(wpb * WAVE), st, a);
+            launch_group<0>(K, dim3(blocks), dim3(threads), st, a);
     } else {
         // every query goes to the wavefront-per-query search
         hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, sc.words, 16,
@@ -1310,6 +1370,10 @@ lkc_status check_cfg(lkc_ctx* ctx, const LaunchCfg& c) {
         return set_error(ctx, LKC_ERR_INVALID_ARG, "merge_min must be in [1, 65]");
     if (c.persistent < 0 || c.persistent > 32)
         return set_error(ctx, LKC_ERR_INVALID_ARG, "persistent must be in [0, 32]");
+    if (c.group_split < 0 || c.group_split > 2)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "group_split must be 0, 1 or 2");
+    if (c.group_split == 2 && c.persistent > 0)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "group_split 2 needs persistent 0");
     return LKC_OK;
 }
 
@@ -1323,13 +1387,14 @@ lkc_status reserve_search(lkc_ctx* ctx, int64_t max_queries) {
 }
 
 LaunchCfg resolve_cfg(const lkc_launch_cfg* c) {
-    LaunchCfg r{0, 0, 4, 12, 0};
+    LaunchCfg r{0, 0, 4, 12, 0, 0};
     if (c) {
         r.algorithm = c->algorithm;
         r.group_reach = c->group_reach;
         if (c->waves_per_block != 0) r.waves_per_block = c->waves_per_block;
         if (c->merge_min != 0) r.merge_min = c->merge_min;
         r.persistent = c->persistent;
+        r.group_split = c->group_split;
     }
     return r;
 }

@@ -60,7 +60,7 @@ class LkcError(RuntimeError):
 class LaunchCfg(ctypes.Structure):
     _fields_ = [("algorithm", ctypes.c_int32), ("group_reach", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("merge_min", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("group_split", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -62,7 +62,7 @@ def test_ctx_create_without_gpu_fails_cleanly(lib):
 
 
 def test_struct_layouts():
-    assert ctypes.sizeof(lkc.LaunchCfg) == 20
+    assert ctypes.sizeof(lkc.LaunchCfg) == 24
     assert ctypes.sizeof(lkc.ScanDesc) == 24
     assert ctypes.sizeof(lkc.GicpStats) == 4 + 4 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lkc.TargetInfo) == 8 * 3 + 4 * 6 + 4 * 3 + 4 + 8

@@ -183,7 +183,8 @@ def test_knn_bad_arguments_raise(lk):
             lkc.lkc_knn_query(ctx, t, q, k, r)
         assert e.value.status == lkc.LKC_ERR_INVALID_ARG
     for cfg in [dict(algorithm=3), dict(waves_per_block=5), dict(merge_min=66),
-                dict(group_reach=5), dict(persistent=33)]:
+                dict(group_reach=5), dict(persistent=33), dict(group_split=3),
+                dict(group_split=2, persistent=1)]:
         with pytest.raises(lkc.LkcError):
             lkc.lkc_knn_query(ctx, t, q, 3, 1.0, cfg=cfg)
     with pytest.raises(lkc.LkcError):
@@ -194,7 +195,9 @@ def test_knn_bad_arguments_raise(lk):
 @pytest.mark.parametrize("cfg", [dict(algorithm=2), dict(algorithm=2, merge_min=65),
                                  dict(algorithm=2, merge_min=1, waves_per_block=1),
                                  dict(group_reach=1), dict(group_reach=3, waves_per_block=2),
-                                 dict(persistent=2), dict(persistent=1, waves_per_block=2)])
+                                 dict(persistent=2), dict(persistent=1, waves_per_block=2),
+                                 dict(group_split=1), dict(group_split=2),
+                                 dict(group_split=2, group_reach=1)])
 def test_knn_launch_shapes_agree(lk, cfg):
     """Both search algorithms and every launch shape give the same bits (the
     result is independent of the order candidates are visited in)."""
@@ -205,6 +208,29 @@ def test_knn_launch_shapes_agree(lk, cfg):
         b = run_knn(lk, p, q, 20, radius, 1.0, cfg=cfg)
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("k", [5, 16, 20, 32])
+def test_group_split_is_bitwise_identical(lk, k):
+    """Two waves per group (half the chunks each, shared thresholds, merged
+    lists) give the same bits as one wave, for self and external queries,
+    with the fused covariance."""
+    lkc, ctx = lk
+    p = workloads.single_scan(seed=8)[::3].copy()
+    t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+    q = dev(p[::2].copy())
+    for radius in (2.0, INF):
+        outs = []
+        for split in (1, 2):
+            cfg = dict(group_split=split)
+            a = lkc.lkc_knn_cov_self(ctx, t, k, radius, 1e-3, cfg=cfg)
+            b = lkc.lkc_knn_cov(ctx, t, q, k, radius, 1e-3, cfg=cfg)
+            torch.cuda.synchronize()
+            outs.append((a, b))
+        for x, y in zip(outs[0], outs[1]):
+            for key in x:
+                assert torch.equal(x[key], y[key]), (k, radius, key)
+    t.free()
 
 
 def test_self_query_matches_plain_and_oracle(lk):
