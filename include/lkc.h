@@ -100,13 +100,15 @@ typedef enum lkc_status {
  *  persistent       0: one wavefront per 64-query group; n > 0: n persistent
  *                   workgroups per compute unit pull groups from per-XCD
  *                   work counters (0..32)
- *  group_split      0 auto; 1 one wavefront per group; 2 two wavefronts per
- *                   group, each streaming half of the candidate chunks (they
- *                   share their k-th distances through LDS and merge their
- *                   lists at the end).  Auto splits when the launch has at
- *                   most 8 groups per compute unit, where the slowest group
- *                   sets the kernel time.  Not with persistent > 0.  Results
- *                   are bit-identical either way. */
+ *  group_split      0 auto; 1 one wavefront per group; 2 or 4 wavefronts
+ *                   per group, each streaming its share of the candidate
+ *                   chunks (they share their k-th distances through LDS and
+ *                   merge their lists pairwise at the end).  Auto splits
+ *                   when the split groups still fit at four wavefronts per
+ *                   SIMD (4 if they do at 4, else 2 at up to 8 groups per
+ *                   compute unit), where the slowest group sets the kernel
+ *                   time.  Not with persistent > 0.  Results are
+ *                   bit-identical either way. */
 typedef struct lkc_launch_cfg {
     int32_t algorithm;
     int32_t group_reach;

@@ -594,18 +594,24 @@ struct GroupArgs {
     uint32_t* fb_count;
     uint32_t* counters;               // per-XCD work counters (persistent mode) or NULL
     uint32_t* prof;                   // optional per-group counters (PROF_WORDS each) or NULL
-    int split;                        // waves per group (1 or 2)
+    int split;                        // waves per group (1, 2 or 4)
 };
 
-// Two waves sharing a group: each streams the chunks it owns (chunk index
-// parity) and publishes its lanes' k-th distances here; the other wave
-// prunes with the smaller of the two, which is still an upper bound of the
+// Waves sharing a group: each streams the chunks it owns (chunk index
+// modulo the split) and publishes its lanes' k-th distances here; the others
+// prune with the smallest of them, which is still an upper bound of the
 // final k-th distance (each list holds k distinct candidates).
 struct SplitShare {
-    volatile float* thr;   // [2][64]
+    volatile float* thr;   // [split][64]
     int sub;               // this wave's index in the group
     int split_mask;        // split - 1
 };
+
+__device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, float own) {
+    for (int w = 0; w <= sh.split_mask; ++w)
+        if (w != sh.sub) own = fminf(own, sh.thr[w * WAVE + lane]);
+    return own;
+}
 
 // per-group profile words: clock cycles, probe rounds, cells streamed,
 // 64-point chunks loaded, candidates tested, insertion pops, member lanes,
@@ -683,7 +689,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         uint32_t keep = 0;
         // this lane's current k-th distance (radius while its list is not full)
         float lthr = kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2);
-        if (sh.split_mask) lthr = fminf(lthr, sh.thr[(sh.sub ^ 1) * WAVE + lane]);
+        if (sh.split_mask) lthr = shared_thr(sh, lane, lthr);
 #pragma unroll
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
             const int sb = cb + q4 * BOX_PTS;
@@ -748,7 +754,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         float own = kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1]);
         if (sh.split_mask) {
             sh.thr[sh.sub * WAVE + lane] = own;
-            own = fminf(own, sh.thr[(sh.sub ^ 1) * WAVE + lane]);
+            own = shared_thr(sh, lane, own);
         }
         gthr = wave_max_dpp(member ? own : -INF);
     }
@@ -871,22 +877,28 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             }
         }
         if (sh.split_mask) {
-            // both waves have streamed their chunks: wave 1 hands its lists to
-            // wave 0 through LDS, wave 0 inserts the entries below its k-th
-            // key (each list is ascending, so a lane stops at its first miss)
-            __syncthreads();
-            if (sh.sub == 1) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) s_kk[j * WAVE + lane] = kk[j];
-            }
-            __syncthreads();
-            if (sh.sub == 0) {
+            // every wave has streamed its chunks: merge the lists pairwise
+            // through LDS (wave w + stride hands its lists to wave w, which
+            // inserts the entries below its k-th key; each list is
+            // ascending, so a lane stops at its first miss)
 #pragma unroll 1
-                for (int j = pad; j < K; ++j) {
-                    const unsigned long long x = s_kk[j * WAVE + lane];
-                    const bool ins = member && x < kk[K - 1];
-                    if (!ballot(ins)) break;
-                    if (ins) lane_insert<K>(kk, x);
+            for (int stride = 1; stride <= sh.split_mask; stride <<= 1) {
+                const int slot = sh.sub / (2 * stride);
+                unsigned long long* buf = s_kk + (int64_t)slot * K * WAVE;
+                __syncthreads();
+                if (sh.sub % (2 * stride) == stride) {
+#pragma unroll
+                    for (int j = 0; j < K; ++j) buf[j * WAVE + lane] = kk[j];
+                }
+                __syncthreads();
+                if (sh.sub % (2 * stride) == 0) {
+#pragma unroll 1
+                    for (int j = pad; j < K; ++j) {
+                        const unsigned long long x = buf[j * WAVE + lane];
+                        const bool ins = member && x < kk[K - 1];
+                        if (!ballot(ins)) break;
+                        if (ins) lane_insert<K>(kk, x);
+                    }
                 }
             }
         }
@@ -971,12 +983,12 @@ __global__ void __launch_bounds__(256) k_group(GroupArgs a) {
     const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
     const SplitShare none{nullptr, 0, 0};
     if (a.split > 1) {
-        // one group per workgroup of two waves
-        __shared__ float s_thr[2 * WAVE];
-        __shared__ unsigned long long s_kk[K * WAVE];
+        // one group per workgroup of `split` waves
+        __shared__ float s_thr[4 * WAVE];
+        __shared__ unsigned long long s_kk[2 * K * WAVE];
         s_thr[threadIdx.x] = a.sp.r2;
         __syncthreads();
-        const SplitShare sh{s_thr, (int)(threadIdx.x / WAVE), 1};
+        const SplitShare sh{s_thr, (int)(threadIdx.x / WAVE), a.split - 1};
         const int64_t g = (int64_t)xcd_tile(blockIdx.x, gridDim.x);
         if (g < n_groups) group_body<K, FUSED>(a, g, sh, s_kk);
         return;
@@ -1321,13 +1333,15 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
         if (cfg.persistent > 0) {
             a.counters = sc.words + 8;
             blocks = (unsigned)(ctx->num_cus * cfg.persistent);
-        } else if (cfg.group_split == 2 ||
-                   (cfg.group_split == 0 && n_groups <= 8 * (int64_t)ctx->num_cus)) {
-            // few groups: the slowest one sets the kernel time, so two waves
-            // share each group
-            a.split = 2;
+        } else if (cfg.group_split > 1 ||
+                   (cfg.group_split == 0 && 2 * n_groups <= 16 * (int64_t)ctx->num_cus)) {
+            // few groups: the slowest one sets the kernel time, so several
+            // waves share each group (as many as still fit at four waves per
+            // SIMD)
+            a.split = cfg.group_split > 1 ? cfg.group_split
+                      : (4 * n_groups <= 16 * (int64_t)ctx->num_cus ? 4 : 2);
             blocks = (unsigned)n_groups;
-            threads = 2 * WAVE;
+            threads = (unsigned)(a.split * WAVE);
         } else {
             blocks = (unsigned)((n_groups + wpb - 1) / wpb);
         }
@@ -1370,10 +1384,10 @@ lkc_status check_cfg(lkc_ctx* ctx, const LaunchCfg& c) {
         return set_error(ctx, LKC_ERR_INVALID_ARG, "merge_min must be in [1, 65]");
     if (c.persistent < 0 || c.persistent > 32)
         return set_error(ctx, LKC_ERR_INVALID_ARG, "persistent must be in [0, 32]");
-    if (c.group_split < 0 || c.group_split > 2)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "group_split must be 0, 1 or 2");
-    if (c.group_split == 2 && c.persistent > 0)
-        return set_error(ctx, LKC_ERR_INVALID_ARG, "group_split 2 needs persistent 0");
+    if (c.group_split < 0 || c.group_split > 4 || c.group_split == 3)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "group_split must be 0, 1, 2 or 4");
+    if (c.group_split > 1 && c.persistent > 0)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "group_split > 1 needs persistent 0");
     return LKC_OK;
 }
 

@@ -184,6 +184,7 @@ def test_knn_bad_arguments_raise(lk):
         assert e.value.status == lkc.LKC_ERR_INVALID_ARG
     for cfg in [dict(algorithm=3), dict(waves_per_block=5), dict(merge_min=66),
                 dict(group_reach=5), dict(persistent=33), dict(group_split=3),
+                dict(group_split=5),
                 dict(group_split=2, persistent=1)]:
         with pytest.raises(lkc.LkcError):
             lkc.lkc_knn_query(ctx, t, q, 3, 1.0, cfg=cfg)
@@ -196,7 +197,7 @@ def test_knn_bad_arguments_raise(lk):
                                  dict(algorithm=2, merge_min=1, waves_per_block=1),
                                  dict(group_reach=1), dict(group_reach=3, waves_per_block=2),
                                  dict(persistent=2), dict(persistent=1, waves_per_block=2),
-                                 dict(group_split=1), dict(group_split=2),
+                                 dict(group_split=1), dict(group_split=2), dict(group_split=4),
                                  dict(group_split=2, group_reach=1)])
 def test_knn_launch_shapes_agree(lk, cfg):
     """Both search algorithms and every launch shape give the same bits (the
@@ -221,15 +222,16 @@ def test_group_split_is_bitwise_identical(lk, k):
     q = dev(p[::2].copy())
     for radius in (2.0, INF):
         outs = []
-        for split in (1, 2):
+        for split in (1, 2, 4):
             cfg = dict(group_split=split)
             a = lkc.lkc_knn_cov_self(ctx, t, k, radius, 1e-3, cfg=cfg)
             b = lkc.lkc_knn_cov(ctx, t, q, k, radius, 1e-3, cfg=cfg)
             torch.cuda.synchronize()
             outs.append((a, b))
-        for x, y in zip(outs[0], outs[1]):
-            for key in x:
-                assert torch.equal(x[key], y[key]), (k, radius, key)
+        for other in outs[1:]:
+            for x, y in zip(outs[0], other):
+                for key in x:
+                    assert torch.equal(x[key], y[key]), (k, radius, key)
     t.free()
 
 
