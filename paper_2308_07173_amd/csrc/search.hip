@@ -543,7 +543,7 @@ struct KnnPtrs {
 // radius, reaches past the block) is handed to the wavefront-per-query
 // search through a fallback list.
 
-constexpr int GROUP_W = 2;   // lanes farther than this (cells) from the anchor fall back
+constexpr int GROUP_W = 2;       // lanes within this many cells of a round's anchor take part
 
 __device__ __forceinline__ unsigned long long lane_key(float d, int32_t idx) {
     return ((unsigned long long)(__float_as_uint(d) + 1u) << 32) | (uint32_t)idx;
@@ -595,6 +595,7 @@ struct GroupArgs {
     uint32_t* counters;               // per-XCD work counters (persistent mode) or NULL
     uint32_t* prof;                   // optional per-group counters (PROF_WORDS each) or NULL
     int split;                        // waves per group (1, 2 or 4)
+    int rounds;                       // anchor rounds per group (lanes left fall back)
 };
 
 // Waves sharing a group: each streams the chunks it owns (chunk index
@@ -776,25 +777,32 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     const int cy = fin ? cell_coord(s.y, T.inv_cell) : 0;
     const int cz = fin ? cell_coord(s.z, T.inv_cell) : 0;
     const bool same = fin && s.tgt == gt;
-    const unsigned long long sm = ballot(same);
-    bool member = false;
-    if (sm) {
-        const int L0 = __builtin_ffsll((long long)sm) - 1;
-        const int ax = readlane(cx, L0), ay = readlane(cy, L0), az = readlane(cz, L0);
-        member = same && abs(cx - ax) <= GROUP_W && abs(cy - ay) <= GROUP_W &&
-                 abs(cz - az) <= GROUP_W;
-    }
     const float r2 = a.sp.r2;
     const int k = a.sp.k;
     const int pad = K - k;
     unsigned long long kk[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) kk[j] = (j < pad) ? 0ull : ~0ull;
-    const unsigned long long mm = ballot(member);
     bool ok = true;
+    // An empty target answers every query with an empty list.
+    bool placed = same && T.n_cells == 0;   // searched by one of the rounds below
     GroupProf gp{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const unsigned long long t_start = a.prof ? __builtin_amdgcn_s_memtime() : 0ull;
-    if (mm && T.n_cells > 0) {
+    // Rounds: each takes the first unplaced lane as anchor and searches for
+    // every unplaced lane within GROUP_W cells of it, so a group whose sorted
+    // queries straddle two clusters can be served in two rounds rather than
+    // handing one cluster to the wavefront-per-query search.  Every round
+    // streams a whole block, so the launch sets the number of rounds.
+    unsigned long long pending = T.n_cells > 0 ? ballot(same) : 0ull;
+#pragma unroll 1
+    for (int round = 0; round < a.rounds && pending; ++round) {
+        const int L0 = __builtin_ffsll((long long)pending) - 1;
+        const int ax = readlane(cx, L0), ay = readlane(cy, L0), az = readlane(cz, L0);
+        const bool member = ((pending >> lane) & 1ull) && abs(cx - ax) <= GROUP_W &&
+                            abs(cy - ay) <= GROUP_W && abs(cz - az) <= GROUP_W;
+        const unsigned long long mm = ballot(member);
+        pending &= ~mm;
+        placed = placed || member;
         const float bx0 = wave_min_dpp(member ? s.x : INF), bx1 = wave_max_dpp(member ? s.x : -INF);
         const float by0 = wave_min_dpp(member ? s.y : INF), by1 = wave_max_dpp(member ? s.y : -INF);
         const float bz0 = wave_min_dpp(member ? s.z : INF), bz1 = wave_max_dpp(member ? s.z : -INF);
@@ -918,8 +926,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             ok = covers || (full && f2 > key_d2(kk[K - 1])) || (a.sp.capped && f2 > r2);
         }
     }
-    if (sh.sub) return;   // the second wave of a split group is done
-    const bool to_fb = (fin && !member) || (member && !ok);
+    if (sh.sub) return;   // the other waves of a split group are done
+    const bool to_fb = (fin && !placed) || (placed && !ok);
     const unsigned long long fm = ballot(to_fb);
     if (a.prof && lane == 0) {
         uint32_t* pw = a.prof + group * PROF_WORDS;
@@ -929,7 +937,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
         pw[3] = gp.chunks;
         pw[4] = gp.cands;
         pw[5] = gp.pops;
-        pw[6] = (uint32_t)__popcll(mm);
+        pw[6] = (uint32_t)__popcll(ballot(placed));
         pw[7] = (uint32_t)__popcll(fm);
         pw[8] = gp.inserts;
         pw[9] = gp.dead;
@@ -978,7 +986,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
 }
 
 template <int K, int FUSED>
-__global__ void __launch_bounds__(256) k_group(GroupArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 20 ? 4 : 2)))
+k_group(GroupArgs a) {
     const int wpb = blockDim.x / WAVE;
     const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
     const SplitShare none{nullptr, 0, 0};
@@ -1274,6 +1283,11 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     a.co = j.co;
     a.eps = j.eps;
     a.wt = j.wt;
+    // Self queries: a group of consecutive target points that straddles two
+    // clusters is cheap to serve in a second round (measured: fewer
+    // wavefront-per-query searches and a shorter search); for external
+    // queries the extra rounds cost more than the fallback they save.
+    a.rounds = j.queries ? 1 : 4;
     a.fb_list = sc.fb_list;
     a.fb_count = sc.words;
     a.counters = nullptr;
