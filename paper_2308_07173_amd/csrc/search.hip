@@ -230,7 +230,7 @@ __device__ int knn_query_wave(const TargetView& T, float qx, float qy, float qz,
             total *= (ext[a] > 0) ? ext[a] : 0;
         }
         const float margin = (fmaxf(qabs, T.max_abs) + (float)(R + 2) * T.cell) * 1e-6f;
-        if (total > 2 * (int64_t)T.n_cells + 256) {
+        if (total > 2 * (int64_t)T.n_cells + 256 || total > (int64_t)UINT32_MAX) {
             // Sweep every occupied cell not yet visited (Chebyshev ring >= R).
             const unsigned long long mx = (1ull << T.sh_y) - 1ull;
             const unsigned long long my = (1ull << (T.sh_z - T.sh_y)) - 1ull;
@@ -262,9 +262,12 @@ __device__ int knn_query_wave(const TargetView& T, float qx, float qy, float qz,
             bool want = false;
             uint32_t st = 0, cn = 0;
             if (t < total) {
-                const int ix = (int)(t % ext[0]);
-                const int iy = (int)((t / ext[0]) % ext[1]);
-                const int iz = (int)(t / ((int64_t)ext[0] * ext[1]));
+                // the sweep above takes every ring of 2^32 cells or more
+                const uint32_t tu = (uint32_t)t, e0 = (uint32_t)ext[0], e1 = (uint32_t)ext[1];
+                const uint32_t t0 = tu / e0;
+                const int ix = (int)(tu - t0 * e0);
+                const int iy = (int)(t0 % e1);
+                const int iz = (int)(t0 / e1);
                 const int cx = lo[0] + ix, cy = lo[1] + iy, cz = lo[2] + iz;
                 const int cheb = max(abs(cx - cq[0]), max(abs(cy - cq[1]), abs(cz - cq[2])));
                 if (cheb == R) {
@@ -840,9 +843,12 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
                 bool want = false;
                 uint32_t st = 0, cn = 0;
                 if (t < total) {
-                    const int c3[3] = {lo[0] + (int)(t % ext[0]),
-                                       lo[1] + (int)((t / ext[0]) % ext[1]),
-                                       lo[2] + (int)(t / ((int64_t)ext[0] * ext[1]))};
+                    // the block has at most (5 + 2 * 4)^3 cells: 32-bit division
+                    const uint32_t tu = (uint32_t)t, e0 = (uint32_t)ext[0],
+                                   e1 = (uint32_t)ext[1];
+                    const uint32_t t0 = tu / e0;
+                    const int c3[3] = {lo[0] + (int)(tu - t0 * e0), lo[1] + (int)(t0 % e1),
+                                       lo[2] + (int)(t0 / e1)};
                     float bd = 0.0f;
                     for (int d = 0; d < 3; ++d) {
                         const float cl = (float)c3[d] * T.cell - margin;
@@ -1374,7 +1380,8 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
         if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     }
     if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
-    const dim3 fgrid((unsigned)(ctx->num_cus * 4));
+    // persistent: five 4-wave workgroups per CU fill the kernel's occupancy
+    const dim3 fgrid((unsigned)(ctx->num_cus * 5));
     if (j.fused == 2)
         hipLaunchKernelGGL(k_fallback<2>, fgrid, dim3(256), 0, st, a);
     else if (j.fused == 1)
