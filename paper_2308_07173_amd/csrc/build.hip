@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ ori
 // Per-tile digit histogram, stored digit-major: counts[d * nblocks + b].
 __global__ void __launch_bounds__(BT) k_radix_hist(const unsigned long long* __restrict__ keys,
                                                    int64_t n, int shift,
-                                                   uint32_t* __restrict__ counts, int nblocks) {
+                                                   uint32_t* __restrict__ counts, int nblocks,
+                                                   int tile_major) {
     __shared__ uint32_t hist[RADIX];
     hist[threadIdx.x] = 0;
     __syncthreads();
@@ -221,7 +222,10 @@ __global__ void __launch_bounds__(BT) k_radix_hist(const unsigned long long* __r
         if (i < n) atomicAdd(&hist[(uint32_t)(keys[i] >> shift) & (RADIX - 1)], 1u);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+    // digit-major for the global scan, tile-major for the scatter's own
+    // offset derivation (one coalesced row per tile)
+    counts[tile_major ? (int64_t)blockIdx.x * RADIX + threadIdx.x
+                      : (int64_t)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
 }
 
 // Exclusive prefix sum of m words in place, one workgroup of 1024 threads.
@@ -285,51 +289,71 @@ __global__ void __launch_bounds__(BT) k_scan_add(uint32_t* __restrict__ data, in
     if (i < m) data[i] += totals[i / SCAN_TILE];
 }
 
-// Stable scatter of one 8-bit digit.  Items of a tile are visited in index
-// order (256 consecutive items per step); within a step the rank of an item
-// among equal digits is (items of that digit in earlier steps) + (in earlier
-// wavefronts of this step) + (in lower lanes of its wavefront).
+// Stable scatter of one 8-bit digit.  A tile is read whole up front (every
+// thread holds its RS_ITEMS items, so the loads overlap); items are ordered
+// by (step, wavefront, lane), i.e. by index.  Each wavefront ranks each of
+// its steps' items among equal digits by ballots and records the digit
+// counts per (step, wavefront) in LDS; one thread per digit then turns its
+// column into exclusive offsets in item order, starting at the digit's
+// global offset, and every item lands at (its column entry) + (its rank).
 //
-// With `raw` set, `offsets` holds the unscanned per-tile histograms and each
-// workgroup derives its own offsets (digit totals scanned across the
-// workgroup, plus the counts of the earlier tiles); used when there are few
-// tiles, so the separate scan launch is saved.
+// With `raw` set, `offsets` holds the unscanned per-tile histograms, tile
+// by tile, and each workgroup derives its own offsets (digit totals scanned
+// across the workgroup, plus the counts of the earlier tiles); used when
+// there are few tiles, so the separate scan launch is saved.
 __global__ void __launch_bounds__(BT) k_radix_scatter(
     const unsigned long long* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n,
     int shift, const uint32_t* __restrict__ offsets, int nblocks, int raw) {
     constexpr int NW = BT / WAVE;
-    __shared__ uint32_t goff[RADIX];
-    __shared__ uint32_t run[RADIX];
-    __shared__ uint32_t wcnt[NW][RADIX];
+    constexpr int COLS = RS_ITEMS * NW;
+    __shared__ uint32_t s_tot[NW];
+    __shared__ uint32_t cnt[COLS][RADIX];
     const int tid = threadIdx.x, w = tid / WAVE, l = tid % WAVE;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    unsigned long long key[RS_ITEMS];
+    uint32_t val[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int64_t i = base + it * BT + tid;
+        key[it] = i < n ? keys_in[i] : 0ull;
+        val[it] = i < n ? vals_in[i] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < COLS; ++j) cnt[j][tid] = 0;
+    // thread tid owns digit tid: its first output position in this tile
+    uint32_t off;
     if (raw) {
-        const uint32_t* row = offsets + (int64_t)tid * nblocks;
         uint32_t tot = 0, pre = 0;
-        for (int b = 0; b < nblocks; ++b) {
-            const uint32_t c = row[b];
-            pre += b < (int)blockIdx.x ? c : 0u;
-            tot += c;
+        constexpr int U = 16;   // rows in flight
+        for (int b0 = 0; b0 < nblocks; b0 += U) {
+            uint32_t c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                c[u] = b0 + u < nblocks ? offsets[(int64_t)(b0 + u) * RADIX + tid] : 0u;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                pre += b0 + u < (int)blockIdx.x ? c[u] : 0u;
+                tot += c[u];
+            }
         }
         // exclusive scan of the digit totals across the workgroup
         const int incl = wave_incl_scan((int)tot);
-        if (l == WAVE - 1) run[w] = (uint32_t)incl;
+        if (l == WAVE - 1) s_tot[w] = (uint32_t)incl;
         __syncthreads();
         uint32_t wo = 0;
-        for (int j = 0; j < w; ++j) wo += run[j];
-        goff[tid] = wo + (uint32_t)incl - tot + pre;
-        __syncthreads();
+        for (int j = 0; j < w; ++j) wo += s_tot[j];
+        off = wo + (uint32_t)incl - tot + pre;
     } else {
-        goff[tid] = offsets[(int64_t)tid * nblocks + blockIdx.x];
+        off = offsets[(int64_t)tid * nblocks + blockIdx.x];
+        __syncthreads();   // the count table is cleared
     }
-    run[tid] = 0;
     const unsigned long long lt_mask = (1ull << l) - 1ull;
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    uint32_t rank[RS_ITEMS];
+#pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
-        const int64_t i = base + it * BT + tid;
-        const bool valid = i < n;
-        const unsigned long long key = valid ? keys_in[i] : 0ull;
-        const uint32_t d = (uint32_t)(key >> shift) & (RADIX - 1);
+        const bool valid = base + it * BT + tid < n;
+        const uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -337,29 +361,28 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
             const unsigned long long bal = __ballot(b);
             peers &= b ? bal : ~bal;
         }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        const uint32_t cnt = (uint32_t)__popcll(peers);
-        __syncthreads();  // previous step's reads of wcnt are done
+        rank[it] = (uint32_t)__popcll(peers & lt_mask);
+        if (valid && rank[it] == 0) cnt[it * NW + w][d] = (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    {
+        uint32_t r = off;
 #pragma unroll
-        for (int j = 0; j < NW; ++j) wcnt[j][tid] = 0;
-        __syncthreads();
-        if (valid && rank == 0) wcnt[w][d] = cnt;
-        __syncthreads();
-        {
-            uint32_t r = run[tid];
-#pragma unroll
-            for (int j = 0; j < NW; ++j) {
-                const uint32_t c = wcnt[j][tid];
-                wcnt[j][tid] = r;
-                r += c;
-            }
-            run[tid] = r;
+        for (int j = 0; j < COLS; ++j) {
+            const uint32_t c = cnt[j][tid];
+            cnt[j][tid] = r;
+            r += c;
         }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = goff[d] + wcnt[w][d] + rank;
-            keys_out[pos] = key;
-            vals_out[pos] = vals_in[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int64_t i = base + it * BT + tid;
+        if (i < n) {
+            const uint32_t d = (uint32_t)(key[it] >> shift) & (RADIX - 1);
+            const uint32_t pos = cnt[it * NW + w][d] + rank[it];
+            keys_out[pos] = key[it];
+            vals_out[pos] = val[it];
         }
     }
 }
@@ -545,7 +568,7 @@ lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsign
     const int raw = nb <= RAW_OFFSET_TILES ? 1 : 0;
     for (int shift = 0; shift < bits && n > 1; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(BT), 0, st, ka, n, shift,
-                           counts, (int)nb);
+                           counts, (int)nb, raw);
         if (!raw) scan_exclusive(st, counts, m, tmp);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(BT), 0, st, ka, va, kb, vb,
                            n, shift, counts, (int)nb, raw);

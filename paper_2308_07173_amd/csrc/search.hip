@@ -680,7 +680,7 @@ __device__ __forceinline__ float box_box_dist2(const float (&a0)[3], const float
 // ties pass it; the pop makes the exact (d2, index) comparison.
 template <int K>
 __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bool member,
-                                         float qx, float qy, float qz, float r2,
+                                         float qx, float qy, float qz, float r2, float lcap,
                                          const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr,
                                          unsigned long long (&kk)[K], int mode,
@@ -691,8 +691,9 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         if (cb == skip_cb) continue;   // streamed first, as the group's own chunk
         if (((cb / WAVE) & sh.split_mask) != sh.sub) continue;   // the other wave's chunk
         uint32_t keep = 0;
-        // this lane's current k-th distance (radius while its list is not full)
-        float lthr = kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2);
+        // this lane's current k-th distance (radius while its list is not
+        // full), never above its bound lcap
+        float lthr = fminf(kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2), lcap);
         if (sh.split_mask) lthr = shared_thr(sh, lane, lthr);
 #pragma unroll
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
@@ -755,7 +756,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             gp.inserts += (uint32_t)__popcll(im);
             gp.dead += im ? 0u : 1u;
         } while (ballot(bits != 0ull));
-        float own = kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1]);
+        float own = fminf(kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1]), lcap);
         if (sh.split_mask) {
             sh.thr[sh.sub * WAVE + lane] = own;
             own = shared_thr(sh, lane, own);
@@ -796,6 +797,24 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     // queries straddle two clusters can be served in two rounds rather than
     // handing one cluster to the wavefront-per-query search.  Every round
     // streams a whole block, so the launch sets the number of rounds.
+    // Self queries: a window of k consecutive slots holding the lane's own
+    // point are k target points, so the largest of their distances bounds
+    // the lane's k-th distance from above (k = 1: its own point, distance
+    // 0); every later test prunes against that bound.
+    float lcap = INF;
+    if (!a.queries && k <= 32) {
+        const int n_act = (int)min((int64_t)WAVE, a.n_slots - group * WAVE);
+        if (n_act >= k) {
+            const int w0 = min(max(lane - (k - 1) / 2, 0), n_act - k);
+            float m = 0.0f;
+#pragma unroll 1
+            for (int j = 0; j < k; ++j) {
+                const int src = w0 + j;
+                m = fmaxf(m, dist2(s.x, s.y, s.z, shfl(s.x, src), shfl(s.y, src), shfl(s.z, src)));
+            }
+            lcap = m;
+        }
+    }
     unsigned long long pending = T.n_cells > 0 ? ballot(same) : 0ull;
 #pragma unroll 1
     for (int round = 0; round < a.rounds && pending; ++round) {
@@ -823,7 +842,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
         const float qabs = fmaxf(fmaxf(fmaxf(fabsf(bx0), fabsf(bx1)), fmaxf(fabsf(by0), fabsf(by1))),
                                  fmaxf(fabsf(bz0), fabsf(bz1)));
         const float margin = (fmaxf(qabs, T.max_abs) + 2.0f * T.cell) * 1e-6f;
-        float gthr = r2;   // largest k-th distance over the members (radius while unfilled)
+        // largest k-th distance bound over the members
+        float gthr = wave_max_dpp(member ? fminf(r2, lcap) : -INF);
         // Self queries: the group's 64 slots are 64 consecutive points of
         // the target's Morton order, i.e. the queries themselves and each
         // other's nearest points; streaming that chunk first fills every
@@ -833,7 +853,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             own_cb = (int)(group * WAVE);
             const uint32_t i0 = gp.inserts;
             scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
-                        s.z, r2, b0, b1, margin, gthr, kk, 2, gp, -1, sh);
+                        s.z, r2, lcap, b0, b1, margin, gthr, kk, 2, gp, -1, sh);
             gp.own += gp.inserts - i0;
         }
         for (int pass = 0; pass < 2; ++pass) {
@@ -873,7 +893,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
                         const int s0 = readlane((int)st, cl);
                         const int e0 = s0 + readlane((int)cn, cl);
                         gp.cells++;
-                        scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, b0, b1, margin, gthr,
+                        scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin, gthr,
                                     kk, mode, gp, own_cb, sh);
                     }
                     const uint32_t di = gp.inserts - i0, dc = gp.cands - c0;
@@ -998,18 +1018,27 @@ k_group(GroupArgs a) {
     const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
     const SplitShare none{nullptr, 0, 0};
     if (a.split > 1) {
-        // one group per workgroup of `split` waves
-        __shared__ float s_thr[4 * WAVE];
-        __shared__ unsigned long long s_kk[2 * K * WAVE];
+        // one group per workgroup of `split` waves; dynamic LDS holds split / 2
+        // merge buffers and the shared k-th distances
+        extern __shared__ unsigned long long s_dyn[];
+        unsigned long long* s_kk = s_dyn;
+        float* s_thr = (float*)(s_kk + (a.split / 2) * K * WAVE);
         s_thr[threadIdx.x] = a.sp.r2;
         __syncthreads();
         const SplitShare sh{s_thr, (int)(threadIdx.x / WAVE), a.split - 1};
-        const int64_t g = (int64_t)xcd_tile(blockIdx.x, gridDim.x);
+        // Groups of separate queries: each XCD takes a contiguous range, so
+        // its L2 holds that range's part of the target.  Self queries (the
+        // target is one scan, a few MB): groups are dealt round-robin over
+        // the XCDs, which spreads the dense regions' heavy groups.
+        const int64_t g = a.queries ? (int64_t)xcd_tile(blockIdx.x, gridDim.x)
+                                    : (int64_t)blockIdx.x;
         if (g < n_groups) group_body<K, FUSED>(a, g, sh, s_kk);
         return;
     }
     if (!a.counters) {
-        const int64_t g = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * wpb + threadIdx.x / WAVE;
+        // many groups: dealt round-robin over the XCDs, so that every XCD
+        // gets a share of the dense regions
+        const int64_t g = (int64_t)blockIdx.x * wpb + threadIdx.x / WAVE;
         if (g < n_groups) group_body<K, FUSED>(a, g, none, nullptr);
         return;
     }
@@ -1246,11 +1275,15 @@ int choose_k_tile(int k) {
 
 template <int FUSED>
 void launch_group(int K, dim3 grid, dim3 block, hipStream_t st, const GroupArgs& a) {
+    const size_t lds = a.split > 1 ? sizeof(unsigned long long) * (size_t)(a.split / 2) *
+                                             (size_t)K * WAVE +
+                                         sizeof(float) * (size_t)a.split * WAVE
+                                   : 0;
     switch (K) {
-        case 8: hipLaunchKernelGGL((k_group<8, FUSED>), grid, block, 0, st, a); break;
-        case 16: hipLaunchKernelGGL((k_group<16, FUSED>), grid, block, 0, st, a); break;
-        case 20: hipLaunchKernelGGL((k_group<20, FUSED>), grid, block, 0, st, a); break;
-        default: hipLaunchKernelGGL((k_group<32, FUSED>), grid, block, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_group<8, FUSED>), grid, block, lds, st, a); break;
+        case 16: hipLaunchKernelGGL((k_group<16, FUSED>), grid, block, lds, st, a); break;
+        case 20: hipLaunchKernelGGL((k_group<20, FUSED>), grid, block, lds, st, a); break;
+        default: hipLaunchKernelGGL((k_group<32, FUSED>), grid, block, lds, st, a); break;
     }
 }
 
