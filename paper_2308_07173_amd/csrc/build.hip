@@ -8,7 +8,10 @@
 //   1. scan_points   cell coordinates floor(p / cell), occupied-cell bounding
 //                    box, finiteness flag, copy of the points as float4
 //   2. make_keys     Morton key of the cell (relative to the bounding box)
-//                    followed by the Morton key of the point's 16x16x16 sub-cell
+//                    followed by the Morton key of the point's sub-cell
+//                    (2^s per axis: the fewest 8-bit sort passes that hold
+//                    the cell key and s = 2, then the largest s <= 4 those
+//                    passes hold)
 //   3. radix sort    stable LSD, 8-bit digits, only as many passes as the
 //                    key has bits
 //   4. reorder       points into that order as float4 (x, y, z, original idx)
@@ -681,7 +684,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         V.max_abs = __builtin_bit_cast(float, hmeta->max_abs_bits);
         V.sh_y = bits[0];
         V.sh_z = bits[0] + bits[1];
-        const int sub_bits = std::max(0, std::min(4, (63 - 3 * wmax) / 3));
+        const int sub_lo = std::max(0, std::min(2, (63 - 3 * wmax) / 3));
+        const int room = std::min(63, 8 * ((3 * wmax + 3 * sub_lo + 7) / 8));
+        const int sub_bits = std::max(sub_lo, std::min(4, (room - 3 * wmax) / 3));
         t->key_bits = 3 * wmax + 3 * sub_bits;
         t->sort_passes = (t->key_bits + 7) / 8;
 

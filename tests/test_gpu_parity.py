@@ -81,8 +81,9 @@ def test_build_cells_partition_points(lk, n, cell, seed):
     assert np.array_equal(packed, ck.astype(np.uint64)[cell_of])
     assert np.unique(ck).size == C                       # one run per cell
     # cells follow the Morton order of their (relative) coordinates; inside
-    # a cell the 16x16x16 sub-cells follow Morton order and ties keep the
-    # original order (stable sort)
+    # a cell the 2^sb per axis sub-cells follow Morton order and ties keep
+    # the original order (stable sort); sb fills the fewest 8-bit passes that
+    # hold the cell key with 2 sub-cell bits per axis, up to 4
     def spread(v):
         out = np.zeros_like(v, dtype=np.uint64)
         for b in range(21):
@@ -91,7 +92,10 @@ def test_build_cells_partition_points(lk, n, cell, seed):
     rel = (c - np.array(info["cell_min"])).astype(np.uint64)
     u = p[orig].astype(np.float32) * inv
     wmax = max(int(info["cell_max"][a] - info["cell_min"][a]).bit_length() for a in range(3))
-    sb = max(0, min(4, (63 - 3 * wmax) // 3))
+    lo = max(0, min(2, (63 - 3 * wmax) // 3))
+    room = min(63, 8 * -(-(3 * wmax + 3 * lo) // 8))
+    sb = max(lo, min(4, (room - 3 * wmax) // 3))
+    assert info["sort_passes"] == -(-(3 * wmax + 3 * sb) // 8)
     sub = np.clip(((u - np.floor(u)) * np.float32(2 ** sb)).astype(np.int64), 0,
                   2 ** sb - 1).astype(np.uint64)
     mort = ((spread(rel[:, 0]) | spread(rel[:, 1]) << np.uint64(1) | spread(rel[:, 2]) << np.uint64(2))
