@@ -14,11 +14,11 @@
 //                    passes hold)
 //   3. radix sort    stable LSD, 8-bit digits, only as many passes as the
 //                    key has bits
-//   4. reorder       points into that order as float4 (x, y, z, original idx)
+//   4. reorder       points into that order as float4 (x, y, z, original idx),
+//                    and the bounding box of every aligned 16-point run
 //   5. cell runs     run boundaries of the cell part of the key
 //   6. hash insert   open addressing, linear probing, capacity 2^ceil(log2 2C);
 //                    the hash key is the row-major compact cell key
-//   7. run boxes     bounding box of every aligned 16-point run
 //
 // Morton order keeps neighbouring cells close in memory, and the sub-cell
 // order makes every 16-point run of a dense cell spatially compact, so a
@@ -439,30 +439,6 @@ __global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __r
     if (i == n - 1) meta->n_cells = cid + (f ? 1u : 0u);
 }
 
-// Bounding box of every aligned 16-point run of the reordered points (one
-// 16-lane quarter of a wavefront per box).
-__global__ void __launch_bounds__(BT) k_chunk_boxes(const float4* __restrict__ pts, int64_t n,
-                                                    float4* __restrict__ boxes) {
-    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    const int64_t box = i / BOX_PTS;
-    const bool v = i < n;
-    const float4 p = v ? pts[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-    float lo[3] = {v ? p.x : INFINITY, v ? p.y : INFINITY, v ? p.z : INFINITY};
-    float hi[3] = {v ? p.x : -INFINITY, v ? p.y : -INFINITY, v ? p.z : -INFINITY};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int s = BOX_PTS / 2; s > 0; s >>= 1) {
-            lo[a] = fminf(lo[a], __shfl_xor(lo[a], s));
-            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], s));
-        }
-    }
-    if (i % BOX_PTS == 0 && box * BOX_PTS < n) {
-        boxes[2 * box] = make_float4(lo[0], lo[1], lo[2], 0.f);
-        boxes[2 * box + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
-    }
-}
-
 __global__ void k_hash_clear(HashSlot* __restrict__ h, int64_t cap) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cap) h[i] = HashSlot{EMPTY_KEY, 0u, 0u};
@@ -495,14 +471,35 @@ __global__ void __launch_bounds__(BT) k_hash_insert(const unsigned long long* __
     }
 }
 
+// Reorder the points into key order, and write the bounding box of every
+// aligned 16-point run (one 16-lane quarter of a wavefront per box).
 __global__ void __launch_bounds__(BT) k_reorder(const float4* __restrict__ orig,
                                                 const uint32_t* __restrict__ vals, int64_t n,
-                                                float4* __restrict__ pts) {
+                                                float4* __restrict__ pts,
+                                                float4* __restrict__ boxes) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t o = vals[i];
-    const float4 p = orig[o];
-    pts[i] = make_float4(p.x, p.y, p.z, __int_as_float((int)o));
+    const int64_t box = i / BOX_PTS;
+    const bool v = i < n;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (v) {
+        const uint32_t o = vals[i];
+        p = orig[o];
+        pts[i] = make_float4(p.x, p.y, p.z, __int_as_float((int)o));
+    }
+    float lo[3] = {v ? p.x : INFINITY, v ? p.y : INFINITY, v ? p.z : INFINITY};
+    float hi[3] = {v ? p.x : -INFINITY, v ? p.y : -INFINITY, v ? p.z : -INFINITY};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int s = BOX_PTS / 2; s > 0; s >>= 1) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], s));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], s));
+        }
+    }
+    if (i % BOX_PTS == 0 && box * BOX_PTS < n) {
+        boxes[2 * box] = make_float4(lo[0], lo[1], lo[2], 0.f);
+        boxes[2 * box + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+    }
 }
 
 __global__ void k_iota(uint32_t* __restrict__ v, int64_t n) {
@@ -606,27 +603,30 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     t->key_bits = 0;
     t->sort_passes = 0;
 
-    // ---- point storage (pts + orig), grow-only
+    // ---- point storage (pts + orig + run boxes), grow-only
     // pts carries 64 spare records: the search loads whole aligned 64-record
     // chunks and may read up to 63 records past the last point
     const size_t pbytes = align256(sizeof(float4) * ((size_t)(n > 0 ? n : 1) + 64));
-    if (t->point_bytes < 2 * pbytes) {
+    const int64_t n_chunks = (n + BOX_PTS - 1) / BOX_PTS;
+    const size_t bx_b = align256(2 * sizeof(float4) * (size_t)(n_chunks > 0 ? n_chunks : 1));
+    if (t->point_bytes < 2 * pbytes + bx_b) {
         if (t->point_mem) {
             LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
             (void)hipFree(t->point_mem);
             t->point_mem = nullptr;
             t->point_bytes = 0;
         }
-        hipError_t e = hipMalloc(&t->point_mem, 2 * pbytes);
+        hipError_t e = hipMalloc(&t->point_mem, 2 * pbytes + bx_b);
         if (e != hipSuccess) {
             t->point_mem = nullptr;
-            return set_error(ctx, LKC_ERR_OOM, "target points (%zu bytes): %s", 2 * pbytes,
-                             hipGetErrorString(e));
+            return set_error(ctx, LKC_ERR_OOM, "target points (%zu bytes): %s",
+                             2 * pbytes + bx_b, hipGetErrorString(e));
         }
-        t->point_bytes = 2 * pbytes;
+        t->point_bytes = 2 * pbytes + bx_b;
     }
     float4* pts = (float4*)t->point_mem;
     float4* orig = (float4*)((char*)t->point_mem + pbytes);
+    float4* boxes = (float4*)((char*)t->point_mem + 2 * pbytes);
 
     // ---- scratch: keys a/b, vals a/b, radix counts, block counts, cell temps
     const int64_t nb_bt = (n + BT - 1) / BT;
@@ -709,7 +709,7 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
 
         // ---- 4. reorder
         hipLaunchKernelGGL(k_reorder, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, vals_a, n,
-                           pts);
+                           pts, boxes);
         // ---- 5. cell runs
         RowKey rk;
         rk.inv_cell = inv_cell;
@@ -732,16 +732,14 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         }
     }
 
-    // ---- 6. cell arrays + hash (sized by the cell count), 7. chunk boxes
+    // ---- 6. cell arrays + hash (sized by the cell count)
     int hbits = 6;
     while (((int64_t)1 << hbits) < 2 * n_cells) ++hbits;
     const int64_t cap = (int64_t)1 << hbits;
-    const int64_t n_chunks = (n + BOX_PTS - 1) / BOX_PTS;
     const size_t ck_b = align256(8 * (size_t)(n_cells > 0 ? n_cells : 1));
     const size_t cs_b = align256(4 * (size_t)(n_cells + 1));
     const size_t h_b = align256(sizeof(HashSlot) * (size_t)cap);
-    const size_t bx_b = align256(2 * sizeof(float4) * (size_t)(n_chunks > 0 ? n_chunks : 1));
-    const size_t cbytes = ck_b + cs_b + h_b + bx_b;
+    const size_t cbytes = ck_b + cs_b + h_b;
     if (t->cell_bytes < cbytes) {
         if (t->cell_mem) {
             LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
@@ -761,13 +759,10 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     auto* ckeys = (unsigned long long*)t->cell_mem;
     auto* cstart = (uint32_t*)((char*)t->cell_mem + ck_b);
     auto* hash = (HashSlot*)((char*)t->cell_mem + ck_b + cs_b);
-    auto* boxes = (float4*)((char*)t->cell_mem + ck_b + cs_b + h_b);
     hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap, BT)), dim3(BT), 0, st, hash, cap);
     if (n_cells > 0) {
         hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n_cells, BT)), dim3(BT), 0, st, tkeys,
                            tstart, n_cells, n, ckeys, cstart, hash, hbits, (uint32_t)(cap - 1));
-        hipLaunchKernelGGL(k_chunk_boxes, dim3(grid_for(n, BT)), dim3(BT), 0, st,
-                           (const float4*)pts, n, boxes);
     } else {
         hipLaunchKernelGGL(k_iota, dim3(1), dim3(1), 0, st, cstart, (int64_t)1);
     }

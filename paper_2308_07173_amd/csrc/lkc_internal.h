@@ -53,7 +53,7 @@ struct lkc_target {
     int32_t sort_passes = 0;
     int64_t hash_capacity = 0;
     // owned allocations and their capacities (bytes)
-    void* point_mem = nullptr;   // pts + orig
+    void* point_mem = nullptr;   // pts + orig + run boxes
     size_t point_bytes = 0;
     void* cell_mem = nullptr;    // cell_keys + cell_start + hash
     size_t cell_bytes = 0;
