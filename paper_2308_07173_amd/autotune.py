@@ -5,8 +5,11 @@ gives the same results; only the time changes.  The tuner builds the target
 at each candidate cell size, times the fused search + covariance on a seeded
 calibration sample of the real queries (HIP events on the launch stream,
 median of a few repetitions after a warm-up) for each launch shape, and
-returns the fastest combination.  Results are cached in memory per
-(target fingerprint, sample fingerprint, k, radius).
+returns the fastest combination.  The sample is made of a few contiguous
+runs of the queries, so that it keeps the local density of whole scans: the
+group search's cost per query depends on how many queries share a group's
+neighbourhood, which a thinned random subset would understate.  Results are
+cached in memory per (target fingerprint, sample fingerprint, k, radius).
 """
 from __future__ import annotations
 
@@ -52,7 +55,10 @@ def autotune(target_points: np.ndarray, queries: np.ndarray, k: int, radius: flo
     rng = np.random.default_rng(seed)
     q = np.ascontiguousarray(queries, np.float32)
     if q.shape[0] > sample:
-        q = q[np.sort(rng.choice(q.shape[0], sample, replace=False))]
+        runs = 4
+        step = sample // runs
+        starts = np.sort(rng.choice(q.shape[0] - step + 1, runs, replace=False))
+        q = np.ascontiguousarray(np.concatenate([q[s:s + step] for s in starts]))
     key = (_fingerprint(target_points), _fingerprint(q), int(k), float(radius),
            tuple(cells), tuple(tuple(sorted(c.items())) for c in cfgs))
     if key in _cache:
