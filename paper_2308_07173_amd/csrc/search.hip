@@ -569,6 +569,41 @@ __device__ __forceinline__ void lane_insert(unsigned long long (&kk)[K], unsigne
     kk[0] = c_hi ? x : kk[0];
 }
 
+// Batcher's odd-even merge sort on P = 2^ceil(log2 K) inputs, keeping the
+// comparators between the first K (the others would compare with +inf
+// padding and never swap).  Built at compile time.
+template <int K>
+struct SortNet {
+    static constexpr int P = K <= 8 ? 8 : (K <= 16 ? 16 : (K <= 32 ? 32 : 64));
+    int a[P * 8], b[P * 8];
+    int n;
+    constexpr SortNet() : a(), b(), n(0) {
+        for (int p = 1; p < P; p += p)
+            for (int k = p; k >= 1; k /= 2)
+                for (int j = k % p; j + k <= P - 1; j += 2 * k)
+                    for (int i = 0; i <= k - 1 && i <= P - j - k - 1; ++i)
+                        if ((i + j) / (2 * p) == (i + j + k) / (2 * p) && i + j + k < K) {
+                            a[n] = i + j;
+                            b[n] = i + j + k;
+                            ++n;
+                        }
+    }
+};
+
+// Sort the list kk ascending in registers.
+template <int K>
+__device__ __forceinline__ void sort_keys(unsigned long long (&kk)[K]) {
+    constexpr SortNet<K> net{};
+#pragma unroll
+    for (int c = 0; c < net.n; ++c) {
+        const unsigned long long x = kk[net.a[c]], y = kk[net.b[c]];
+        const bool sw = y < x;
+        kk[net.a[c]] = sw ? y : x;
+        kk[net.b[c]] = sw ? x : y;
+        __builtin_amdgcn_sched_barrier(0);   // in order: bounded register use
+    }
+}
+
 __device__ __forceinline__ float wave_minf(float v) {
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) v = fminf(v, shfl_xor(v, s));
@@ -684,7 +719,8 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                                          const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr,
                                          unsigned long long (&kk)[K], int mode,
-                                         GroupProf& gp, int skip_cb, const SplitShare& sh) {
+                                         GroupProf& gp, int skip_cb, const SplitShare& sh,
+                                         int win_k = 0, int win_n = 0) {
     const int lane = lane_id();
 #pragma unroll 1
     for (int cb = s0 & ~(WAVE - 1); cb < e0; cb += WAVE) {
@@ -739,6 +775,12 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                 bhi |= b;
         }
         unsigned long long bits = ((unsigned long long)bhi << 32) | blo;
+        if (win_k) {
+            // a member's window of win_k slots (of the win_n active ones)
+            // is already in its list
+            const int w0 = min(max(lane - (win_k - 1) / 2, 0), win_n - win_k);
+            bits &= member ? ~(((1ull << win_k) - 1ull) << w0) : ~0ull;
+        }
         if (!ballot(bits != 0ull)) continue;
         do {
             gp.pops++;
@@ -802,9 +844,11 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     // the lane's k-th distance from above (k = 1: its own point, distance
     // 0); every later test prunes against that bound.
     float lcap = INF;
-    if (!a.queries && k <= 32) {
-        const int n_act = (int)min((int64_t)WAVE, a.n_slots - group * WAVE);
-        if (n_act >= k) {
+    const int n_act = (int)min((int64_t)WAVE, a.n_slots - group * WAVE);
+    const bool win = !a.queries && k <= 32 && n_act >= k;   // (uniform) the windows exist
+    if (win) {
+        {
+            // the lane's window: slots [w0, w0 + k) of the group
             const int w0 = min(max(lane - (k - 1) / 2, 0), n_act - k);
             float m = 0.0f;
 #pragma unroll 1
@@ -851,9 +895,33 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
         int own_cb = -1;
         if (!a.queries) {
             own_cb = (int)(group * WAVE);
+            // The wave that streams the own chunk starts each member's list
+            // with its window (the exact keys of its points within the
+            // radius, sorted by a network instead of k insertions) and
+            // streams the rest of the chunk.
+            int win_k = 0;
+            if (win && ((own_cb / WAVE) & sh.split_mask) == sh.sub) {
+                const int w0 = min(max(lane - (k - 1) / 2, 0), n_act - k);
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    if (j >= pad) {
+                        const int src = w0 + j - pad;
+                        const float px = shfl(s.x, src), py = shfl(s.y, src), pz = shfl(s.z, src);
+                        const int32_t pi = shfl((int32_t)s.qi, src);
+                        const float d = dist2(s.x, s.y, s.z, px, py, pz);
+                        // a window point beyond the radius is no neighbour
+                        const unsigned long long key = d <= r2 ? lane_key(d, pi) : ~0ull;
+                        kk[j] = member ? key : kk[j];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // one key at a time (registers)
+                }
+                sort_keys<K>(kk);
+                win_k = k;
+                gp.inserts += (uint32_t)__popcll(ballot(member)) * (uint32_t)k;
+            }
             const uint32_t i0 = gp.inserts;
             scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
-                        s.z, r2, lcap, b0, b1, margin, gthr, kk, 2, gp, -1, sh);
+                        s.z, r2, lcap, b0, b1, margin, gthr, kk, 2, gp, -1, sh, win_k, n_act);
             gp.own += gp.inserts - i0;
         }
         for (int pass = 0; pass < 2; ++pass) {
