@@ -261,28 +261,32 @@ __global__ void __launch_bounds__(1024) k_scan_exclusive(uint32_t* __restrict__ 
 }
 
 // Multi-block exclusive scan, step 1: every workgroup scans its 4096-entry
-// tile in place and records the tile total.
+// tile in place and records the tile total.  Each thread holds 16
+// consecutive entries (all loaded up front), scans them in registers, and
+// one workgroup scan of the thread totals gives the offsets.
 __global__ void __launch_bounds__(BT) k_scan_tiles(uint32_t* __restrict__ data, int64_t m,
                                                    uint32_t* __restrict__ totals) {
+    constexpr int PER = SCAN_TILE / BT;
     __shared__ uint32_t s_w[BT / WAVE];
-    __shared__ uint32_t s_carry;
     const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    if (threadIdx.x == 0) s_carry = 0;
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    for (int it = 0; it < SCAN_TILE / BT; ++it) {
-        const int64_t i = base + it * BT + threadIdx.x;
-        const uint32_t v = i < m ? data[i] : 0u;
-        const int incl = wave_incl_scan((int)v);
-        if (l == WAVE - 1) s_w[w] = (uint32_t)incl;
-        __syncthreads();
-        uint32_t wo = s_carry;
-        for (int j = 0; j < w; ++j) wo += s_w[j];
-        if (i < m) data[i] = wo + (uint32_t)incl - v;
-        __syncthreads();
-        if (threadIdx.x == BT - 1) s_carry = wo + (uint32_t)incl;
-        __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * PER;
+    uint32_t v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] = base + u < m ? data[base + u] : 0u;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) sum += v[u];
+    const int incl = wave_incl_scan((int)sum);
+    if (l == WAVE - 1) s_w[w] = (uint32_t)incl;
+    __syncthreads();
+    uint32_t run = (uint32_t)incl - sum;
+    for (int j = 0; j < w; ++j) run += s_w[j];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (base + u < m) data[base + u] = run;
+        run += v[u];
     }
-    if (threadIdx.x == 0) totals[blockIdx.x] = s_carry;
+    if (threadIdx.x == BT - 1) totals[blockIdx.x] = run;
 }
 
 // step 3: add the scanned tile totals

@@ -1418,8 +1418,13 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
                     wmax = std::max(wmax, bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2)));
             }
             // Morton key of the (clamped) query cell, then of its sub-cell
+            // (as many sub-cell bits, from 2 to 4 per axis, as the fewest
+            // 8-bit sort passes holding the key with 2 of them allow)
             const int tbits = j.n_targets > 1 ? bitw((uint32_t)(j.n_targets - 1)) : 0;
-            const int sub_bits = std::max(0, std::min(4, (63 - tbits - 3 * wmax) / 3));
+            const int sub_lo = std::max(0, std::min(2, (63 - tbits - 3 * wmax) / 3));
+            const int room =
+                std::min(63, 8 * ((tbits + 3 * wmax + 3 * sub_lo + 7) / 8)) - tbits;
+            const int sub_bits = std::max(sub_lo, std::min(4, (room - 3 * wmax) / 3));
             const int tshift = 3 * wmax + 3 * sub_bits;
             if (tshift + tbits > 63)
                 return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",
