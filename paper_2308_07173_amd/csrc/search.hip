@@ -834,8 +834,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     bool placed = same && T.n_cells == 0;   // searched by one of the rounds below
     GroupProf gp{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const unsigned long long t_start = a.prof ? __builtin_amdgcn_s_memtime() : 0ull;
-    // Rounds: each takes the first unplaced lane as anchor and searches for
-    // every unplaced lane within GROUP_W cells of it, so a group whose sorted
+    // Rounds: each picks an anchor cell among the unplaced lanes and searches
+    // for every unplaced lane within GROUP_W cells of it, so a group whose sorted
     // queries straddle two clusters can be served in two rounds rather than
     // handing one cluster to the wavefront-per-query search.  Every round
     // streams a whole block, so the launch sets the number of rounds.
@@ -862,10 +862,48 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     unsigned long long pending = T.n_cells > 0 ? ballot(same) : 0ull;
 #pragma unroll 1
     for (int round = 0; round < a.rounds && pending; ++round) {
+        // The anchor box is GROUP_W cells around the first pending lane's
+        // cell.  A single-round launch (whose leftover lanes all fall back)
+        // takes instead the box that holds the most pending lanes, of three:
+        // around the first pending lane's cell, the last one's, and the
+        // middle of the pending lanes' cells.
+        const bool pend = (pending >> lane) & 1ull;
+        auto takes = [&](int x, int y, int z) {
+            return pend && abs(cx - x) <= GROUP_W && abs(cy - y) <= GROUP_W &&
+                   abs(cz - z) <= GROUP_W;
+        };
         const int L0 = __builtin_ffsll((long long)pending) - 1;
-        const int ax = readlane(cx, L0), ay = readlane(cy, L0), az = readlane(cz, L0);
-        const bool member = ((pending >> lane) & 1ull) && abs(cx - ax) <= GROUP_W &&
-                            abs(cy - ay) <= GROUP_W && abs(cz - az) <= GROUP_W;
+        const int L1 = 63 - __builtin_clzll(pending);
+        int ax = readlane(cx, L0), ay = readlane(cy, L0), az = readlane(cz, L0);
+        if (a.rounds == 1) {
+            int best = __popcll(ballot(takes(ax, ay, az)));
+            {
+                const int bx = readlane(cx, L1), by = readlane(cy, L1), bz = readlane(cz, L1);
+                const int c = __popcll(ballot(takes(bx, by, bz)));
+                if (c > best) {
+                    best = c;
+                    ax = bx;
+                    ay = by;
+                    az = bz;
+                }
+            }
+            {
+                const float fx = pend ? (float)cx : INF, fy = pend ? (float)cy : INF,
+                            fz = pend ? (float)cz : INF;
+                const float gx = pend ? (float)cx : -INF, gy = pend ? (float)cy : -INF,
+                            gz = pend ? (float)cz : -INF;
+                const int bx = ((int)wave_min_dpp(fx) + (int)wave_max_dpp(gx)) >> 1;
+                const int by = ((int)wave_min_dpp(fy) + (int)wave_max_dpp(gy)) >> 1;
+                const int bz = ((int)wave_min_dpp(fz) + (int)wave_max_dpp(gz)) >> 1;
+                const int c = __popcll(ballot(takes(bx, by, bz)));
+                if (c > best) {
+                    ax = bx;
+                    ay = by;
+                    az = bz;
+                }
+            }
+        }
+        const bool member = takes(ax, ay, az);
         const unsigned long long mm = ballot(member);
         pending &= ~mm;
         placed = placed || member;
