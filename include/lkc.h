@@ -163,8 +163,12 @@ lkc_status lkc_synchronize(lkc_ctx *ctx);
  * coordinates floor(p / cell_size) (clamped to [-2^20, 2^20)), sorted by a
  * compact key with an LSD radix sort, reordered into cell runs, and the
  * occupied cells are inserted into an open-addressed hash (Sec. III-C.3's
- * GPU hash map).  Synchronises twice (to size the sort and the hash).  The
- * caller's buffer may be reused once this call returns.  n = 0 builds an
+ * GPU hash map).  The key layout and the hash size are derived on the
+ * device; a first build synchronises twice (to learn how many sort passes
+ * the key needs, then at the end), a rebuild once (it runs the previous
+ * build's number of passes and sorts again only if the new key needs
+ * more).  The hash and cell arrays are sized by n.  The caller's buffer may
+ * be reused once this call returns.  n = 0 builds an
  * empty target.  A non-finite coordinate fails with LKC_ERR_NONFINITE and
  * returns no target. */
 lkc_status lkc_build_target(lkc_ctx *ctx, const float *points, int64_t n, float cell_size,

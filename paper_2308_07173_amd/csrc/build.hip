@@ -40,13 +40,21 @@ constexpr int RADIX = 256;
 constexpr int SCAN_TILE = 4096;  // entries per workgroup of the multi-block scan
 constexpr int RAW_OFFSET_TILES = 96;  // sorts of up to this many tiles skip the scan launch
 
+// Written by the build kernels: the occupied-cell box, and the key layout
+// and hash size derived from it on the device, so that the kernels after
+// the box need no host round trip.
 struct BuildMeta {
     int cmin[3];
     int cmax[3];
     int nonfinite;
     uint32_t n_cells;
     uint32_t max_abs_bits;  // float bits of max |coordinate| (non-negative floats order as uints)
-    uint32_t pad[7];
+    int sh_y, sh_z;         // row-major cell key: kx | ky << sh_y | kz << sh_z
+    int sub_bits;           // Morton bits per axis of the sub-cell below the cell key
+    int key_bits;           // bits of the sort key
+    int passes;             // 8-bit sort passes the key needs
+    int hash_bits;          // log2 of the hash capacity (2^bits >= 2 x cells, >= 64)
+    uint32_t pad;
 };
 static_assert(sizeof(BuildMeta) == 64, "BuildMeta layout");
 
@@ -184,28 +192,42 @@ __global__ void __launch_bounds__(1024) k_meta_reduce(const MetaPart* __restrict
         meta->nonfinite = vb;
         meta->max_abs_bits = va;
         meta->n_cells = 0;
+        meta->hash_bits = 6;
+        // key layout: the cell's Morton key relative to the box, then the
+        // sub-cell's (2^s per axis: the fewest 8-bit passes that hold the
+        // cell key and s = 2, then the largest s <= 4 those passes hold)
+        int bits[3] = {0, 0, 0}, wmax = 0;
+        if (!vb)
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t e = (uint32_t)(meta->cmax[a] - meta->cmin[a]);
+                bits[a] = e ? 32 - __clz((int)e) : 0;
+                wmax = max(wmax, bits[a]);
+            }
+        const int sub_lo = max(0, min(2, (63 - 3 * wmax) / 3));
+        const int room = min(63, 8 * ((3 * wmax + 3 * sub_lo + 7) / 8));
+        const int sub = max(sub_lo, min(4, (room - 3 * wmax) / 3));
+        meta->sh_y = bits[0];
+        meta->sh_z = bits[0] + bits[1];
+        meta->sub_bits = sub;
+        meta->key_bits = 3 * wmax + 3 * sub;
+        meta->passes = (3 * wmax + 3 * sub + 7) / 8;
     }
 }
 
-struct KeyParams {
-    float inv_cell;
-    int cmin[3];
-    int sub_bits;    // Morton bits per axis of the sub-cell below the cell key
-};
-
 __global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ orig, int64_t n,
-                                                  KeyParams kp, unsigned long long* __restrict__ keys,
+                                                  float inv_cell, const BuildMeta* __restrict__ meta,
+                                                  unsigned long long* __restrict__ keys,
                                                   uint32_t* __restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= n) return;
     const float4 p = orig[i];
-    const uint32_t cx = (uint32_t)(cell_coord(p.x, kp.inv_cell) - kp.cmin[0]);
-    const uint32_t cy = (uint32_t)(cell_coord(p.y, kp.inv_cell) - kp.cmin[1]);
-    const uint32_t cz = (uint32_t)(cell_coord(p.z, kp.inv_cell) - kp.cmin[2]);
-    const int sb = kp.sub_bits;
+    const uint32_t cx = (uint32_t)(cell_coord(p.x, inv_cell) - meta->cmin[0]);
+    const uint32_t cy = (uint32_t)(cell_coord(p.y, inv_cell) - meta->cmin[1]);
+    const uint32_t cz = (uint32_t)(cell_coord(p.z, inv_cell) - meta->cmin[2]);
+    const int sb = meta->sub_bits;
     const unsigned long long sub =
-        morton3(sub_cell(p.x, kp.inv_cell, sb), sub_cell(p.y, kp.inv_cell, sb),
-                sub_cell(p.z, kp.inv_cell, sb));
+        morton3(sub_cell(p.x, inv_cell, sb), sub_cell(p.y, inv_cell, sb),
+                sub_cell(p.z, inv_cell, sb));
     keys[i] = (morton3(cx, cy, cz) << (3 * sb)) | sub;
     vals[i] = (uint32_t)i;
 }
@@ -397,30 +419,27 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
 // Cell runs: flag(i) = cell part of key[i] differs from key[i-1]'s.  Pass 1
 // counts flags per block.
 __global__ void __launch_bounds__(BT) k_cell_count(const unsigned long long* __restrict__ keys,
-                                                   int64_t n, int sub_shift,
+                                                   int64_t n, const BuildMeta* __restrict__ meta,
                                                    uint32_t* __restrict__ bcount) {
+    const int sub_shift = 3 * meta->sub_bits;
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     const bool f = i < n && (i == 0 || (keys[i] >> sub_shift) != (keys[i - 1] >> sub_shift));
     const int c = __syncthreads_count(f);
     if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)c;
 }
 
-struct RowKey {
-    float inv_cell;
-    int cmin[3];
-    int sh_y, sh_z;
-};
-
 // Pass 2: each run start writes its cell's row-major key (recomputed from the
-// reordered point) and its first position.
+// reordered point) and its first position; the last point records the cell
+// count and the hash size.
 __global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __restrict__ keys,
                                                    const float4* __restrict__ pts, int64_t n,
-                                                   int sub_shift,
-                                                   const uint32_t* __restrict__ boff, RowKey rk,
+                                                   float inv_cell,
+                                                   const uint32_t* __restrict__ boff,
                                                    unsigned long long* __restrict__ ckeys,
                                                    uint32_t* __restrict__ cstart,
                                                    BuildMeta* __restrict__ meta) {
     __shared__ uint32_t s_w[BT / WAVE];
+    const int sub_shift = 3 * meta->sub_bits;
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     const bool f = i < n && (i == 0 || (keys[i] >> sub_shift) != (keys[i - 1] >> sub_shift));
     const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
@@ -433,28 +452,39 @@ __global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __r
     const uint32_t cid = boff[blockIdx.x] + wo + pre;
     if (f) {
         const float4 p = pts[i];
-        const uint32_t cx = (uint32_t)(cell_coord(p.x, rk.inv_cell) - rk.cmin[0]);
-        const uint32_t cy = (uint32_t)(cell_coord(p.y, rk.inv_cell) - rk.cmin[1]);
-        const uint32_t cz = (uint32_t)(cell_coord(p.z, rk.inv_cell) - rk.cmin[2]);
-        ckeys[cid] = (unsigned long long)cx | ((unsigned long long)cy << rk.sh_y) |
-                     ((unsigned long long)cz << rk.sh_z);
+        const uint32_t cx = (uint32_t)(cell_coord(p.x, inv_cell) - meta->cmin[0]);
+        const uint32_t cy = (uint32_t)(cell_coord(p.y, inv_cell) - meta->cmin[1]);
+        const uint32_t cz = (uint32_t)(cell_coord(p.z, inv_cell) - meta->cmin[2]);
+        ckeys[cid] = (unsigned long long)cx | ((unsigned long long)cy << meta->sh_y) |
+                     ((unsigned long long)cz << meta->sh_z);
         cstart[cid] = (uint32_t)i;
     }
-    if (i == n - 1) meta->n_cells = cid + (f ? 1u : 0u);
+    if (i == n - 1) {
+        const uint32_t nc = cid + (f ? 1u : 0u);
+        int hb = 6;
+        while ((1ull << hb) < 2ull * nc) ++hb;
+        meta->n_cells = nc;
+        meta->hash_bits = hb;
+    }
 }
 
-__global__ void k_hash_clear(HashSlot* __restrict__ h, int64_t cap) {
+// Clears the hash slots in use: 2^bits, or 2^meta->hash_bits with bits = 0.
+__global__ void k_hash_clear(HashSlot* __restrict__ h, const BuildMeta* __restrict__ meta,
+                             int bits) {
+    const int64_t cap = (int64_t)1 << (bits > 0 ? bits : meta->hash_bits);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < cap) h[i] = HashSlot{EMPTY_KEY, 0u, 0u};
 }
 
 __global__ void __launch_bounds__(BT) k_hash_insert(const unsigned long long* __restrict__ tkeys,
                                                     const uint32_t* __restrict__ tstart,
-                                                    int64_t n_cells, int64_t n,
+                                                    const BuildMeta* __restrict__ meta, int64_t n,
                                                     unsigned long long* __restrict__ ckeys,
                                                     uint32_t* __restrict__ cstart,
-                                                    HashSlot* __restrict__ hash, int bits,
-                                                    uint32_t mask) {
+                                                    HashSlot* __restrict__ hash) {
+    const int64_t n_cells = meta->n_cells;
+    const int bits = meta->hash_bits;
+    const uint32_t mask = (uint32_t)((1ull << bits) - 1ull);
     const int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x;
     if (c >= n_cells) return;
     const unsigned long long key = tkeys[c];
@@ -604,6 +634,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     V = TargetView{};
     V.cell = cell;
     V.inv_cell = inv_cell;
+    // the previous build's sort passes: a rebuild launches that many before
+    // it knows the new key (and checks at its one synchronisation)
+    const int prev_passes = t->sort_passes;
     t->key_bits = 0;
     t->sort_passes = 0;
 
@@ -664,85 +697,14 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     auto* meta = (BuildMeta*)ctx->meta_dev;
     auto* hmeta = (BuildMeta*)ctx->meta_host;
 
-    int64_t n_cells = 0;
-    if (n > 0) {
-        // ---- 1. cell coordinates, bounding box, finiteness
-        hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
-                           inv_cell, orig, mparts);
-        hipLaunchKernelGGL(k_meta_reduce, dim3(1), dim3(1024), 0, st, (const MetaPart*)mparts,
-                           nb_bt, meta);
-        LKC_HIP_TRY(ctx, hipGetLastError());
-        LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
-        LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
-        if (hmeta->nonfinite) {
-            V.n = 0;
-            return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
-        }
-        int bits[3], wmax = 0;
-        for (int a = 0; a < 3; ++a) {
-            V.cmin[a] = hmeta->cmin[a];
-            V.cmax[a] = hmeta->cmax[a];
-            bits[a] = bit_width((uint32_t)(hmeta->cmax[a] - hmeta->cmin[a]));
-            wmax = std::max(wmax, bits[a]);
-        }
-        V.max_abs = __builtin_bit_cast(float, hmeta->max_abs_bits);
-        V.sh_y = bits[0];
-        V.sh_z = bits[0] + bits[1];
-        const int sub_lo = std::max(0, std::min(2, (63 - 3 * wmax) / 3));
-        const int room = std::min(63, 8 * ((3 * wmax + 3 * sub_lo + 7) / 8));
-        const int sub_bits = std::max(sub_lo, std::min(4, (room - 3 * wmax) / 3));
-        t->key_bits = 3 * wmax + 3 * sub_bits;
-        t->sort_passes = (t->key_bits + 7) / 8;
-
-        // ---- 2. keys
-        KeyParams kp;
-        kp.inv_cell = inv_cell;
-        for (int a = 0; a < 3; ++a) kp.cmin[a] = V.cmin[a];
-        kp.sub_bits = sub_bits;
-        hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, n, kp,
-                           keys_a, vals_a);
-
-        // ---- 3. LSD radix sort on the occupied key bits
-        bool in_b = false;
-        s = sort_pairs(ctx, keys_a, vals_a, keys_b, vals_b, n, t->key_bits, rcounts, &in_b);
-        if (s != LKC_OK) return s;
-        if (in_b) {
-            std::swap(keys_a, keys_b);
-            std::swap(vals_a, vals_b);
-        }
-
-        // ---- 4. reorder
-        hipLaunchKernelGGL(k_reorder, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, vals_a, n,
-                           pts, boxes);
-        // ---- 5. cell runs
-        RowKey rk;
-        rk.inv_cell = inv_cell;
-        for (int a = 0; a < 3; ++a) rk.cmin[a] = V.cmin[a];
-        rk.sh_y = V.sh_y;
-        rk.sh_z = V.sh_z;
-        hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a, n,
-                           3 * sub_bits, bcounts);
-        scan_exclusive(st, bcounts, nb_bt, btmp);
-        hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, keys_a,
-                           (const float4*)pts, n, 3 * sub_bits, bcounts, rk, tkeys, tstart, meta);
-        LKC_HIP_TRY(ctx, hipGetLastError());
-        LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
-        LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
-        n_cells = hmeta->n_cells;
-    } else {
-        for (int a = 0; a < 3; ++a) {
-            V.cmin[a] = 0;
-            V.cmax[a] = -1;
-        }
-    }
-
-    // ---- 6. cell arrays + hash (sized by the cell count)
-    int hbits = 6;
-    while (((int64_t)1 << hbits) < 2 * n_cells) ++hbits;
-    const int64_t cap = (int64_t)1 << hbits;
-    const size_t ck_b = align256(8 * (size_t)(n_cells > 0 ? n_cells : 1));
-    const size_t cs_b = align256(4 * (size_t)(n_cells + 1));
-    const size_t h_b = align256(sizeof(HashSlot) * (size_t)cap);
+    // ---- cell arrays + hash, sized by the point count (the cell count is
+    // only known on the device; the hash uses 2^hash_bits of its slots)
+    int cap_bits = 6;
+    while (((int64_t)1 << cap_bits) < 2 * n) ++cap_bits;
+    const int64_t cap_max = (int64_t)1 << cap_bits;
+    const size_t ck_b = align256(8 * nn);
+    const size_t cs_b = align256(4 * (nn + 1));
+    const size_t h_b = align256(sizeof(HashSlot) * (size_t)cap_max);
     const size_t cbytes = ck_b + cs_b + h_b;
     if (t->cell_bytes < cbytes) {
         if (t->cell_mem) {
@@ -763,14 +725,98 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     auto* ckeys = (unsigned long long*)t->cell_mem;
     auto* cstart = (uint32_t*)((char*)t->cell_mem + ck_b);
     auto* hash = (HashSlot*)((char*)t->cell_mem + ck_b + cs_b);
-    hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap, BT)), dim3(BT), 0, st, hash, cap);
-    if (n_cells > 0) {
-        hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n_cells, BT)), dim3(BT), 0, st, tkeys,
-                           tstart, n_cells, n, ckeys, cstart, hash, hbits, (uint32_t)(cap - 1));
+
+    // Steps 2-6 for a sort of `passes` 8-bit passes; every layout parameter
+    // is read from the device meta.
+    auto enqueue = [&](int passes) -> lkc_status {
+        unsigned long long *ka = keys_a, *kb = keys_b;
+        uint32_t *va = vals_a, *vb = vals_b;
+        // ---- 2. keys
+        hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, n,
+                           inv_cell, (const BuildMeta*)meta, ka, va);
+        // ---- 3. LSD radix sort
+        bool in_b = false;
+        lkc_status r = sort_pairs(ctx, ka, va, kb, vb, n, 8 * passes, rcounts, &in_b);
+        if (r != LKC_OK) return r;
+        if (in_b) {
+            std::swap(ka, kb);
+            std::swap(va, vb);
+        }
+        // ---- 4. reorder (+ run boxes)
+        hipLaunchKernelGGL(k_reorder, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, va, n,
+                           pts, boxes);
+        // ---- 5. cell runs
+        hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb_bt), dim3(BT), 0, st, ka, n,
+                           (const BuildMeta*)meta, bcounts);
+        scan_exclusive(st, bcounts, nb_bt, btmp);
+        hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, ka,
+                           (const float4*)pts, n, inv_cell, bcounts, tkeys, tstart, meta);
+        // ---- 6. hash
+        hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap_max, BT)), dim3(BT), 0, st, hash,
+                           (const BuildMeta*)meta, 0);
+        hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n, BT)), dim3(BT), 0, st, tkeys, tstart,
+                           (const BuildMeta*)meta, n, ckeys, cstart, hash);
+        LKC_HIP_TRY(ctx, hipGetLastError());
+        LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
+        LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+        return LKC_OK;
+    };
+
+    int64_t n_cells = 0;
+    int hbits = 6;
+    if (n > 0) {
+        // ---- 1. cell coordinates, bounding box, finiteness, key layout
+        hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
+                           inv_cell, orig, mparts);
+        hipLaunchKernelGGL(k_meta_reduce, dim3(1), dim3(1024), 0, st, (const MetaPart*)mparts,
+                           nb_bt, meta);
+        LKC_HIP_TRY(ctx, hipGetLastError());
+        // A first build reads the box (and the passes it needs) back first;
+        // a rebuild runs on with the previous build's passes.
+        int passes = prev_passes;
+        if (passes <= 0) {
+            LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta),
+                                            hipMemcpyDeviceToHost, st));
+            LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
+            if (hmeta->nonfinite) {
+                V.n = 0;
+                return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
+            }
+            passes = hmeta->passes;
+        }
+        s = enqueue(passes);
+        if (s != LKC_OK) return s;
+        if (hmeta->nonfinite) {
+            V.n = 0;
+            return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
+        }
+        if (hmeta->passes > passes) {
+            // the key outgrew the previous build's passes: sort again in full
+            s = enqueue(hmeta->passes);
+            if (s != LKC_OK) return s;
+        }
+        for (int a = 0; a < 3; ++a) {
+            V.cmin[a] = hmeta->cmin[a];
+            V.cmax[a] = hmeta->cmax[a];
+        }
+        V.max_abs = __builtin_bit_cast(float, hmeta->max_abs_bits);
+        V.sh_y = hmeta->sh_y;
+        V.sh_z = hmeta->sh_z;
+        t->key_bits = hmeta->key_bits;
+        t->sort_passes = hmeta->passes;
+        n_cells = hmeta->n_cells;
+        hbits = hmeta->hash_bits;
     } else {
+        for (int a = 0; a < 3; ++a) {
+            V.cmin[a] = 0;
+            V.cmax[a] = -1;
+        }
+        hipLaunchKernelGGL(k_hash_clear, dim3(1), dim3(64), 0, st, hash, (const BuildMeta*)meta,
+                           hbits);
         hipLaunchKernelGGL(k_iota, dim3(1), dim3(1), 0, st, cstart, (int64_t)1);
+        LKC_HIP_TRY(ctx, hipGetLastError());
     }
-    LKC_HIP_TRY(ctx, hipGetLastError());
+    const int64_t cap = (int64_t)1 << hbits;
 
     V.pts = pts;
     V.orig = orig;

@@ -59,6 +59,12 @@ def test_build_cells_partition_points(lk, n, cell, seed):
     lkc, ctx = lk
     p = workloads.random_cloud(n, seed, scale=20.0, offset=(100.0, -40.0, 3.0))
     t = lkc.lkc_build_target(ctx, dev(p), cell)
+    check_layout(t, p, cell)
+    t.free()
+
+
+def check_layout(t, p, cell):
+    n = p.shape[0]
     info = t.info()
     pts, cs, ck = t.arrays()
     pts, cs, ck = pts.numpy(), cs.numpy().astype(np.int64), ck.numpy()
@@ -104,6 +110,42 @@ def test_build_cells_partition_points(lk, n, cell, seed):
     order = np.lexsort((orig, mort))
     assert np.array_equal(order, np.arange(n))
     assert info["hash_capacity"] >= 2 * C
+
+
+def test_rebuild_reuses_the_target(lk):
+    """Rebuilding one target with clouds whose keys need more, then fewer,
+    sort passes than the previous build (a rebuild runs the previous build's
+    passes and sorts again when the new key needs more), growing and
+    shrinking n: the layout is the fresh build's and kNN matches the oracle;
+    a non-finite cloud fails and leaves the target empty, and the target
+    builds again afterwards."""
+    lkc, ctx = lk
+    # sort passes of the keys: 2, 5 (after 2), 3 (after 5), 3, 4 (after 3)
+    clouds = [workloads.random_cloud(3_000, 11, scale=2.0),
+              workloads.random_cloud(50_000, 12, scale=300.0),
+              workloads.random_cloud(20_000, 13, scale=6.0),
+              workloads.random_cloud(20_000, 14, scale=6.0, offset=(900.0, 0.0, 0.0)),
+              workloads.random_cloud(60_000, 15, scale=40.0)]
+    t = lkc.lkc_build_target(ctx, dev(clouds[0]), 1.0)
+    passes = []
+    for p in clouds:
+        t.rebuild(dev(p))
+        check_layout(t, p, 1.0)
+        passes.append(t.info()["sort_passes"])
+        q = p[::97].copy()
+        idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(q), 8, 1.5)
+        parity.check_knn(p, q, 8, 1.5, host(idx), host(d2), host(cnt))
+    assert passes == [2, 5, 3, 3, 4]
+    bad = clouds[2].copy()
+    bad[777, 2] = np.inf
+    with pytest.raises(lkc.LkcError) as e:
+        t.rebuild(dev(bad))
+    assert e.value.status == lkc.LKC_ERR_NONFINITE
+    assert t.info()["n_points"] == 0
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(clouds[2][:50]), 4)
+    assert int(cnt.sum()) == 0
+    t.rebuild(dev(clouds[2]))
+    check_layout(t, clouds[2], 1.0)
     t.free()
 
 
