@@ -124,6 +124,9 @@ def served(args, lkc, workloads, torch):
     serve.serve_loop(warm, ex, time_scale=math.inf)
     res = serve.summarize(serve.serve_loop(reqs, ex, time_scale=args.time_scale))
     plain = serve.summarize(serve.plain_loop(reqs, ex, time_scale=args.time_scale))
+    # the same requests released all at once: the loops' capacity
+    sat = serve.summarize(serve.serve_loop(reqs, ex, time_scale=math.inf))
+    sat_plain = serve.summarize(serve.plain_loop(reqs, ex, time_scale=math.inf))
     ex.close()
     out = {
         "metric": METRIC, "value": res["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
@@ -136,6 +139,10 @@ def served(args, lkc, workloads, torch):
                    "time_scale": args.time_scale, "k": k, "radius_m": radius, "cell_m": cell,
                    "hbm_budget_bytes": budget, "slot_capacity_queries": ex.capacity},
         "served": res, "plain_per_scan": plain,
+        "saturated": {"served_queries_per_s": sat["queries_per_s"],
+                      "plain_queries_per_s": sat_plain["queries_per_s"],
+                      "served_mean_batch_requests": sat["mean_batch_requests"],
+                      "served_wall_s": sat["wall_s"], "plain_wall_s": sat_plain["wall_s"]},
         "latency_ms": {"p50": res["p50_ms"], "p99": res["p99_ms"]},
     }
     print(json.dumps(out))
