@@ -214,11 +214,15 @@ __global__ void __launch_bounds__(1024) k_meta_reduce(const MetaPart* __restrict
     }
 }
 
+// Sort keys; the threads also clear the hash's slots (all `cap` of them,
+// ahead of the insert, which uses the first 2^hash_bits).
 __global__ void __launch_bounds__(BT) k_make_keys(const float4* __restrict__ orig, int64_t n,
                                                   float inv_cell, const BuildMeta* __restrict__ meta,
                                                   unsigned long long* __restrict__ keys,
-                                                  uint32_t* __restrict__ vals) {
+                                                  uint32_t* __restrict__ vals,
+                                                  HashSlot* __restrict__ hash, int64_t cap) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    for (int64_t h = i; h < cap; h += (int64_t)gridDim.x * BT) hash[h] = HashSlot{EMPTY_KEY, 0u, 0u};
     if (i >= n) return;
     const float4 p = orig[i];
     const uint32_t cx = (uint32_t)(cell_coord(p.x, inv_cell) - meta->cmin[0]);
@@ -416,18 +420,7 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
     }
 }
 
-// Cell runs: flag(i) = cell part of key[i] differs from key[i-1]'s.  Pass 1
-// counts flags per block.
-__global__ void __launch_bounds__(BT) k_cell_count(const unsigned long long* __restrict__ keys,
-                                                   int64_t n, const BuildMeta* __restrict__ meta,
-                                                   uint32_t* __restrict__ bcount) {
-    const int sub_shift = 3 * meta->sub_bits;
-    const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
-    const bool f = i < n && (i == 0 || (keys[i] >> sub_shift) != (keys[i - 1] >> sub_shift));
-    const int c = __syncthreads_count(f);
-    if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)c;
-}
-
+// Cell runs (their per-block counts come from k_reorder).
 // Pass 2: each run start writes its cell's row-major key (recomputed from the
 // reordered point) and its first position; the last point records the cell
 // count and the hash size.
@@ -505,13 +498,22 @@ __global__ void __launch_bounds__(BT) k_hash_insert(const unsigned long long* __
     }
 }
 
-// Reorder the points into key order, and write the bounding box of every
-// aligned 16-point run (one 16-lane quarter of a wavefront per box).
+// Reorder the points into key order, write the bounding box of every
+// aligned 16-point run (one 16-lane quarter of a wavefront per box), and
+// count the cell runs starting in each block (flag(i): the cell part of
+// key[i] differs from key[i-1]'s).
 __global__ void __launch_bounds__(BT) k_reorder(const float4* __restrict__ orig,
                                                 const uint32_t* __restrict__ vals, int64_t n,
                                                 float4* __restrict__ pts,
-                                                float4* __restrict__ boxes) {
+                                                float4* __restrict__ boxes,
+                                                const unsigned long long* __restrict__ keys,
+                                                const BuildMeta* __restrict__ meta,
+                                                uint32_t* __restrict__ bcount) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    const int sub_shift = 3 * meta->sub_bits;
+    const bool f = i < n && (i == 0 || (keys[i] >> sub_shift) != (keys[i - 1] >> sub_shift));
+    const int c = __syncthreads_count(f);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = (uint32_t)c;
     const int64_t box = i / BOX_PTS;
     const bool v = i < n;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -733,7 +735,7 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         uint32_t *va = vals_a, *vb = vals_b;
         // ---- 2. keys
         hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, n,
-                           inv_cell, (const BuildMeta*)meta, ka, va);
+                           inv_cell, (const BuildMeta*)meta, ka, va, hash, cap_max);
         // ---- 3. LSD radix sort
         bool in_b = false;
         lkc_status r = sort_pairs(ctx, ka, va, kb, vb, n, 8 * passes, rcounts, &in_b);
@@ -742,18 +744,14 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
             std::swap(ka, kb);
             std::swap(va, vb);
         }
-        // ---- 4. reorder (+ run boxes)
-        hipLaunchKernelGGL(k_reorder, dim3(grid_for(n, BT)), dim3(BT), 0, st, orig, va, n,
-                           pts, boxes);
+        // ---- 4. reorder (+ run boxes, run counts per block)
+        hipLaunchKernelGGL(k_reorder, dim3((unsigned)nb_bt), dim3(BT), 0, st, orig, va, n, pts,
+                           boxes, (const unsigned long long*)ka, (const BuildMeta*)meta, bcounts);
         // ---- 5. cell runs
-        hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb_bt), dim3(BT), 0, st, ka, n,
-                           (const BuildMeta*)meta, bcounts);
         scan_exclusive(st, bcounts, nb_bt, btmp);
         hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, ka,
                            (const float4*)pts, n, inv_cell, bcounts, tkeys, tstart, meta);
-        // ---- 6. hash
-        hipLaunchKernelGGL(k_hash_clear, dim3(grid_for(cap_max, BT)), dim3(BT), 0, st, hash,
-                           (const BuildMeta*)meta, 0);
+        // ---- 6. hash (cleared by k_make_keys)
         hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n, BT)), dim3(BT), 0, st, tkeys, tstart,
                            (const BuildMeta*)meta, n, ckeys, cstart, hash);
         LKC_HIP_TRY(ctx, hipGetLastError());

@@ -767,7 +767,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             for (int t = max(lo, q4 * BOX_PTS); t < t1; ++t) {
                 const float cx = readlane(c.x, t), cy = readlane(c.y, t), cz = readlane(c.z, t);
                 const float d = dist2(qx, qy, qz, cx, cy, cz);
-                b |= d <= tthr ? (1u << (t & 31)) : 0u;
+                b |= (d <= tthr ? 1u : 0u) << (t & 31);
             }
             if (q4 < 2)
                 blo |= b;
