@@ -39,6 +39,7 @@ constexpr int RS_TILE = BT * RS_ITEMS;
 constexpr int RADIX = 256;
 constexpr int SCAN_TILE = 4096;  // entries per workgroup of the multi-block scan
 constexpr int RAW_OFFSET_TILES = 96;  // sorts of up to this many tiles skip the scan launch
+constexpr int RAW_RUN_BLOCKS = 2048;  // cell-run numbering of up to this many blocks skips it too
 
 // Written by the build kernels: the occupied-cell box, and the key layout
 // and hash size derived from it on the device, so that the kernels after
@@ -423,26 +424,36 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
 // Cell runs (their per-block counts come from k_reorder).
 // Pass 2: each run start writes its cell's row-major key (recomputed from the
 // reordered point) and its first position; the last point records the cell
-// count and the hash size.
+// count and the hash size.  `boff` holds the blocks' first cell ids, or with
+// `raw` the blocks' run counts, which each block then sums itself (for up
+// to RAW_RUN_BLOCKS blocks, saving the scan launch).
 __global__ void __launch_bounds__(BT) k_cell_write(const unsigned long long* __restrict__ keys,
                                                    const float4* __restrict__ pts, int64_t n,
                                                    float inv_cell,
                                                    const uint32_t* __restrict__ boff,
                                                    unsigned long long* __restrict__ ckeys,
                                                    uint32_t* __restrict__ cstart,
-                                                   BuildMeta* __restrict__ meta) {
-    __shared__ uint32_t s_w[BT / WAVE];
+                                                   BuildMeta* __restrict__ meta, int raw) {
+    __shared__ uint32_t s_w[BT / WAVE], s_b[BT / WAVE];
     const int sub_shift = 3 * meta->sub_bits;
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
+    uint32_t before = 0;
+    if (raw)
+        for (int j = threadIdx.x; j < (int)blockIdx.x; j += BT) before += boff[j];
     const bool f = i < n && (i == 0 || (keys[i] >> sub_shift) != (keys[i - 1] >> sub_shift));
     const int l = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     const unsigned long long bal = __ballot(f);
     const uint32_t pre = (uint32_t)__popcll(bal & ((1ull << l) - 1ull));
-    if (l == 0) s_w[w] = (uint32_t)__popcll(bal);
+    for (int sft = WAVE / 2; sft > 0; sft >>= 1) before += (uint32_t)__shfl_xor((int)before, sft);
+    if (l == 0) {
+        s_w[w] = (uint32_t)__popcll(bal);
+        s_b[w] = before;
+    }
     __syncthreads();
-    uint32_t wo = 0;
+    uint32_t wo = 0, base = 0;
     for (int j = 0; j < w; ++j) wo += s_w[j];
-    const uint32_t cid = boff[blockIdx.x] + wo + pre;
+    for (int j = 0; j < BT / WAVE; ++j) base += s_b[j];
+    const uint32_t cid = (raw ? base : boff[blockIdx.x]) + wo + pre;
     if (f) {
         const float4 p = pts[i];
         const uint32_t cx = (uint32_t)(cell_coord(p.x, inv_cell) - meta->cmin[0]);
@@ -748,9 +759,11 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         hipLaunchKernelGGL(k_reorder, dim3((unsigned)nb_bt), dim3(BT), 0, st, orig, va, n, pts,
                            boxes, (const unsigned long long*)ka, (const BuildMeta*)meta, bcounts);
         // ---- 5. cell runs
-        scan_exclusive(st, bcounts, nb_bt, btmp);
+        const int raw_runs = nb_bt <= RAW_RUN_BLOCKS ? 1 : 0;
+        if (!raw_runs) scan_exclusive(st, bcounts, nb_bt, btmp);
         hipLaunchKernelGGL(k_cell_write, dim3((unsigned)nb_bt), dim3(BT), 0, st, ka,
-                           (const float4*)pts, n, inv_cell, bcounts, tkeys, tstart, meta);
+                           (const float4*)pts, n, inv_cell, bcounts, tkeys, tstart, meta,
+                           raw_runs);
         // ---- 6. hash (cleared by k_make_keys)
         hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n, BT)), dim3(BT), 0, st, tkeys, tstart,
                            (const BuildMeta*)meta, n, ckeys, cstart, hash);
