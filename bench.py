@@ -548,7 +548,7 @@ def main():
                   "step": "one persistent batched kNN+covariance launch"}
         if not args.no_autotune and not args.cfg:
             from paper_2308_07173_amd import autotune
-            tune = autotune.autotune(m, allq, k, radius, sample=262_144, ctx=ctx)
+            tune = autotune.autotune(m, allq, k, radius, sample=allq.shape[0], ctx=ctx)
             cell, cfg = tune["cell"], (tune["cfg"] or None)
             config["cell_m"] = cell
             config["autotune"] = {"cell_m": cell, "cfg": tune["cfg"], "sample": tune["sample"],
