@@ -659,9 +659,28 @@ __device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, floa
 // runs touching the query box, the rest of the query cells, the other cells;
 // then insertions from the group's own chunk (self queries)
 constexpr int PROF_WORDS = 17;
+// A profile counter that compiles away in the unprofiled kernels (their
+// counters are never read, so the arithmetic feeding them is dead).
+template <bool ON>
+struct ProfCount {
+    uint32_t v = 0;
+    __device__ ProfCount& operator++() {
+        if (ON) ++v;
+        return *this;
+    }
+    __device__ void operator++(int) {
+        if (ON) ++v;
+    }
+    __device__ ProfCount& operator+=(uint32_t x) {
+        if (ON) v += x;
+        return *this;
+    }
+    __device__ operator uint32_t() const { return ON ? v : 0u; }
+};
+template <bool ON>
 struct GroupProf {
-    uint32_t probes, cells, chunks, cands, pops, inserts, dead;
-    uint32_t ins0, ins1, ins2, cand0, cand1, cand2, own;
+    ProfCount<ON> probes, cells, chunks, cands, pops, inserts, dead;
+    ProfCount<ON> ins0, ins1, ins2, cand0, cand1, cand2, own;
 };
 
 struct SlotQuery {
@@ -713,13 +732,13 @@ __device__ __forceinline__ float box_box_dist2(const float (&a0)[3], const float
 // candidate that any lane wants.  The test compares float d2 with the
 // lane's k-th distance (the radius while its list is not full), so exact
 // ties pass it; the pop makes the exact (d2, index) comparison.
-template <int K>
+template <int K, bool PROF>
 __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bool member,
                                          float qx, float qy, float qz, float r2, float lcap,
                                          const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr,
                                          unsigned long long (&kk)[K], int mode,
-                                         GroupProf& gp, int skip_cb, const SplitShare& sh,
+                                         GroupProf<PROF>& gp, int skip_cb, const SplitShare& sh,
                                          int win_k = 0, int win_n = 0) {
     const int lane = lane_id();
 #pragma unroll 1
@@ -807,7 +826,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
     }
 }
 
-template <int K, int FUSED>
+template <int K, int FUSED, bool PROF>
 __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& sh,
                            unsigned long long* s_kk) {
     const int lane = lane_id();
@@ -832,8 +851,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     bool ok = true;
     // An empty target answers every query with an empty list.
     bool placed = same && T.n_cells == 0;   // searched by one of the rounds below
-    GroupProf gp{0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    const unsigned long long t_start = a.prof ? __builtin_amdgcn_s_memtime() : 0ull;
+    GroupProf<PROF> gp{};
+    const unsigned long long t_start = PROF ? __builtin_amdgcn_s_memtime() : 0ull;
     // Rounds: each picks an anchor cell among the unplaced lanes and searches
     // for every unplaced lane within GROUP_W cells of it, so a group whose sorted
     // queries straddle two clusters can be served in two rounds rather than
@@ -1061,7 +1080,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     if (sh.sub) return;   // the other waves of a split group are done
     const bool to_fb = (fin && !placed) || (placed && !ok);
     const unsigned long long fm = ballot(to_fb);
-    if (a.prof && lane == 0) {
+    if (PROF && lane == 0) {
         uint32_t* pw = a.prof + group * PROF_WORDS;
         pw[0] = (uint32_t)(__builtin_amdgcn_s_memtime() - t_start);
         pw[1] = gp.probes;
@@ -1117,7 +1136,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     }
 }
 
-template <int K, int FUSED>
+// PROF: record the per-group profile words (a.prof is set).
+template <int K, int FUSED, bool PROF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 20 ? 4 : 2)))
 k_group(GroupArgs a) {
     const int wpb = blockDim.x / WAVE;
@@ -1138,14 +1158,14 @@ k_group(GroupArgs a) {
         // the XCDs, which spreads the dense regions' heavy groups.
         const int64_t g = a.queries ? (int64_t)xcd_tile(blockIdx.x, gridDim.x)
                                     : (int64_t)blockIdx.x;
-        if (g < n_groups) group_body<K, FUSED>(a, g, sh, s_kk);
+        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, sh, s_kk);
         return;
     }
     if (!a.counters) {
         // many groups: dealt round-robin over the XCDs, so that every XCD
         // gets a share of the dense regions
         const int64_t g = (int64_t)blockIdx.x * wpb + threadIdx.x / WAVE;
-        if (g < n_groups) group_body<K, FUSED>(a, g, none, nullptr);
+        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, none, nullptr);
         return;
     }
     // persistent: the groups are split into 8 contiguous ranges, one per XCD
@@ -1162,7 +1182,7 @@ k_group(GroupArgs a) {
             t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             const int64_t g = g_lo + t;
             if (g >= g_hi) break;
-            group_body<K, FUSED>(a, g, none, nullptr);
+            group_body<K, FUSED, PROF>(a, g, none, nullptr);
         }
     }
 }
@@ -1386,10 +1406,22 @@ void launch_group(int K, dim3 grid, dim3 block, hipStream_t st, const GroupArgs&
                                          sizeof(float) * (size_t)a.split * WAVE
                                    : 0;
     switch (K) {
-        case 8: hipLaunchKernelGGL((k_group<8, FUSED>), grid, block, lds, st, a); break;
-        case 16: hipLaunchKernelGGL((k_group<16, FUSED>), grid, block, lds, st, a); break;
-        case 20: hipLaunchKernelGGL((k_group<20, FUSED>), grid, block, lds, st, a); break;
-        default: hipLaunchKernelGGL((k_group<32, FUSED>), grid, block, lds, st, a); break;
+        case 8:
+            if (a.prof) hipLaunchKernelGGL((k_group<8, FUSED, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_group<8, FUSED, false>), grid, block, lds, st, a);
+            break;
+        case 16:
+            if (a.prof) hipLaunchKernelGGL((k_group<16, FUSED, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_group<16, FUSED, false>), grid, block, lds, st, a);
+            break;
+        case 20:
+            if (a.prof) hipLaunchKernelGGL((k_group<20, FUSED, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_group<20, FUSED, false>), grid, block, lds, st, a);
+            break;
+        default:
+            if (a.prof) hipLaunchKernelGGL((k_group<32, FUSED, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_group<32, FUSED, false>), grid, block, lds, st, a);
+            break;
     }
 }
 
