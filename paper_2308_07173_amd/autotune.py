@@ -28,6 +28,7 @@ DEFAULT_CFGS = (
     dict(waves_per_block=1),
     dict(persistent=4),
     dict(persistent=8, waves_per_block=2),
+    dict(algorithm=2),                        # one wavefront per query (small launches)
 )
 
 _cache: Dict[Tuple, Dict] = {}

@@ -547,6 +547,7 @@ struct KnnPtrs {
 // search through a fallback list.
 
 constexpr int GROUP_W = 2;       // lanes within this many cells of a round's anchor take part
+constexpr int64_t WHOLE_N = 4096;  // targets this small are streamed whole by every group
 
 __device__ __forceinline__ unsigned long long lane_key(float d, int32_t idx) {
     return ((unsigned long long)(__float_as_uint(d) + 1u) << 32) | (uint32_t)idx;
@@ -922,7 +923,9 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
                 }
             }
         }
-        const bool member = takes(ax, ay, az);
+        // A small target is streamed whole, in one round, for every lane.
+        const bool whole = T.n <= WHOLE_N;
+        const bool member = whole ? pend : takes(ax, ay, az);
         const unsigned long long mm = ballot(member);
         pending &= ~mm;
         placed = placed || member;
@@ -981,7 +984,10 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
                         s.z, r2, lcap, b0, b1, margin, gthr, kk, 2, gp, -1, sh, win_k, n_act);
             gp.own += gp.inserts - i0;
         }
-        for (int pass = 0; pass < 2; ++pass) {
+        if (whole)
+            scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin, gthr,
+                        kk, 2, gp, own_cb, sh);
+        for (int pass = 0; pass < (whole ? 0 : 2); ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
                 gp.probes++;
                 const int64_t t = base + lane;
@@ -1074,7 +1080,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             f -= margin;
             const float f2 = f > 0.0f ? f * f * (1.0f - 1e-6f) : 0.0f;
             const bool full = kk[K - 1] != ~0ull;
-            ok = covers || (full && f2 > key_d2(kk[K - 1])) || (a.sp.capped && f2 > r2);
+            ok = whole || covers || (full && f2 > key_d2(kk[K - 1])) || (a.sp.capped && f2 > r2);
         }
     }
     if (sh.sub) return;   // the other waves of a split group are done
