@@ -5,28 +5,33 @@
 // corresponding nearest points, then estimate the covariance that models
 // the point as a Gaussian in GICP.
 //
-// Search -- one wavefront per query:
-//   * cells are visited in Chebyshev rings around the query's cell; lanes
-//     enumerate a ring's cells in parallel, drop cells whose box lies beyond
-//     the radius or the current k-th distance, and probe the cell hash;
-//   * the surviving cells' point runs are concatenated and streamed 64 at a
-//     time (lane j loads the j-th candidate: one coalesced 1 KB read);
-//   * the running top-k is one sorted list spread over the lanes (lane j
-//     holds entry j as (d2, original index, reordered position)); a batch
-//     with few qualifying candidates inserts them one by one (a ballot finds
-//     the slot, a DPP wave shift opens it), a batch with many is merged with
-//     a 64-lane bitonic network;
-//   * the search stops once the distance from the query to the unvisited
-//     region exceeds the k-th distance (or the radius); a query whose rings
-//     would outgrow the number of occupied cells finishes with one sweep of
-//     the cell table, so uncapped searches stay bounded.
-// Ordering everywhere is lexicographic on (float32 d2, original index).
+// Search -- two kernels:
+//   * the group search (k_group) takes 64 queries per wavefront (queries
+//     sorted by the Morton code of their cell; self queries are the target's
+//     own sorted points), one lane per query with its top-k in registers:
+//     the group streams the point runs of its block of cells once, each
+//     candidate broadcast to all lanes, and answers every lane whose result
+//     the block proves exact;
+//   * the wavefront-per-query search (k_fallback, and the whole search with
+//     algorithm 2) answers the rest: cells in Chebyshev rings around the
+//     query's cell, lanes enumerating a ring's cells in parallel and probing
+//     the cell hash; the surviving runs streamed 64 candidates at a time
+//     (one coalesced read); the running top-k one sorted list spread over
+//     the lanes (entry j in lane j), few qualifying candidates inserted one
+//     by one (a ballot finds the slot, a DPP wave shift opens it), many
+//     merged by a 64-lane bitonic network; it stops once the unvisited
+//     region lies beyond the k-th distance (or the radius), and a query
+//     whose rings would outgrow the occupied cells finishes with one sweep
+//     of the cell table, so uncapped searches stay bounded.
+// Ordering everywhere is lexicographic on (float32 d2, original index), so
+// both kernels, every launch shape and every visiting order give the same
+// bits.
 //
-// Covariance -- one lane per query, two passes over the neighbours relative
-// to the query point (centred, 1/n), then a float32 cyclic Jacobi
-// eigen-decomposition of the 3x3 for the GICP plane regulariser.  The fused
-// kernel keeps each wavefront's neighbour lists in LDS and runs the
-// covariances of its tile of queries lane-parallel after the searches.
+// Covariance -- two passes over the neighbours relative to the query point
+// (centred, 1/n), then a float32 cyclic Jacobi eigen-decomposition of the
+// 3x3 for the GICP plane regulariser; fused into both searches (one lane
+// per query in the group search, the whole wavefront in the other) and
+// standalone in k_cov.
 #include <cmath>
 
 #include "lkc_internal.h"
