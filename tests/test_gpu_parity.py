@@ -305,6 +305,34 @@ def test_self_query_matches_plain_and_oracle(lk):
         t.free()
 
 
+@pytest.mark.parametrize("n", [4096, 4097])
+def test_whole_target_boundary(lk, n):
+    """Targets of up to 4,096 points are streamed whole by every group (one
+    round, no block, no fallback); one point more takes the block search.
+    Both sides of the boundary match the oracle and the wavefront-per-query
+    search bit for bit, for self and external queries, capped and not."""
+    lkc, ctx = lk
+    p = workloads.plane_wall(n, seed=31)
+    q = workloads.random_cloud(3000, 32, scale=12.0)
+    t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+    for radius in (1.0, INF):
+        a = lkc.lkc_knn_cov_self(ctx, t, 12, radius, 1e-3)
+        a2 = lkc.lkc_knn_cov_self(ctx, t, 12, radius, 1e-3, cfg=dict(algorithm=2))
+        b = lkc.lkc_knn_cov(ctx, t, dev(q), 12, radius, 1e-3)
+        b2 = lkc.lkc_knn_cov(ctx, t, dev(q), 12, radius, 1e-3, cfg=dict(algorithm=2))
+        torch.cuda.synchronize()
+        for key in a:
+            assert torch.equal(a[key], a2[key]), key
+            assert torch.equal(b[key], b2[key]), key
+        for qs, o in ((p, a), (q, b)):
+            o = {kk: host(v) for kk, v in o.items()}
+            rows = np.arange(qs.shape[0])[::7]
+            parity.check_knn(p, qs, 12, radius, o["idx"], o["d2"], o["count"], rows=rows)
+            parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"],
+                             o["valid"], rows=rows, search=(qs, 12, radius))
+    t.free()
+
+
 # ------------------------------------------------------------ covariance --
 
 def test_cov_tiny_config_against_oracle(lk):
