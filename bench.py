@@ -383,7 +383,8 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=0.0,
                     help="served: device memory budget (0 = 80 %% of free)")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="batched: skip the autotuner (1 m cells, default launch)")
+                    help="batched and tiny: skip the autotuner (default launch shape; "
+                         "batched also 1 m cells)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cfg", default="", help="launch cfg, e.g. tile_queries=32,merge_min=8")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -440,6 +441,13 @@ def main():
             config = {"workload": "2048-point plane + wall, self-query", "n_points": 2048,
                       "k": k, "radius_m": None, "cell_m": cell,
                       "step": "grid rebuild + fused kNN+covariance"}
+            if not args.no_autotune and not args.cfg:
+                # the launch shape only (the cell is the configuration's)
+                from paper_2308_07173_amd import autotune
+                tune = autotune.autotune(pts, pts, k, radius, cells=(cell,),
+                                         sample=pts.shape[0], ctx=ctx)
+                cfg = tune["cfg"] or None
+                config["autotune"] = {"cfg": tune["cfg"], "candidates": len(tune["table"])}
         p = torch.from_numpy(pts).to(dev)
         Q = p.shape[0]
         tgt = lkc.lkc_build_target(ctx, p, cell)
@@ -603,15 +611,17 @@ def main():
     sort_ms, group_ms, fb_ms = (float(ph[:, i].mean()) for i in range(3))
     fb_q = int(ph[-1, 3])
     extra["fallback_queries"] = fb_q
-    # dominant kernel: the group search; its algorithmic bytes are those of
-    # the queries it answers (the rest go to the wavefront search)
+    # dominant kernel: the group search, its algorithmic bytes those of the
+    # queries it answers (the rest go to the wavefront search); or the
+    # wavefront search when it takes longer (one wavefront per query)
     group_q = queries_per_launch - fb_q
-    achieved = group_q * b_alg(k) / (group_ms * 1e-3) / 1e9
+    dom = ("k_group", group_q, group_ms) if group_ms >= fb_ms else ("k_fallback", fb_q, fb_ms)
+    achieved = dom[1] * b_alg(k) / (dom[2] * 1e-3) / 1e9
     path_achieved = queries_per_launch * b_alg(k) / (kern_ms * 1e-3) / 1e9
     extra["phases_ms"] = {"query_sort": sort_ms, "k_group": group_ms, "k_fallback": fb_ms}
     extra["search_call"] = {"ms": kern_ms, "achieved_GBs": path_achieved,
                             "frac": path_achieved / HBM_PEAK_GBS}
-    traffic = committed_traffic(args.workload)
+    traffic = committed_traffic(args.workload) if dom[0] == "k_group" else None
     if args.workload == "weighted":
         config["note"] = "roofline bytes as the plain path: the weights add no HBM traffic"
     res = {
@@ -630,8 +640,8 @@ def main():
         "config": config,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_group", "bytes_per_query": b_alg(k),
-                     "queries_per_launch": int(group_q), "kernel_ms": group_ms},
+                     "kernel": dom[0], "bytes_per_query": b_alg(k),
+                     "queries_per_launch": int(dom[1]), "kernel_ms": dom[2]},
     }
     res.update(extra)
     if cfg:
