@@ -262,24 +262,55 @@ __device__ int knn_query_wave(const TargetView& T, float qx, float qy, float qz,
             }
             break;
         }
-        for (int64_t base = 0; base < total; base += WAVE) {
-            const int64_t t = base + lane;
+        // The ring's cells, face by face (clamped to the occupied box): the
+        // two z faces whole, the y faces without the z faces' rows, the x
+        // faces without both; R = 0 is the query's own cell.
+        const int zi0 = max(cq[2] - R + 1, T.cmin[2]), zi1 = min(cq[2] + R - 1, T.cmax[2]);
+        const int yi0 = max(cq[1] - R + 1, T.cmin[1]), yi1 = min(cq[1] + R - 1, T.cmax[1]);
+        const uint32_t nz_in = (uint32_t)max(zi1 - zi0 + 1, 0), ny_in = (uint32_t)max(yi1 - yi0 + 1, 0);
+        const uint32_t exy = (uint32_t)ext[0] * (uint32_t)ext[1];
+        uint32_t fc[6];
+        fc[0] = (R > 0 && cq[2] - R >= T.cmin[2]) ? exy : (R == 0 ? 1u : 0u);
+        fc[1] = (R > 0 && cq[2] + R <= T.cmax[2]) ? exy : 0u;
+        fc[2] = (R > 0 && cq[1] - R >= T.cmin[1]) ? (uint32_t)ext[0] * nz_in : 0u;
+        fc[3] = (R > 0 && cq[1] + R <= T.cmax[1]) ? (uint32_t)ext[0] * nz_in : 0u;
+        fc[4] = (R > 0 && cq[0] - R >= T.cmin[0]) ? ny_in * nz_in : 0u;
+        fc[5] = (R > 0 && cq[0] + R <= T.cmax[0]) ? ny_in * nz_in : 0u;
+        // (none when the ring misses the occupied box)
+        const uint32_t shell = total > 0 ? fc[0] + fc[1] + fc[2] + fc[3] + fc[4] + fc[5] : 0u;
+        for (uint32_t base = 0; base < shell; base += WAVE) {
+            const uint32_t t = base + (uint32_t)lane;
             bool want = false;
             uint32_t st = 0, cn = 0;
-            if (t < total) {
-                // the sweep above takes every ring of 2^32 cells or more
-                const uint32_t tu = (uint32_t)t, e0 = (uint32_t)ext[0], e1 = (uint32_t)ext[1];
-                const uint32_t t0 = tu / e0;
-                const int ix = (int)(tu - t0 * e0);
-                const int iy = (int)(t0 % e1);
-                const int iz = (int)(t0 / e1);
-                const int cx = lo[0] + ix, cy = lo[1] + iy, cz = lo[2] + iz;
-                const int cheb = max(abs(cx - cq[0]), max(abs(cy - cq[1]), abs(cz - cq[2])));
-                if (cheb == R) {
-                    const float bd = box_dist2(T, qx, qy, qz, cx, cy, cz, margin);
-                    if (bd <= sp.r2 && bd * (1.0f - 1e-6f) <= L.thr_d)
-                        want = hash_find(T, pack_key(T, cx, cy, cz), st, cn) && cn > 0;
+            if (t < shell) {
+                uint32_t u = t;
+                int f = 0;
+#pragma unroll
+                for (int g = 0; g < 5; ++g) {
+                    const bool past = f == g && u >= fc[g];
+                    u = past ? u - fc[g] : u;
+                    f = past ? g + 1 : f;
                 }
+                int cx, cy, cz;
+                if (f < 2) {
+                    const uint32_t e0 = (uint32_t)ext[0], v = u / e0;
+                    cx = lo[0] + (int)(u - v * e0);
+                    cy = lo[1] + (int)v;
+                    cz = R == 0 ? cq[2] : cq[2] + (f ? R : -R);
+                } else if (f < 4) {
+                    const uint32_t e0 = (uint32_t)ext[0], v = u / e0;
+                    cx = lo[0] + (int)(u - v * e0);
+                    cy = cq[1] + (f == 3 ? R : -R);
+                    cz = zi0 + (int)v;
+                } else {
+                    const uint32_t d = ny_in > 0u ? ny_in : 1u, v = u / d;
+                    cx = cq[0] + (f == 5 ? R : -R);
+                    cy = yi0 + (int)(u - v * d);
+                    cz = zi0 + (int)v;
+                }
+                const float bd = box_dist2(T, qx, qy, qz, cx, cy, cz, margin);
+                if (bd <= sp.r2 && bd * (1.0f - 1e-6f) <= L.thr_d)
+                    want = hash_find(T, pack_key(T, cx, cy, cz), st, cn) && cn > 0;
             }
             scan_cells(T, qx, qy, qz, sp, want, st, cn, L);
         }
