@@ -188,6 +188,13 @@ lkc_status lkc_target_get_info(const lkc_target *target, lkc_target_info *info);
  * NULL. */
 lkc_status lkc_target_arrays(const lkc_target *target, const void **pts, const void **cell_start,
                              const void **cell_keys);
+/* Status of the target's last build or rebuild: LKC_OK, or the error that
+ * left it empty (a rebuild from points with a non-finite coordinate leaves
+ * LKC_ERR_NONFINITE here until the next successful rebuild).  Synchronises
+ * the context's stream first, so an asynchronous HIP error of earlier work
+ * on that stream is reported as LKC_ERR_HIP.  A NULL target is
+ * LKC_ERR_INVALID_ARG. */
+lkc_status lkc_target_status(lkc_ctx *ctx, const lkc_target *target);
 
 /* k nearest neighbours of each query (device [q][3]) in `target`:
  * idx int32 [q][k] (original target indices, -1 padding), d2 float [q][k]
@@ -443,6 +450,42 @@ lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
  * n_groups = 0 turns it off.
  * The caller owns the buffer. */
 lkc_status lkc_ctx_set_profile(lkc_ctx *ctx, void *buffer, int64_t n_groups);
+
+/* Autotuner (host logic; outside the hot path).  The grid is an exact
+ * accelerator, so every cell size and launch shape gives the same results
+ * and only the time differs.  For each candidate cell size the target is
+ * built from `target_points` (device [n][3], n >= 1), and lkc_knn_cov
+ * (k, radius, plane_eps as there) is timed for each candidate launch shape
+ * on a sample of `queries` (device [q][3], q >= 1): all of them when
+ * q <= sample, else four contiguous runs of sample / 4 queries at starts
+ * drawn by splitmix64 from `seed`, which keeps the local density of whole
+ * scans.  Time = median of `reps` (1..100) runs after one warm-up, from HIP
+ * events on the context's stream.
+ *   cells    host [n_cells] candidate cell sizes (> 0); n_cells = 0 takes
+ *            0.5, 0.75, 1, 1.5, 2 m
+ *   cfgs     host [n_cfgs] candidate launch shapes; n_cfgs = 0 takes a
+ *            default list of seven (group search with automatic, reach-1,
+ *            2- and 1-wavefront workgroups, two persistent shapes, and the
+ *            wavefront-per-query search)
+ *   times_ms host [n_cells][n_cfgs] median times, or NULL
+ *   result   host: the fastest pair.
+ * Allocates and frees device memory for the sample and its outputs, and
+ * synchronises: not for use under graph capture.  Errors of the builds and
+ * searches it runs are returned as they are. */
+typedef struct lkc_autotune_result {
+    float cell_size;        /* chosen cell size */
+    int32_t cfg_index;      /* index of the chosen shape in cfgs (or the default list) */
+    lkc_launch_cfg cfg;     /* chosen launch shape */
+    float ms;               /* its median time on the sample */
+    int32_t reserved;
+    int64_t sample;         /* queries in the timed sample */
+} lkc_autotune_result;
+lkc_status lkc_autotune(lkc_ctx *ctx, const float *target_points, int64_t n,
+                        const float *queries, int64_t q, int32_t k, float radius,
+                        float plane_eps, const float *cells, int32_t n_cells,
+                        const lkc_launch_cfg *cfgs, int32_t n_cfgs, int64_t sample,
+                        uint64_t seed, int32_t reps, float *times_ms,
+                        lkc_autotune_result *result);
 
 /* Grow the context's search scratch (query sort buffers and the fallback
  * list, about 36 bytes per query) to `max_queries` now, so that later

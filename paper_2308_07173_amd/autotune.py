@@ -1,22 +1,19 @@
-"""Autotuner for the search: grid cell size and launch shape.
+"""Autotuner binding: grid cell size and launch shape (``lkc_autotune``).
 
-The hashed grid is an exact accelerator, so every cell size and launch shape
-gives the same results; only the time changes.  The tuner builds the target
-at each candidate cell size, times the fused search + covariance on a seeded
-calibration sample of the real queries (HIP events on the launch stream,
-median of a few repetitions after a warm-up) for each launch shape, and
-returns the fastest combination.  The sample is made of a few contiguous
-runs of the queries, so that it keeps the local density of whole scans: the
-group search's cost per query depends on how many queries share a group's
-neighbourhood, which a thinned random subset would understate.  Results are
-cached in memory per (target fingerprint, sample fingerprint, k, radius).
+The tuning itself runs in the library (``csrc/autotune.hip``): it builds the
+target at each candidate cell size and times the fused search + covariance
+on a sample of the real queries (four contiguous runs, so that the sample
+keeps the local density of whole scans) with HIP events on the launch
+stream, and returns the fastest combination.  This module marshals the
+arguments and caches results in memory per (target fingerprint, query
+fingerprint, k, radius, candidates).
 """
 from __future__ import annotations
 
+import ctypes
 import hashlib
-import itertools
 import math
-from typing import Dict, Iterable, Optional, Sequence, Tuple
+from typing import Dict, Iterable, Sequence, Tuple
 
 import numpy as np
 
@@ -53,47 +50,34 @@ def autotune(target_points: np.ndarray, queries: np.ndarray, k: int, radius: flo
     import torch
     from paper_2308_07173_amd import lkc
 
-    rng = np.random.default_rng(seed)
-    q = np.ascontiguousarray(queries, np.float32)
-    if q.shape[0] > sample:
-        runs = 4
-        step = sample // runs
-        starts = np.sort(rng.choice(q.shape[0] - step + 1, runs, replace=False))
-        q = np.ascontiguousarray(np.concatenate([q[s:s + step] for s in starts]))
-    key = (_fingerprint(target_points), _fingerprint(q), int(k), float(radius),
-           tuple(cells), tuple(tuple(sorted(c.items())) for c in cfgs))
+    cfgs = [dict(c) for c in cfgs]
+    cells = [float(c) for c in cells]
+    key = (_fingerprint(target_points), _fingerprint(queries), int(k), float(radius),
+           tuple(cells), tuple(tuple(sorted(c.items())) for c in cfgs), int(sample), int(seed))
     if key in _cache:
         return _cache[key]
     own_ctx = ctx is None
     ctx = ctx or lkc.Context()
     dev = torch.device("cuda", torch.cuda.current_device())
     tp = torch.from_numpy(np.ascontiguousarray(target_points, np.float32)).to(dev)
-    qd = torch.from_numpy(q).to(dev)
-    ctx.reserve(q.shape[0])
-    stream = torch.cuda.current_stream()
-    table = []
-    out = None
-    for cell in cells:
-        t = lkc.lkc_build_target(ctx, tp, cell)
-        for cfg in cfgs:
-            out = lkc.lkc_knn_cov(ctx, t, qd, k, radius, 1e-3, out=out, cfg=cfg)  # warm-up
-            times = []
-            for _ in range(reps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record(stream)
-                lkc.lkc_knn_cov(ctx, t, qd, k, radius, 1e-3, out=out, cfg=cfg)
-                b.record(stream)
-                b.synchronize()
-                times.append(a.elapsed_time(b))
-            ms = float(np.median(times))
-            table.append((cell, dict(cfg), ms))
-            if verbose:
-                print(f"autotune cell={cell} cfg={cfg} {ms:.3f} ms")
-        t.free()
-    best = min(table, key=lambda r: r[2])
-    res = {"cell": best[0], "cfg": best[1], "ms": best[2], "table": table,
-           "sample": int(q.shape[0])}
-    _cache[key] = res
+    qd = torch.from_numpy(np.ascontiguousarray(queries, np.float32)).to(dev)
+    c_cells = (ctypes.c_float * len(cells))(*cells)
+    c_cfgs = (lkc.LaunchCfg * len(cfgs))(*[lkc.LaunchCfg(**c) for c in cfgs])
+    times = (ctypes.c_float * (len(cells) * len(cfgs)))()
+    res = lkc.AutotuneResult()
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_autotune(
+        ctx.handle, ctypes.c_void_p(tp.data_ptr()), tp.shape[0], ctypes.c_void_p(qd.data_ptr()),
+        qd.shape[0], int(k), float(radius), 1e-3, c_cells, len(cells), c_cfgs, len(cfgs),
+        int(sample), int(seed), int(reps), times, ctypes.byref(res)))
+    table = [(cells[i], cfgs[j], float(times[i * len(cfgs) + j]))
+             for i in range(len(cells)) for j in range(len(cfgs))]
+    if verbose:
+        for cell, cfg, ms in table:
+            print(f"autotune cell={cell} cfg={cfg} {ms:.3f} ms")
+    out = {"cell": float(res.cell_size), "cfg": dict(cfgs[res.cfg_index]), "ms": float(res.ms),
+           "table": table, "sample": int(res.sample)}
+    _cache[key] = out
     if own_ctx:
         ctx.close()
-    return res
+    return out

@@ -16,7 +16,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblkc.so")
-SOURCES = ["api.hip", "build.hip", "search.hip", "gicp.hip", "voxel.hip", "walls.hip"]
+SOURCES = ["api.hip", "build.hip", "search.hip", "gicp.hip", "voxel.hip", "walls.hip",
+           "autotune.hip"]
 ARCH = "gfx950"
 
 

@@ -181,8 +181,21 @@ lkc_status lkc_target_rebuild(lkc_ctx* ctx, lkc_target* t, const float* points, 
         const lkc_status keep = s;
         const std::string msg = ctx->err;
         if (lkc::build_into(ctx, t, nullptr, 0) == LKC_OK) ctx->err = msg;
+        t->status = keep;
         return keep;
     }
+    t->status = LKC_OK;
+    return LKC_OK;
+}
+
+lkc_status lkc_target_status(lkc_ctx* ctx, const lkc_target* t) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
+    LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (t->status != LKC_OK)
+        return set_error(ctx, t->status, "the target's last rebuild failed (status %d)",
+                         (int)t->status);
     return LKC_OK;
 }
 

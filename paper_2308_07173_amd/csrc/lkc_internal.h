@@ -52,6 +52,7 @@ struct lkc_target {
     int32_t key_bits = 0;
     int32_t sort_passes = 0;
     int64_t hash_capacity = 0;
+    lkc_status status = LKC_OK;  // of the last build or rebuild
     // owned allocations and their capacities (bytes)
     void* point_mem = nullptr;   // pts + orig + run boxes
     size_t point_bytes = 0;

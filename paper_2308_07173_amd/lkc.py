@@ -45,6 +45,7 @@ EXPORTED_SYMBOLS = (
     "lkc_ctx_set_timing", "lkc_ctx_set_profile", "lkc_covariances_weighted",
     "lkc_knn_cov_weighted", "lkc_gicp_linearize", "lkc_gicp_align", "lkc_voxel_filter",
     "lkc_submap_extract", "lkc_submap_build", "lkc_zvote", "lkc_euclid_cluster",
+    "lkc_target_status", "lkc_autotune",
 )
 
 # neighbour weight kernels of lkc_covariances_weighted / lkc_knn_cov_weighted
@@ -78,6 +79,12 @@ class SearchStats(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_int64), ("fallback_queries", ctypes.c_int64),
                 ("sort_ms", ctypes.c_float), ("group_ms", ctypes.c_float),
                 ("fallback_ms", ctypes.c_float), ("reduce_ms", ctypes.c_float)]
+
+
+class AutotuneResult(ctypes.Structure):
+    _fields_ = [("cell_size", ctypes.c_float), ("cfg_index", ctypes.c_int32),
+                ("cfg", LaunchCfg), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32),
+                ("sample", ctypes.c_int64)]
 
 
 class ScanDesc(ctypes.Structure):
@@ -148,6 +155,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_submap_build": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64), PP], I32),
             "lkc_zvote": ([P, P, I64, F, I32, P, P], I32),
             "lkc_euclid_cluster": ([P, P, I64, F, P, P, ctypes.POINTER(ctypes.c_int64)], I32),
+            "lkc_target_status": ([P, P], I32),
+            "lkc_autotune": ([P, P, I64, P, I64, I32, F, F, P, I32, P, I32, I64,
+                              ctypes.c_uint64, I32, P, ctypes.POINTER(AutotuneResult)], I32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -292,6 +302,12 @@ class Target:
         self.ctx.check(self.ctx.lib.lkc_target_rebuild(self.ctx.handle, self.handle,
                                                        ctypes.c_void_p(_ptr(points)),
                                                        points.shape[0]))
+
+    def status(self) -> int:
+        """lkc_target_status: LKC_OK, or the error of the last (re)build
+        that left the target empty (synchronises)."""
+        self.ctx._bind()
+        return int(self.ctx.lib.lkc_target_status(self.ctx.handle, self.handle))
 
     def free(self):
         if self.handle:

@@ -66,3 +66,5 @@ def test_struct_layouts():
     assert ctypes.sizeof(lkc.ScanDesc) == 24
     assert ctypes.sizeof(lkc.GicpStats) == 4 + 4 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(lkc.TargetInfo) == 8 * 3 + 4 * 6 + 4 * 3 + 4 + 8
+    assert ctypes.sizeof(lkc.AutotuneResult) == 4 + 4 + 24 + 4 + 4 + 8
+    assert lkc.AutotuneResult.sample.offset == 40

@@ -136,16 +136,20 @@ def test_rebuild_reuses_the_target(lk):
         idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(q), 8, 1.5)
         parity.check_knn(p, q, 8, 1.5, host(idx), host(d2), host(cnt))
     assert passes == [2, 5, 3, 3, 4]
+    assert t.status() == lkc.LKC_OK
     bad = clouds[2].copy()
     bad[777, 2] = np.inf
     with pytest.raises(lkc.LkcError) as e:
         t.rebuild(dev(bad))
     assert e.value.status == lkc.LKC_ERR_NONFINITE
     assert t.info()["n_points"] == 0
+    assert t.status() == lkc.LKC_ERR_NONFINITE     # sticky until the next good rebuild
     idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(clouds[2][:50]), 4)
     assert int(cnt.sum()) == 0
+    assert t.status() == lkc.LKC_ERR_NONFINITE
     t.rebuild(dev(clouds[2]))
     check_layout(t, clouds[2], 1.0)
+    assert t.status() == lkc.LKC_OK
     t.free()
 
 
@@ -331,6 +335,42 @@ def test_whole_target_boundary(lk, n):
             parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"],
                              o["valid"], rows=rows, search=(qs, 12, radius))
     t.free()
+
+
+def test_autotune_picks_a_candidate_and_keeps_the_results(lk):
+    """lkc_autotune times every (cell, launch shape) pair on a sample made of
+    four contiguous runs of the queries and returns the fastest; the chosen
+    pair gives the same bits as the default, and argument errors raise."""
+    import ctypes
+    from paper_2308_07173_amd import autotune
+    lkc, ctx = lk
+    p = workloads.single_scan(seed=5)[::2].copy()
+    q = p[::3].copy()
+    cells = (0.75, 1.5)
+    cfgs = (dict(), dict(group_split=1), dict(algorithm=2))
+    r = autotune.autotune(p, q, 20, 2.0, cells=cells, cfgs=cfgs, sample=8_000, ctx=ctx)
+    assert r["sample"] == 8_000
+    assert len(r["table"]) == len(cells) * len(cfgs)
+    assert all(ms > 0 for _, _, ms in r["table"])
+    assert r["ms"] == min(ms for _, _, ms in r["table"])
+    assert r["cell"] in cells and r["cfg"] in [dict(c) for c in cfgs]
+    small = autotune.autotune(p, q[:500], 20, 2.0, cells=(1.0,), cfgs=cfgs, sample=8_000,
+                              ctx=ctx)
+    assert small["sample"] == 500 and small["cell"] == 1.0
+    base = run_knn(lk, p, q, 20, 2.0, 1.0)
+    tuned = run_knn(lk, p, q, 20, 2.0, r["cell"], cfg=r["cfg"])
+    for x, y in zip(base, tuned):
+        assert np.array_equal(x, y)
+    res = lkc.AutotuneResult()
+    tp, tq = dev(p), dev(q)
+    bad = (ctypes.c_float * 1)(0.0)
+    for args in [(bad, 1, None, 0, 8_000, 3), (None, 0, None, 0, 3, 3),
+                 (None, 0, None, 0, 8_000, 0)]:
+        st = ctx.lib.lkc_autotune(ctx.handle, ctypes.c_void_p(tp.data_ptr()), tp.shape[0],
+                                  ctypes.c_void_p(tq.data_ptr()), tq.shape[0], 20, 2.0, 1e-3,
+                                  args[0], args[1], args[2], args[3], args[4], 0, args[5], None,
+                                  ctypes.byref(res))
+        assert st == lkc.LKC_ERR_INVALID_ARG
 
 
 # ------------------------------------------------------------ covariance --
