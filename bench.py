@@ -46,6 +46,18 @@ def b_alg(k: int) -> int:
     return 20 * k + 100
 
 
+def b_floor(k: int) -> int:
+    """Algorithmic bytes without the neighbour gather (query, idx, d2,
+    count, mean, cov, reg_cov): 8k + 100."""
+    return 8 * k + 100
+
+
+# VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one wave64 instruction occupies a SIMD for four cycles; packed FP32 not
+# counted)
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+
+
 # GICP reduction: source point (12) + its covariance (36) + correspondence
 # (4) + the target point (16, float4 record) + its covariance (36)
 B_GICP_REDUCE = 104
@@ -75,6 +87,51 @@ def committed_traffic(workload: str):
     if d.get("kernel_src_sha") != kernel_src_sha():
         return None
     return d.get("traffic_bytes")
+
+
+def committed_valu(workload: str):
+    """VALU instructions (wavefront level) per search-kernel launch from the
+    committed PMC summary, under the same source check as the traffic."""
+    path = os.path.join(ROOT, "profiles", f"pmc_search_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_src_sha") != kernel_src_sha():
+        return None
+    return d.get("valu_insts_per_dispatch")
+
+
+def copy_bandwidth(torch, dev, mib: int = 1024, reps: int = 10) -> float:
+    """Achievable HBM bandwidth, GB/s: a streaming elementwise kernel that
+    reads and writes `mib` MiB each, timed with events."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.add(src, 1.0, out=dst)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.add(src, 1.0, out=dst)
+    b.record()
+    b.synchronize()
+    gbs = 2 * (mib << 20) * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
+def group_counts(torch, dev, ctx, step, n_queries: int):
+    """Candidates tested and insertion steps of the group search, summed over
+    its groups, from one profiled run of `step` (outside the timed region)."""
+    groups = (n_queries + 63) // 64
+    buf = torch.zeros((groups, 17), dtype=torch.int32, device=dev)
+    ctx.set_profile(buf)
+    step()
+    torch.cuda.synchronize()
+    ctx.set_profile(None)
+    P = buf.cpu().numpy().view(np.uint32).astype(np.int64)
+    return {"chunk_candidates": int(P[:, 4].sum()), "pops": int(P[:, 5].sum()),
+            "lane_inserts": int(P[:, 8].sum())}
 
 
 def cpu_threads() -> int:
@@ -622,6 +679,21 @@ def main():
     extra["search_call"] = {"ms": kern_ms, "achieved_GBs": path_achieved,
                             "frac": path_achieved / HBM_PEAK_GBS}
     traffic = committed_traffic(args.workload) if dom[0] == "k_group" else None
+    hbm_meas = copy_bandwidth(torch, dev)
+    floor_achieved = dom[1] * b_floor(k) / (dom[2] * 1e-3) / 1e9
+    if dom[0] == "k_group":
+        # the group search is bound by VALU issue, not HBM: every query
+        # examines hundreds of candidates for its 20k + 100 bytes
+        gc = group_counts(torch, dev, ctx, step, queries_per_launch)
+        pairs = 64 * gc["chunk_candidates"]    # each broadcast candidate meets 64 lanes
+        cand = {"pairs_tested": pairs, "pairs_per_s": pairs / (group_ms * 1e-3),
+                "insertion_steps": gc["pops"], "lane_insertions": gc["lane_inserts"]}
+        vi = committed_valu(args.workload)
+        if vi is not None:
+            lane_ops = 64 * vi / (group_ms * 1e-3)
+            cand["valu"] = {"insts_per_launch": vi, "lane_ops_per_s": lane_ops,
+                            "peak": VALU_LANE_OPS_PEAK, "frac": lane_ops / VALU_LANE_OPS_PEAK}
+        extra["group_search_work"] = cand
     if args.workload == "weighted":
         config["note"] = "roofline bytes as the plain path: the weights add no HBM traffic"
     res = {
@@ -641,7 +713,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": dom[0], "bytes_per_query": b_alg(k),
-                     "queries_per_launch": int(dom[1]), "kernel_ms": dom[2]},
+                     "queries_per_launch": int(dom[1]), "kernel_ms": dom[2],
+                     "measured_peak": hbm_meas, "frac_of_measured": achieved / hbm_meas,
+                     "floor_bytes_per_query": b_floor(k), "floor_achieved": floor_achieved,
+                     "floor_frac": floor_achieved / HBM_PEAK_GBS},
     }
     res.update(extra)
     if cfg:

@@ -447,7 +447,11 @@ lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
  * candidates (3 words) in the three streaming phases: runs of the queries'
  * own cells touching the query box, the rest of those cells, the other
  * cells, and insertions from the group's own chunk (self queries).
- * n_groups = 0 turns it off.
+ * The counts of what was streamed (chunks onwards, except the member and
+ * fallback lanes) are summed over the wavefronts of a split group; the
+ * clock, probe and cell words are the first wavefront's.  The library
+ * clears the groups' words (hipMemsetAsync) before each search, so keep
+ * profiling off under graph capture.  n_groups = 0 turns it off.
  * The caller owns the buffer. */
 lkc_status lkc_ctx_set_profile(lkc_ctx *ctx, void *buffer, int64_t n_groups);
 

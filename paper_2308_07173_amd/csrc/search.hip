@@ -1119,6 +1119,15 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             ok = whole || covers || (full && f2 > key_d2(kk[K - 1])) || (a.sp.capped && f2 > r2);
         }
     }
+    if (PROF && lane == 0) {
+        // every wave of the group adds what it streamed (the buffer is
+        // cleared before the launch)
+        uint32_t* pw = a.prof + group * PROF_WORDS;
+        const uint32_t add[12] = {gp.chunks, gp.cands, gp.pops, gp.inserts, gp.dead, gp.ins0,
+                                  gp.ins1, gp.ins2, gp.cand0, gp.cand1, gp.cand2, gp.own};
+        const int at[12] = {3, 4, 5, 8, 9, 10, 11, 12, 13, 14, 15, 16};
+        for (int i = 0; i < 12; ++i) atomicAdd(pw + at[i], add[i]);
+    }
     if (sh.sub) return;   // the other waves of a split group are done
     const bool to_fb = (fin && !placed) || (placed && !ok);
     const unsigned long long fm = ballot(to_fb);
@@ -1127,20 +1136,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
         pw[0] = (uint32_t)(__builtin_amdgcn_s_memtime() - t_start);
         pw[1] = gp.probes;
         pw[2] = gp.cells;
-        pw[3] = gp.chunks;
-        pw[4] = gp.cands;
-        pw[5] = gp.pops;
         pw[6] = (uint32_t)__popcll(ballot(placed));
         pw[7] = (uint32_t)__popcll(fm);
-        pw[8] = gp.inserts;
-        pw[9] = gp.dead;
-        pw[10] = gp.ins0;
-        pw[11] = gp.ins1;
-        pw[12] = gp.ins2;
-        pw[13] = gp.cand0;
-        pw[14] = gp.cand1;
-        pw[15] = gp.cand2;
-        pw[16] = gp.own;
     }
     if (fm) {
         const int leader = __builtin_ffsll((long long)fm) - 1;
@@ -1512,6 +1509,11 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     a.counters = nullptr;
     a.prof = (ctx->prof_buf && (j.n_slots + WAVE - 1) / WAVE <= ctx->prof_groups)
                  ? (uint32_t*)ctx->prof_buf : nullptr;
+    if (a.prof)
+        LKC_HIP_TRY(ctx, hipMemsetAsync(a.prof, 0,
+                                        sizeof(uint32_t) * PROF_WORDS *
+                                            (size_t)((j.n_slots + WAVE - 1) / WAVE),
+                                        st));
     ctx->last_fallback_count = sc.words;
     ctx->last_queries = j.n_slots;
     ctx->ev_valid = ctx->timing;
