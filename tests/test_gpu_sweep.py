@@ -1,0 +1,109 @@
+"""Seeded randomised parity sweep through the C ABI.
+
+Each case draws a cloud (uniform random, plane + wall, integer lattice with
+exact ties, a subset of a LiDAR scan, or a cloud of duplicated points), a
+size, self or external queries, k (1..64), a radius (or none), a cell size
+and a launch shape.  The result must equal the default launch shape's bit
+for bit and match the oracle on a sample of rows (kNN and covariance, under
+the rules of ``tests/parity.py``).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2308_07173_amd import workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CFGS = [dict(), dict(group_split=1), dict(group_split=2), dict(group_split=4),
+        dict(group_reach=1), dict(group_reach=3), dict(group_reach=4, waves_per_block=2),
+        dict(persistent=1), dict(persistent=8, waves_per_block=2),
+        dict(persistent=3, waves_per_block=1), dict(algorithm=2), dict(algorithm=2, merge_min=1),
+        dict(algorithm=2, merge_min=65), dict(algorithm=1)]
+
+
+@pytest.fixture(scope="module")
+def lk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_07173_amd import lkc
+    ctx = lkc.Context()
+    yield lkc, ctx
+    ctx.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def draw_case(case):
+    rng = np.random.default_rng(1000 + case)
+    kind = str(rng.choice(["cloud", "plane", "lattice", "scan", "dup"]))
+    n = int(np.exp(rng.uniform(0, np.log(30000))))
+    if kind == "cloud":
+        scale = float(rng.choice([0.5, 3.0, 20.0, 200.0]))
+        p = workloads.random_cloud(n, int(rng.integers(1 << 30)), scale=scale,
+                                   offset=tuple(rng.uniform(-500, 500, 3)))
+    elif kind == "plane":
+        p = workloads.plane_wall(max(n, 1), seed=int(rng.integers(1 << 30)))
+        scale = 10.0
+    elif kind == "lattice":
+        s = int(max(2, round(n ** (1 / 3))))
+        p = workloads.lattice_nd((s, s, max(1, s // 2)), a=float(rng.choice([0.25, 1.0])))
+        scale = float(s)
+    elif kind == "scan":
+        full = workloads.single_scan(seed=int(rng.integers(50)))
+        p = full[rng.choice(full.shape[0], min(n, full.shape[0]), replace=False)]
+        scale = 20.0
+    else:
+        base = workloads.random_cloud(max(1, n // 3), int(rng.integers(1 << 30)), scale=2.0)
+        p = np.repeat(base, 3, axis=0)
+        scale = 2.0
+    p = np.ascontiguousarray(p, np.float32)
+    self_q = bool(rng.integers(2))
+    if self_q:
+        q = p
+    else:
+        nq = int(np.exp(rng.uniform(0, np.log(6000))))
+        if rng.integers(2):
+            q = p[rng.integers(0, p.shape[0], nq)] + rng.normal(0, 0.05 * scale, (nq, 3))
+        else:
+            q = workloads.random_cloud(nq, int(rng.integers(1 << 30)), scale=scale)
+        q = np.ascontiguousarray(q, np.float32)
+    k = int(rng.integers(1, 65)) if rng.uniform() < 0.3 else int(rng.choice([1, 5, 10, 16, 20, 32]))
+    radius = math.inf if rng.uniform() < 0.4 else float(rng.uniform(0.05, 3.0))
+    cell = float(rng.choice([0.25, 0.5, 1.0, 2.0, 3.0]))
+    cfg = CFGS[int(rng.integers(len(CFGS)))]
+    rows = np.sort(rng.choice(q.shape[0], min(q.shape[0], 200), replace=False))
+    return kind, p, self_q, q, k, radius, cell, cfg, rows
+
+
+@pytest.mark.parametrize("block", range(6))
+def test_random_sweep(lk, block):
+    lkc, ctx = lk
+    for case in range(50 * block, 50 * block + 50):
+        kind, p, self_q, q, k, radius, cell, cfg, rows = draw_case(case)
+        desc = (f"case {case}: {kind} n={p.shape[0]} self={self_q} q={q.shape[0]} k={k} "
+                f"r={radius} cell={cell} cfg={cfg}")
+        t = lkc.lkc_build_target(ctx, dev(p), cell)
+        if self_q:
+            a = lkc.lkc_knn_cov_self(ctx, t, k, radius, 1e-3, cfg=cfg)
+            b = lkc.lkc_knn_cov_self(ctx, t, k, radius, 1e-3)
+        else:
+            a = lkc.lkc_knn_cov(ctx, t, dev(q), k, radius, 1e-3, cfg=cfg)
+            b = lkc.lkc_knn_cov(ctx, t, dev(q), k, radius, 1e-3)
+        torch.cuda.synchronize()
+        for key in a:
+            assert torch.equal(a[key], b[key]), f"{desc}: {key} differs from the default shape"
+        o = {kk: v.cpu().numpy() for kk, v in a.items()}
+        t.free()
+        try:
+            parity.check_knn(p, q, k, radius, o["idx"], o["d2"], o["count"], rows=rows)
+            parity.check_cov(p, o["idx"], o["count"], o["mean"], o["cov"], o["reg"], o["valid"],
+                             rows=rows, search=(q, k, radius))
+        except AssertionError as e:
+            raise AssertionError(f"{desc}: {e}") from e
