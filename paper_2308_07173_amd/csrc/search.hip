@@ -656,7 +656,9 @@ struct GroupArgs {
     const TargetView* views;          // device array, one per target
     const float* queries;             // [q][3]; NULL: the queries are the target's own points
     const uint32_t* order;            // sorted slot -> query index (NULL with self queries)
-    const unsigned long long* skeys;  // sorted keys, target index in bits >= tshift (NULL: one target)
+    // query keys, target index in bits >= tshift: sorted for the group
+    // search, by query without it (NULL: one target)
+    const unsigned long long* skeys;
     int tshift;
     int R;                            // block reach in cells
     int64_t n_slots;
@@ -1521,32 +1523,37 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     const int K = choose_k_tile(j.k);
     const bool group = K > 0 && cfg.algorithm != 2;
     const unsigned wpb = (unsigned)cfg.waves_per_block;
+    // Separate queries get keys: the group search sorts them by cell, and a
+    // batch over several targets carries each query's target in the key's
+    // top bits (the wavefront-per-query search reads it unsorted).
+    int tshift = 0, tbits = 0;
+    if (j.queries && (group || j.n_targets > 1)) {
+        int wmax = 1;
+        for (int t = 0; t < j.n_targets; ++t) {
+            const TargetView& V = j.host_views[t];
+            for (int d = 0; d < 3; ++d)
+                wmax = std::max(wmax, bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2)));
+        }
+        // Morton key of the (clamped) query cell, then of its sub-cell (as
+        // many sub-cell bits, from 2 to 4 per axis, as the fewest 8-bit sort
+        // passes holding the key with 2 of them allow)
+        tbits = j.n_targets > 1 ? bitw((uint32_t)(j.n_targets - 1)) : 0;
+        const int sub_lo = std::max(0, std::min(2, (63 - tbits - 3 * wmax) / 3));
+        const int room = std::min(63, 8 * ((tbits + 3 * wmax + 3 * sub_lo + 7) / 8)) - tbits;
+        const int sub_bits = std::max(sub_lo, std::min(4, (room - 3 * wmax) / 3));
+        tshift = 3 * wmax + 3 * sub_bits;
+        if (tshift + tbits > 63)
+            return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",
+                             tshift + tbits);
+        QueryKeyArgs qa{j.queries, j.n_slots, j.views_dev, j.scans_dev, j.hdr_dev, tshift,
+                        sub_bits, sc.ka, sc.va};
+        hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256), 0,
+                           st, qa);
+    }
     if (group) {
         hipLaunchKernelGGL(k_set_words, dim3(1), dim3(64), 0, st, sc.words, 16, 0u);
         if (j.queries) {
-            // sort the queries by their cell in the target grid
-            int wmax = 1;
-            for (int t = 0; t < j.n_targets; ++t) {
-                const TargetView& V = j.host_views[t];
-                for (int d = 0; d < 3; ++d)
-                    wmax = std::max(wmax, bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2)));
-            }
-            // Morton key of the (clamped) query cell, then of its sub-cell
-            // (as many sub-cell bits, from 2 to 4 per axis, as the fewest
-            // 8-bit sort passes holding the key with 2 of them allow)
-            const int tbits = j.n_targets > 1 ? bitw((uint32_t)(j.n_targets - 1)) : 0;
-            const int sub_lo = std::max(0, std::min(2, (63 - tbits - 3 * wmax) / 3));
-            const int room =
-                std::min(63, 8 * ((tbits + 3 * wmax + 3 * sub_lo + 7) / 8)) - tbits;
-            const int sub_bits = std::max(sub_lo, std::min(4, (room - 3 * wmax) / 3));
-            const int tshift = 3 * wmax + 3 * sub_bits;
-            if (tshift + tbits > 63)
-                return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",
-                                 tshift + tbits);
-            QueryKeyArgs qa{j.queries, j.n_slots, j.views_dev, j.scans_dev, j.hdr_dev, tshift,
-                            sub_bits, sc.ka, sc.va};
-            hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256),
-                               0, st, qa);
+            // sort the queries by their key
             bool in_b = false;
             s = sort_pairs(ctx, sc.ka, sc.va, sc.kb, sc.vb, j.n_slots, tshift + tbits, sc.counts,
                            &in_b);
@@ -1597,6 +1604,12 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
                            (uint32_t)j.n_slots);
         hipLaunchKernelGGL(k_fill_iota, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256), 0,
                            st, sc.fb_list, j.n_slots);
+        if (j.queries && j.n_targets > 1) {
+            // slots are the queries themselves: the unsorted keys give each
+            // one's target
+            a.skeys = sc.ka;
+            a.tshift = tshift;
+        }
         if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     }
     if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));

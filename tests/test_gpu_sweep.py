@@ -107,3 +107,62 @@ def test_random_sweep(lk, block):
                              rows=rows, search=(q, k, radius))
         except AssertionError as e:
             raise AssertionError(f"{desc}: {e}") from e
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_batched_sweep(lk, case):
+    """Batched launches over 1-4 targets of different cell sizes (one may be
+    empty or small enough to be streamed whole), uneven scans (some empty),
+    random k, radius and launch shape: every scan's rows equal lkc_knn_cov
+    on that scan alone, bit for bit."""
+    lkc, ctx = lk
+    rng = np.random.default_rng(5000 + case)
+    n_t = int(rng.integers(1, 5))
+    clouds, cells = [], []
+    for i in range(n_t):
+        kind = int(rng.integers(4))
+        n = int(rng.integers(0, 40000)) if kind else int(rng.integers(0, 4097))
+        if kind == 3:
+            n = int(rng.integers(1, 3000))
+            c = np.repeat(workloads.random_cloud(n, int(rng.integers(1 << 30)), scale=3.0), 2, 0)
+        else:
+            c = workloads.random_cloud(n, int(rng.integers(1 << 30)), scale=float(rng.choice([2.0, 15.0])),
+                                       offset=tuple(rng.uniform(-50, 50, 3)))
+        clouds.append(np.ascontiguousarray(c, np.float32))
+        cells.append(float(rng.choice([0.3, 0.5, 1.0, 2.0])))
+    targets = [lkc.lkc_build_target(ctx, dev(c), cell) for c, cell in zip(clouds, cells)]
+    k = int(rng.integers(1, 65)) if rng.uniform() < 0.3 else int(rng.choice([1, 8, 20, 32]))
+    radius = math.inf if rng.uniform() < 0.3 else float(rng.uniform(0.1, 3.0))
+    cfg = CFGS[int(rng.integers(len(CFGS)))]
+    cfg = {kk: v for kk, v in cfg.items() if kk != "group_split"}   # no split in batched launches
+    scans, parts, off = [], [], 0
+    for _ in range(int(rng.integers(1, 20))):
+        ti = int(rng.integers(n_t))
+        nq = int(rng.integers(0, 5000))
+        src = clouds[ti] if clouds[ti].shape[0] else workloads.random_cloud(8, 1, scale=5.0)
+        part = src[rng.integers(0, src.shape[0], nq)] + rng.normal(0, 0.2, (nq, 3))
+        parts.append(np.ascontiguousarray(part, np.float32).reshape(-1, 3))
+        scans.append((off, nq, ti))
+        off += nq
+    allq = np.concatenate(parts)
+    tset = lkc.TargetSet(ctx, targets, max_scans=len(scans))
+    tset.stage(scans)
+    got = lkc.lkc_knn_cov_batched(ctx, tset, dev(allq), k, radius, 1e-3, cfg=cfg)
+    torch.cuda.synchronize()
+    desc = f"case {case}: targets={[c.shape[0] for c in clouds]} cells={cells} k={k} r={radius} cfg={cfg}"
+    for (o, n, ti), part in zip(scans, parts):
+        if n == 0:
+            continue
+        alone = lkc.lkc_knn_cov(ctx, targets[ti], dev(part), k, radius, 1e-3)
+        torch.cuda.synchronize()
+        for key in alone:
+            assert torch.equal(alone[key], got[key][o:o + n]), f"{desc}: scan at {o}: {key}"
+    o, n, ti = max(scans, key=lambda s: s[1])
+    if n:
+        r = np.sort(rng.choice(n, min(n, 100), replace=False))
+        g = {kk: v[o:o + n].cpu().numpy() for kk, v in got.items()}
+        parity.check_knn(clouds[ti], parts[scans.index((o, n, ti))], k, radius, g["idx"], g["d2"],
+                         g["count"], rows=r)
+    tset.free()
+    for t in targets:
+        t.free()
