@@ -166,3 +166,67 @@ def test_random_batched_sweep(lk, case):
     tset.free()
     for t in targets:
         t.free()
+
+
+def _cloud(rng, n):
+    kind = int(rng.integers(4))
+    if kind == 0:
+        p = workloads.random_cloud(n, int(rng.integers(1 << 30)),
+                                   scale=float(rng.choice([1.0, 8.0, 40.0])),
+                                   offset=tuple(rng.uniform(-300, 300, 3)))
+    elif kind == 1:
+        p = workloads.plane_wall(max(n, 1), seed=int(rng.integers(1 << 30)))
+    elif kind == 2:
+        base = workloads.random_cloud(max(1, n // 4), int(rng.integers(1 << 30)), scale=3.0)
+        p = np.repeat(base, 4, axis=0)
+    else:
+        s = int(max(2, round(max(n, 8) ** (1 / 3))))
+        p = workloads.lattice_nd((s, s, s), a=float(rng.choice([0.2, 0.5])))
+    return np.ascontiguousarray(p, np.float32)
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_rebuild_and_grid_ops_sweep(lk, case):
+    """One target rebuilt through random clouds (sizes and extents that need
+    more and fewer sort passes), each checked by kNN against the oracle; then
+    the voxel filter, the z-vote and the (masked) clustering of the last
+    cloud against the oracle, exactly."""
+    from oracle import oracle
+    lkc, ctx = lk
+    rng = np.random.default_rng(9000 + case)
+    cell = float(rng.choice([0.3, 0.75, 1.5]))
+    t = lkc.lkc_build_target(ctx, dev(_cloud(rng, 100)), cell)
+    for step in range(4):
+        p = _cloud(rng, int(np.exp(rng.uniform(0, np.log(50000)))))
+        t.rebuild(dev(p))
+        q = np.ascontiguousarray(p[rng.integers(0, p.shape[0], 300)]
+                                 + rng.normal(0, 0.3, (300, 3)), np.float32)
+        k = int(rng.choice([1, 7, 20, 40]))
+        radius = math.inf if rng.uniform() < 0.5 else float(rng.uniform(0.2, 2.5))
+        idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(q), k, radius)
+        desc = f"case {case} step {step}: n={p.shape[0]} cell={cell} k={k} r={radius}"
+        try:
+            parity.check_knn(p, q, k, radius, idx.cpu().numpy(), d2.cpu().numpy(),
+                             cnt.cpu().numpy())
+        except AssertionError as e:
+            raise AssertionError(f"{desc}: {e}") from e
+        assert t.status() == lkc.LKC_OK
+    t.free()
+    leaf = float(rng.choice([0.1, 0.2, 0.5, 1.0]))
+    origin = tuple(float(x) for x in rng.uniform(-1, 1, 3))
+    out = lkc.lkc_voxel_filter(ctx, dev(p), leaf, origin=origin)
+    ref = oracle.voxel_filter(p, leaf, origin=origin)
+    np.testing.assert_array_equal(out["voxel"].cpu().numpy(), ref["voxel"])
+    np.testing.assert_array_equal(out["count"].cpu().numpy(), ref["count"])
+    np.testing.assert_array_equal(out["centroid"].cpu().numpy(), ref["centroid"].astype(np.float32))
+    zc, tau = float(rng.choice([0.2, 0.5])), int(rng.integers(1, 8))
+    keep, votes = lkc.lkc_zvote(ctx, dev(p), zc, tau)
+    ok, ov = oracle.zvote(p, zc, tau)
+    np.testing.assert_array_equal(votes.cpu().numpy(), ov)
+    np.testing.assert_array_equal(keep.cpu().numpy(), ok)
+    sub = p[: min(p.shape[0], 8000)]
+    eps = float(rng.choice([0.1, 0.3, 0.6]))
+    labels, nc = lkc.lkc_euclid_cluster(ctx, dev(sub), eps)
+    ol, onc = oracle.euclid_cluster(sub, eps)
+    assert nc == onc
+    np.testing.assert_array_equal(labels.cpu().numpy(), ol)
