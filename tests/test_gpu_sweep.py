@@ -230,3 +230,51 @@ def test_random_rebuild_and_grid_ops_sweep(lk, case):
     ol, onc = oracle.euclid_cluster(sub, eps)
     assert nc == onc
     np.testing.assert_array_equal(labels.cpu().numpy(), ol)
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_random_given_lists_sweep(lk, case):
+    """Covariances of neighbour lists made on the host by the oracle (random
+    k and radius, with the queries as origin or NULL), plain and
+    kernel-weighted (widths that keep the weight exponents small), against
+    the oracle."""
+    from oracle import oracle
+    lkc, ctx = lk
+    rng = np.random.default_rng(12000 + case)
+    n = int(rng.integers(2000, 20000))
+    p = workloads.random_cloud(n, int(rng.integers(1 << 30)), scale=float(rng.choice([2.0, 3.0])),
+                               offset=tuple(rng.uniform(-100, 100, 3)))
+    if rng.integers(2):
+        p = np.ascontiguousarray(np.repeat(p[: n // 2], 2, axis=0), np.float32)
+    q = np.ascontiguousarray(p[rng.integers(0, p.shape[0], 500)] + rng.normal(0, 0.05, (500, 3)),
+                             np.float32)
+    k = int(rng.integers(1, 65))
+    radius = math.inf if rng.uniform() < 0.4 else float(rng.uniform(0.1, 0.6))
+    o_idx, _, o_cnt = oracle.knn(p, q, k, radius)
+    t = lkc.lkc_build_target(ctx, dev(p), float(rng.choice([0.25, 0.5, 1.0])))
+    use_q = bool(rng.integers(2))
+    di = torch.from_numpy(np.ascontiguousarray(o_idx)).cuda()
+    dc = torch.from_numpy(np.ascontiguousarray(o_cnt)).cuda()
+    out = lkc.lkc_covariances(ctx, t, di, dc, queries=dev(q) if use_q else None)
+    o = {kk: v.cpu().numpy() for kk, v in out.items()}
+    desc = f"case {case}: n={p.shape[0]} k={k} r={radius} queries={use_q}"
+    try:
+        parity.check_cov(p, o_idx, o_cnt, o["mean"], o["cov"], o["reg"], o["valid"],
+                         floor=parity.rounding_floor(p, o_idx, o_cnt, q if use_q else None))
+    except AssertionError as e:
+        raise AssertionError(f"{desc}: {e}") from e
+    kind, sigma = [("laplacian", 0.3), ("gaussian", 0.3), ("rbf", 4.0), ("none", 1.0)][case % 4]
+    w = lkc.lkc_covariances_weighted(ctx, t, di, dc, kind, sigma,
+                                     queries=dev(q) if use_q else None)
+    if kind == "none":   # the plain estimate, bit for bit
+        for kk in w:
+            assert torch.equal(w[kk], out[kk]), f"{desc}: weight 'none' differs in {kk}"
+        t.free()
+        return
+    o = {kk: v.cpu().numpy() for kk, v in w.items()}
+    try:
+        parity.check_cov_weighted(p, o_idx, o_cnt, o["mean"], o["cov"], o["reg"], o["valid"],
+                                  kind, sigma, queries=q if use_q else None)
+    except AssertionError as e:
+        raise AssertionError(f"{desc} {kind} {sigma}: {e}") from e
+    t.free()
