@@ -278,3 +278,35 @@ def test_random_given_lists_sweep(lk, case):
     except AssertionError as e:
         raise AssertionError(f"{desc} {kind} {sigma}: {e}") from e
     t.free()
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_gicp_linearize_sweep(lk, case):
+    """One GICP linearisation at a random rigid transform, target and source
+    sizes, scale, cell and correspondence distance: correspondences equal
+    the FP64 brute force except at float32 near-ties, and the FP64 system
+    matches the oracle's (the rules of ``tests/test_gpu_gicp.py``)."""
+    from oracle import oracle
+    from tests import test_gpu_gicp as G
+    lkc, ctx = lk
+    rng = np.random.default_rng(20000 + case)
+    n_t = int(np.exp(rng.uniform(np.log(10), np.log(40000))))
+    n_s = int(np.exp(rng.uniform(0, np.log(20000))))
+    scale = float(rng.choice([2.0, 10.0, 50.0]))
+    off = tuple(rng.uniform(-200, 200, 3))
+    tgt = workloads.random_cloud(n_t, int(rng.integers(1 << 30)), scale=scale, offset=off)
+    src = workloads.random_cloud(n_s, int(rng.integers(1 << 30)), scale=scale)
+    T = G.rigid(*rng.uniform(-0.5, 0.5, 3), list(off))
+    md = math.inf if rng.uniform() < 0.3 else float(rng.uniform(0.2, 3.0))
+    cell = float(rng.choice([0.5, 1.0, 2.0]))
+    sc = G.random_spd(n_s, int(rng.integers(1 << 30)))
+    tc = G.random_spd(n_t, int(rng.integers(1 << 30)))
+    t = lkc.lkc_build_target(ctx, G.dev(tgt), cell)
+    system, corr = lkc.lkc_gicp_linearize(ctx, t, G.dev(tc), G.dev(src), G.dev(sc), T, md)
+    torch.cuda.synchronize()
+    g_corr = corr.cpu().numpy()
+    o_corr, ndiff = G.check_corr(src, tgt, T, md, g_corr)
+    assert ndiff <= max(2, n_s // 5000)
+    c = np.where(g_corr != o_corr, g_corr, o_corr)
+    G.check_system(lkc.split_system(system), oracle.gicp_linearize(src, sc, tgt, tc, T, c))
+    t.free()
