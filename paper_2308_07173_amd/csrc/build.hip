@@ -331,10 +331,12 @@ __global__ void __launch_bounds__(BT) k_scan_add(uint32_t* __restrict__ data, in
 // column into exclusive offsets in item order, starting at the digit's
 // global offset, and every item lands at (its column entry) + (its rank).
 //
-// With `raw` set, `offsets` holds the unscanned per-tile histograms, tile
+// With `raw` = 1, `offsets` holds the unscanned per-tile histograms, tile
 // by tile, and each workgroup derives its own offsets (digit totals scanned
 // across the workgroup, plus the counts of the earlier tiles); used when
-// there are few tiles, so the separate scan launch is saved.
+// there are few tiles, so the separate scan launch is saved.  With `raw` =
+// 2 (a single tile) the workgroup takes the digit totals from its own
+// ranking counts, so no histogram is launched either.
 __global__ void __launch_bounds__(BT) k_radix_scatter(
     const unsigned long long* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     unsigned long long* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n,
@@ -357,7 +359,7 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
     for (int j = 0; j < COLS; ++j) cnt[j][tid] = 0;
     // thread tid owns digit tid: its first output position in this tile
     uint32_t off;
-    if (raw) {
+    if (raw == 1) {
         uint32_t tot = 0, pre = 0;
         constexpr int U = 16;   // rows in flight
         for (int b0 = 0; b0 < nblocks; b0 += U) {
@@ -378,6 +380,9 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
         uint32_t wo = 0;
         for (int j = 0; j < w; ++j) wo += s_tot[j];
         off = wo + (uint32_t)incl - tot + pre;
+    } else if (raw == 2) {
+        off = 0;           // one tile: its own counts, after the ranking
+        __syncthreads();   // the count table is cleared
     } else {
         off = offsets[(int64_t)tid * nblocks + blockIdx.x];
         __syncthreads();   // the count table is cleared
@@ -399,6 +404,18 @@ __global__ void __launch_bounds__(BT) k_radix_scatter(
         if (valid && rank[it] == 0) cnt[it * NW + w][d] = (uint32_t)__popcll(peers);
     }
     __syncthreads();
+    if (raw == 2) {
+        // a single tile: digit tid starts after the smaller digits' counts
+        uint32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < COLS; ++j) tot += cnt[j][tid];
+        const int incl = wave_incl_scan((int)tot);
+        if (l == WAVE - 1) s_tot[w] = (uint32_t)incl;
+        __syncthreads();
+        uint32_t wo = 0;
+        for (int j = 0; j < w; ++j) wo += s_tot[j];
+        off = wo + (uint32_t)incl - tot;
+    }
     {
         uint32_t r = off;
 #pragma unroll
@@ -612,10 +629,14 @@ lkc_status sort_pairs(lkc_ctx* ctx, unsigned long long* ka, uint32_t* va, unsign
     const int64_t m = (int64_t)RADIX * nb;
     uint32_t* tmp = counts + m;
     bool b = false;
-    const int raw = nb <= RAW_OFFSET_TILES ? 1 : 0;
+    // raw 2: a single tile ranks and counts its own digits (no histogram
+    // launch); raw 1: few tiles derive their offsets from the tile-major
+    // histograms (no scan launch)
+    const int raw = nb == 1 ? 2 : (nb <= RAW_OFFSET_TILES ? 1 : 0);
     for (int shift = 0; shift < bits && n > 1; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(BT), 0, st, ka, n, shift,
-                           counts, (int)nb, raw);
+        if (raw != 2)
+            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(BT), 0, st, ka, n, shift,
+                               counts, (int)nb, raw);
         if (!raw) scan_exclusive(st, counts, m, tmp);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(BT), 0, st, ka, va, kb, vb,
                            n, shift, counts, (int)nb, raw);
