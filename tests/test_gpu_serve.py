@@ -49,9 +49,11 @@ def alone(ex, req):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("use_graphs", [False, True])
-def test_each_result_is_the_same_alone_and_in_the_mix(maps, use_graphs):
-    ex = serve.GpuExecutor(maps, cell=1.0, k=20, radius=2.0, hbm_budget_bytes=64 << 20,
+@pytest.mark.parametrize("use_graphs,k", [(False, 20), (True, 20), (False, 40), (True, 40)])
+def test_each_result_is_the_same_alone_and_in_the_mix(maps, use_graphs, k):
+    # k = 40: every query takes the wavefront-per-query search, which must
+    # find each query's own map in the mixed batch
+    ex = serve.GpuExecutor(maps, cell=1.0, k=k, radius=2.0, hbm_budget_bytes=64 << 20,
                            use_graphs=use_graphs, keep_results=True)
     try:
         reqs = make_requests(maps)
