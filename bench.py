@@ -1,18 +1,25 @@
 """Benchmark: kNN (k = 20) + covariance query points/s on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload scan|map|batched|tiny]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|scan|map|tiny|served|...]
 
-Default workload ``scan``: one spinning-LiDAR scan (128 x 1024 rays, 10 %
-dropout, ~118k points, sensor frame) queried against itself, k = 20,
-r = 2 m, 1 m cells.  One step = rebuild the hashed grid from the scan +
-fused search + covariance of every point, i.e. the whole per-scan path; the
-step ends when the results are on the device (per-scan latency).
+Default workload ``batched``, the largest single-GPU configuration: 48
+uneven LiDAR scans (16 frames x 3 sensors, 20k-131k points each, 3,757,703
+queries) against the resident 2,000,000-point voxelised track map, k = 20,
+r = 2 m; cell size and launch shape from the autotuner.  One step is one
+``lkc_knn_cov_batched`` call over all 48 scans: the query key and radix
+sort launches, the group search (``k_group``) and the wavefront-per-query
+search of the queries it hands over (``k_fallback``).  The plain
+one-call-per-scan loop is timed beside it, the same call replayed from a
+captured HIP graph is timed as an extra, and a short served stream (3
+sensors at 20 Hz, real time) reports p50/p99 per-scan latency for the
+served and the plain loop (``--served-seconds``, 0 = off).
 
-Other workloads: ``map`` (65,536-point scan against the resident
-2,000,000-point voxelised map; a step is one fused launch), ``batched``
-(48 uneven scans against the map in one persistent launch; a step is one
-launch, and the plain one-launch-per-scan loop is timed beside it), ``tiny``
-(2,048-point plane + wall, k = 10, no cap).
+Other workloads: ``scan`` (one spinning-LiDAR scan, ~118k points, sensor
+frame, self-query, k = 20, r = 2 m, 1 m cells; a step is rebuild + fused
+search), ``map`` (65,536-point scan against the resident map; a step is one
+fused call), ``tiny`` (2,048-point plane + wall, k = 10, no cap),
+``served`` (the served stream alone), ``weighted``, ``gicp``, ``voxel``,
+``submap``, ``walls``.
 
 Prints ONE JSON line.  ``value`` = queries/s over the timed steps (inputs
 resident in HBM).  ``roofline`` is for the search kernel: algorithmic bytes
@@ -161,45 +168,56 @@ def pct(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if len(xs) else float("nan")
 
 
-def served(args, lkc, workloads, torch):
+def served_stream(args, lkc, workloads, torch, duration, time_scale, saturated=True):
     """Served stream: 3 sensors x 20 Hz Poisson arrivals, scans of 10k-131k
     points against 4 resident maps (0.5, 1, 2, 4 M points), continuous
-    batching in two slots, beside the plain one-call-per-scan loop."""
+    batching in two slots, beside the plain one-call-per-scan loop under the
+    same arrivals.  ``saturated`` also replays the same requests released all
+    at once (the loops' capacity)."""
     from paper_2308_07173_amd import serve
     k, radius, cell = 20, 2.0, 1.0
     maps = workloads.served_maps()
     pool = workloads.served_scan_pool()
-    sched = workloads.served_schedule(duration=args.duration, seed=5)
+    sched = workloads.served_schedule(duration=duration, seed=5)
     reqs = [serve.ServeRequest(i, r.t_arrival, r.map_id,
                                np.ascontiguousarray(pool[i % len(pool)][:r.n_points]), r.sensor)
             for i, r in enumerate(sched)]
-    free, _ = torch.cuda.mem_get_info()
-    budget = int(0.8 * free) if args.hbm_budget_gb <= 0 else int(args.hbm_budget_gb * 2**30)
+    budget = None if args.hbm_budget_gb <= 0 else int(args.hbm_budget_gb * 2**30)
     ex = serve.GpuExecutor(maps, cell=cell, k=k, radius=radius, hbm_budget_bytes=budget,
                            use_graphs=True)
     warm = reqs[: min(12, len(reqs))]
     serve.serve_loop(warm, ex, time_scale=math.inf)
-    res = serve.summarize(serve.serve_loop(reqs, ex, time_scale=args.time_scale))
-    plain = serve.summarize(serve.plain_loop(reqs, ex, time_scale=args.time_scale))
-    # the same requests released all at once: the loops' capacity
-    sat = serve.summarize(serve.serve_loop(reqs, ex, time_scale=math.inf))
-    sat_plain = serve.summarize(serve.plain_loop(reqs, ex, time_scale=math.inf))
+    res = serve.summarize(serve.serve_loop(reqs, ex, time_scale=time_scale))
+    plain = serve.summarize(serve.plain_loop(reqs, ex, time_scale=time_scale))
+    out = {"requests": res["requests"], "duration_s": duration, "time_scale": time_scale,
+           "k": k, "radius_m": radius, "cell_m": cell, "hbm_budget_bytes": ex.budget,
+           "resident_map_bytes": ex.resident_bytes, "served": res, "plain_per_scan": plain}
+    if saturated:
+        sat = serve.summarize(serve.serve_loop(reqs, ex, time_scale=math.inf))
+        sat_plain = serve.summarize(serve.plain_loop(reqs, ex, time_scale=math.inf))
+        out["saturated"] = {"served_queries_per_s": sat["queries_per_s"],
+                            "plain_queries_per_s": sat_plain["queries_per_s"],
+                            "served_mean_batch_requests": sat["mean_batch_requests"],
+                            "served_wall_s": sat["wall_s"], "plain_wall_s": sat_plain["wall_s"]}
     ex.close()
+    return out
+
+
+def served(args, lkc, workloads, torch):
+    r = served_stream(args, lkc, workloads, torch, args.duration, args.time_scale)
+    res = r["served"]
     out = {
         "metric": METRIC, "value": res["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
-        "steps": res["batches"], "warmup": len(warm), "ms_per_step": res["wall_s"] / max(1, res["batches"]) * 1e3,
+        "steps": res["batches"], "warmup": 12,
+        "ms_per_step": res["wall_s"] / max(1, res["batches"]) * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded ray-cast race-track LiDAR)",
         "config": {"workload": "served stream: 3 LiDARs x 20 Hz Poisson, 10k-131k-point scans, "
                                "4 resident maps (0.5/1/2/4 M points)",
-                   "requests": res["requests"], "duration_s": args.duration,
-                   "time_scale": args.time_scale, "k": k, "radius_m": radius, "cell_m": cell,
-                   "hbm_budget_bytes": budget, "slot_capacity_queries": ex.capacity},
-        "served": res, "plain_per_scan": plain,
-        "saturated": {"served_queries_per_s": sat["queries_per_s"],
-                      "plain_queries_per_s": sat_plain["queries_per_s"],
-                      "served_mean_batch_requests": sat["mean_batch_requests"],
-                      "served_wall_s": sat["wall_s"], "plain_wall_s": sat_plain["wall_s"]},
+                   **{key: r[key] for key in ("requests", "duration_s", "time_scale", "k",
+                                              "radius_m", "cell_m", "hbm_budget_bytes",
+                                              "resident_map_bytes")}},
+        "served": res, "plain_per_scan": r["plain_per_scan"], "saturated": r["saturated"],
         "latency_ms": {"p50": res["p50_ms"], "p99": res["p99_ms"]},
     }
     print(json.dumps(out))
@@ -429,13 +447,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="scan",
+    ap.add_argument("--workload", default="batched",
                     choices=["scan", "map", "weighted", "gicp", "batched", "tiny", "served",
                              "voxel", "submap", "walls"])
     ap.add_argument("--sigma", type=float, default=0.2,
                     help="weighted: Laplacian kernel width in metres")
-    ap.add_argument("--time-scale", type=float, default=10.0,
-                    help="served: schedule compression (inf = open loop)")
+    ap.add_argument("--time-scale", type=float, default=1.0,
+                    help="served: schedule compression (1 = real time, inf = open loop)")
+    ap.add_argument("--served-seconds", type=float, default=20.0,
+                    help="batched: seconds of served stream (real time) whose p50/p99 "
+                         "latency are reported beside the batched line (0 = off)")
     ap.add_argument("--duration", type=float, default=60.0, help="served: stream seconds")
     ap.add_argument("--hbm-budget-gb", type=float, default=0.0,
                     help="served: device memory budget (0 = 80 %% of free)")
@@ -610,7 +631,9 @@ def main():
         config = {"workload": "48 uneven scans (16 frames x 3 LiDARs) vs 2,000,000-point map",
                   "n_points": int(Q), "scans": len(scans), "map_points": 2_000_000, "k": k,
                   "radius_m": radius, "cell_m": cell,
-                  "step": "one persistent batched kNN+covariance launch"}
+                  "step": "one lkc_knn_cov_batched call over all scans: query keys + radix "
+                          "sort, group search (k_group), wavefront search of the queries "
+                          "it hands over (k_fallback)"}
         if not args.no_autotune and not args.cfg:
             from paper_2308_07173_amd import autotune
             tune = autotune.autotune(m, allq, k, radius, sample=allq.shape[0], ctx=ctx)
@@ -660,8 +683,23 @@ def main():
         plain_ms = pe[0].elapsed_time(pe[1])
         extra["plain_per_scan_loop_ms"] = plain_ms
         extra["plain_per_scan_loop_qps"] = Q / (plain_ms * 1e-3)
-        rows = np.sort(np.random.default_rng(0).choice(Q, Q // 256, replace=False))
-        baseline_args = (m, allq, k, radius, rows, "seeded 1/256 subsample")
+        # the same call replayed from a captured HIP graph (bitwise equal to
+        # the eager call)
+        ref = {key: v.clone() for key, v in out.items()}
+        ctx.set_timing(False)     # no phase events inside the capture
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            lkc.lkc_knn_cov_batched(ctx, tset, aq, k, radius, 1e-3, out=out, cfg=cfg)
+        ctx.set_timing(True)
+        g.replay()
+        torch.cuda.synchronize()
+        same = all(torch.equal(ref[key], out[key]) for key in ref)
+        gms, _ = timed_calls(torch, g.replay, K, 2)
+        extra["graph_replay"] = {"ms": gms, "queries_per_s": Q / (gms * 1e-3),
+                                 "bitwise_equal_to_eager": bool(same)}
+        del g
+        rows = np.sort(np.random.default_rng(0).choice(Q, Q // 64, replace=False))
+        baseline_args = (m, allq, k, radius, rows, "seeded 1/64 subsample")
 
     value = queries_per_launch * K / total
     ph = np.array(phases, dtype=np.float64)
@@ -723,6 +761,22 @@ def main():
         res["launch_cfg"] = cfg
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = oracle_baseline(*baseline_args)
+    if args.workload == "batched" and args.served_seconds > 0:
+        # the served stream in real time: per-scan latency of the served and
+        # the plain one-call-per-scan loop under the same arrivals
+        sv = served_stream(args, lkc, workloads, torch, args.served_seconds, 1.0,
+                           saturated=False)
+        res["served_stream"] = {
+            "workload": "3 LiDARs x 20 Hz Poisson, 10k-131k-point scans, 4 resident maps "
+                        "(0.5/1/2/4 M points), real time",
+            "seconds": args.served_seconds, "requests": sv["requests"],
+            "served": {key: sv["served"][key] for key in ("p50_ms", "p99_ms", "max_ms",
+                                                          "queries_per_s",
+                                                          "mean_batch_requests")},
+            "plain_per_scan": {key: sv["plain_per_scan"][key]
+                               for key in ("p50_ms", "p99_ms", "max_ms", "queries_per_s")}}
+        res["latency_ms"] = {"p50": sv["served"]["p50_ms"], "p99": sv["served"]["p99_ms"],
+                             "source": "served stream (real time), arrival to results"}
     if args.calib_copy_mib > 0:
         # a plain streaming kernel of known size: reads nb bytes, writes nb
         # bytes (an elementwise add; a device copy may go to the DMA engine)

@@ -155,7 +155,7 @@ class GpuExecutor(Executor):
     BUCKETS = (1 << 15, 1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21, 1 << 22)
 
     def __init__(self, targets_points: Sequence[np.ndarray], cell: float = 1.0, k: int = 20,
-                 radius: float = 2.0, eps: float = 1e-3, hbm_budget_bytes: int = 1 << 30,
+                 radius: float = 2.0, eps: float = 1e-3, hbm_budget_bytes: Optional[int] = None,
                  n_slots: int = 2, use_graphs: bool = True, max_scans: int = 256,
                  keep_results: bool = False, cfg=None):
         import torch
@@ -166,11 +166,24 @@ class GpuExecutor(Executor):
         self.keep_results = keep_results
         self.results: Dict[int, Dict[str, np.ndarray]] = {}
         self.dev = torch.device("cuda", torch.cuda.current_device())
+        if hbm_budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info()
+            hbm_budget_bytes = int(0.8 * free)
+        self.budget = int(hbm_budget_bytes)
+        # resident maps: built once on a set-up context, counted against the
+        # budget before any request
+        self.setup_ctx = lkc.Context()
+        self.map_dev = [torch.from_numpy(np.ascontiguousarray(p)).to(self.dev)
+                        for p in targets_points]
+        self.targets = [lkc.lkc_build_target(self.setup_ctx, m, cell) for m in self.map_dev]
+        torch.cuda.synchronize()
+        self.resident_bytes = int(sum(t.info()["device_bytes"] for t in self.targets) +
+                                  sum(m.numel() * 4 for m in self.map_dev))
         per_q = bytes_per_query(k)
-        cap = hbm_budget_bytes // (n_slots * per_q)
+        cap = (self.budget - self.resident_bytes) // (n_slots * per_q)
         cap = min(cap, self.BUCKETS[-1])
         if cap < 1:
-            raise ValueError("HBM budget too small for one query")
+            raise ValueError("HBM budget too small for one query beside the resident maps")
         self.capacity = int(cap)
         self.use_graphs = use_graphs
         # resident maps: built once on a set-up context

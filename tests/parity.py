@@ -45,16 +45,23 @@ def rounding_terms(target, idx, cnt, origin=None):
     deviation from the mean.  The origin is the query (``origin`` rows),
     else the first neighbour."""
     t = np.asarray(target, np.float64)
+    idx = np.asarray(idx)
+    cnt = np.asarray(cnt).astype(np.int64)
     g, e = np.zeros(len(cnt)), np.zeros(len(cnt))
-    for r in range(len(cnt)):
-        n = int(cnt[r])
-        if n == 0:
-            continue
-        T = t[np.asarray(idx[r, :n])]
-        o = T[0] if origin is None else np.asarray(origin[r], np.float64)
-        A = float(np.sqrt(((T - o) ** 2).sum(axis=1)).max())
-        e[r] = float(np.sqrt(((T - T.mean(axis=0)) ** 2).sum(axis=1)).max())
-        g[r] = (n + 2) * F32_U * A
+    if len(cnt) == 0:
+        return g, e
+    kk = idx.shape[1]
+    m = np.arange(kk)[None, :] < cnt[:, None]
+    safe = np.where(m, idx, 0)
+    T = t[safe]                                            # [rows, k, 3]
+    o = T[:, 0, :] if origin is None else np.asarray(origin, np.float64).reshape(-1, 3)
+    A = np.where(m, np.sqrt(((T - o[:, None, :]) ** 2).sum(axis=2)), 0.0).max(axis=1)
+    n = np.maximum(cnt, 1)[:, None]
+    mu = np.where(m[:, :, None], T, 0.0).sum(axis=1) / n
+    E = np.where(m, np.sqrt(((T - mu[:, None, :]) ** 2).sum(axis=2)), 0.0).max(axis=1)
+    has = cnt > 0
+    g[has] = (cnt[has] + 2) * F32_U * A[has]
+    e[has] = E[has]
     return g, e
 
 
@@ -65,13 +72,19 @@ def rounding_floor(target, idx, cnt, origin=None):
     return {"mean": g, "cov": g * (2.0 * e + g)}
 
 
-def check_knn(target, queries, k, radius, g_idx, g_d2, g_cnt, rows=None, exact=False):
-    """Compare GPU kNN rows with the oracle; returns the number of near-tie rows."""
+def check_knn(target, queries, k, radius, g_idx, g_d2, g_cnt, rows=None, exact=False,
+              oracle_out=None):
+    """Compare GPU kNN rows with the oracle; returns the number of near-tie rows.
+    ``oracle_out`` = (idx, d2, count) of ``oracle.knn`` on those rows, if
+    already computed."""
     target = np.asarray(target, np.float32)
     queries = np.asarray(queries, np.float32)
     rows = np.arange(queries.shape[0]) if rows is None else np.asarray(rows)
     qs = queries[rows]
-    o_idx, o_d2, o_cnt = oracle.knn(target, qs, k, radius)
+    if oracle_out is None:
+        o_idx, o_d2, o_cnt = oracle.knn(target, qs, k, radius)
+    else:
+        o_idx, o_d2, o_cnt = (np.array(a) for a in oracle_out)
     g_idx, g_d2, g_cnt = g_idx[rows], g_d2[rows], g_cnt[rows]
     if exact:
         assert np.array_equal(g_cnt, o_cnt), "count differs"
@@ -83,25 +96,37 @@ def check_knn(target, queries, k, radius, g_idx, g_d2, g_cnt, rows=None, exact=F
     t64 = target.astype(np.float64)
     q64 = qs.astype(np.float64)
     r2 = np.inf if np.isinf(radius) else float(np.float32(radius)) ** 2
-    near = 0
-    for r in range(qs.shape[0]):
+    g_cnt = np.asarray(g_cnt).astype(np.int64)
+    o_cnt = np.asarray(o_cnt).astype(np.int64)
+    kk = g_idx.shape[1]
+    m = np.arange(kk)[None, :] < g_cnt[:, None]
+    bad = np.flatnonzero((g_cnt < 0) | (g_cnt > k))
+    assert bad.size == 0, f"row {rows[bad[0]]}: count out of range"
+    bad = np.flatnonzero(((g_idx != -1) & ~m).any(axis=1) | (~np.isinf(g_d2) & ~m).any(axis=1))
+    assert bad.size == 0, f"row {rows[bad[0]]}: bad padding"
+    bad = np.flatnonzero((m & ((g_idx < 0) | (g_idx >= target.shape[0]))).any(axis=1))
+    assert bad.size == 0, f"row {rows[bad[0]]}: index out of range"
+    gs = np.sort(np.where(m, g_idx, -1), axis=1)
+    bad = np.flatnonzero(((gs[:, 1:] == gs[:, :-1]) & (gs[:, 1:] >= 0)).any(axis=1))
+    assert bad.size == 0, f"row {rows[bad[0]]}: duplicate index"
+    safe = np.where(m, g_idx, 0)
+    rec = ((t64[safe] - q64[:, None, :]) ** 2).sum(axis=2)
+    gd = np.where(m, g_d2.astype(np.float64), 0.0)
+    rec = np.where(m, rec, 0.0)
+    bad = np.flatnonzero((np.abs(gd - rec) > KNN_D2_REL * rec + KNN_D2_ABS).any(axis=1))
+    assert bad.size == 0, f"row {rows[bad[0]]}: d2 off the FP64 distance"
+    pair = m[:, 1:]
+    asc = (gd[:, :-1] < gd[:, 1:]) | ((gd[:, :-1] == gd[:, 1:]) & (g_idx[:, :-1] < g_idx[:, 1:]))
+    bad = np.flatnonzero((pair & ~asc).any(axis=1))
+    assert bad.size == 0, f"row {rows[bad[0]]}: not ascending"
+    bad = np.flatnonzero((m & (rec > r2 * (1 + NEAR_TIE_REL))).any(axis=1))
+    assert bad.size == 0, f"row {rows[bad[0]]}: beyond radius"
+    om = np.arange(o_idx.shape[1])[None, :] < o_cnt[:, None]
+    os_ = np.sort(np.where(om, o_idx, -1), axis=1)
+    differ = np.flatnonzero((g_cnt != o_cnt) | (gs != os_).any(axis=1))
+    for r in differ:
         gc, oc = int(g_cnt[r]), int(o_cnt[r])
-        gi = g_idx[r, :gc]
-        assert gc <= k and np.all(g_idx[r, gc:] == -1) and np.all(np.isinf(g_d2[r, gc:])), \
-            f"row {rows[r]}: bad padding"
-        assert np.all((gi >= 0) & (gi < target.shape[0])), f"row {rows[r]}: index out of range"
-        assert len(set(gi.tolist())) == gc, f"row {rows[r]}: duplicate index"
-        rec = ((t64[gi] - q64[r]) ** 2).sum(axis=1)
-        gd = g_d2[r, :gc].astype(np.float64)
-        assert np.all(np.abs(gd - rec) <= KNN_D2_REL * rec + KNN_D2_ABS), \
-            f"row {rows[r]}: d2 off the FP64 distance"
-        for a in range(gc - 1):
-            assert (gd[a], gi[a]) <= (gd[a + 1], gi[a + 1]), f"row {rows[r]}: not ascending"
-        assert np.all(rec <= r2 * (1 + NEAR_TIE_REL)), f"row {rows[r]}: beyond radius"
-        oi = o_idx[r, :oc]
-        if gc == oc and np.array_equal(np.sort(gi), np.sort(oi)):
-            continue
-        near += 1
+        gi, oi = g_idx[r, :gc], o_idx[r, :oc]
         # differing members must be near-ties of the k-th distance or the radius
         dk = o_d2[r, oc - 1] if oc > 0 else 0.0
         edge = [dk] + ([r2] if np.isfinite(r2) else [])
@@ -111,10 +136,51 @@ def check_knn(target, queries, k, radius, g_idx, g_d2, g_cnt, rows=None, exact=F
                 f"row {rows[r]}: index {j} (D={dj}) is not a near-tie of D_k={dk}"
         if gc != oc:
             assert np.isfinite(r2), f"row {rows[r]}: count {gc} != {oc} without a radius"
-    return near
+    return int(differ.size)
 
 
-def reference_sets(target, g_idx, g_cnt, rows, search):
+def check_self_consistent(target, queries, k, radius, g_idx, g_d2, g_cnt):
+    """Properties every row must have, at any size (no oracle): counts in
+    [0, k], -1 / +inf padding, indices in range and distinct, each d2 within
+    1e-6 D + 1e-12 of the FP64 distance recomputed for its index, ascending
+    (d2, index), inside the (inclusive) radius.  Rows are processed in
+    blocks so that millions of rows fit in memory."""
+    q = np.asarray(queries, np.float32)
+    for a in range(0, q.shape[0], 200_000):
+        b = min(a + 200_000, q.shape[0])
+        _consistent_block(target, q[a:b], k, radius, g_idx[a:b], g_d2[a:b], g_cnt[a:b], a)
+
+
+def _consistent_block(target, qs, k, radius, g_idx, g_d2, g_cnt, base):
+    t64 = np.asarray(target, np.float32).astype(np.float64)
+    q64 = qs.astype(np.float64)
+    r2 = np.inf if np.isinf(radius) else float(np.float32(radius)) ** 2
+    g_cnt = np.asarray(g_cnt).astype(np.int64)
+    m = np.arange(g_idx.shape[1])[None, :] < g_cnt[:, None]
+    fails = {
+        "count out of range": (g_cnt < 0) | (g_cnt > k),
+        "bad padding": ((g_idx != -1) & ~m).any(axis=1) | (~np.isinf(g_d2) & ~m).any(axis=1),
+        "index out of range": (m & ((g_idx < 0) | (g_idx >= t64.shape[0]))).any(axis=1),
+    }
+    for what, f in fails.items():
+        bad = np.flatnonzero(f)
+        assert bad.size == 0, f"row {base + bad[0]}: {what}"
+    gs = np.sort(np.where(m, g_idx, -1), axis=1)
+    bad = np.flatnonzero(((gs[:, 1:] == gs[:, :-1]) & (gs[:, 1:] >= 0)).any(axis=1))
+    assert bad.size == 0, f"row {base + bad[0]}: duplicate index"
+    safe = np.where(m, g_idx, 0)
+    rec = np.where(m, ((t64[safe] - q64[:, None, :]) ** 2).sum(axis=2), 0.0)
+    gd = np.where(m, g_d2.astype(np.float64), 0.0)
+    bad = np.flatnonzero((np.abs(gd - rec) > KNN_D2_REL * rec + KNN_D2_ABS).any(axis=1))
+    assert bad.size == 0, f"row {base + bad[0]}: d2 off the FP64 distance"
+    asc = (gd[:, :-1] < gd[:, 1:]) | ((gd[:, :-1] == gd[:, 1:]) & (g_idx[:, :-1] < g_idx[:, 1:]))
+    bad = np.flatnonzero((m[:, 1:] & ~asc).any(axis=1))
+    assert bad.size == 0, f"row {base + bad[0]}: not ascending"
+    bad = np.flatnonzero((m & (rec > r2 * (1 + NEAR_TIE_REL))).any(axis=1))
+    assert bad.size == 0, f"row {base + bad[0]}: beyond radius"
+
+
+def reference_sets(target, g_idx, g_cnt, rows, search, oracle_out=None):
     """Neighbour sets the expected covariances are computed on.
 
     ``search = (queries, k, radius)``: the oracle's own kNN of those rows,
@@ -126,13 +192,18 @@ def reference_sets(target, g_idx, g_cnt, rows, search):
     if search is None:
         return g_idx[rows], g_cnt[rows]
     queries, k, radius = search
-    qs = np.asarray(queries, np.float32).reshape(-1, 3)[rows]
-    o_idx, _, o_cnt = oracle.knn(target, qs, k, radius)
-    gi, gc = g_idx[rows], g_cnt[rows]
-    for r in range(len(rows)):
-        a, b = int(gc[r]), int(o_cnt[r])
-        if a != b or not np.array_equal(np.sort(gi[r, :a]), np.sort(o_idx[r, :b])):
-            o_idx[r], o_cnt[r] = gi[r], gc[r]
+    if oracle_out is None:
+        qs = np.asarray(queries, np.float32).reshape(-1, 3)[rows]
+        o_idx, _, o_cnt = oracle.knn(target, qs, k, radius)
+    else:
+        o_idx, o_cnt = np.array(oracle_out[0]), np.array(oracle_out[2])
+    gi, gc = g_idx[rows], np.asarray(g_cnt)[rows]
+    kk = gi.shape[1]
+    gm = np.arange(kk)[None, :] < gc[:, None]
+    om = np.arange(kk)[None, :] < o_cnt[:, None]
+    differ = (gc != o_cnt) | (np.sort(np.where(gm, gi, -1), axis=1) !=
+                              np.sort(np.where(om, o_idx, -1), axis=1)).any(axis=1)
+    o_idx[differ], o_cnt[differ] = gi[differ], gc[differ]
     return o_idx, o_cnt
 
 
@@ -151,12 +222,12 @@ def check_cov_weighted(target, g_idx, g_cnt, mean, cov, reg, valid, kind, sigma,
 
 
 def check_cov(target, g_idx, g_cnt, mean, cov, reg, valid, eps=1e-3, rows=None, ref=None,
-              search=None, floor=None):
+              search=None, floor=None, oracle_out=None):
     """Compare GPU covariance outputs with the oracle's on the sets
-    ``reference_sets`` names."""
+    ``reference_sets`` names (``oracle_out`` as in ``check_knn``)."""
     rows = np.arange(g_idx.shape[0]) if rows is None else np.asarray(rows)
     if ref is None:
-        r_idx, r_cnt = reference_sets(target, g_idx, g_cnt, rows, search)
+        r_idx, r_cnt = reference_sets(target, g_idx, g_cnt, rows, search, oracle_out)
         ref = oracle.covariances(target, r_idx, r_cnt, eps=eps, with_eig=True)
         if floor is None:
             origin = None if search is None else \

@@ -114,7 +114,8 @@ def test_random_batched_sweep(lk, case):
     """Batched launches over 1-4 targets of different cell sizes (one may be
     empty or small enough to be streamed whole), uneven scans (some empty),
     random k, radius and launch shape: every scan's rows equal lkc_knn_cov
-    on that scan alone, bit for bit."""
+    on that scan alone, bit for bit, and sampled rows of every scan match the
+    oracle (kNN and the batched covariances)."""
     lkc, ctx = lk
     rng = np.random.default_rng(5000 + case)
     n_t = int(rng.integers(1, 5))
@@ -157,12 +158,19 @@ def test_random_batched_sweep(lk, case):
         torch.cuda.synchronize()
         for key in alone:
             assert torch.equal(alone[key], got[key][o:o + n]), f"{desc}: scan at {o}: {key}"
-    o, n, ti = max(scans, key=lambda s: s[1])
-    if n:
-        r = np.sort(rng.choice(n, min(n, 100), replace=False))
+    # every non-empty scan: sampled rows against the oracle, kNN and the
+    # batched call's own mean / cov / reg_cov
+    for (o, n, ti), part in zip(scans, parts):
+        if n == 0:
+            continue
+        r = np.sort(rng.choice(n, min(n, 60), replace=False))
         g = {kk: v[o:o + n].cpu().numpy() for kk, v in got.items()}
-        parity.check_knn(clouds[ti], parts[scans.index((o, n, ti))], k, radius, g["idx"], g["d2"],
-                         g["count"], rows=r)
+        try:
+            parity.check_knn(clouds[ti], part, k, radius, g["idx"], g["d2"], g["count"], rows=r)
+            parity.check_cov(clouds[ti], g["idx"], g["count"], g["mean"], g["cov"], g["reg"],
+                             g["valid"], rows=r, search=(part, k, radius))
+        except AssertionError as e:
+            raise AssertionError(f"{desc}: scan at {o} (target {ti}): {e}") from e
     tset.free()
     for t in targets:
         t.free()
