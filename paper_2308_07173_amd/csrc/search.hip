@@ -680,9 +680,12 @@ struct GroupArgs {
 // prune with the smallest of them, which is still an upper bound of the
 // final k-th distance (each list holds k distinct candidates).
 struct SplitShare {
-    volatile float* thr;   // [split][64]
-    int sub;               // this wave's index in the group
-    int split_mask;        // split - 1
+    volatile float* thr;     // [split][64]
+    volatile uint32_t* flag; // [split][64]: lanes a wave cannot answer exactly
+    uint32_t* dist;          // [split / 2][K][64]: merge buffers (d2 bits)
+    uint32_t* pos;           // [split / 2][K][64]: and the entries' positions
+    int sub;                 // this wave's index in the group
+    int split_mask;          // split - 1
 };
 
 __device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, float own) {
@@ -696,8 +699,11 @@ __device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, floa
 // fallback lanes, insertions (over all lanes), pops in which no lane
 // inserted; then insertions and candidates split by phase: the query cells'
 // runs touching the query box, the rest of the query cells, the other cells;
-// then insertions from the group's own chunk (self queries)
-constexpr int PROF_WORDS = 17;
+// then insertions from the group's own chunk (self queries); then the lanes
+// handed on because their decoded entries stayed out of order or tied, because
+// the last entry shared the k-th distance's bucket, or because the wave ran
+// out of chunk names
+constexpr int PROF_WORDS = 20;
 // A profile counter that compiles away in the unprofiled kernels (their
 // counters are never read, so the arithmetic feeding them is dead).
 template <bool ON>
@@ -720,6 +726,7 @@ template <bool ON>
 struct GroupProf {
     ProfCount<ON> probes, cells, chunks, cands, pops, inserts, dead;
     ProfCount<ON> ins0, ins1, ins2, cand0, cand1, cand2, own;
+    ProfCount<ON> amb_order, amb_bucket, amb_names;
 };
 
 struct SlotQuery {
@@ -757,37 +764,113 @@ __device__ __forceinline__ float box_box_dist2(const float (&a0)[3], const float
     return gx * gx + gy * gy + gz * gz;
 }
 
-// Stream the reordered points [s0, e0) through every member lane's top-k.
+// Packed insertion keys.  While a block is streamed, a lane keeps its
+// nearest candidates as 32-bit keys: the float32 bits of d2 with the low
+// ID_BITS bits replaced by the candidate's name (the ordinal of its 64-point
+// chunk in the wave's stream of this round, and its lane in that chunk).
+// Non-negative floats order as their bits, so the key order is the d2 order
+// up to buckets of 2^-9 relative width, and the name order inside a bucket.
+// A sorted list of such keys takes a candidate with one v_med3_u32 per entry
+// (the median of the entry before, the candidate and the entry itself is the
+// entry's new value), where a sorted list of exact 64-bit (d2, index) keys
+// costs a compare and four selects per entry.  The list holds SLACK entries
+// past the k-th.  When the block is done every entry is decoded to its exact
+// (d2, index) key and the k smallest of those are the exact result, unless
+// the last entry's bucket is the exact k-th distance's bucket: a candidate
+// the list dropped may then tie with the k-th inside the bucket, and the lane
+// is handed to the wavefront-per-query search.  Ordinals start at 1, so
+// that a real key is never 0, the value of the front pads of a list for
+// k < K.
+constexpr int SLACK = 4;
+constexpr int ID_BITS = 14;
+constexpr uint32_t ID_MASK = (1u << ID_BITS) - 1u;
+constexpr int MAX_CHUNKS = 1 << (ID_BITS - 6);   // chunk ordinals (0 unused)
+
+__device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t x, uint32_t b) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(x), "v"(b));
+    return r;
+}
+
+// Insert x into the ascending list L; a no-op when x is not below L[N-1].
+template <int N>
+__device__ __forceinline__ void pk_insert(uint32_t (&L)[N], uint32_t x) {
+#pragma unroll
+    for (int j = N - 1; j >= 1; --j) L[j] = med3_u32(L[j - 1], x, L[j]);
+    L[0] = min(L[0], x);
+}
+
+// Insert x (below D[K-1]) into the ascending 32-bit list D, its payload xp
+// moving into P alongside.
+template <int K>
+__device__ __forceinline__ void insert_p(uint32_t (&D)[K], uint32_t (&P)[K], uint32_t x,
+                                         uint32_t xp) {
+    bool c_hi = x < D[K - 1];
+#pragma unroll
+    for (int j = K - 1; j >= 1; --j) {
+        const bool c_lo = x < D[j - 1];
+        const uint32_t tp = c_hi ? xp : P[j];
+        P[j] = c_lo ? P[j - 1] : tp;
+        D[j] = med3_u32(D[j - 1], x, D[j]);
+        c_hi = c_lo;
+    }
+    P[0] = c_hi ? xp : P[0];
+    D[0] = min(D[0], x);
+}
+
+// The largest d2 of a key's bucket (NaN for the bucket of +inf).
+__device__ __forceinline__ float pk_upper(uint32_t key) { return __uint_as_float(key | ID_MASK); }
+
+// A lane's pruning bound: the top of its k-th entry's bucket (the radius
+// while it holds fewer than k entries), never above its bound lcap.  The
+// k-th entry sits at K - 1: k < K lists start with K - k zero pads.
+template <int K>
+__device__ __forceinline__ float pk_bound(const uint32_t (&L)[K + SLACK], float r2, float lcap) {
+    const uint32_t e = L[K - 1];
+    return fminf(e == ~0u ? r2 : fminf(pk_upper(e), r2), lcap);
+}
+
+// Sort 32-bit keys ascending in registers.
+template <int N>
+__device__ __forceinline__ void sort_u32(uint32_t (&L)[N]) {
+    constexpr SortNet<N> net{};
+#pragma unroll
+    for (int c = 0; c < net.n; ++c) {
+        const uint32_t x = L[net.a[c]], y = L[net.b[c]];
+        L[net.a[c]] = min(x, y);
+        L[net.b[c]] = max(x, y);
+    }
+}
+
+// Stream the reordered points [s0, e0) through every member lane's list.
 // The run is walked in aligned 64-point chunks made of four 16-point runs
 // with their own bounding boxes; mode 0 takes only the 16-point runs whose
 // box touches the group's query box, mode 1 only the others, mode 2 all of
 // them, and modes 1-2 skip a 16-point run whose box is farther from the
-// query box than the radius or the group's largest k-th distance.  A kept
-// chunk is loaded once (lane t holds point t, one coalesced read); each
-// candidate is broadcast from its lane and tested by every lane, which only
-// sets a bit per passing candidate; the insertions follow as "pops" in which
-// every lane inserts its own next passing candidate, so a chunk costs as
-// many insertion steps as its busiest lane needs rather than one per
-// candidate that any lane wants.  The test compares float d2 with the
-// lane's k-th distance (the radius while its list is not full), so exact
-// ties pass it; the pop makes the exact (d2, index) comparison.
+// query box than the radius or the group's largest k-th bound.  A kept chunk
+// is named (its ordinal in this wave's stream, recorded in s_tab; fixed_ord
+// names a chunk the caller registered) and loaded once (lane t holds point
+// t, one coalesced read); each candidate is broadcast from its lane and
+// tested by every lane, which only sets a bit per passing candidate; the
+// insertions follow as "pops" in which every lane inserts its own next
+// passing candidate, so a chunk costs as many insertion steps as its busiest
+// lane needs rather than one per candidate that any lane wants.  A wave that
+// runs out of names sets n_ch past MAX_CHUNKS (its members fall back).
 template <int K, bool PROF>
 __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bool member,
                                          float qx, float qy, float qz, float r2, float lcap,
                                          const float (&b0)[3], const float (&b1)[3],
-                                         float margin, float& gthr,
-                                         unsigned long long (&kk)[K], int mode,
-                                         GroupProf<PROF>& gp, int skip_cb, const SplitShare& sh,
-                                         int win_k = 0, int win_n = 0) {
+                                         float margin, float& gthr, uint32_t (&L)[K + SLACK],
+                                         int mode, GroupProf<PROF>& gp, int skip_cb,
+                                         const SplitShare& sh, int& n_ch, uint32_t* s_tab,
+                                         int fixed_ord = -1, int win_k = 0, int win_n = 0) {
     const int lane = lane_id();
 #pragma unroll 1
     for (int cb = s0 & ~(WAVE - 1); cb < e0; cb += WAVE) {
         if (cb == skip_cb) continue;   // streamed first, as the group's own chunk
         if (((cb / WAVE) & sh.split_mask) != sh.sub) continue;   // the other wave's chunk
         uint32_t keep = 0;
-        // this lane's current k-th distance (radius while its list is not
-        // full), never above its bound lcap
-        float lthr = fminf(kk[K - 1] == ~0ull ? r2 : fminf(key_d2(kk[K - 1]), r2), lcap);
+        float lthr = pk_bound<K>(L, r2, lcap);
         if (sh.split_mask) lthr = shared_thr(sh, lane, lthr);
 #pragma unroll
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
@@ -801,7 +884,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             const bool want = mode == 0 ? bd == 0.0f : (mode == 1 ? (bd > 0.0f && near) : near);
             if (!want) continue;
             // and some lane needs it: the run's box is within that lane's own
-            // k-th distance (or radius)
+            // bound
             const float gx = fmaxf(fmaxf(blo.x - qx, qx - bhi.x) - margin, 0.0f);
             const float gy = fmaxf(fmaxf(blo.y - qy, qy - bhi.y) - margin, 0.0f);
             const float gz = fmaxf(fmaxf(blo.z - qz, qz - bhi.z) - margin, 0.0f);
@@ -809,6 +892,15 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             if (ballot(member && ld * (1.0f - 1e-6f) <= lthr)) keep |= 1u << q4;
         }
         if (!keep) continue;
+        int ord = fixed_ord;
+        if (ord < 0) {
+            if (n_ch >= MAX_CHUNKS) {
+                n_ch = MAX_CHUNKS + 1;
+                continue;
+            }
+            ord = n_ch++;   // n_ch starts at 1
+            if (lane == 0) s_tab[ord] = (uint32_t)(cb / WAVE);
+        }
         gp.chunks++;
         const float4 c = T.pts[cb + lane];   // padded: reads past n stay in bounds
         // non-members never pass (d2 >= 0)
@@ -840,23 +932,26 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             bits &= member ? ~(((1ull << win_k) - 1ull) << w0) : ~0ull;
         }
         if (!ballot(bits != 0ull)) continue;
+        const uint32_t name0 = (uint32_t)ord << 6;
         do {
             gp.pops++;
             const int j = bits ? __builtin_ffsll((long long)bits) - 1 : 0;
             const float cx = shfl(c.x, j), cy = shfl(c.y, j), cz = shfl(c.z, j);
-            const int32_t ci = shfl(__float_as_int(c.w), j);
-            bool ins = false;
+            uint32_t x = ~0u;
             if (bits) {
                 bits &= bits - 1;
-                const unsigned long long key = lane_key(dist2(qx, qy, qz, cx, cy, cz), ci);
-                ins = key < kk[K - 1];
-                if (ins) lane_insert<K>(kk, key);
+                // d2 <= the lane's bound <= r2: within the radius
+                const uint32_t db = __float_as_uint(dist2(qx, qy, qz, cx, cy, cz));
+                x = (db & ~ID_MASK) | name0 | (uint32_t)j;
             }
-            const unsigned long long im = ballot(ins);
-            gp.inserts += (uint32_t)__popcll(im);
-            gp.dead += im ? 0u : 1u;
+            if (PROF) {
+                const unsigned long long im = ballot(x < L[K + SLACK - 1]);
+                gp.inserts += (uint32_t)__popcll(im);
+                gp.dead += im ? 0u : 1u;
+            }
+            pk_insert<K + SLACK>(L, x);
         } while (ballot(bits != 0ull));
-        float own = fminf(kk[K - 1] == ~0ull ? r2 : key_d2(kk[K - 1]), lcap);
+        float own = pk_bound<K>(L, r2, lcap);
         if (sh.split_mask) {
             sh.thr[sh.sub * WAVE + lane] = own;
             own = shared_thr(sh, lane, own);
@@ -865,9 +960,78 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
     }
 }
 
+// Write one query's neighbour row from the ascending exact d2 bits D and
+// the points' positions P in the reordered array (K - k pads first, ~0u
+// empty): d2 and the count; the indices too unless the fused covariance
+// writes them as it gathers the points (positions left in s_pos, column c
+// at s_pos[(K - k + c) * 64 + lane]).  Returns the count.
+template <int K, int FUSED>
+__device__ __forceinline__ int emit_row(const GroupArgs& a, const TargetView& T, int64_t qi,
+                                        int k, const uint32_t (&D)[K], const uint32_t (&P)[K],
+                                        uint32_t* s_pos) {
+    int cnt = 0;
+    int32_t* ip = a.ko.idx + qi * k - (K - k);   // entry j is column j - (K - k)
+    float* dp = a.ko.d2 + qi * k - (K - k);
+    const int lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (P[j] != ~0u) {   // not a pad
+            const bool have = D[j] != ~0u;
+            dp[j] = have ? __uint_as_float(D[j]) : INF;
+            if (!FUSED) ip[j] = have ? __float_as_int(T.pts[P[j]].w) : -1;
+            if (FUSED && !have) ip[j] = -1;
+            cnt += have ? 1 : 0;
+        }
+        if (FUSED) s_pos[j * WAVE + lane] = P[j];
+    }
+    a.ko.count[qi] = cnt;
+    return cnt;
+}
+
+// The covariance of a written row: its first cnt neighbours, gathered from
+// the reordered points (the copy the search has just streamed through the
+// caches; the same values as the caller-order copy) by the positions in
+// s_pos, writing each neighbour's index into the row on the way.
+template <int K, int FUSED>
+__device__ __forceinline__ void emit_cov(const GroupArgs& a, const TargetView& T, int64_t qi,
+                                         float qx, float qy, float qz, int k, int cnt,
+                                         const uint32_t* s_pos) {
+    const float4* pts = T.pts;
+    const uint32_t* sp = s_pos + (K - k) * WAVE + lane_id();
+    int32_t* irow = a.ko.idx + qi * k;
+    const auto fetch = [&](int j) {
+        const float4 t = pts[sp[j * WAVE]];
+        irow[j] = __float_as_int(t.w);
+        return t;
+    };
+    CovOut c;
+    if (FUSED == 1)
+        covariance(qx, qy, qz, cnt, fetch, a.eps, c);
+    else
+        covariance_weighted(qx, qy, qz, cnt, fetch, a.wt, a.eps, c);
+    store_cov(a.co, qi, c);
+}
+
+// An empty result row (non-finite query, empty target).
+template <int FUSED>
+__device__ __forceinline__ void emit_empty(const GroupArgs& a, int64_t qi, int k) {
+#pragma unroll 1
+    for (int j = 0; j < k; ++j) {
+        a.ko.idx[qi * k + j] = -1;
+        a.ko.d2[qi * k + j] = INF;
+    }
+    a.ko.count[qi] = 0;
+    if (FUSED) {
+        CovOut c;
+        cov_empty(c);
+        store_cov(a.co, qi, c);
+    }
+}
+
 template <int K, int FUSED, bool PROF>
 __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& sh,
-                           unsigned long long* s_kk) {
+                           uint32_t* s_tab, uint32_t* s_pos) {
+    constexpr int KP = K + SLACK;
     const int lane = lane_id();
     const int64_t slot = group * WAVE + lane;
     const bool active = slot < a.n_slots;
@@ -884,12 +1048,11 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     const float r2 = a.sp.r2;
     const int k = a.sp.k;
     const int pad = K - k;
-    unsigned long long kk[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) kk[j] = (j < pad) ? 0ull : ~0ull;
-    bool ok = true;
     // An empty target answers every query with an empty list.
-    bool placed = same && T.n_cells == 0;   // searched by one of the rounds below
+    const bool empty_tgt = same && T.n_cells == 0;
+    bool placed = empty_tgt;   // searched by one of the rounds below
+    bool to_fb = false;        // handed to the wavefront-per-query search
+    int row_cnt = -1;          // count of the row this wave wrote (-1: none)
     GroupProf<PROF> gp{};
     const unsigned long long t_start = PROF ? __builtin_amdgcn_s_memtime() : 0ull;
     // Rounds: each picks an anchor cell among the unplaced lanes and searches
@@ -905,17 +1068,15 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
     const int n_act = (int)min((int64_t)WAVE, a.n_slots - group * WAVE);
     const bool win = !a.queries && k <= 32 && n_act >= k;   // (uniform) the windows exist
     if (win) {
-        {
-            // the lane's window: slots [w0, w0 + k) of the group
-            const int w0 = min(max(lane - (k - 1) / 2, 0), n_act - k);
-            float m = 0.0f;
+        // the lane's window: slots [w0, w0 + k) of the group
+        const int w0 = min(max(lane - (k - 1) / 2, 0), n_act - k);
+        float m = 0.0f;
 #pragma unroll 1
-            for (int j = 0; j < k; ++j) {
-                const int src = w0 + j;
-                m = fmaxf(m, dist2(s.x, s.y, s.z, shfl(s.x, src), shfl(s.y, src), shfl(s.z, src)));
-            }
-            lcap = m;
+        for (int j = 0; j < k; ++j) {
+            const int src = w0 + j;
+            m = fmaxf(m, dist2(s.x, s.y, s.z, shfl(s.x, src), shfl(s.y, src), shfl(s.z, src)));
         }
+        lcap = m;
     }
     unsigned long long pending = T.n_cells > 0 ? ballot(same) : 0ull;
 #pragma unroll 1
@@ -986,6 +1147,13 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
         const float margin = (fmaxf(qabs, T.max_abs) + 2.0f * T.cell) * 1e-6f;
         // largest k-th distance bound over the members
         float gthr = wave_max_dpp(member ? fminf(r2, lcap) : -INF);
+        // this round's lists: K - k zero pads, then empty entries
+        uint32_t L[KP];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) L[j] = ~0u;
+#pragma unroll 1
+        for (int j = 0; j < pad; ++j) pk_insert<KP>(L, 0u);
+        int n_ch = 1;
         // Self queries: the group's 64 slots are 64 consecutive points of
         // the target's Morton order, i.e. the queries themselves and each
         // other's nearest points; streaming that chunk first fills every
@@ -993,38 +1161,41 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
         int own_cb = -1;
         if (!a.queries) {
             own_cb = (int)(group * WAVE);
-            // The wave that streams the own chunk starts each member's list
-            // with its window (the exact keys of its points within the
-            // radius, sorted by a network instead of k insertions) and
-            // streams the rest of the chunk.
-            int win_k = 0;
-            if (win && ((own_cb / WAVE) & sh.split_mask) == sh.sub) {
-                const int w0 = min(max(lane - (k - 1) / 2, 0), n_act - k);
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    if (j >= pad) {
-                        const int src = w0 + j - pad;
+            if (((own_cb / WAVE) & sh.split_mask) == sh.sub) {
+                // the own chunk is this wave's chunk 1
+                n_ch = 2;
+                if (lane == 0) s_tab[1] = (uint32_t)(own_cb / WAVE);
+                // The wave that streams the own chunk starts each member's
+                // list with its window (the keys of its points within the
+                // radius) and streams the rest of the chunk.
+                int win_k = 0;
+                if (win) {
+                    const int w0 = min(max(lane - (k - 1) / 2, 0), n_act - k);
+#pragma unroll 1
+                    for (int j = 0; j < k; ++j) {
+                        const int src = w0 + j;
                         const float px = shfl(s.x, src), py = shfl(s.y, src), pz = shfl(s.z, src);
-                        const int32_t pi = shfl((int32_t)s.qi, src);
                         const float d = dist2(s.x, s.y, s.z, px, py, pz);
                         // a window point beyond the radius is no neighbour
-                        const unsigned long long key = d <= r2 ? lane_key(d, pi) : ~0ull;
-                        kk[j] = member ? key : kk[j];
+                        const uint32_t key = member && d <= r2
+                                                 ? (__float_as_uint(d) & ~ID_MASK) | (1u << 6) |
+                                                       (uint32_t)src
+                                                 : ~0u;
+                        pk_insert<KP>(L, key);
                     }
-                    __builtin_amdgcn_sched_barrier(0);   // one key at a time (registers)
+                    win_k = k;
+                    gp.inserts += (uint32_t)__popcll(ballot(member)) * (uint32_t)k;
                 }
-                sort_keys<K>(kk);
-                win_k = k;
-                gp.inserts += (uint32_t)__popcll(ballot(member)) * (uint32_t)k;
+                const uint32_t i0 = gp.inserts;
+                scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
+                            s.z, r2, lcap, b0, b1, margin, gthr, L, 2, gp, -1, sh, n_ch, s_tab, 1,
+                            win_k, n_act);
+                gp.own += gp.inserts - i0;
             }
-            const uint32_t i0 = gp.inserts;
-            scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
-                        s.z, r2, lcap, b0, b1, margin, gthr, kk, 2, gp, -1, sh, win_k, n_act);
-            gp.own += gp.inserts - i0;
         }
         if (whole)
             scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin, gthr,
-                        kk, 2, gp, own_cb, sh);
+                        L, 2, gp, own_cb, sh, n_ch, s_tab);
         for (int pass = 0; pass < (whole ? 0 : 2); ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
                 gp.probes++;
@@ -1062,8 +1233,8 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
                         const int s0 = readlane((int)st, cl);
                         const int e0 = s0 + readlane((int)cn, cl);
                         gp.cells++;
-                        scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin, gthr,
-                                    kk, mode, gp, own_cb, sh);
+                        scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin,
+                                    gthr, L, mode, gp, own_cb, sh, n_ch, s_tab);
                     }
                     const uint32_t di = gp.inserts - i0, dc = gp.cands - c0;
                     if (mode == 0) {
@@ -1079,34 +1250,107 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
                 }
             }
         }
+        // Decode every entry to its exact d2 bits (in place) and its
+        // position in the reordered points (pads get position ~0u).  The
+        // packed order is the exact order except inside a bucket, which
+        // rarely holds more than two entries: four alternating odd-even
+        // transposition phases fix up to four; a lane still out of order, or
+        // whose order among equal distances the index would decide, or a
+        // full list whose last entry shares the exact k-th distance's
+        // bucket (a candidate it dropped may tie inside the bucket), or a
+        // wave that ran out of chunk names, hands its lane on.
+        const uint32_t last = L[KP - 1];
+        uint32_t P[KP];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+            const uint32_t e = L[j];
+            uint32_t pos = e == 0u ? ~0u : 0u;
+            if (member && e != 0u && e != ~0u) {
+                const uint32_t id = e & ID_MASK;
+                pos = s_tab[id >> 6] * (uint32_t)WAVE + (id & 63u);
+                const float4 p = T.pts[pos];
+                L[j] = __float_as_uint(dist2(s.x, s.y, s.z, p.x, p.y, p.z));
+            }
+            P[j] = pos;
+            if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bounded loads in flight
+        }
+        const auto cmpx_p = [&](int j) {
+            const uint32_t d0 = L[j - 1], d1 = L[j], p0 = P[j - 1], p1 = P[j];
+            const bool sw = d1 < d0;
+            L[j - 1] = min(d0, d1);
+            L[j] = max(d0, d1);
+            P[j - 1] = sw ? p1 : p0;
+            P[j] = sw ? p0 : p1;
+        };
+#pragma unroll
+        for (int ph = 0; ph < 4; ++ph) {
+#pragma unroll
+            for (int j = 1 + (ph & 1); j < KP; j += 2) cmpx_p(j);
+        }
+        bool amb = false;
+#pragma unroll
+        for (int j = 1; j < KP; ++j) {
+            // out of order, or two real entries at one distance up to the
+            // (k+1)-th (pads and empty entries excepted)
+            const bool real = P[j - 1] != ~0u && L[j] != ~0u;
+            amb = amb || L[j] < L[j - 1] || (j <= K && real && L[j] == L[j - 1]);
+        }
+        const bool amb_b = last != ~0u && L[K - 1] != ~0u &&
+                           (last >> ID_BITS) <= (L[K - 1] >> ID_BITS);
+        if (PROF) {
+            gp.amb_order += (uint32_t)__popcll(ballot(member && amb));
+            gp.amb_bucket += (uint32_t)__popcll(ballot(member && !amb && amb_b));
+            gp.amb_names += n_ch > MAX_CHUNKS ? (uint32_t)__popcll(ballot(member)) : 0u;
+        }
+        amb = member && (amb || n_ch > MAX_CHUNKS || amb_b);
+        uint32_t D[K], Q[K];   // the first K: the row
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            D[j] = L[j];
+            Q[j] = P[j];
+        }
         if (sh.split_mask) {
             // every wave has streamed its chunks: merge the lists pairwise
             // through LDS (wave w + stride hands its lists to wave w, which
-            // inserts the entries below its k-th key; each list is
-            // ascending, so a lane stops at its first miss)
+            // inserts the entries below its k-th distance; each list is
+            // ascending, so a lane stops at its first miss, which must not
+            // tie with the k-th); a lane is handed on if it is in any wave
 #pragma unroll 1
             for (int stride = 1; stride <= sh.split_mask; stride <<= 1) {
                 const int slot = sh.sub / (2 * stride);
-                unsigned long long* buf = s_kk + (int64_t)slot * K * WAVE;
+                uint32_t* bd = sh.dist + (int64_t)slot * K * WAVE;
+                uint32_t* bp = sh.pos + (int64_t)slot * K * WAVE;
                 __syncthreads();
                 if (sh.sub % (2 * stride) == stride) {
 #pragma unroll
-                    for (int j = 0; j < K; ++j) buf[j * WAVE + lane] = kk[j];
+                    for (int j = 0; j < K; ++j) {
+                        bd[j * WAVE + lane] = D[j];
+                        bp[j * WAVE + lane] = Q[j];
+                    }
                 }
                 __syncthreads();
                 if (sh.sub % (2 * stride) == 0) {
 #pragma unroll 1
                     for (int j = pad; j < K; ++j) {
-                        const unsigned long long x = buf[j * WAVE + lane];
-                        const bool ins = member && x < kk[K - 1];
+                        const uint32_t x = bd[j * WAVE + lane];
+                        const bool ins = member && x < D[K - 1];
+                        amb = amb || (member && x != ~0u && x == D[K - 1]);
                         if (!ballot(ins)) break;
-                        if (ins) lane_insert<K>(kk, x);
+                        if (ins) insert_p<K>(D, Q, x, bp[j * WAVE + lane]);
                     }
                 }
             }
+            // equal distances brought together by the merge
+#pragma unroll
+            for (int j = 1; j < K; ++j)
+                amb = amb || (member && Q[j - 1] != ~0u && D[j] != ~0u && D[j] == D[j - 1]);
+            sh.flag[sh.sub * WAVE + lane] = amb ? 1u : 0u;
+            __syncthreads();
+            for (int w = 0; w <= sh.split_mask; ++w) amb = amb || sh.flag[w * WAVE + lane] != 0u;
+            __syncthreads();   // the flags are rewritten next round
         }
-        // exactness: every point outside the (unclamped) block is at least f away
         if (member) {
+            // exactness: every point outside the (unclamped) block is at least f away
             bool covers = true;
             float f = INF;
             const float q3[3] = {s.x, s.y, s.z};
@@ -1117,21 +1361,29 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             }
             f -= margin;
             const float f2 = f > 0.0f ? f * f * (1.0f - 1e-6f) : 0.0f;
-            const bool full = kk[K - 1] != ~0ull;
-            ok = whole || covers || (full && f2 > key_d2(kk[K - 1])) || (a.sp.capped && f2 > r2);
+            const bool full = D[K - 1] != ~0u;
+            const bool ok = whole || covers || (full && f2 > __uint_as_float(D[K - 1])) ||
+                            (a.sp.capped && f2 > r2);
+            if (!ok || amb) {
+                to_fb = true;
+            } else if (sh.sub == 0) {
+                row_cnt = emit_row<K, FUSED>(a, T, s.qi, k, D, Q, s_pos);
+            }
         }
     }
     if (PROF && lane == 0) {
         // every wave of the group adds what it streamed (the buffer is
         // cleared before the launch)
         uint32_t* pw = a.prof + group * PROF_WORDS;
-        const uint32_t add[12] = {gp.chunks, gp.cands, gp.pops, gp.inserts, gp.dead, gp.ins0,
-                                  gp.ins1, gp.ins2, gp.cand0, gp.cand1, gp.cand2, gp.own};
-        const int at[12] = {3, 4, 5, 8, 9, 10, 11, 12, 13, 14, 15, 16};
-        for (int i = 0; i < 12; ++i) atomicAdd(pw + at[i], add[i]);
+        const uint32_t add[15] = {gp.chunks,    gp.cands, gp.pops,  gp.inserts,    gp.dead,
+                                  gp.ins0,      gp.ins1,  gp.ins2,  gp.cand0,      gp.cand1,
+                                  gp.cand2,     gp.own,   gp.amb_order, gp.amb_bucket,
+                                  gp.amb_names};
+        const int at[15] = {3, 4, 5, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19};
+        for (int i = 0; i < 15; ++i) atomicAdd(pw + at[i], add[i]);
     }
     if (sh.sub) return;   // the other waves of a split group are done
-    const bool to_fb = (fin && !placed) || (placed && !ok);
+    to_fb = to_fb || (fin && !placed);
     const unsigned long long fm = ballot(to_fb);
     if (PROF && lane == 0) {
         uint32_t* pw = a.prof + group * PROF_WORDS;
@@ -1149,64 +1401,62 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
         if (to_fb)
             a.fb_list[base + __popcll(fm & ((1ull << lane) - 1ull))] = (uint32_t)slot;
     }
-    if (!active || to_fb) return;
-    // results (also for non-finite queries: empty)
-    int cnt = 0;
-    int32_t* irow = a.ko.idx + s.qi * k;
-    float* drow = a.ko.d2 + s.qi * k;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        if (j >= pad) {
-            const unsigned long long key = kk[j];
-            const bool have = key != ~0ull;
-            irow[j - pad] = have ? (int32_t)(uint32_t)key : -1;
-            drow[j - pad] = have ? key_d2(key) : INF;
-            cnt += have ? 1 : 0;
-        }
-    }
-    a.ko.count[s.qi] = cnt;
-    if (FUSED) {
-        const float4* orig = T.orig;
-        CovOut c;
-        if (FUSED == 1)
-            covariance(s.x, s.y, s.z, cnt, [&](int j) { return orig[irow[j]]; }, a.eps, c);
-        else
-            covariance_weighted(s.x, s.y, s.z, cnt, [&](int j) { return orig[irow[j]]; }, a.wt,
-                                a.eps, c);
-        store_cov(a.co, s.qi, c);
-    }
+    // covariances of the written rows (after the rounds: the lists are dead)
+    if (FUSED && row_cnt >= 0) emit_cov<K, FUSED>(a, T, s.qi, s.x, s.y, s.z, k, row_cnt, s_pos);
+    // non-finite queries and queries against an empty target: empty results
+    if (active && (!fin || empty_tgt)) emit_empty<FUSED>(a, s.qi, k);
+}
+// PROF: record the per-group profile words (a.prof is set).
+// Dynamic LDS of the group search (32-bit words): each wave's chunk names;
+// the positions of the rows' neighbours (fused covariance; one wave emits
+// in a split group); in a split group the merge buffers (d2 bits and
+// positions), the shared k-th bounds and the lane flags.
+__host__ __device__ inline size_t group_lds_words(int K, int fused, int split, int waves) {
+    const size_t w = WAVE;
+    size_t n = (size_t)waves * MAX_CHUNKS;
+    if (fused) n += (size_t)(split > 1 ? 1 : waves) * K * w;
+    if (split > 1) n += 2 * (size_t)(split / 2) * K * w + 2 * (size_t)split * w;
+    return n;
 }
 
-// PROF: record the per-group profile words (a.prof is set).
 template <int K, int FUSED, bool PROF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 20 ? 4 : 2)))
 k_group(GroupArgs a) {
     const int wpb = blockDim.x / WAVE;
+    const int wid = threadIdx.x / WAVE;
     const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
-    const SplitShare none{nullptr, 0, 0};
+    extern __shared__ uint32_t s_dyn[];
+    uint32_t* s_tab = s_dyn + wid * MAX_CHUNKS;
+    uint32_t* s_free = s_dyn + wpb * MAX_CHUNKS;
+    uint32_t* s_pos = nullptr;
+    if (FUSED) {
+        s_pos = s_free + (a.split > 1 ? 0 : wid) * K * WAVE;
+        s_free += (a.split > 1 ? 1 : wpb) * K * WAVE;
+    }
+    const SplitShare none{nullptr, nullptr, nullptr, nullptr, 0, 0};
     if (a.split > 1) {
-        // one group per workgroup of `split` waves; dynamic LDS holds split / 2
-        // merge buffers and the shared k-th distances
-        extern __shared__ unsigned long long s_dyn[];
-        unsigned long long* s_kk = s_dyn;
-        float* s_thr = (float*)(s_kk + (a.split / 2) * K * WAVE);
+        // one group per workgroup of `split` waves
+        uint32_t* s_md = s_free;
+        uint32_t* s_mp = s_md + (a.split / 2) * K * WAVE;
+        float* s_thr = (float*)(s_mp + (a.split / 2) * K * WAVE);
+        uint32_t* s_flag = (uint32_t*)(s_thr + a.split * WAVE);
         s_thr[threadIdx.x] = a.sp.r2;
         __syncthreads();
-        const SplitShare sh{s_thr, (int)(threadIdx.x / WAVE), a.split - 1};
+        const SplitShare sh{s_thr, s_flag, s_md, s_mp, wid, a.split - 1};
         // Groups of separate queries: each XCD takes a contiguous range, so
         // its L2 holds that range's part of the target.  Self queries (the
         // target is one scan, a few MB): groups are dealt round-robin over
         // the XCDs, which spreads the dense regions' heavy groups.
         const int64_t g = a.queries ? (int64_t)xcd_tile(blockIdx.x, gridDim.x)
                                     : (int64_t)blockIdx.x;
-        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, sh, s_kk);
+        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, sh, s_tab, s_pos);
         return;
     }
     if (!a.counters) {
         // many groups: dealt round-robin over the XCDs, so that every XCD
         // gets a share of the dense regions
-        const int64_t g = (int64_t)blockIdx.x * wpb + threadIdx.x / WAVE;
-        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, none, nullptr);
+        const int64_t g = (int64_t)blockIdx.x * wpb + wid;
+        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, none, s_tab, s_pos);
         return;
     }
     // persistent: the groups are split into 8 contiguous ranges, one per XCD
@@ -1223,7 +1473,7 @@ k_group(GroupArgs a) {
             t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
             const int64_t g = g_lo + t;
             if (g >= g_hi) break;
-            group_body<K, FUSED, PROF>(a, g, none, nullptr);
+            group_body<K, FUSED, PROF>(a, g, none, s_tab, s_pos);
         }
     }
 }
@@ -1442,10 +1692,7 @@ int choose_k_tile(int k) {
 
 template <int FUSED>
 void launch_group(int K, dim3 grid, dim3 block, hipStream_t st, const GroupArgs& a) {
-    const size_t lds = a.split > 1 ? sizeof(unsigned long long) * (size_t)(a.split / 2) *
-                                             (size_t)K * WAVE +
-                                         sizeof(float) * (size_t)a.split * WAVE
-                                   : 0;
+    const size_t lds = sizeof(uint32_t) * group_lds_words(K, FUSED, a.split, (int)(block.x / WAVE));
     switch (K) {
         case 8:
             if (a.prof) hipLaunchKernelGGL((k_group<8, FUSED, true>), grid, block, lds, st, a);
