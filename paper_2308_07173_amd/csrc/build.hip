@@ -678,8 +678,10 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     // pts carries 64 spare records: the search loads whole aligned 64-record
     // chunks and may read up to 63 records past the last point
     const size_t pbytes = align256(sizeof(float4) * ((size_t)(n > 0 ? n : 1) + 64));
+    // run boxes carry 4 spare runs: the search loads the boxes of whole
+    // aligned 64-record chunks (4 runs)
     const int64_t n_chunks = (n + BOX_PTS - 1) / BOX_PTS;
-    const size_t bx_b = align256(2 * sizeof(float4) * (size_t)(n_chunks > 0 ? n_chunks : 1));
+    const size_t bx_b = align256(2 * sizeof(float4) * (size_t)(n_chunks + 4));
     if (t->point_bytes < 2 * pbytes + bx_b) {
         if (t->point_mem) {
             LKC_HIP_TRY(ctx, hipStreamSynchronize(st));

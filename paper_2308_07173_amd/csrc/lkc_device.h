@@ -75,6 +75,19 @@ __device__ __forceinline__ unsigned long long pack_key(const TargetView& T, int 
            ((unsigned long long)(uint32_t)(cz - T.cmin[2]) << T.sh_z);
 }
 
+// Loads through global-memory views of device pointers: global instructions
+// rather than flat ones (a flat load also counts against the LDS wait
+// counter, so waiting for an LDS result would wait for it too).
+typedef __attribute__((address_space(1))) const float gfloat;
+typedef __attribute__((address_space(1))) const uint32_t gu32;
+
+__device__ __forceinline__ float4 gload(const float4* p) {
+    gfloat* q = (gfloat*)p;
+    return make_float4(q[0], q[1], q[2], q[3]);
+}
+__device__ __forceinline__ float gload(const float* p) { return *(gfloat*)p; }
+__device__ __forceinline__ uint32_t gload(const uint32_t* p) { return *(gu32*)p; }
+
 __device__ __forceinline__ uint32_t hash_slot(unsigned long long key, int bits) {
     return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - bits));
 }
@@ -84,13 +97,14 @@ __device__ __forceinline__ bool hash_find(const TargetView& T, unsigned long lon
                                           uint32_t& start, uint32_t& count) {
     uint32_t s = hash_slot(key, T.hash_bits);
     for (;;) {
-        const HashSlot h = T.hash[s];
-        if (h.key == key) {
-            start = h.start;
-            count = h.count;
+        gu32* h = (gu32*)(T.hash + s);
+        const unsigned long long hk = (unsigned long long)h[0] | ((unsigned long long)h[1] << 32);
+        if (hk == key) {
+            start = h[2];
+            count = h[3];
             return true;
         }
-        if (h.key == EMPTY_KEY) return false;
+        if (hk == EMPTY_KEY) return false;
         s = (s + 1) & T.hash_mask;
     }
 }

@@ -165,7 +165,7 @@ __device__ __forceinline__ void scan_cells(const TargetView& T, float qx, float 
         float d = INF;
         int32_t oi = IDX_SENTINEL;
         if (valid) {
-            const float4 t = T.pts[src];
+            const float4 t = gload(T.pts + src);
             d = dist2(qx, qy, qz, t.x, t.y, t.z);
             oi = __float_as_int(t.w);
         }
@@ -702,8 +702,10 @@ __device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, floa
 // then insertions from the group's own chunk (self queries); then the lanes
 // handed on because their decoded entries stayed out of order or tied, because
 // the last entry shared the k-th distance's bucket, or because the wave ran
-// out of chunk names
-constexpr int PROF_WORDS = 20;
+// out of chunk names; then clock cycles of the first wavefront in the
+// streaming (probes and chunks), in decoding and merging the lists, and in
+// the covariances
+constexpr int PROF_WORDS = 23;
 // A profile counter that compiles away in the unprofiled kernels (their
 // counters are never read, so the arithmetic feeding them is dead).
 template <bool ON>
@@ -727,6 +729,7 @@ struct GroupProf {
     ProfCount<ON> probes, cells, chunks, cands, pops, inserts, dead;
     ProfCount<ON> ins0, ins1, ins2, cand0, cand1, cand2, own;
     ProfCount<ON> amb_order, amb_bucket, amb_names;
+    ProfCount<ON> t_walk, t_final, t_cov;
 };
 
 struct SlotQuery {
@@ -739,12 +742,12 @@ __device__ __forceinline__ SlotQuery load_slot(const GroupArgs& a, const TargetV
     SlotQuery s;
     s.tgt = a.skeys ? (int)(a.skeys[slot] >> a.tshift) : 0;
     if (a.queries) {
-        s.qi = a.order ? (int64_t)a.order[slot] : slot;
-        s.x = a.queries[3 * s.qi];
-        s.y = a.queries[3 * s.qi + 1];
-        s.z = a.queries[3 * s.qi + 2];
+        s.qi = a.order ? (int64_t)gload(a.order + slot) : slot;
+        s.x = gload(a.queries + 3 * s.qi);
+        s.y = gload(a.queries + 3 * s.qi + 1);
+        s.z = gload(a.queries + 3 * s.qi + 2);
     } else {
-        const float4 p = T.pts[slot];
+        const float4 p = gload(T.pts + slot);
         s.qi = __float_as_int(p.w);
         s.x = p.x;
         s.y = p.y;
@@ -849,8 +852,7 @@ __device__ __forceinline__ void sort_u32(uint32_t (&L)[N]) {
 // them, and modes 1-2 skip a 16-point run whose box is farther from the
 // query box than the radius or the group's largest k-th bound.  A kept chunk
 // is named (its ordinal in this wave's stream, recorded in s_tab; fixed_ord
-// names a chunk the caller registered) and loaded once (lane t holds point
-// t, one coalesced read); each candidate is broadcast from its lane and
+// names a chunk the caller registered); each candidate is broadcast from its lane and
 // tested by every lane, which only sets a bit per passing candidate; the
 // insertions follow as "pops" in which every lane inserts its own next
 // passing candidate, so a chunk costs as many insertion steps as its busiest
@@ -869,6 +871,15 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
     for (int cb = s0 & ~(WAVE - 1); cb < e0; cb += WAVE) {
         if (cb == skip_cb) continue;   // streamed first, as the group's own chunk
         if (((cb / WAVE) & sh.split_mask) != sh.sub) continue;   // the other wave's chunk
+        // the chunk's load goes out with its boxes' (lane t holds point t,
+        // one coalesced read; padded: reads past n stay in bounds)
+        const float4 c = gload(T.pts + cb + lane);
+        // and so do the boxes of its four runs (one scalar burst; the boxes
+        // carry 4 spare runs)
+        float4 bb[2 * (WAVE / BOX_PTS)];
+#pragma unroll
+        for (int i = 0; i < 2 * (WAVE / BOX_PTS); ++i)
+            bb[i] = load_uniform(T.boxes + 2 * (cb / BOX_PTS) + i);
         uint32_t keep = 0;
         float lthr = pk_bound<K>(L, r2, lcap);
         if (sh.split_mask) lthr = shared_thr(sh, lane, lthr);
@@ -876,8 +887,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
             const int sb = cb + q4 * BOX_PTS;
             if (sb + BOX_PTS <= s0 || sb >= e0) continue;
-            const float4 blo = load_uniform(T.boxes + 2 * (sb / BOX_PTS));
-            const float4 bhi = load_uniform(T.boxes + 2 * (sb / BOX_PTS) + 1);
+            const float4 blo = bb[2 * q4], bhi = bb[2 * q4 + 1];
             const float bd =
                 box_box_dist2(b0, b1, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, margin);
             const bool near = bd <= r2 && bd * (1.0f - 1e-6f) <= gthr;
@@ -902,7 +912,6 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             if (lane == 0) s_tab[ord] = (uint32_t)(cb / WAVE);
         }
         gp.chunks++;
-        const float4 c = T.pts[cb + lane];   // padded: reads past n stay in bounds
         // non-members never pass (d2 >= 0)
         const float tthr = member ? lthr : -1.0f;
         uint32_t blo = 0, bhi = 0;
@@ -978,7 +987,7 @@ __device__ __forceinline__ int emit_row(const GroupArgs& a, const TargetView& T,
         if (P[j] != ~0u) {   // not a pad
             const bool have = D[j] != ~0u;
             dp[j] = have ? __uint_as_float(D[j]) : INF;
-            if (!FUSED) ip[j] = have ? __float_as_int(T.pts[P[j]].w) : -1;
+            if (!FUSED) ip[j] = have ? __float_as_int(gload(T.pts + P[j]).w) : -1;
             if (FUSED && !have) ip[j] = -1;
             cnt += have ? 1 : 0;
         }
@@ -990,26 +999,31 @@ __device__ __forceinline__ int emit_row(const GroupArgs& a, const TargetView& T,
 
 // The covariance of a written row: its first cnt neighbours, gathered from
 // the reordered points (the copy the search has just streamed through the
-// caches; the same values as the caller-order copy) by the positions in
-// s_pos, writing each neighbour's index into the row on the way.
-template <int K, int FUSED>
-__device__ __forceinline__ void emit_cov(const GroupArgs& a, const TargetView& T, int64_t qi,
-                                         float qx, float qy, float qz, int k, int cnt,
-                                         const uint32_t* s_pos) {
-    const float4* pts = T.pts;
-    const uint32_t* sp = s_pos + (K - k) * WAVE + lane_id();
-    int32_t* irow = a.ko.idx + qi * k;
-    const auto fetch = [&](int j) {
-        const float4 t = pts[sp[j * WAVE]];
-        irow[j] = __float_as_int(t.w);
-        return t;
-    };
+// caches; the same values as the caller-order copy) by the positions in sp
+// (column c at sp[c * 64], LDS), then the row's indices.  Restrict-qualified
+// so that the gathers of a pass can all be in flight together.
+template <int FUSED>
+__device__ __forceinline__ void cov_gather(const float4* __restrict__ pts,
+                                           const uint32_t* __restrict__ sp,
+                                           int32_t* __restrict__ irow, const GroupArgs& a,
+                                           int64_t qi, float qx, float qy, float qz, int cnt) {
+    const auto fetch = [&](int j) { return gload(pts + sp[j * WAVE]); };
     CovOut c;
     if (FUSED == 1)
         covariance(qx, qy, qz, cnt, fetch, a.eps, c);
     else
         covariance_weighted(qx, qy, qz, cnt, fetch, a.wt, a.eps, c);
     store_cov(a.co, qi, c);
+#pragma unroll 4
+    for (int j = 0; j < cnt; ++j) irow[j] = __float_as_int(gload(pts + sp[j * WAVE]).w);
+}
+
+template <int K, int FUSED>
+__device__ __forceinline__ void emit_cov(const GroupArgs& a, const TargetView& T, int64_t qi,
+                                         float qx, float qy, float qz, int k, int cnt,
+                                         const uint32_t* s_pos) {
+    cov_gather<FUSED>(T.pts, s_pos + (K - k) * WAVE + lane_id(), a.ko.idx + qi * k, a, qi, qx,
+                      qy, qz, cnt);
 }
 
 // An empty result row (non-finite query, empty target).
@@ -1029,7 +1043,7 @@ __device__ __forceinline__ void emit_empty(const GroupArgs& a, int64_t qi, int k
 }
 
 template <int K, int FUSED, bool PROF>
-__device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& sh,
+__device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& sh,
                            uint32_t* s_tab, uint32_t* s_pos) {
     constexpr int KP = K + SLACK;
     const int lane = lane_id();
@@ -1154,6 +1168,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
 #pragma unroll 1
         for (int j = 0; j < pad; ++j) pk_insert<KP>(L, 0u);
         int n_ch = 1;
+        const unsigned long long t_round = PROF ? __builtin_amdgcn_s_memtime() : 0ull;
         // Self queries: the group's 64 slots are 64 consecutive points of
         // the target's Morton order, i.e. the queries themselves and each
         // other's nearest points; streaming that chunk first fills every
@@ -1250,6 +1265,7 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
                 }
             }
         }
+        const unsigned long long t_dec = PROF ? __builtin_amdgcn_s_memtime() : 0ull;
         // Decode every entry to its exact d2 bits (in place) and its
         // position in the reordered points (pads get position ~0u).  The
         // packed order is the exact order except inside a bucket, which
@@ -1268,11 +1284,11 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             if (member && e != 0u && e != ~0u) {
                 const uint32_t id = e & ID_MASK;
                 pos = s_tab[id >> 6] * (uint32_t)WAVE + (id & 63u);
-                const float4 p = T.pts[pos];
+                const float4 p = gload(T.pts + pos);
                 L[j] = __float_as_uint(dist2(s.x, s.y, s.z, p.x, p.y, p.z));
             }
             P[j] = pos;
-            if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bounded loads in flight
+            if ((j % 12) == 11) __builtin_amdgcn_sched_barrier(0);   // bounded loads in flight
         }
         const auto cmpx_p = [&](int j) {
             const uint32_t d0 = L[j - 1], d1 = L[j], p0 = P[j - 1], p1 = P[j];
@@ -1349,6 +1365,11 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             for (int w = 0; w <= sh.split_mask; ++w) amb = amb || sh.flag[w * WAVE + lane] != 0u;
             __syncthreads();   // the flags are rewritten next round
         }
+        if (PROF) {
+            const unsigned long long t_now = __builtin_amdgcn_s_memtime();
+            gp.t_walk += (uint32_t)(t_dec - t_round);
+            gp.t_final += (uint32_t)(t_now - t_dec);
+        }
         if (member) {
             // exactness: every point outside the (unclamped) block is at least f away
             bool covers = true;
@@ -1402,7 +1423,14 @@ __device__ void group_body(const GroupArgs& a, int64_t group, const SplitShare& 
             a.fb_list[base + __popcll(fm & ((1ull << lane) - 1ull))] = (uint32_t)slot;
     }
     // covariances of the written rows (after the rounds: the lists are dead)
+    const unsigned long long t_cov0 = PROF ? __builtin_amdgcn_s_memtime() : 0ull;
     if (FUSED && row_cnt >= 0) emit_cov<K, FUSED>(a, T, s.qi, s.x, s.y, s.z, k, row_cnt, s_pos);
+    if (PROF && lane == 0 && sh.sub == 0) {
+        uint32_t* pw = a.prof + group * PROF_WORDS;
+        pw[20] = gp.t_walk;
+        pw[21] = gp.t_final;
+        pw[22] = (uint32_t)(__builtin_amdgcn_s_memtime() - t_cov0);
+    }
     // non-finite queries and queries against an empty target: empty results
     if (active && (!fin || empty_tgt)) emit_empty<FUSED>(a, s.qi, k);
 }
@@ -1433,7 +1461,11 @@ k_group(GroupArgs a) {
         s_pos = s_free + (a.split > 1 ? 0 : wid) * K * WAVE;
         s_free += (a.split > 1 ? 1 : wpb) * K * WAVE;
     }
-    const SplitShare none{nullptr, nullptr, nullptr, nullptr, 0, 0};
+    // One call site, so that the body is inlined: its arguments then stay
+    // in scalar registers (a called function takes them in vector registers
+    // and reaches the kernel arguments through a stack copy).
+    SplitShare sh{nullptr, nullptr, nullptr, nullptr, 0, 0};
+    int64_t g;
     if (a.split > 1) {
         // one group per workgroup of `split` waves
         uint32_t* s_md = s_free;
@@ -1442,39 +1474,43 @@ k_group(GroupArgs a) {
         uint32_t* s_flag = (uint32_t*)(s_thr + a.split * WAVE);
         s_thr[threadIdx.x] = a.sp.r2;
         __syncthreads();
-        const SplitShare sh{s_thr, s_flag, s_md, s_mp, wid, a.split - 1};
+        sh = SplitShare{s_thr, s_flag, s_md, s_mp, wid, a.split - 1};
         // Groups of separate queries: each XCD takes a contiguous range, so
         // its L2 holds that range's part of the target.  Self queries (the
         // target is one scan, a few MB): groups are dealt round-robin over
         // the XCDs, which spreads the dense regions' heavy groups.
-        const int64_t g = a.queries ? (int64_t)xcd_tile(blockIdx.x, gridDim.x)
-                                    : (int64_t)blockIdx.x;
-        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, sh, s_tab, s_pos);
-        return;
-    }
-    if (!a.counters) {
+        g = a.queries ? (int64_t)xcd_tile(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    } else {
         // many groups: dealt round-robin over the XCDs, so that every XCD
         // gets a share of the dense regions
-        const int64_t g = (int64_t)blockIdx.x * wpb + wid;
-        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, none, s_tab, s_pos);
-        return;
+        g = (int64_t)blockIdx.x * wpb + wid;
     }
     // persistent: the groups are split into 8 contiguous ranges, one per XCD
     // (workgroups are dealt round-robin over the XCDs); a wave drains its own
     // XCD's range, then helps the others
+    const bool persist = a.split <= 1 && a.counters != nullptr;
     const int lane = lane_id();
     const int x0 = blockIdx.x % 8;
-    for (int s = 0; s < 8; ++s) {
-        const int x = (x0 + s) % 8;
-        const int64_t g_lo = n_groups * x / 8, g_hi = n_groups * (x + 1) / 8;
-        for (;;) {
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(&a.counters[x], 1u);
-            t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
-            const int64_t g = g_lo + t;
-            if (g >= g_hi) break;
-            group_body<K, FUSED, PROF>(a, g, none, s_tab, s_pos);
+    int xs = 0;
+    for (;;) {
+        if (persist) {
+            g = -1;
+            while (xs < 8) {
+                const int x = (x0 + xs) % 8;
+                const int64_t g_lo = n_groups * x / 8, g_hi = n_groups * (x + 1) / 8;
+                uint32_t t = 0;
+                if (lane == 0) t = atomicAdd(&a.counters[x], 1u);
+                t = (uint32_t)__builtin_amdgcn_readfirstlane((int)t);
+                if (g_lo + (int64_t)t < g_hi) {
+                    g = g_lo + t;
+                    break;
+                }
+                ++xs;
+            }
+            if (g < 0) break;
         }
+        if (g < n_groups) group_body<K, FUSED, PROF>(a, g, sh, s_tab, s_pos);
+        if (!persist) break;
     }
 }
 
@@ -1507,7 +1543,7 @@ __global__ void __launch_bounds__(256) k_fallback(GroupArgs a) {
             // position is read from lane j); lane 0 stores it
             const float4* pts = T.pts;
             CovOut c;
-            const auto fetch = [&](int j) { return pts[readlane(L.p, j)]; };
+            const auto fetch = [&](int j) { return gload(pts + readlane(L.p, j)); };
             if (FUSED == 1)
                 covariance(s.x, s.y, s.z, cnt, fetch, a.eps, c);
             else
