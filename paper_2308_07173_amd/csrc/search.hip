@@ -28,8 +28,8 @@
 // bits.
 //
 // Covariance -- two passes over the neighbours relative to the query point
-// (centred, 1/n), then a float32 cyclic Jacobi eigen-decomposition of the
-// 3x3 for the GICP plane regulariser; fused into both searches (one lane
+// (centred, 1/n), then the smallest eigenvector of the 3x3 in closed form
+// (float32) for the GICP plane regulariser; fused into both searches (one lane
 // per query in the group search, the whole wavefront in the other) and
 // standalone in k_cov.
 #include <cmath>
@@ -340,59 +340,116 @@ struct CovOut {
     bool valid;
 };
 
-template <int P, int Q>
-__device__ __forceinline__ void jacobi_rotate(float (&a)[3][3], float (&v)[3][3]) {
-    const float apq = a[P][Q];
-    if (apq == 0.0f) return;
-    const float tau = (a[Q][Q] - a[P][P]) / (2.0f * apq);
-    const float t = (tau >= 0.0f) ? 1.0f / (tau + sqrtf(1.0f + tau * tau))
-                                  : -1.0f / (-tau + sqrtf(1.0f + tau * tau));
-    const float c = 1.0f / sqrtf(1.0f + t * t);
-    const float s = t * c;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const float arp = a[r][P], arq = a[r][Q];
-        a[r][P] = c * arp - s * arq;
-        a[r][Q] = s * arp + c * arq;
+// Unit eigenvector of the smallest eigenvalue of a symmetric 3x3 C (xx xy
+// xz yy yz zz), by the closed form of its characteristic cubic (O. K. Smith,
+// "Eigenvalues of a symmetric 3x3 matrix", CACM 4(4), 1961): with
+// q = tr C / 3 and p^2 = |C - qI|_F^2 / 6, the eigenvalues are
+// q + 2p cos(phi + 2 pi j / 3), phi = acos(det((C - qI) / p) / 2) / 3, and
+// j = 1 gives the smallest, lambda.  Its eigenvector is the largest cross
+// product of two rows of C - lambda I; the Rayleigh quotient of that vector
+// refines lambda (acos loses digits when two eigenvalues are close) and the
+// cross product is taken once more.  When lambda is (nearly) repeated, the
+// rows of C - lambda I are (nearly) parallel to the other eigenvector and
+// any vector orthogonal to the largest row spans the smallest eigenvalues'
+// plane; C = qI (or 0) gives x.  No iteration: every lane runs the same
+// instructions.  C is first scaled by a power of two (exactly) so that its
+// largest entry lies in [1, 2).
+__device__ __forceinline__ void eig_cross(const float (&c)[6], float lam, float (&e)[3],
+                                          float& best, float& nrow) {
+    const float m0[3] = {c[0] - lam, c[1], c[2]}, m1[3] = {c[1], c[3] - lam, c[4]},
+                m2[3] = {c[2], c[4], c[5] - lam};
+    const auto cross = [](const float (&u)[3], const float (&w)[3], float (&o)[3]) {
+        o[0] = u[1] * w[2] - u[2] * w[1];
+        o[1] = u[2] * w[0] - u[0] * w[2];
+        o[2] = u[0] * w[1] - u[1] * w[0];
+    };
+    const auto norm2 = [](const float (&u)[3]) { return u[0] * u[0] + u[1] * u[1] + u[2] * u[2]; };
+    float t[3];
+    cross(m0, m1, e);
+    best = norm2(e);
+    cross(m0, m2, t);
+    float nt = norm2(t);
+    if (nt > best) {
+        best = nt;
+        e[0] = t[0]; e[1] = t[1]; e[2] = t[2];
     }
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const float apc = a[P][r], aqc = a[Q][r];
-        a[P][r] = c * apc - s * aqc;
-        a[Q][r] = s * apc + c * aqc;
+    cross(m1, m2, t);
+    nt = norm2(t);
+    if (nt > best) {
+        best = nt;
+        e[0] = t[0]; e[1] = t[1]; e[2] = t[2];
     }
-    a[P][Q] = 0.0f;
-    a[Q][P] = 0.0f;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        const float vrp = v[r][P], vrq = v[r][Q];
-        v[r][P] = c * vrp - s * vrq;
-        v[r][Q] = s * vrp + c * vrq;
+    // the largest row
+    const float n0 = norm2(m0), n1 = norm2(m1), n2 = norm2(m2);
+    const float* rr = m0;
+    nrow = n0;
+    if (n1 > nrow) { nrow = n1; rr = m1; }
+    if (n2 > nrow) { nrow = n2; rr = m2; }
+    // rows (nearly) parallel: orthogonal to the largest row, through the
+    // axis it has least of
+    if (!(best > 1e-6f * nrow * nrow)) {
+        if (nrow > 0.0f) {
+            const float ax = fabsf(rr[0]), ay = fabsf(rr[1]), az = fabsf(rr[2]);
+            const int k = (ax <= ay && ax <= az) ? 0 : (ay <= az ? 1 : 2);
+            const float ek[3] = {k == 0 ? 1.0f : 0.0f, k == 1 ? 1.0f : 0.0f, k == 2 ? 1.0f : 0.0f};
+            const float r3[3] = {rr[0], rr[1], rr[2]};
+            cross(r3, ek, e);
+            best = norm2(e);
+        } else {
+            e[0] = 1.0f; e[1] = 0.0f; e[2] = 0.0f;
+            best = 1.0f;
+        }
+        nrow = -1.0f;   // degenerate: no refinement
     }
 }
 
-// Unit eigenvector of the smallest eigenvalue of a symmetric 3x3 (float32
-// cyclic Jacobi, Golub & Van Loan Sec. 8.5).
-__device__ __forceinline__ void smallest_eigvec(const float (&c)[6], float (&v0)[3]) {
-    float a[3][3] = {{c[0], c[1], c[2]}, {c[1], c[3], c[4]}, {c[2], c[4], c[5]}};
-    float v[3][3] = {{1.f, 0.f, 0.f}, {0.f, 1.f, 0.f}, {0.f, 0.f, 1.f}};
-    for (int sweep = 0; sweep < 16; ++sweep) {
-        const float off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
-        const float dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
-        if (!(off > 1e-16f * dia)) break;
-        jacobi_rotate<0, 1>(a, v);
-        jacobi_rotate<0, 2>(a, v);
-        jacobi_rotate<1, 2>(a, v);
+__device__ __forceinline__ void smallest_eigvec(const float (&cin)[6], float (&v0)[3]) {
+    // scaled by a power of two (exact) to bring the largest entry to [1, 2):
+    // the eigenvectors are unchanged and tiny covariances do not underflow
+    float mx = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) mx = fmaxf(mx, fabsf(cin[i]));
+    if (!(mx > 0.0f)) {
+        v0[0] = 1.0f;
+        v0[1] = 0.0f;
+        v0[2] = 0.0f;
+        return;
     }
-    int m = 0;
-    if (a[1][1] < a[m][m]) m = 1;
-    if (a[2][2] < a[m][m]) m = 2;
-    const float x = (m == 0) ? v[0][0] : (m == 1) ? v[0][1] : v[0][2];
-    const float y = (m == 0) ? v[1][0] : (m == 1) ? v[1][1] : v[1][2];
-    const float z = (m == 0) ? v[2][0] : (m == 1) ? v[2][1] : v[2][2];
-    v0[0] = x;
-    v0[1] = y;
-    v0[2] = z;
+    const float sc = __int_as_float((254 - ((__float_as_int(mx) >> 23) & 0xff)) << 23);
+    float c[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) c[i] = cin[i] * sc;
+    const float xx = c[0], xy = c[1], xz = c[2], yy = c[3], yz = c[4], zz = c[5];
+    const float q = (xx + yy + zz) * (1.0f / 3.0f);
+    const float d0 = xx - q, d1 = yy - q, d2 = zz - q;
+    const float p1 = xy * xy + xz * xz + yz * yz;
+    const float p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0f * p1;
+    float lam = q;
+    if (p2 > 0.0f) {
+        const float p = sqrtf(p2 * (1.0f / 6.0f));
+        const float ip = 1.0f / p;
+        const float b00 = d0 * ip, b11 = d1 * ip, b22 = d2 * ip;
+        const float b01 = xy * ip, b02 = xz * ip, b12 = yz * ip;
+        const float det = b00 * (b11 * b22 - b12 * b12) - b01 * (b01 * b22 - b12 * b02) +
+                          b02 * (b01 * b12 - b11 * b02);
+        const float r = fminf(fmaxf(0.5f * det, -1.0f), 1.0f);
+        const float phi = acosf(r) * (1.0f / 3.0f);
+        lam = q + 2.0f * p * cosf(phi + 2.09439510239319549f);   // + 2 pi / 3
+    }
+    float e[3], best, nrow;
+    eig_cross(c, lam, e, best, nrow);
+    if (nrow > 0.0f) {
+        // Rayleigh quotient of e, then the cross product again
+        const float ce0 = xx * e[0] + xy * e[1] + xz * e[2];
+        const float ce1 = xy * e[0] + yy * e[1] + yz * e[2];
+        const float ce2 = xz * e[0] + yz * e[1] + zz * e[2];
+        lam = (e[0] * ce0 + e[1] * ce1 + e[2] * ce2) / best;
+        eig_cross(c, lam, e, best, nrow);
+    }
+    const float inv = 1.0f / sqrtf(best);
+    v0[0] = e[0] * inv;
+    v0[1] = e[1] * inv;
+    v0[2] = e[2] * inv;
 }
 
 __device__ __forceinline__ void cov_empty(CovOut& out) {
