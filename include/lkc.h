@@ -227,6 +227,25 @@ lkc_status lkc_knn_cov(lkc_ctx *ctx, const lkc_target *target, const float *quer
                        int32_t *count, float *mean, float *cov, float *reg_cov, uint8_t *valid,
                        const lkc_launch_cfg *cfg);
 
+/* lkc_knn_cov for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bit for bit) as lkc_knn_cov, but the
+ * search scratch (sort keys and values, radix counts, work words, fallback
+ * list) lives in a static device array of 4 MiB that each device holds
+ * until the process ends, so the call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine) and the per-group profile
+ * (lkc_ctx_set_profile) is off.  q <= 131,072 (a full 128 x 1024 scan);
+ * larger q fails with LKC_ERR_BUDGET and enqueues nothing.  The array's
+ * address on a device is looked up once (at lkc_ctx_create, else at the
+ * first call on that device).  Every call on one device shares that
+ * device's array and starts by resetting what must start at zero: calls
+ * that overlap on one device (two streams, two contexts, two host threads)
+ * race, so serialise them. */
+lkc_status lkc_knn_cov_noalloc(lkc_ctx *ctx, const lkc_target *target, const float *queries,
+                               int64_t q, int32_t k, float radius, float plane_eps, int32_t *idx,
+                               float *d2, int32_t *count, float *mean, float *cov,
+                               float *reg_cov, uint8_t *valid, const lkc_launch_cfg *cfg);
+
 /* Kernel-descriptor weighted covariance (the paper's table of kernel
  * descriptors, Sec. III-C.1, which uses them as similarity measures in the
  * GPU covariance estimate and finds the Laplacian best).  Neighbour j of a

@@ -101,6 +101,9 @@ lkc_status lkc_ctx_create(void* hip_stream, lkc_ctx** out) {
         delete c;
         return set_error(nullptr, LKC_ERR_OOM, "context buffers");
     }
+    // the allocation-free search's scratch address on this device (looked
+    // up again by lkc_knn_cov_noalloc if this fails)
+    (void)lkc::noalloc_init(c);
     *out = c;
     return LKC_OK;
 }
@@ -276,6 +279,22 @@ lkc_status lkc_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* queries, 
         return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
     return lkc::launch_knn_cov(ctx, t, queries, q, k, radius, plane_eps, idx, d2, count, mean,
                                cov, reg_cov, valid, lkc::resolve_cfg(cfg));
+}
+
+lkc_status lkc_knn_cov_noalloc(lkc_ctx* ctx, const lkc_target* t, const float* queries,
+                               int64_t q, int32_t k, float radius, float plane_eps, int32_t* idx,
+                               float* d2, int32_t* count, float* mean, float* cov,
+                               float* reg_cov, uint8_t* valid, const lkc_launch_cfg* cfg) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if ((s = check_k_radius(ctx, k, radius)) != LKC_OK) return s;
+    if ((s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
+    if (q < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "q < 0");
+    if (q > 0 && (!queries || !idx || !d2 || !count || !valid))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL query or output pointer");
+    return lkc::launch_knn_cov_noalloc(ctx, t, queries, q, k, radius, plane_eps, idx, d2, count,
+                                       mean, cov, reg_cov, valid, lkc::resolve_cfg(cfg));
 }
 
 namespace {

@@ -157,6 +157,14 @@ lkc_status launch_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* querie
                           int32_t k, float radius, float eps, int32_t* idx, float* d2,
                           int32_t* count, float* mean, float* cov, float* reg, uint8_t* valid,
                           const LaunchCfg& cfg, const CovWeight& wt = CovWeight{0, 0.0f});
+// The allocation-free variant of launch_knn_cov: scratch from a static
+// device array (at most 131,072 queries); noalloc_init looks up its address
+// on the context's device, once per device.
+lkc_status noalloc_init(lkc_ctx* ctx);
+lkc_status launch_knn_cov_noalloc(lkc_ctx* ctx, const lkc_target* t, const float* queries,
+                                  int64_t q, int32_t k, float radius, float eps, int32_t* idx,
+                                  float* d2, int32_t* count, float* mean, float* cov,
+                                  float* reg, uint8_t* valid, const LaunchCfg& cfg);
 // implemented in gicp.hip
 struct GicpScratch {
     float* queries;

@@ -33,6 +33,7 @@
 // per query in the group search, the whole wavefront in the other) and
 // standalone in k_cov.
 #include <cmath>
+#include <mutex>
 
 #include "lkc_internal.h"
 
@@ -1736,18 +1737,45 @@ struct Scratch {
     uint32_t *va, *vb, *counts, *words, *fb_list;
 };
 
-lkc_status search_scratch(lkc_ctx* ctx, int64_t n, Scratch& s) {
+// Offsets of the search scratch of n queries: sort keys and values (two
+// buffers each), radix counts, work words, fallback list.
+struct ScratchLayout {
+    size_t ka, kb, va, vb, counts, words, fb, bytes;
+};
+
+ScratchLayout scratch_layout(int64_t n) {
     const size_t nn = (size_t)(n > 0 ? n : 1);
+    ScratchLayout L{};
     size_t off = 0;
     auto carve = [&](size_t b) {
         const size_t o = off;
         off += align256(b);
         return o;
     };
-    const size_t o_ka = carve(8 * nn), o_kb = carve(8 * nn), o_va = carve(4 * nn),
-                 o_vb = carve(4 * nn), o_c = carve(4 * sort_count_words(n)), o_w = carve(256),
-                 o_fb = carve(4 * nn);
-    if (ctx->search_scratch_bytes < off) {
+    L.ka = carve(8 * nn);
+    L.kb = carve(8 * nn);
+    L.va = carve(4 * nn);
+    L.vb = carve(4 * nn);
+    L.counts = carve(4 * sort_count_words(n));
+    L.words = carve(256);
+    L.fb = carve(4 * nn);
+    L.bytes = off;
+    return L;
+}
+
+void carve_scratch(char* b, const ScratchLayout& L, Scratch& s) {
+    s.ka = (unsigned long long*)(b + L.ka);
+    s.kb = (unsigned long long*)(b + L.kb);
+    s.va = (uint32_t*)(b + L.va);
+    s.vb = (uint32_t*)(b + L.vb);
+    s.counts = (uint32_t*)(b + L.counts);
+    s.words = (uint32_t*)(b + L.words);
+    s.fb_list = (uint32_t*)(b + L.fb);
+}
+
+lkc_status search_scratch(lkc_ctx* ctx, int64_t n, Scratch& s) {
+    const ScratchLayout L = scratch_layout(n);
+    if (ctx->search_scratch_bytes < L.bytes) {
         if (ctx->search_scratch) {
             LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
             (void)hipFree(ctx->search_scratch);
@@ -1755,7 +1783,7 @@ lkc_status search_scratch(lkc_ctx* ctx, int64_t n, Scratch& s) {
             ctx->search_scratch_bytes = 0;
             ctx->last_fallback_count = nullptr;
         }
-        const size_t bytes = off + off / 4;   // headroom for slightly larger calls
+        const size_t bytes = L.bytes + L.bytes / 4;   // headroom for slightly larger calls
         hipError_t e = hipMalloc(&ctx->search_scratch, bytes);
         if (e != hipSuccess) {
             ctx->search_scratch = nullptr;
@@ -1764,16 +1792,23 @@ lkc_status search_scratch(lkc_ctx* ctx, int64_t n, Scratch& s) {
         }
         ctx->search_scratch_bytes = bytes;
     }
-    char* b = (char*)ctx->search_scratch;
-    s.ka = (unsigned long long*)(b + o_ka);
-    s.kb = (unsigned long long*)(b + o_kb);
-    s.va = (uint32_t*)(b + o_va);
-    s.vb = (uint32_t*)(b + o_vb);
-    s.counts = (uint32_t*)(b + o_c);
-    s.words = (uint32_t*)(b + o_w);
-    s.fb_list = (uint32_t*)(b + o_fb);
+    carve_scratch((char*)ctx->search_scratch, L, s);
     return LKC_OK;
 }
+
+// The allocation-free search (lkc_knn_cov_noalloc) keeps its scratch -- the
+// sort keys and values, radix counts, work words and fallback list of up to
+// NOALLOC_MAX_QUERIES queries -- in this file-scope device array.  Each
+// device holds its own copy until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device
+// (the array's name is no device address on the host).
+constexpr int64_t NOALLOC_MAX_QUERIES = 131072;
+constexpr size_t NOALLOC_BYTES = size_t(4) << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
 
 int choose_k_tile(int k) {
     if (k <= 8) return 8;
@@ -1823,11 +1858,18 @@ struct SearchJob {
     CovWeight wt;
 };
 
-lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
+// `fixed`: scratch the caller provides (then nothing is allocated and the
+// per-group profile is off).
+lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg,
+                      const Scratch* fixed = nullptr) {
     if (j.n_slots == 0) return LKC_OK;
     hipStream_t st = ctx->stream;
     Scratch sc;
-    lkc_status s = search_scratch(ctx, j.n_slots, sc);
+    lkc_status s = LKC_OK;
+    if (fixed)
+        sc = *fixed;
+    else
+        s = search_scratch(ctx, j.n_slots, sc);
     if (s != LKC_OK) return s;
     GroupArgs a{};
     a.views = j.views_dev;
@@ -1849,7 +1891,7 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg) {
     a.fb_list = sc.fb_list;
     a.fb_count = sc.words;
     a.counters = nullptr;
-    a.prof = (ctx->prof_buf && (j.n_slots + WAVE - 1) / WAVE <= ctx->prof_groups)
+    a.prof = (!fixed && ctx->prof_buf && (j.n_slots + WAVE - 1) / WAVE <= ctx->prof_groups)
                  ? (uint32_t*)ctx->prof_buf : nullptr;
     if (a.prof)
         LKC_HIP_TRY(ctx, hipMemsetAsync(a.prof, 0,
@@ -2027,6 +2069,49 @@ lkc_status launch_knn_cov(lkc_ctx* ctx, const lkc_target* t, const float* querie
     SearchJob j{t->view_dev, &t->view, 1, queries, q, nullptr, nullptr, k, radius, eps,
                 mode, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}, wt};
     return run_search(ctx, j, cfg);
+}
+
+lkc_status noalloc_init(lkc_ctx* ctx) {
+    const int dev = ctx->device;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return set_error(ctx, LKC_ERR_UNSUPPORTED, "device %d beyond the %d the library serves",
+                         dev, NOALLOC_MAX_DEVICES);
+    if (scratch_layout(NOALLOC_MAX_QUERIES).bytes > NOALLOC_BYTES)
+        return set_error(ctx, LKC_ERR_UNSUPPORTED, "allocation-free scratch layout too large");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[dev]) return LKC_OK;
+    int cur = -1;
+    LKC_HIP_TRY(ctx, hipGetDevice(&cur));
+    if (cur != dev) LKC_HIP_TRY(ctx, hipSetDevice(dev));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return hip_error(ctx, e, "hipGetSymbolAddress(scratch)");
+    g_noalloc_ptr[dev] = p;
+    return LKC_OK;
+}
+
+lkc_status launch_knn_cov_noalloc(lkc_ctx* ctx, const lkc_target* t, const float* queries,
+                                  int64_t q, int32_t k, float radius, float eps, int32_t* idx,
+                                  float* d2, int32_t* count, float* mean, float* cov,
+                                  float* reg, uint8_t* valid, const LaunchCfg& cfg) {
+    lkc_status s = check_cfg(ctx, cfg);
+    if (s != LKC_OK) return s;
+    if (q > NOALLOC_MAX_QUERIES)
+        return set_error(ctx, LKC_ERR_BUDGET,
+                         "lkc_knn_cov_noalloc takes at most %lld queries (got %lld)",
+                         (long long)NOALLOC_MAX_QUERIES, (long long)q);
+    if ((s = noalloc_init(ctx)) != LKC_OK) return s;   // set once per device
+    void* base;
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        base = g_noalloc_ptr[ctx->device];
+    }
+    Scratch sc;
+    carve_scratch((char*)base, scratch_layout(q), sc);
+    SearchJob j{t->view_dev, &t->view, 1, queries, q, nullptr, nullptr, k, radius, eps,
+                valid != nullptr ? 1 : 0, KnnPtrs{idx, d2, count}, CovPtrs{mean, cov, reg, valid}};
+    return run_search(ctx, j, cfg, &sc);
 }
 
 lkc_status launch_knn_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float radius,

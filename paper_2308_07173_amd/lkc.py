@@ -45,7 +45,7 @@ EXPORTED_SYMBOLS = (
     "lkc_ctx_set_timing", "lkc_ctx_set_profile", "lkc_covariances_weighted",
     "lkc_knn_cov_weighted", "lkc_gicp_linearize", "lkc_gicp_align", "lkc_voxel_filter",
     "lkc_submap_extract", "lkc_submap_build", "lkc_zvote", "lkc_euclid_cluster",
-    "lkc_target_status", "lkc_autotune",
+    "lkc_target_status", "lkc_autotune", "lkc_knn_cov_noalloc",
 )
 
 # neighbour weight kernels of lkc_covariances_weighted / lkc_knn_cov_weighted
@@ -134,6 +134,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_knn_query": ([P, P, P, I64, I32, F, P, P, P, P], I32),
             "lkc_covariances": ([P, P, P, P, P, I64, I32, F, P, P, P, P], I32),
             "lkc_knn_cov": ([P, P, P, I64, I32, F, F, P, P, P, P, P, P, P, P], I32),
+            "lkc_knn_cov_noalloc": ([P, P, P, I64, I32, F, F, P, P, P, P, P, P, P, P], I32),
             "lkc_target_set_create": ([P, P, I32, I32, PP], I32),
             "lkc_target_set_free": ([P, P], I32),
             "lkc_target_set_stage": ([P, P, P, I32], I32),
@@ -395,7 +396,11 @@ def lkc_covariances(ctx: Context, target: Target, idx, count, queries=None,
 
 
 def lkc_knn_cov(ctx: Context, target: Target, queries, k: int, radius: float = math.inf,
-                plane_eps: float = 1e-3, out: Optional[Dict] = None, cfg=None):
+                plane_eps: float = 1e-3, out: Optional[Dict] = None, cfg=None,
+                noalloc: bool = False):
+    """noalloc: call lkc_knn_cov_noalloc (static scratch, no device
+    allocation, q <= 131,072); the outputs must then be allocated already
+    (pass `out`) for the call itself to allocate nothing."""
     torch = _torch()
     _check_dev(queries, "queries", torch.float32, (3,))
     q = queries.shape[0]
@@ -405,7 +410,8 @@ def lkc_knn_cov(ctx: Context, target: Target, queries, k: int, radius: float = m
                    d2=torch.empty(q, k, dtype=torch.float32, device=queries.device),
                    count=torch.empty(q, dtype=torch.int32, device=queries.device))
     ctx._bind()
-    ctx.check(ctx.lib.lkc_knn_cov(
+    fn = ctx.lib.lkc_knn_cov_noalloc if noalloc else ctx.lib.lkc_knn_cov
+    ctx.check(fn(
         ctx.handle, target.handle, ctypes.c_void_p(_ptr(queries)), q, int(k), float(radius),
         float(plane_eps), ctypes.c_void_p(_ptr(out["idx"])), ctypes.c_void_p(_ptr(out["d2"])),
         ctypes.c_void_p(_ptr(out["count"])), ctypes.c_void_p(_ptr(out.get("mean"))),
