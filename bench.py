@@ -131,7 +131,7 @@ def group_counts(torch, dev, ctx, step, n_queries: int):
     """Candidates tested and insertion steps of the group search, summed over
     its groups, from one profiled run of `step` (outside the timed region)."""
     groups = (n_queries + 63) // 64
-    buf = torch.zeros((groups, 23), dtype=torch.int32, device=dev)
+    buf = torch.zeros((groups, 25), dtype=torch.int32, device=dev)
     ctx.set_profile(buf)
     step()
     torch.cuda.synchronize()

@@ -457,7 +457,7 @@ lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
  * events are not captured-graph safe, so keep timing off under capture. */
 lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
 
-/* Diagnostics: when `buffer` (device, 23 uint32 per group) holds at least
+/* Diagnostics: when `buffer` (device, 25 uint32 per group) holds at least
  * the number of 64-query groups of a search, the group search writes per
  * group: clock cycles, probe rounds, cells streamed, 64-point chunks
  * loaded, candidates tested, insertion steps, member lanes, lanes handed
@@ -469,8 +469,9 @@ lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
  * the lanes handed to the fallback search because their decoded entries
  * stayed out of order or tied, because the last kept entry shared the
  * k-th distance's bucket, or because the wavefront ran out of chunk names,
- * and the first wavefront's clock cycles in streaming, in decoding and
- * merging its lists, and in the covariances.
+ * the first wavefront's clock cycles in streaming, in decoding and
+ * merging its lists, and in the covariances, and that wavefront's 16-point
+ * runs whose box passed the group's test and those a lane's bound kept.
  * The counts of what was streamed (chunks onwards, except the member and
  * fallback lanes) are summed over the wavefronts of a split group; the
  * clock, probe and cell words are the first wavefront's.  The library

@@ -499,8 +499,8 @@ __device__ __forceinline__ void covariance(float ox, float oy, float oz, int n, 
         sy += t.y - oy;
         sz += t.z - oz;
     }
-    const float fn = (float)n;
-    const float mx = sx / fn, my = sy / fn, mz = sz / fn;
+    const float inv_n = 1.0f / (float)n;
+    const float mx = sx * inv_n, my = sy * inv_n, mz = sz * inv_n;
     float cxx = 0.f, cxy = 0.f, cxz = 0.f, cyy = 0.f, cyz = 0.f, czz = 0.f;
     for (int j = 0; j < n; ++j) {
         const float4 t = fetch(j);
@@ -512,12 +512,12 @@ __device__ __forceinline__ void covariance(float ox, float oy, float oz, int n, 
         cyz = fmaf(dy, dz, cyz);
         czz = fmaf(dz, dz, czz);
     }
-    out.cov[0] = cxx / fn;
-    out.cov[1] = cxy / fn;
-    out.cov[2] = cxz / fn;
-    out.cov[3] = cyy / fn;
-    out.cov[4] = cyz / fn;
-    out.cov[5] = czz / fn;
+    out.cov[0] = cxx * inv_n;
+    out.cov[1] = cxy * inv_n;
+    out.cov[2] = cxz * inv_n;
+    out.cov[3] = cyy * inv_n;
+    out.cov[4] = cyz * inv_n;
+    out.cov[5] = czz * inv_n;
     out.mean[0] = ox + mx;
     out.mean[1] = oy + my;
     out.mean[2] = oz + mz;
@@ -762,8 +762,9 @@ __device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, floa
 // the last entry shared the k-th distance's bucket, or because the wave ran
 // out of chunk names; then clock cycles of the first wavefront in the
 // streaming (probes and chunks), in decoding and merging the lists, and in
-// the covariances
-constexpr int PROF_WORDS = 23;
+// the covariances; then the 16-point runs whose box passed the group's
+// test and those some lane's own bound kept
+constexpr int PROF_WORDS = 25;
 // A profile counter that compiles away in the unprofiled kernels (their
 // counters are never read, so the arithmetic feeding them is dead).
 template <bool ON>
@@ -787,7 +788,7 @@ struct GroupProf {
     ProfCount<ON> probes, cells, chunks, cands, pops, inserts, dead;
     ProfCount<ON> ins0, ins1, ins2, cand0, cand1, cand2, own;
     ProfCount<ON> amb_order, amb_bucket, amb_names;
-    ProfCount<ON> t_walk, t_final, t_cov;
+    ProfCount<ON> t_walk, t_final, t_cov, runs_grp, runs_kept;
 };
 
 struct SlotQuery {
@@ -951,13 +952,17 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             const bool near = bd <= r2 && bd * (1.0f - 1e-6f) <= gthr;
             const bool want = mode == 0 ? bd == 0.0f : (mode == 1 ? (bd > 0.0f && near) : near);
             if (!want) continue;
+            gp.runs_grp++;
             // and some lane needs it: the run's box is within that lane's own
             // bound
             const float gx = fmaxf(fmaxf(blo.x - qx, qx - bhi.x) - margin, 0.0f);
             const float gy = fmaxf(fmaxf(blo.y - qy, qy - bhi.y) - margin, 0.0f);
             const float gz = fmaxf(fmaxf(blo.z - qz, qz - bhi.z) - margin, 0.0f);
             const float ld = gx * gx + gy * gy + gz * gz;
-            if (ballot(member && ld * (1.0f - 1e-6f) <= lthr)) keep |= 1u << q4;
+            if (ballot(member && ld * (1.0f - 1e-6f) <= lthr)) {
+                keep |= 1u << q4;
+                gp.runs_kept++;
+            }
         }
         if (!keep) continue;
         int ord = fixed_ord;
@@ -1269,6 +1274,7 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
         if (whole)
             scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin, gthr,
                         L, 2, gp, own_cb, sh, n_ch, s_tab);
+        const float ie0 = 1.0f / (float)max(ext[0], 1), ie1 = 1.0f / (float)max(ext[1], 1);
         for (int pass = 0; pass < (whole ? 0 : 2); ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
                 gp.probes++;
@@ -1276,12 +1282,15 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                 bool want = false;
                 uint32_t st = 0, cn = 0;
                 if (t < total) {
-                    // the block has at most (5 + 2 * 4)^3 cells: 32-bit division
+                    // the block has at most (5 + 2 * 4)^3 cells: the quotients
+                    // by float reciprocal ((a + 0.5) / b lies at least 0.5 / b
+                    // from an integer; exact for a < 2^22)
                     const uint32_t tu = (uint32_t)t, e0 = (uint32_t)ext[0],
                                    e1 = (uint32_t)ext[1];
-                    const uint32_t t0 = tu / e0;
-                    const int c3[3] = {lo[0] + (int)(tu - t0 * e0), lo[1] + (int)(t0 % e1),
-                                       lo[2] + (int)(t0 / e1)};
+                    const uint32_t t0 = (uint32_t)(((float)tu + 0.5f) * ie0);
+                    const uint32_t t1 = (uint32_t)(((float)t0 + 0.5f) * ie1);
+                    const int c3[3] = {lo[0] + (int)(tu - t0 * e0), lo[1] + (int)(t0 - t1 * e1),
+                                       lo[2] + (int)t1};
                     float bd = 0.0f;
                     for (int d = 0; d < 3; ++d) {
                         const float cl = (float)c3[d] * T.cell - margin;
@@ -1488,6 +1497,8 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
         pw[20] = gp.t_walk;
         pw[21] = gp.t_final;
         pw[22] = (uint32_t)(__builtin_amdgcn_s_memtime() - t_cov0);
+        pw[23] = gp.runs_grp;
+        pw[24] = gp.runs_kept;
     }
     // non-finite queries and queries against an empty target: empty results
     if (active && (!fin || empty_tgt)) emit_empty<FUSED>(a, s.qi, k);

@@ -240,7 +240,7 @@ class Context:
 
     def set_profile(self, buf=None):
         """Per-group counters of the group search into `buf` (device int32
-        tensor [groups, 23]) or off (None)."""
+        tensor [groups, 25]) or off (None)."""
         if buf is None:
             self.check(self.lib.lkc_ctx_set_profile(self.handle, None, 0))
         else:
