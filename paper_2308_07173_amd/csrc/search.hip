@@ -524,6 +524,65 @@ __device__ __forceinline__ void covariance(float ox, float oy, float oz, int n, 
     cov_regularise(n, eps, out);
 }
 
+// The same arithmetic, in the same order, for at most NMAX neighbours: each
+// neighbour is loaded once, all loads in flight together, and its offset
+// from o kept in registers for the second pass.  Results equal
+// covariance()'s bit for bit.
+template <int NMAX, typename Fetch>
+__device__ __forceinline__ void covariance_n(float ox, float oy, float oz, int n, Fetch fetch,
+                                             float eps, CovOut& out) {
+    if (n <= 0) {
+        cov_empty(out);
+        return;
+    }
+    float ux[NMAX], uy[NMAX], uz[NMAX];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        if (j < n) {
+            const float4 t = fetch(j);
+            ux[j] = t.x - ox;
+            uy[j] = t.y - oy;
+            uz[j] = t.z - oz;
+        } else {
+            ux[j] = uy[j] = uz[j] = 0.0f;
+        }
+    }
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        if (j < n) {
+            sx += ux[j];
+            sy += uy[j];
+            sz += uz[j];
+        }
+    }
+    const float inv_n = 1.0f / (float)n;
+    const float mx = sx * inv_n, my = sy * inv_n, mz = sz * inv_n;
+    float cxx = 0.f, cxy = 0.f, cxz = 0.f, cyy = 0.f, cyz = 0.f, czz = 0.f;
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        if (j < n) {
+            const float dx = ux[j] - mx, dy = uy[j] - my, dz = uz[j] - mz;
+            cxx = fmaf(dx, dx, cxx);
+            cxy = fmaf(dx, dy, cxy);
+            cxz = fmaf(dx, dz, cxz);
+            cyy = fmaf(dy, dy, cyy);
+            cyz = fmaf(dy, dz, cyz);
+            czz = fmaf(dz, dz, czz);
+        }
+    }
+    out.cov[0] = cxx * inv_n;
+    out.cov[1] = cxy * inv_n;
+    out.cov[2] = cxz * inv_n;
+    out.cov[3] = cyy * inv_n;
+    out.cov[4] = cyz * inv_n;
+    out.cov[5] = czz * inv_n;
+    out.mean[0] = ox + mx;
+    out.mean[1] = oy + my;
+    out.mean[2] = oz + mz;
+    cov_regularise(n, eps, out);
+}
+
 // Exponent of the kernel descriptor for squared distance d2.
 __device__ __forceinline__ float weight_exponent(const CovWeight& W, float d2) {
     return W.kind == LKC_WEIGHT_LAPLACIAN ? sqrtf(d2) * W.scale : d2 * W.scale;
@@ -1065,27 +1124,34 @@ __device__ __forceinline__ int emit_row(const GroupArgs& a, const TargetView& T,
 // caches; the same values as the caller-order copy) by the positions in sp
 // (column c at sp[c * 64], LDS), then the row's indices.  Restrict-qualified
 // so that the gathers of a pass can all be in flight together.
-template <int FUSED>
+template <int K, int FUSED>
 __device__ __forceinline__ void cov_gather(const float4* __restrict__ pts,
                                            const uint32_t* __restrict__ sp,
                                            int32_t* __restrict__ irow, const GroupArgs& a,
                                            int64_t qi, float qx, float qy, float qz, int cnt) {
-    const auto fetch = [&](int j) { return gload(pts + sp[j * WAVE]); };
     CovOut c;
-    if (FUSED == 1)
-        covariance(qx, qy, qz, cnt, fetch, a.eps, c);
-    else
+    if (FUSED == 1) {
+        // each neighbour gathered once; its index written on the way
+        const auto fetch = [&](int j) {
+            const float4 t = gload(pts + sp[j * WAVE]);
+            irow[j] = __float_as_int(t.w);
+            return t;
+        };
+        covariance_n<K>(qx, qy, qz, cnt, fetch, a.eps, c);
+    } else {
+        const auto fetch = [&](int j) { return gload(pts + sp[j * WAVE]); };
         covariance_weighted(qx, qy, qz, cnt, fetch, a.wt, a.eps, c);
-    store_cov(a.co, qi, c);
 #pragma unroll 4
-    for (int j = 0; j < cnt; ++j) irow[j] = __float_as_int(gload(pts + sp[j * WAVE]).w);
+        for (int j = 0; j < cnt; ++j) irow[j] = __float_as_int(gload(pts + sp[j * WAVE]).w);
+    }
+    store_cov(a.co, qi, c);
 }
 
 template <int K, int FUSED>
 __device__ __forceinline__ void emit_cov(const GroupArgs& a, const TargetView& T, int64_t qi,
                                          float qx, float qy, float qz, int k, int cnt,
                                          const uint32_t* s_pos) {
-    cov_gather<FUSED>(T.pts, s_pos + (K - k) * WAVE + lane_id(), a.ko.idx + qi * k, a, qi, qx,
+    cov_gather<K, FUSED>(T.pts, s_pos + (K - k) * WAVE + lane_id(), a.ko.idx + qi * k, a, qi, qx,
                       qy, qz, cnt);
 }
 
@@ -1306,7 +1372,7 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                 // touch the query box (they set tight k-th distances), then
                 // the rest; the surrounding cells after that, pruned
                 const unsigned long long wm0 = ballot(want);
-                for (int mode = (pass == 0 ? 0 : 2); mode <= (pass == 0 ? 1 : 2); ++mode) {
+                for (int mode = 2; mode <= 2; ++mode) {
                     unsigned long long wm = wm0;
                     const uint32_t i0 = gp.inserts, c0 = gp.cands;
                     while (wm) {
