@@ -463,9 +463,9 @@ lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
  * loaded, candidates tested, insertion steps, member lanes, lanes handed
  * to the fallback search, insertions summed over the lanes, insertion
  * steps in which no lane inserted, then insertions (3 words) and
- * candidates (3 words) in the three streaming phases: runs of the queries'
- * own cells touching the query box, the rest of those cells, the other
- * cells, and insertions from the group's own chunk (self queries), then
+ * candidates (3 words) in the three streaming phases: the cells holding the
+ * queries, the surrounding cells, a small target streamed whole, and
+ * insertions from the group's own chunk (self queries), then
  * the lanes handed to the fallback search because their decoded entries
  * stayed out of order or tied, because the last kept entry shared the
  * k-th distance's bucket, or because the wavefront ran out of chunk names,
@@ -489,7 +489,9 @@ lkc_status lkc_ctx_set_profile(lkc_ctx *ctx, void *buffer, int64_t n_groups);
  * q <= sample, else four contiguous runs of sample / 4 queries at starts
  * drawn by splitmix64 from `seed`, which keeps the local density of whole
  * scans.  Time = median of `reps` (1..100) runs after one warm-up, from HIP
- * events on the context's stream.
+ * events on the context's stream.  Candidates are tried in order (cells
+ * outer, shapes inner) and one replaces the best so far only when it is
+ * more than 2 % faster, so that repeated tunings agree.
  *   cells    host [n_cells] candidate cell sizes (> 0); n_cells = 0 takes
  *            0.5, 0.75, 1, 1.5, 2 m
  *   cfgs     host [n_cfgs] candidate launch shapes; n_cfgs = 0 takes a
