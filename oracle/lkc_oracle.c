@@ -678,21 +678,21 @@ int64_t oracle_voxel_filter(const float *pts, int64_t n, const float *origin, fl
 
 /* Sliding-window submap (Sec. III-C.3: only the map points near the current
  * race-line pose are queried): the indices of the points within `radius` of
- * `center`, inclusive, ascending.  The decision d2 <= radius^2 is taken in
- * float32 in the kernel's order, d2 = fma(dz, dz, fma(dy, dy, dx * dx)) with
- * d = p - center.  Returns the count. */
+ * `center`, inclusive, ascending.  The decision is the definition, taken in
+ * FP64 on the float32 inputs: |p - center|^2 <= radius^2.  Returns the
+ * count. */
 int64_t oracle_submap(const float *pts, int64_t n, const float *center, float radius,
                       int32_t *out)
 {
     if (n < 0 || !(radius > 0.0f))
         return -1;
-    const float r2 = radius * radius;
+    const double r2 = (double)radius * (double)radius;
     int64_t m = 0;
     for (int64_t i = 0; i < n; ++i) {
-        const float dx = pts[3 * i] - center[0];
-        const float dy = pts[3 * i + 1] - center[1];
-        const float dz = pts[3 * i + 2] - center[2];
-        const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const double dx = (double)pts[3 * i] - (double)center[0];
+        const double dy = (double)pts[3 * i + 1] - (double)center[1];
+        const double dz = (double)pts[3 * i + 2] - (double)center[2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
         if (d2 <= r2)
             out[m++] = (int32_t)i;
     }
@@ -759,8 +759,8 @@ int oracle_zvote(const float *pts, int64_t n, float g, int32_t tau, uint8_t *kee
 
 /* Euclidean-distance clustering (Sec. III-D.2): the clusters are the
  * connected components of the graph joining points i and j when
- * d2(i, j) <= eps^2, with d2 = fma(dz, dz, fma(dy, dy, dx * dx)) in float32
- * (the kernel's decision precision).  The paper's Eq. eq_clustering is
+ * |p_i - p_j|^2 <= eps^2, decided in FP64 on the float32 inputs.  The
+ * paper's Eq. eq_clustering is
  * printed in k-means notation; the text and citations describe region
  * growing by distance, which is this definition.  label[i] = the smallest
  * index in i's component.  Brute force over all pairs with a union-find
@@ -779,7 +779,7 @@ int64_t oracle_euclid_cluster(const float *pts, int64_t n, float eps, int32_t *l
 {
     if (n < 0 || !(eps > 0.0f))
         return -1;
-    const float e2 = eps * eps;
+    const double e2 = (double)eps * (double)eps;
     int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i)
         par[i] = i;
@@ -789,8 +789,9 @@ int64_t oracle_euclid_cluster(const float *pts, int64_t n, float eps, int32_t *l
             continue;
         for (int64_t j = i + 1; j < n; ++j) {
             const float *q = pts + 3 * j;
-            const float dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
-            const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const double dx = (double)p[0] - (double)q[0], dy = (double)p[1] - (double)q[1],
+                         dz = (double)p[2] - (double)q[2];
+            const double d2 = dx * dx + dy * dy + dz * dz;
             if (d2 <= e2) {
                 const int64_t a = uf_find(par, i), b = uf_find(par, j);
                 if (a != b)

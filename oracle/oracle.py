@@ -235,7 +235,7 @@ def voxel_filter(points, leaf: float, origin=(0.0, 0.0, 0.0)):
 
 
 def submap(points, center, radius: float):
-    """Ascending indices of the points within radius of center (float32 decision)."""
+    """Ascending indices of the points within radius of center (FP64 decision)."""
     p = _f32(points)
     c = np.ascontiguousarray(center, np.float32)
     out = np.empty(max(p.shape[0], 1), np.int32)

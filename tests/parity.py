@@ -23,6 +23,19 @@ covariances, e.g. a set of duplicated points),
 compared at 1e-4 relative Frobenius where the oracle's eigen-gap
 ``(l1 - l0) / l2 >= 1e-2``, else checked for symmetry, eigenvalues
 {eps, 1, 1} and for its eps-direction being a near-minimiser of C.
+
+Distance thresholds outside the search (the submap window, the clustering
+edges): the oracle decides in FP64; the GPU decides in float32, whose
+squared distance (two roundings of the differences, three of the sums of
+squares) and squared threshold are each within a few 2^-24 of the exact
+values, so its decision may differ only for points (pairs) whose FP64
+squared distance lies within ``BAND_REL = 1e-6`` of the squared threshold.
+Window: the oracle's window at the threshold shrunk by the band is a subset
+of the GPU's, which is a subset of the oracle's at the grown threshold.
+Clusters: the oracle's partition with the band edges dropped refines the
+GPU's, which refines the oracle's with them kept; the GPU labels each
+cluster with its smallest index.  Without points in the band the match is
+exact.
 """
 from __future__ import annotations
 
@@ -37,6 +50,7 @@ COV_REL = 1e-4
 MEAN_REL = 1e-5
 GAP_MIN = 1e-2
 F32_U = 2.0 ** -24
+BAND_REL = 1e-6
 
 
 def rounding_terms(target, idx, cnt, origin=None):
@@ -266,3 +280,52 @@ def check_cov(target, g_idx, g_cnt, mean, cov, reg, valid, eps=1e-3, rows=None, 
         bound = ev[small, 1] + 1e-5 * np.linalg.norm(ref["cov"][small], axis=(1, 2))
         assert np.all(quad <= bound), "eps-direction is not a near-minimiser of C"
     return dict(cov_rel=worst, n_small_gap=int(small.sum()))
+
+
+def _scaled(x: float, f: float) -> float:
+    """float32 threshold x * sqrt(f) rounded away from x (so that the band
+    is at least the stated one)."""
+    y = np.float32(x * np.sqrt(f))
+    return float(np.nextafter(y, np.float32(np.inf if f > 1 else 0.0)))
+
+
+def check_submap(points, center, radius: float, got):
+    """The GPU's window (ascending indices) against the FP64 definition with
+    the boundary band."""
+    got = np.asarray(got)
+    assert np.all(np.diff(got) > 0), "window indices not ascending and distinct"
+    inner = oracle.submap(points, center, _scaled(radius, 1.0 - BAND_REL))
+    outer = oracle.submap(points, center, _scaled(radius, 1.0 + BAND_REL))
+    g = set(got.tolist())
+    missing = set(inner.tolist()) - g
+    extra = g - set(outer.tolist())
+    assert not missing, f"{len(missing)} points inside the window missing"
+    assert not extra, f"{len(extra)} points outside the window returned"
+    return dict(band=len(outer) - len(inner))
+
+
+def _components_agree(fine, coarse):
+    """True when every class of `fine` lies inside one class of `coarse`."""
+    f = np.asarray(fine)
+    c = np.asarray(coarse)
+    first = {}
+    for a, b in zip(f.tolist(), c.tolist()):
+        if first.setdefault(a, b) != b:
+            return False
+    return True
+
+
+def check_clusters(points, eps: float, labels, n_clusters: int):
+    """GPU cluster labels against the FP64 definition with the band rule."""
+    labels = np.asarray(labels).astype(np.int64)
+    n = len(labels)
+    lo, k_lo = oracle.euclid_cluster(points, _scaled(eps, 1.0 - BAND_REL))
+    hi, k_hi = oracle.euclid_cluster(points, _scaled(eps, 1.0 + BAND_REL))
+    assert k_hi <= n_clusters <= k_lo, f"{n_clusters} clusters, expected {k_hi}..{k_lo}"
+    assert _components_agree(lo, labels), "a cluster of the definition is split"
+    assert _components_agree(labels, hi), "clusters of the definition are merged"
+    # each label is its cluster's smallest index
+    idx = np.arange(n)
+    assert np.all(labels <= idx) and np.all(labels[labels] == labels), "labels not minimal"
+    assert len(np.unique(labels)) == n_clusters
+    return dict(exact=bool(k_lo == k_hi))

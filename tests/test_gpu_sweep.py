@@ -235,9 +235,7 @@ def test_random_rebuild_and_grid_ops_sweep(lk, case):
     sub = p[: min(p.shape[0], 8000)]
     eps = float(rng.choice([0.1, 0.3, 0.6]))
     labels, nc = lkc.lkc_euclid_cluster(ctx, dev(sub), eps)
-    ol, onc = oracle.euclid_cluster(sub, eps)
-    assert nc == onc
-    np.testing.assert_array_equal(labels.cpu().numpy(), ol)
+    parity.check_clusters(sub, eps, labels.cpu().numpy(), nc)
 
 
 @pytest.mark.parametrize("case", range(8))

@@ -5,13 +5,18 @@ Voxel filter: the voxel decision is taken in float32 on both sides, so the
 voxel set, order and counts must match the oracle exactly; the GPU sums
 each voxel in FP64 in the oracle's order, so every centroid must equal the
 float32 rounding of the oracle's FP64 mean, bit for bit.  Submap: the
-decision is float32 in the same operation order on both sides, so the index
-list must match exactly.
+oracle decides |p - c|^2 <= r^2 in FP64 on the float32 inputs; the kernel's
+float32 distance can differ from it only for points within a relative 1e-6
+of the radius, so the index list is checked under the boundary-band rule
+(tests/parity.py): it contains every point inside r*(1-1e-6), none outside
+r*(1+1e-6), in ascending order.  On an integer lattice every distance is
+exact and the list must match exactly.
 """
 import numpy as np
 import pytest
 
 from oracle import oracle
+from tests import parity
 from paper_2308_07173_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -96,7 +101,7 @@ def test_submap_extract_exact(lk, radius):
     rng = np.random.default_rng(7)
     for c in m[rng.choice(len(m), 3, replace=False)]:
         idx = lkc.lkc_submap_extract(ctx, t, c, radius).cpu().numpy()
-        np.testing.assert_array_equal(idx, oracle.submap(m, c, radius))
+        parity.check_submap(m, c, radius, idx)
     t.free()
 
 
@@ -124,7 +129,7 @@ def test_submap_build_queries_like_the_window(lk):
     c = m[12345]
     sub, idx = lkc.lkc_submap_build(ctx, t, c, 15.0)
     idx = idx.cpu().numpy()
-    np.testing.assert_array_equal(idx, oracle.submap(m, c, 15.0))
+    parity.check_submap(m, c, 15.0, idx)
     assert sub.info()["n_points"] == len(idx)
     w = m[idx]
     q = w[:: max(1, len(w) // 500)]

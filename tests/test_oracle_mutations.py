@@ -100,8 +100,8 @@ VOXEL_MUTATIONS = {
     "voxel_reciprocal": ("const float q = (p[d] - origin[d]) / leaf;",
                          "const float q = (p[d] - origin[d]) * (1.0f / leaf);"),
     "submap_exclusive": ("if (d2 <= r2)\n            out[m++]", "if (d2 < r2)\n            out[m++]"),
-    "submap_dropped_z": ("const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));\n        if (d2 <= r2)",
-                         "const float d2 = fmaf(dy, dy, dx * dx);\n        if (d2 <= r2)"),
+    "submap_dropped_z": ("const double d2 = dx * dx + dy * dy + dz * dz;\n        if (d2 <= r2)",
+                         "const double d2 = dx * dx + dy * dy;\n        if (d2 <= r2)"),
 }
 
 VOXEL_PINS = [getattr(vpins, n) for n in dir(vpins) if n.startswith("test_")]
@@ -117,8 +117,8 @@ WALL_MUTATIONS = {
     "cluster_exclusive": ("if (d2 <= e2) {", "if (d2 < e2) {"),
     "cluster_max_label": ("par[a > b ? a : b] = a < b ? a : b;",
                           "par[a < b ? a : b] = a > b ? a : b;"),
-    "cluster_dropped_dz": ("const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));\n            if (d2 <= e2)",
-                           "const float d2 = fmaf(dy, dy, dx * dx);\n            if (d2 <= e2)"),
+    "cluster_dropped_dz": ("const double d2 = dx * dx + dy * dy + dz * dz;\n            if (d2 <= e2)",
+                           "const double d2 = dx * dx + dy * dy;\n            if (d2 <= e2)"),
 }
 
 WALL_PINS = [getattr(wlpins, n) for n in dir(wlpins) if n.startswith("test_")]
