@@ -814,9 +814,9 @@ __device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, floa
 // per-group profile words: clock cycles, probe rounds, cells streamed,
 // 64-point chunks loaded, candidates tested, insertion pops, member lanes,
 // fallback lanes, insertions (over all lanes), pops in which no lane
-// inserted; then insertions and candidates split by phase: the query cells'
-// runs touching the query box, the rest of the query cells, the other cells;
-// then insertions from the group's own chunk (self queries); then the lanes
+// inserted; then insertions and candidates split by phase: the cells holding
+// the queries, the surrounding cells, a small target streamed whole; then
+// insertions from the group's own chunk (self queries); then the lanes
 // handed on because their decoded entries stayed out of order or tied, because
 // the last entry shared the k-th distance's bucket, or because the wave ran
 // out of chunk names; then clock cycles of the first wavefront in the
@@ -965,10 +965,9 @@ __device__ __forceinline__ void sort_u32(uint32_t (&L)[N]) {
 
 // Stream the reordered points [s0, e0) through every member lane's list.
 // The run is walked in aligned 64-point chunks made of four 16-point runs
-// with their own bounding boxes; mode 0 takes only the 16-point runs whose
-// box touches the group's query box, mode 1 only the others, mode 2 all of
-// them, and modes 1-2 skip a 16-point run whose box is farther from the
-// query box than the radius or the group's largest k-th bound.  A kept chunk
+// with their own bounding boxes; a 16-point run whose box is farther from
+// the query box than the radius or the group's largest k-th bound, or from
+// every member's query than its own bound, is skipped.  A kept chunk
 // is named (its ordinal in this wave's stream, recorded in s_tab; fixed_ord
 // names a chunk the caller registered); each candidate is broadcast from its lane and
 // tested by every lane, which only sets a bit per passing candidate; the
@@ -981,7 +980,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
                                          float qx, float qy, float qz, float r2, float lcap,
                                          const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr, uint32_t (&L)[K + SLACK],
-                                         int mode, GroupProf<PROF>& gp, int skip_cb,
+                                         GroupProf<PROF>& gp, int skip_cb,
                                          const SplitShare& sh, int& n_ch, uint32_t* s_tab,
                                          int fixed_ord = -1, int win_k = 0, int win_n = 0) {
     const int lane = lane_id();
@@ -1008,9 +1007,7 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             const float4 blo = bb[2 * q4], bhi = bb[2 * q4 + 1];
             const float bd =
                 box_box_dist2(b0, b1, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, margin);
-            const bool near = bd <= r2 && bd * (1.0f - 1e-6f) <= gthr;
-            const bool want = mode == 0 ? bd == 0.0f : (mode == 1 ? (bd > 0.0f && near) : near);
-            if (!want) continue;
+            if (!(bd <= r2 && bd * (1.0f - 1e-6f) <= gthr)) continue;
             gp.runs_grp++;
             // and some lane needs it: the run's box is within that lane's own
             // bound
@@ -1332,14 +1329,18 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                 }
                 const uint32_t i0 = gp.inserts;
                 scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
-                            s.z, r2, lcap, b0, b1, margin, gthr, L, 2, gp, -1, sh, n_ch, s_tab, 1,
+                            s.z, r2, lcap, b0, b1, margin, gthr, L, gp, -1, sh, n_ch, s_tab, 1,
                             win_k, n_act);
                 gp.own += gp.inserts - i0;
             }
         }
-        if (whole)
+        if (whole) {
+            const uint32_t i0 = gp.inserts, c0 = gp.cands;
             scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin, gthr,
-                        L, 2, gp, own_cb, sh, n_ch, s_tab);
+                        L, gp, own_cb, sh, n_ch, s_tab);
+            gp.ins2 += gp.inserts - i0;
+            gp.cand2 += gp.cands - c0;
+        }
         const float ie0 = 1.0f / (float)max(ext[0], 1), ie1 = 1.0f / (float)max(ext[1], 1);
         for (int pass = 0; pass < (whole ? 0 : 2); ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
@@ -1368,33 +1369,25 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                     if (inside == (pass == 0) && bd <= r2 && bd * (1.0f - 1e-6f) <= gthr)
                         want = hash_find(T, pack_key(T, c3[0], c3[1], c3[2]), st, cn) && cn > 0;
                 }
-                // the cells holding the queries: first the 16-point runs that
-                // touch the query box (they set tight k-th distances), then
-                // the rest; the surrounding cells after that, pruned
-                const unsigned long long wm0 = ballot(want);
-                for (int mode = 2; mode <= 2; ++mode) {
-                    unsigned long long wm = wm0;
-                    const uint32_t i0 = gp.inserts, c0 = gp.cands;
-                    while (wm) {
-                        const int cl = __builtin_ffsll((long long)wm) - 1;
-                        wm &= wm - 1;
-                        const int s0 = readlane((int)st, cl);
-                        const int e0 = s0 + readlane((int)cn, cl);
-                        gp.cells++;
-                        scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin,
-                                    gthr, L, mode, gp, own_cb, sh, n_ch, s_tab);
-                    }
-                    const uint32_t di = gp.inserts - i0, dc = gp.cands - c0;
-                    if (mode == 0) {
-                        gp.ins0 += di;
-                        gp.cand0 += dc;
-                    } else if (mode == 1) {
-                        gp.ins1 += di;
-                        gp.cand1 += dc;
-                    } else {
-                        gp.ins2 += di;
-                        gp.cand2 += dc;
-                    }
+                // the cells holding the queries first (they set tight k-th
+                // distances), the surrounding cells after them
+                unsigned long long wm = ballot(want);
+                const uint32_t i0 = gp.inserts, c0 = gp.cands;
+                while (wm) {
+                    const int cl = __builtin_ffsll((long long)wm) - 1;
+                    wm &= wm - 1;
+                    const int s0 = readlane((int)st, cl);
+                    const int e0 = s0 + readlane((int)cn, cl);
+                    gp.cells++;
+                    scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin,
+                                gthr, L, gp, own_cb, sh, n_ch, s_tab);
+                }
+                if (pass == 0) {
+                    gp.ins0 += gp.inserts - i0;
+                    gp.cand0 += gp.cands - c0;
+                } else {
+                    gp.ins1 += gp.inserts - i0;
+                    gp.cand1 += gp.cands - c0;
                 }
             }
         }
