@@ -20,6 +20,8 @@
  *   lkc_voxel_filter    voxel centroids of a cloud
  *   lkc_submap_extract / lkc_submap_build
  *                       the map points within a radius of a pose
+ *   lkc_raceline_build / lkc_submap_window / lkc_submap_window_build
+ *                       race-line keyed map parts and the sliding window
  *   lkc_zvote / lkc_euclid_cluster
  *                       vertical-feature filter and distance clustering
  *   lkc_knn_cov_batched many scans against several targets in one persistent
@@ -349,12 +351,14 @@ lkc_status lkc_voxel_filter(lkc_ctx *ctx, const float *points, int64_t n, const 
                             float leaf, float *centroid, int32_t *count, int32_t *voxel,
                             int64_t capacity, int64_t *n_out);
 
-/* Sliding-window submap (Sec. III-C.3: only the map points near the
- * current race-line pose are queried): the original indices of the points
- * of `map` within `radius` of `center` (host float [3]), inclusive, with
- * d2 = fma(dz, dz, fma(dy, dy, dx * dx)) in float32, ascending.  idx:
- * device int32 [capacity]; *n_out (host) receives the count;
- * LKC_ERR_BUDGET when it exceeds capacity.  Synchronises once. */
+/* Sliding-window submap around an arbitrary centre (Sec. III-C.3: only the
+ * map points near the current pose are queried), by a pass over every map
+ * point: the original indices of the points of `map` within `radius` of
+ * `center` (host float [3]), inclusive, with d2 = fma(dz, dz, fma(dy, dy,
+ * dx * dx)) in float32, ascending.  idx: device int32 [capacity]; *n_out
+ * (host) receives the count; LKC_ERR_BUDGET when it exceeds capacity.
+ * Synchronises once.  lkc_submap_window below reads only the window's part
+ * of the map and does not synchronise. */
 lkc_status lkc_submap_extract(lkc_ctx *ctx, const lkc_target *map, const float *center,
                               float radius, int32_t *idx, int64_t capacity, int64_t *n_out);
 
@@ -365,6 +369,89 @@ lkc_status lkc_submap_extract(lkc_ctx *ctx, const lkc_target *map, const float *
 lkc_status lkc_submap_build(lkc_ctx *ctx, const lkc_target *map, const float *center,
                             float radius, int32_t *idx, int64_t capacity, int64_t *n_out,
                             lkc_target **out);
+
+/* ---- Race-line keyed window (Sec. III-C.3: each race-line pose is
+ * associated with its part of the map through a GPU hash, and scan matching
+ * uses a sliding window of the map around the current pose).
+ *
+ * lkc_raceline_build cuts the closed race-line polyline `line` (host float
+ * [m][3], m >= 2, driving order; the last point joins the first) into
+ * ceil(length / bin_length) equal arc-length bins, bin b's anchor being the
+ * race-line point at the middle of the bin.  A device hash maps the 2-D pose
+ * cell (floor(x * (1/g)), floor(y * (1/g)), float32, g = the bin length) of
+ * every cell within `lateral` metres of the race line to a bin; each bin
+ * holds the map cells within its coverage radius as runs of the map's cell
+ * table (contiguous ranges of the map's points).  The coverage radius is
+ * `radius` plus the farthest a tabled pose cell reaches from its anchor,
+ * horizontally, and `lateral` vertically: every window of radius <= `radius`
+ * around a pose that the hash accepts, with its z within `lateral` of the
+ * race line, lies inside its bin's ranges.  The map must stay alive and
+ * must not be rebuilt while the index is used (calls on a rebuilt map fail
+ * with LKC_ERR_INVALID_ARG); free the index before the map.  Synchronises
+ * (build time only).  Errors: LKC_ERR_INVALID_ARG (bad sizes, non-finite or
+ * zero-length line, more than 2^20 bins), LKC_ERR_OOM. */
+typedef struct lkc_raceline lkc_raceline;
+
+typedef struct {
+    int64_t n_bins;           /* arc-length bins */
+    int64_t n_ranges;         /* point ranges over all bins */
+    int64_t pose_cells;       /* entries of the pose hash */
+    int64_t max_bin_points;   /* most map points in one bin's ranges */
+    int64_t sum_bin_points;   /* map points over all bins' ranges */
+    float bin_length;         /* arc length of a bin (<= the requested length) */
+    float pose_grid;          /* pose-cell size */
+    float radius;             /* largest window radius */
+    float lateral;            /* pose tolerance off the race line */
+    float cover_radius;       /* radius of every bin's ranges around its anchor */
+    int32_t reserved;
+    int64_t device_bytes;
+} lkc_raceline_info;
+
+lkc_status lkc_raceline_build(lkc_ctx *ctx, const lkc_target *map, const float *line, int64_t m,
+                              float bin_length, float radius, float lateral,
+                              lkc_raceline **out);
+lkc_status lkc_raceline_free(lkc_ctx *ctx, lkc_raceline *rl);
+lkc_status lkc_raceline_get_info(const lkc_raceline *rl, lkc_raceline_info *info);
+/* Host copies of the bins' anchors (float [n_bins][3]) and point counts
+ * (int64 [n_bins]); either may be NULL. */
+lkc_status lkc_raceline_bins(const lkc_raceline *rl, float *anchors, int64_t *bin_points);
+
+/* Window statuses written by lkc_submap_window (info[2]). */
+enum {
+    LKC_WINDOW_OK = 0,
+    LKC_WINDOW_NO_BIN = 1,      /* the pose's cell is not in the pose hash (or not finite) */
+    LKC_WINDOW_UNCOVERED = 2,   /* |pose - anchor| + radius exceeds the coverage radius */
+    LKC_WINDOW_OVERFLOW = 3     /* more window points than capacity (the first written) */
+};
+
+/* The window: the original indices of the map points p with
+ * fma(dz, dz, fma(dy, dy, dx * dx)) <= radius^2 (float32, d = pose - p),
+ * ascending, found among the ranges of the pose's bin only.  pose: DEVICE
+ * float [3] (read by the kernels, so a captured graph can be replayed with
+ * a new pose); radius in (0, the index's radius].  idx: device int32
+ * [capacity]; points: device float [capacity][3] or NULL (the window's
+ * coordinates).  info: device int64 [3] = {count, bin (-1 if none), status}.
+ * A window never holds more than max_bin_points points, so a capacity of
+ * that size cannot overflow; on LKC_WINDOW_OVERFLOW the first `capacity`
+ * indices are written and info[0] is the full count; on NO_BIN / UNCOVERED
+ * the count is 0.  Enqueued on the context's stream: no synchronisation,
+ * no device allocation (the index owns its bitmap), graph-capturable.
+ * Calls that use one index must be ordered on one stream (they share its
+ * bitmap).  Host-side errors: LKC_ERR_INVALID_ARG (NULL pointers, radius
+ * out of range, capacity < 0, map rebuilt since the index was built). */
+lkc_status lkc_submap_window(lkc_ctx *ctx, const lkc_raceline *rl, const float *pose,
+                             float radius, int32_t *idx, float *points, int64_t capacity,
+                             int64_t *info);
+
+/* The window of `pose` (device float [3]) built into a new target with the
+ * map's cell size; target index j is the window's j-th point, and idx
+ * (device int32 [capacity], may be NULL) receives its map index.
+ * Synchronises once (the count sizes the target's build).  Errors as
+ * lkc_submap_window, plus LKC_ERR_INVALID_ARG when the pose has no bin or
+ * is not covered, LKC_ERR_BUDGET when the window exceeds capacity. */
+lkc_status lkc_submap_window_build(lkc_ctx *ctx, const lkc_raceline *rl, const float *pose,
+                                   float radius, int32_t *idx, int64_t capacity, int64_t *n_out,
+                                   lkc_target **out);
 
 /* ---- Wall-detection front end (paper Sec. III-D).
  *

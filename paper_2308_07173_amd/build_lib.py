@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblkc.so")
 SOURCES = ["api.hip", "build.hip", "search.hip", "gicp.hip", "voxel.hip", "walls.hip",
-           "autotune.hip"]
+           "autotune.hip", "raceline.hip"]
 ARCH = "gfx950"
 
 

@@ -713,4 +713,174 @@ lkc_status lkc_ctx_reserve(lkc_ctx* ctx, int64_t max_queries) {
     return lkc::reserve_search(ctx, max_queries);
 }
 
+
+lkc_status lkc_raceline_build(lkc_ctx* ctx, const lkc_target* map, const float* line, int64_t m,
+                              float bin_length, float radius, float lateral,
+                              lkc_raceline** out) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if ((s = check_target(ctx, map)) != LKC_OK) return s;
+    if (!out) return set_error(ctx, LKC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!line) return set_error(ctx, LKC_ERR_INVALID_ARG, "line is NULL");
+    if (m < 2 || m > (1LL << 24))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "m = %lld outside [2, 2^24]", (long long)m);
+    for (int64_t i = 0; i < 3 * m; ++i)
+        if (!std::isfinite(line[i]))
+            return set_error(ctx, LKC_ERR_INVALID_ARG, "race line has a non-finite coordinate");
+    if (!(bin_length > 0.0f) || !std::isfinite(bin_length))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "bin_length must be finite and > 0");
+    if (!(radius > 0.0f) || !std::isfinite(radius * radius))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "radius must be finite and > 0");
+    if (!(lateral >= 0.0f) || !std::isfinite(lateral))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "lateral must be finite and >= 0");
+    lkc_raceline* rl = new (std::nothrow) lkc_raceline();
+    if (!rl) return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    s = lkc::raceline_build(ctx, map, line, m, bin_length, radius, lateral, rl);
+    if (s != LKC_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        lkc::raceline_free_memory(rl);
+        delete rl;
+        return s;
+    }
+    *out = rl;
+    return LKC_OK;
+}
+
+lkc_status lkc_raceline_free(lkc_ctx* ctx, lkc_raceline* rl) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!rl) return LKC_OK;
+    LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    lkc::raceline_free_memory(rl);
+    delete rl;
+    return LKC_OK;
+}
+
+lkc_status lkc_raceline_get_info(const lkc_raceline* rl, lkc_raceline_info* info) {
+    if (!rl || !info) return set_error(nullptr, LKC_ERR_INVALID_ARG, "rl or info is NULL");
+    info->n_bins = rl->n_bins;
+    info->n_ranges = rl->n_ranges;
+    info->pose_cells = rl->pose_cells;
+    info->max_bin_points = rl->max_points;
+    info->sum_bin_points = rl->sum_points;
+    info->bin_length = rl->bin_length;
+    info->pose_grid = rl->grid;
+    info->radius = rl->radius;
+    info->lateral = rl->lateral;
+    info->cover_radius = rl->cover;
+    info->reserved = 0;
+    info->device_bytes = (int64_t)rl->bytes;
+    return LKC_OK;
+}
+
+lkc_status lkc_raceline_bins(const lkc_raceline* rl, float* anchors, int64_t* bin_points) {
+    if (!rl) return set_error(nullptr, LKC_ERR_INVALID_ARG, "rl is NULL");
+    for (int32_t b = 0; b < rl->n_bins; ++b) {
+        if (anchors)
+            for (int k = 0; k < 3; ++k) anchors[3 * b + k] = (float)rl->anchors_host[3 * b + k];
+        if (bin_points) bin_points[b] = rl->bin_points[b];
+    }
+    return LKC_OK;
+}
+
+namespace {
+
+lkc_status check_window_call(lkc_ctx* ctx, const lkc_raceline* rl, const float* pose,
+                             float radius, int64_t capacity) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!rl) return set_error(ctx, LKC_ERR_INVALID_ARG, "race-line index is NULL");
+    if (!pose) return set_error(ctx, LKC_ERR_INVALID_ARG, "pose is NULL");
+    if (!(radius > 0.0f && radius <= rl->radius))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "radius %g outside (0, %g]", (double)radius,
+                         (double)rl->radius);
+    if (capacity < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "capacity < 0");
+    if (rl->map->generation != rl->map_generation)
+        return set_error(ctx, LKC_ERR_INVALID_ARG,
+                         "the map was rebuilt after the race-line index was built");
+    return LKC_OK;
+}
+
+}  // namespace
+
+lkc_status lkc_submap_window(lkc_ctx* ctx, const lkc_raceline* rl, const float* pose,
+                             float radius, int32_t* idx, float* points, int64_t capacity,
+                             int64_t* info) {
+    lkc_status s = check_window_call(ctx, rl, pose, radius, capacity);
+    if (s != LKC_OK) return s;
+    if (!info) return set_error(ctx, LKC_ERR_INVALID_ARG, "info is NULL");
+    if (capacity > 0 && !idx) return set_error(ctx, LKC_ERR_INVALID_ARG, "idx is NULL");
+    return lkc::launch_window(ctx, rl, pose, radius, idx, points, capacity, info);
+}
+
+lkc_status lkc_submap_window_build(lkc_ctx* ctx, const lkc_raceline* rl, const float* pose,
+                                   float radius, int32_t* idx, int64_t capacity, int64_t* n_out,
+                                   lkc_target** out) {
+    lkc_status s = check_window_call(ctx, rl, pose, radius, capacity);
+    if (s != LKC_OK) return s;
+    if (!n_out || !out) return set_error(ctx, LKC_ERR_INVALID_ARG, "n_out or out is NULL");
+    *n_out = 0;
+    *out = nullptr;
+    if (capacity > 0 && !idx) return set_error(ctx, LKC_ERR_INVALID_ARG, "idx is NULL");
+    // the window (indices into a buffer that holds any window, points, info)
+    const int64_t mp = rl->max_points > 0 ? rl->max_points : 1;
+    const size_t ib = (4 * (size_t)mp + 255) & ~size_t(255);
+    const size_t pb = (12 * (size_t)mp + 255) & ~size_t(255);
+    void* tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, ib + pb + 64);
+    if (e != hipSuccess)
+        return set_error(ctx, LKC_ERR_OOM, "window buffer: %s", hipGetErrorString(e));
+    int32_t* widx = (int32_t*)tmp;
+    float* wpts = (float*)((char*)tmp + ib);
+    int64_t* winfo = (int64_t*)((char*)tmp + ib + pb);
+    int64_t hinfo[3] = {0, -1, 0};
+    lkc_target* t = nullptr;
+    s = lkc::launch_window(ctx, rl, pose, radius, widx, wpts, mp, winfo);
+    if (s == LKC_OK) {
+        e = hipMemcpyAsync(hinfo, winfo, sizeof(hinfo), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) s = lkc::hip_error(ctx, e, "window read-back");
+    }
+    if (s == LKC_OK) {
+        if (hinfo[2] == LKC_WINDOW_NO_BIN)
+            s = set_error(ctx, LKC_ERR_INVALID_ARG, "the pose is not within the race line's band");
+        else if (hinfo[2] == LKC_WINDOW_UNCOVERED)
+            s = set_error(ctx, LKC_ERR_INVALID_ARG,
+                          "pose distance to its anchor plus radius exceeds the coverage radius");
+        else if (hinfo[2] != LKC_WINDOW_OK)
+            s = set_error(ctx, LKC_ERR_HIP, "window status %lld", (long long)hinfo[2]);
+        else if (idx && hinfo[0] > capacity)
+            s = set_error(ctx, LKC_ERR_BUDGET, "%lld window points exceed the capacity %lld",
+                          (long long)hinfo[0], (long long)capacity);
+    }
+    if (s == LKC_OK) {
+        *n_out = hinfo[0];
+        if (idx && hinfo[0] > 0) {
+            e = hipMemcpyAsync(idx, widx, 4 * (size_t)hinfo[0], hipMemcpyDeviceToDevice,
+                               ctx->stream);
+            if (e != hipSuccess) s = lkc::hip_error(ctx, e, "window indices");
+        }
+    }
+    if (s == LKC_OK) {
+        t = new (std::nothrow) lkc_target();
+        if (!t) s = set_error(ctx, LKC_ERR_OOM, "host allocation");
+    }
+    if (s == LKC_OK) {
+        t->cell_size = rl->map->cell_size;
+        s = lkc::build_into(ctx, t, wpts, hinfo[0]);
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp);
+    if (s != LKC_OK) {
+        if (t) {
+            lkc::free_target_memory(t);
+            delete t;
+        }
+        return s;
+    }
+    *out = t;
+    return LKC_OK;
+}
+
 }  // extern "C"

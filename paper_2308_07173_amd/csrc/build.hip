@@ -666,6 +666,7 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     const float inv_cell = 1.0f / cell;
     TargetView& V = t->view;
     V = TargetView{};
+    ++t->generation;
     V.cell = cell;
     V.inv_cell = inv_cell;
     // the previous build's sort passes: a rebuild launches that many before

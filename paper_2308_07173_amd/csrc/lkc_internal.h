@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/lkc.h"
 #include "lkc_device.h"
@@ -48,6 +49,7 @@ struct lkc_ctx {
 
 struct lkc_target {
     lkc::TargetView view{};
+    uint64_t generation = 0;     // counts builds and rebuilds (race-line indices check it)
     float cell_size = 1.0f;
     int32_t key_bits = 0;
     int32_t sort_passes = 0;
@@ -91,6 +93,48 @@ struct lkc_target_set {
 
 namespace lkc {
 
+// Pose-hash slot of a race-line index: 2-D pose cell (gx, gy) -> bin
+// (gx == INT32_MIN marks an empty slot).
+struct RaceLineSlot {
+    int32_t gx, gy, bin, pad;
+};
+
+// Everything the window kernels read of a race-line index (kernel argument).
+struct RaceLineView {
+    const float4* pts;          // the map's cell-ordered points (w = original index bits)
+    const float4* anchors;      // [bins] anchor of each bin
+    const uint32_t* roff;       // [bins + 1] first range of each bin
+    const uint32_t* tot;        // [bins] points in the bin's ranges
+    const uint32_t* rstart;     // [ranges] first point of each range
+    const uint32_t* rpre;       // [ranges] points of the bin's earlier ranges
+    const RaceLineSlot* hash;   // [hash_mask + 1]
+    uint32_t hash_mask;
+    float inv_grid;             // 1 / pose-cell size
+    float cover;                // coverage radius of every bin's ranges
+};
+
+}  // namespace lkc
+
+struct lkc_raceline {
+    lkc::RaceLineView view{};
+    const lkc_target* map = nullptr;
+    uint64_t map_generation = 0;
+    int64_t map_n = 0;
+    const float4* orig = nullptr;   // the map's points in original order
+    uint32_t* bits = nullptr;       // [words] window bitmap, all zero between calls
+    uint32_t* partials = nullptr;   // [blocks] set bits per block of words
+    int64_t words = 0, blocks = 0;
+    int32_t n_bins = 0;
+    int64_t n_ranges = 0, pose_cells = 0, max_points = 0, sum_points = 0;
+    float bin_length = 0.0f, grid = 0.0f, radius = 0.0f, lateral = 0.0f, cover = 0.0f;
+    std::vector<double> anchors_host;    // [bins][3]
+    std::vector<uint32_t> bin_points;    // [bins]
+    void* mem = nullptr;
+    size_t bytes = 0;
+};
+
+namespace lkc {
+
 lkc_status set_error(lkc_ctx* ctx, lkc_status st, const char* fmt, ...);
 lkc_status hip_error(lkc_ctx* ctx, hipError_t e, const char* what);
 
@@ -117,6 +161,14 @@ lkc_status submap_extract(lkc_ctx* ctx, const lkc_target* t, const float* center
                           int32_t* idx, float* gathered, int64_t cap, int64_t* n_out);
 lkc_status submap_build(lkc_ctx* ctx, const lkc_target* map, const float* center, float radius,
                         int32_t* idx, int64_t cap, int64_t* n_out, lkc_target* out);
+
+// implemented in raceline.hip
+lkc_status raceline_build(lkc_ctx* ctx, const lkc_target* map, const float* line, int64_t m,
+                          float bin_len, float radius, float lateral, lkc_raceline* rl);
+void raceline_free_memory(lkc_raceline* rl);
+// Enqueues the window of `pose` (device float [3]): no synchronisation, no allocation.
+lkc_status launch_window(lkc_ctx* ctx, const lkc_raceline* rl, const float* pose, float radius,
+                         int32_t* idx, float* pts, int64_t cap, int64_t* info);
 
 // implemented in walls.hip
 lkc_status zvote(lkc_ctx* ctx, const float* pts, int64_t n, float g, int32_t tau,

@@ -45,8 +45,16 @@ EXPORTED_SYMBOLS = (
     "lkc_ctx_set_timing", "lkc_ctx_set_profile", "lkc_covariances_weighted",
     "lkc_knn_cov_weighted", "lkc_gicp_linearize", "lkc_gicp_align", "lkc_voxel_filter",
     "lkc_submap_extract", "lkc_submap_build", "lkc_zvote", "lkc_euclid_cluster",
-    "lkc_target_status", "lkc_autotune", "lkc_knn_cov_noalloc",
+    "lkc_target_status", "lkc_autotune", "lkc_knn_cov_noalloc", "lkc_raceline_build",
+    "lkc_raceline_free", "lkc_raceline_get_info", "lkc_raceline_bins", "lkc_submap_window",
+    "lkc_submap_window_build",
 )
+
+# window statuses (info[2] of lkc_submap_window)
+LKC_WINDOW_OK = 0
+LKC_WINDOW_NO_BIN = 1
+LKC_WINDOW_UNCOVERED = 2
+LKC_WINDOW_OVERFLOW = 3
 
 # neighbour weight kernels of lkc_covariances_weighted / lkc_knn_cov_weighted
 WEIGHT_KERNELS = {"none": 0, "rbf": 1, "gaussian": 2, "laplacian": 3}
@@ -85,6 +93,18 @@ class AutotuneResult(ctypes.Structure):
     _fields_ = [("cell_size", ctypes.c_float), ("cfg_index", ctypes.c_int32),
                 ("cfg", LaunchCfg), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32),
                 ("sample", ctypes.c_int64)]
+
+
+class RaceLineInfo(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int64), ("n_ranges", ctypes.c_int64),
+                ("pose_cells", ctypes.c_int64), ("max_bin_points", ctypes.c_int64),
+                ("sum_bin_points", ctypes.c_int64), ("bin_length", ctypes.c_float),
+                ("pose_grid", ctypes.c_float), ("radius", ctypes.c_float),
+                ("lateral", ctypes.c_float), ("cover_radius", ctypes.c_float),
+                ("reserved", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class ScanDesc(ctypes.Structure):
@@ -157,6 +177,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_zvote": ([P, P, I64, F, I32, P, P], I32),
             "lkc_euclid_cluster": ([P, P, I64, F, P, P, ctypes.POINTER(ctypes.c_int64)], I32),
             "lkc_target_status": ([P, P], I32),
+            "lkc_raceline_build": ([P, P, P, I64, F, F, F, PP], I32),
+            "lkc_raceline_free": ([P, P], I32),
+            "lkc_raceline_get_info": ([P, ctypes.POINTER(RaceLineInfo)], I32),
+            "lkc_raceline_bins": ([P, P, P], I32),
+            "lkc_submap_window": ([P, P, P, F, P, P, I64, P], I32),
+            "lkc_submap_window_build": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64),
+                                         PP], I32),
             "lkc_autotune": ([P, P, I64, P, I64, I32, F, F, P, I32, P, I32, I64,
                               ctypes.c_uint64, I32, P, ctypes.POINTER(AutotuneResult)], I32),
         }
@@ -595,6 +622,119 @@ def lkc_submap_build(ctx: Context, target: Target, center, radius: float, with_i
                                        c.ctypes.data_as(ctypes.c_void_p), float(radius),
                                        ctypes.c_void_p(_ptr(idx)), n if with_idx else 0,
                                        ctypes.byref(m), ctypes.byref(h)))
+    return Target(ctx, h), (idx[:m.value] if with_idx else None)
+
+
+class RaceLine:
+    """A race-line keyed index of a map target (``lkc_raceline``)."""
+
+    def __init__(self, ctx: Context, handle: ctypes.c_void_p, target: Target):
+        self.ctx = ctx
+        self.handle = handle
+        self.target = target      # the map must outlive the index
+
+    def info(self) -> Dict:
+        inf = RaceLineInfo()
+        self.ctx.check(self.ctx.lib.lkc_raceline_get_info(self.handle, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def bins(self):
+        """(anchors float32 [bins, 3], points per bin int64 [bins]) on the host."""
+        import numpy as np
+        b = self.info()["n_bins"]
+        a = np.empty((b, 3), np.float32)
+        c = np.empty(b, np.int64)
+        self.ctx.check(self.ctx.lib.lkc_raceline_bins(self.handle,
+                                                      a.ctypes.data_as(ctypes.c_void_p),
+                                                      c.ctypes.data_as(ctypes.c_void_p)))
+        return a, c
+
+    def free(self):
+        if self.handle:
+            self.ctx._bind()
+            self.ctx.lib.lkc_raceline_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle and self.ctx.handle:
+                self.free()
+        except Exception:  # pragma: no cover
+            pass
+
+
+def lkc_raceline_build(ctx: Context, target: Target, line, bin_length: float, radius: float,
+                       lateral: float) -> RaceLine:
+    """Race-line index of ``target``: ``line`` is the closed race line, host
+    float [m, 3] in driving order."""
+    import numpy as np
+    ln = np.ascontiguousarray(line, np.float32)
+    if ln.ndim != 2 or ln.shape[1] != 3:
+        raise ValueError("line must be [m, 3]")
+    h = ctypes.c_void_p()
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_raceline_build(ctx.handle, target.handle,
+                                         ln.ctypes.data_as(ctypes.c_void_p), ln.shape[0],
+                                         float(bin_length), float(radius), float(lateral),
+                                         ctypes.byref(h)))
+    return RaceLine(ctx, h, target)
+
+
+def _pose_dev(pose):
+    torch = _torch()
+    if isinstance(pose, torch.Tensor) and pose.is_cuda:
+        _check_dev(pose, "pose", torch.float32)
+        if pose.numel() != 3:
+            raise ValueError("pose must hold 3 floats")
+        return pose
+    import numpy as np
+    p = np.ascontiguousarray(pose, np.float32).reshape(3)
+    return torch.from_numpy(p).to(torch.device("cuda", torch.cuda.current_device()))
+
+
+def lkc_submap_window(ctx: Context, rl: RaceLine, pose, radius: float, capacity=None,
+                      with_points: bool = False, out=None):
+    """Enqueue the window of ``pose`` (no synchronisation).  Returns device
+    tensors (idx int32 [capacity], points float32 [capacity, 3] or None,
+    info int64 [3] = count, bin, status); ``out`` may pass those three
+    buffers in (for graph capture).  The first ``info[0]`` entries of idx
+    are the window."""
+    torch = _torch()
+    pose = _pose_dev(pose)
+    if out is None:
+        cap = rl.info()["max_bin_points"] if capacity is None else int(capacity)
+        dev = pose.device
+        idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        pts = torch.empty(max(cap, 1), 3, dtype=torch.float32, device=dev) if with_points \
+            else None
+        info = torch.empty(3, dtype=torch.int64, device=dev)
+    else:
+        idx, pts, info = out
+        cap = idx.shape[0] if capacity is None else int(capacity)
+        if cap > idx.shape[0] or (pts is not None and cap > pts.shape[0]):
+            raise ValueError("capacity exceeds the output buffers")
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_submap_window(ctx.handle, rl.handle, ctypes.c_void_p(_ptr(pose)),
+                                        float(radius), ctypes.c_void_p(_ptr(idx)),
+                                        ctypes.c_void_p(_ptr(pts)), cap,
+                                        ctypes.c_void_p(_ptr(info))))
+    return idx, pts, info
+
+
+def lkc_submap_window_build(ctx: Context, rl: RaceLine, pose, radius: float,
+                            with_idx: bool = True):
+    """The window of ``pose`` built into a new Target; returns (Target, idx)."""
+    torch = _torch()
+    pose = _pose_dev(pose)
+    cap = rl.info()["max_bin_points"]
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=pose.device) if with_idx else None
+    m = ctypes.c_int64(0)
+    h = ctypes.c_void_p()
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_submap_window_build(ctx.handle, rl.handle, ctypes.c_void_p(_ptr(pose)),
+                                              float(radius), ctypes.c_void_p(_ptr(idx)),
+                                              cap if with_idx else 0, ctypes.byref(m),
+                                              ctypes.byref(h)))
     return Target(ctx, h), (idx[:m.value] if with_idx else None)
 
 
