@@ -162,7 +162,7 @@ lkc_status lkc_synchronize(lkc_ctx *ctx);
 
 /* Build the hashed voxel grid of `points` [n][3] (device) with cubic cells
  * of edge `cell_size` (metres, > 0).  Points are keyed by integer cell
- * coordinates floor(p / cell_size) (clamped to [-2^20, 2^20)), sorted by a
+ * coordinates floor(p * (1 / cell_size)) in [-2^20, 2^20), sorted by a
  * compact key with an LSD radix sort, reordered into cell runs, and the
  * occupied cells are inserted into an open-addressed hash (Sec. III-C.3's
  * GPU hash map).  The key layout and the hash size are derived on the
@@ -171,8 +171,9 @@ lkc_status lkc_synchronize(lkc_ctx *ctx);
  * build's number of passes and sorts again only if the new key needs
  * more).  The hash and cell arrays are sized by n.  The caller's buffer may
  * be reused once this call returns.  n = 0 builds an
- * empty target.  A non-finite coordinate fails with LKC_ERR_NONFINITE and
- * returns no target. */
+ * empty target.  A non-finite coordinate fails with LKC_ERR_NONFINITE, a
+ * cell coordinate outside [-2^20, 2^20) (e.g. |x| > 104.8 km at 0.1 m
+ * cells) with LKC_ERR_INVALID_ARG; either returns no target. */
 lkc_status lkc_build_target(lkc_ctx *ctx, const float *points, int64_t n, float cell_size,
                             lkc_target **out);
 /* Rebuild `target` in place from new points (same cell size), reusing its

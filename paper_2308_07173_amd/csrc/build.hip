@@ -44,10 +44,14 @@ constexpr int RAW_RUN_BLOCKS = 2048;  // cell-run numbering of up to this many b
 // Written by the build kernels: the occupied-cell box, and the key layout
 // and hash size derived from it on the device, so that the kernels after
 // the box need no host round trip.
+// BuildMeta::nonfinite bits
+constexpr int BAD_NONFINITE = 1;   // a coordinate is NaN or infinite
+constexpr int BAD_RANGE = 2;       // a cell coordinate falls outside [-2^20, 2^20)
+
 struct BuildMeta {
     int cmin[3];
     int cmax[3];
-    int nonfinite;
+    int nonfinite;          // BAD_* bits
     uint32_t n_cells;
     uint32_t max_abs_bits;  // float bits of max |coordinate| (non-negative floats order as uints)
     int sh_y, sh_z;         // row-major cell key: kx | ky << sh_y | kz << sh_z
@@ -67,6 +71,11 @@ __device__ __forceinline__ int wave_min(int v) {
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int s = 32; s > 0; s >>= 1) v = max(v, __shfl_xor(v, s));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v |= __shfl_xor(v, s);
     return v;
 }
 __device__ __forceinline__ uint32_t wave_maxu(uint32_t v) {
@@ -97,8 +106,13 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
         const float x = p[3 * i], y = p[3 * i + 1], z = p[3 * i + 2];
         orig[i] = make_float4(x, y, z, 0.0f);
         if (!finite3(x, y, z)) {
-            bad = 1;
+            bad = BAD_NONFINITE;
         } else {
+            // cell coordinates beyond [-2^20, 2^20) would be clamped into an
+            // edge cell whose box does not hold the point: refused
+            const float f[3] = {floorf(x * inv_cell), floorf(y * inv_cell), floorf(z * inv_cell)};
+            for (int a = 0; a < 3; ++a)
+                if (!(f[a] >= -(float)CELL_CLAMP && f[a] < (float)CELL_CLAMP)) bad = BAD_RANGE;
             const int c[3] = {cell_coord(x, inv_cell), cell_coord(y, inv_cell),
                               cell_coord(z, inv_cell)};
             for (int a = 0; a < 3; ++a) mn[a] = mx[a] = c[a];
@@ -116,7 +130,7 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
         }
     }
     const uint32_t vab = wave_maxu(mabs);
-    const int vbad = wave_max(bad);
+    const int vbad = wave_or(bad);
     if (l == 0) {
         s_abs[w] = vab;
         s_bad[w] = vbad;
@@ -167,7 +181,7 @@ __global__ void __launch_bounds__(1024) k_meta_reduce(const MetaPart* __restrict
         }
     }
     const uint32_t vab = wave_maxu(ab);
-    const int vbad = wave_max(bad);
+    const int vbad = wave_or(bad);
     if (l == 0) {
         s_ab[w] = vab;
         s_bad[w] = vbad;
@@ -806,6 +820,13 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
         hipLaunchKernelGGL(k_meta_reduce, dim3(1), dim3(1024), 0, st, (const MetaPart*)mparts,
                            nb_bt, meta);
         LKC_HIP_TRY(ctx, hipGetLastError());
+        auto refuse = [&]() {
+            V.n = 0;
+            if (hmeta->nonfinite & BAD_NONFINITE)
+                return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
+            return set_error(ctx, LKC_ERR_INVALID_ARG,
+                             "a target point's cell coordinate (|p| / cell) reaches 2^20");
+        };
         // A first build reads the box (and the passes it needs) back first;
         // a rebuild runs on with the previous build's passes.
         int passes = prev_passes;
@@ -813,18 +834,12 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
             LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta),
                                             hipMemcpyDeviceToHost, st));
             LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
-            if (hmeta->nonfinite) {
-                V.n = 0;
-                return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
-            }
+            if (hmeta->nonfinite) return refuse();
             passes = hmeta->passes;
         }
         s = enqueue(passes);
         if (s != LKC_OK) return s;
-        if (hmeta->nonfinite) {
-            V.n = 0;
-            return set_error(ctx, LKC_ERR_NONFINITE, "target has a non-finite coordinate");
-        }
+        if (hmeta->nonfinite) return refuse();
         if (hmeta->passes > passes) {
             // the key outgrew the previous build's passes: sort again in full
             s = enqueue(hmeta->passes);

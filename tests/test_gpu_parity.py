@@ -170,6 +170,42 @@ def test_build_empty_and_nonfinite(lk):
 
 # ------------------------------------------------------------------ kNN --
 
+
+def test_build_refuses_cell_coordinates_past_the_key_range(lk):
+    """Cell coordinates must lie in [-2^20, 2^20): a point beyond (here
+    x = 110 km at 0.1 m cells) fails the build instead of sharing a clamped
+    edge cell whose box does not hold it; the last cell inside builds."""
+    lkc, ctx = lk
+    p = workloads.random_cloud(1000, seed=41, scale=5.0)
+    far = p.copy()
+    far[17, 0] = 110_000.0
+    with pytest.raises(lkc.LkcError) as e:
+        lkc.lkc_build_target(ctx, dev(far), 0.1)
+    assert e.value.status == lkc.LKC_ERR_INVALID_ARG
+    far[17, 0] = -110_000.0
+    with pytest.raises(lkc.LkcError) as e:
+        lkc.lkc_build_target(ctx, dev(far), 0.1)
+    assert e.value.status == lkc.LKC_ERR_INVALID_ARG
+    # a rebuild with such a point leaves the target empty with that status
+    t = lkc.lkc_build_target(ctx, dev(p), 0.1)
+    with pytest.raises(lkc.LkcError):
+        t.rebuild(dev(far))
+    assert t.status() == lkc.LKC_ERR_INVALID_ARG
+    t.rebuild(dev(p))
+    assert t.status() == lkc.LKC_OK
+    t.free()
+    # just inside: floor(x / 1) = 2^20 - 1 and -2^20
+    edge = p.copy()
+    edge[3, 0] = float((1 << 20) - 1) + 0.5
+    edge[4, 1] = -float(1 << 20) + 0.25
+    t = lkc.lkc_build_target(ctx, dev(edge), 1.0)
+    assert t.info()["n_points"] == 1000
+    idx, d2, cnt = (x.cpu().numpy() for x in lkc.lkc_knn_query(ctx, t, dev(edge[3:5]), 1, 1.0))
+    np.testing.assert_array_equal(idx[:, 0], [3, 4])
+    np.testing.assert_array_equal(cnt, [1, 1])
+    t.free()
+
+
 @pytest.mark.parametrize("shape,k", [((64,), 1), ((64,), 2), ((64,), 7), ((64,), 8),
                                      ((9, 9), 7), ((5, 5, 5), 9), ((6, 7, 5), 27), ((10, 10), 64)])
 @pytest.mark.parametrize("cell", [0.7, 1.0, 2.5])
