@@ -548,13 +548,14 @@ def main():
             k, radius, cell = 20, 2.0, 1.0
             config = {"workload": "one 128x1024 spinning-LiDAR scan, self-query",
                       "n_points": int(pts.shape[0]), "k": k, "radius_m": radius,
-                      "cell_m": cell, "step": "grid rebuild + fused kNN+covariance"}
+                      "cell_m": cell,
+                      "step": "grid rebuild (asynchronous) + fused kNN+covariance"}
         else:
             pts = workloads.plane_wall(2048, seed=0)
             k, radius, cell = 10, math.inf, 1.0
             config = {"workload": "2048-point plane + wall, self-query", "n_points": 2048,
                       "k": k, "radius_m": None, "cell_m": cell,
-                      "step": "grid rebuild + fused kNN+covariance"}
+                      "step": "grid rebuild (asynchronous) + fused kNN+covariance"}
             if not args.no_autotune and not args.cfg:
                 # the launch shape only (the cell is the configuration's)
                 from paper_2308_07173_amd import autotune
@@ -568,7 +569,7 @@ def main():
         out = lkc.lkc_knn_cov_self(ctx, tgt, k, radius, 1e-3, cfg=cfg)
 
         def step(kstart=None, kend=None):
-            tgt.rebuild(p)
+            tgt.rebuild(p, sync=False)
             if kstart is not None:
                 kstart.record(stream)
             lkc.lkc_knn_cov_self(ctx, tgt, k, radius, 1e-3, out=out, cfg=cfg)

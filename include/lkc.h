@@ -180,6 +180,22 @@ lkc_status lkc_build_target(lkc_ctx *ctx, const float *points, int64_t n, float 
  * device memory when large enough.  Same semantics as lkc_build_target; on
  * error the target is left empty (n = 0) but still valid to free. */
 lkc_status lkc_target_rebuild(lkc_ctx *ctx, lkc_target *target, const float *points, int64_t n);
+/* The same rebuild (Sec. III-C.3: the per-scan GPU hash map) with no host
+ * round trip, when the target's memory already holds n points and it has
+ * been built before: the key layout is fitted on the device to the previous
+ * build's sort passes (the sub-cell bits below the cell key give way first),
+ * and the device writes the target's view.  Nothing is synchronised, so a
+ * scan can be rebuilt and searched back to back on one stream.  Errors found
+ * on the device (a non-finite or out-of-range coordinate:
+ * LKC_ERR_NONFINITE / LKC_ERR_INVALID_ARG; a cell key that no longer fits
+ * the passes: LKC_ERR_UNSUPPORTED) leave the target empty -- searches then
+ * return count 0 -- and are reported by lkc_target_status, as after a failed
+ * lkc_target_rebuild.  The first call after it that needs the target's
+ * host-side layout (every call but lkc_knn_cov_self) synchronises once to
+ * read that layout back.  The first build of a target is always
+ * synchronous. */
+lkc_status lkc_target_rebuild_async(lkc_ctx *ctx, lkc_target *target, const float *points,
+                                    int64_t n);
 /* Free a target.  Synchronises the context's stream first, so work already
  * enqueued that reads the target completes.  NULL is a no-op. */
 lkc_status lkc_target_free(lkc_ctx *ctx, lkc_target *target);

@@ -60,7 +60,19 @@ lkc_status check_k_radius(lkc_ctx* ctx, int32_t k, float radius) {
     return LKC_OK;
 }
 
+// A target whose host-side view is current (read back after an
+// asynchronous rebuild, which synchronises once).
 lkc_status check_target(lkc_ctx* ctx, const lkc_target* t) {
+    if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
+    if (!t->cell_mem || !t->view_dev)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "target is not built");
+    if (t->host_stale) return lkc::refresh_host_view(ctx, const_cast<lkc_target*>(t));
+    return LKC_OK;
+}
+
+// A built target, whatever the state of its host-side view (for the calls
+// that read only the device view).
+lkc_status check_target_device(lkc_ctx* ctx, const lkc_target* t) {
     if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
     if (!t->cell_mem || !t->view_dev)
         return set_error(ctx, LKC_ERR_INVALID_ARG, "target is not built");
@@ -96,7 +108,8 @@ lkc_status lkc_ctx_create(void* hip_stream, lkc_ctx** out) {
     (void)hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (c->num_cus <= 0) c->num_cus = 256;
     if (hipMalloc(&c->meta_dev, META_BYTES) != hipSuccess ||
-        hipHostMalloc(&c->meta_host, META_BYTES, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&c->meta_host, META_BYTES, hipHostMallocDefault) != hipSuccess ||
+        hipMemset(c->meta_dev, 0, META_BYTES) != hipSuccess) {   // block counters start at 0
         if (c->meta_dev) (void)hipFree(c->meta_dev);
         delete c;
         return set_error(nullptr, LKC_ERR_OOM, "context buffers");
@@ -191,11 +204,38 @@ lkc_status lkc_target_rebuild(lkc_ctx* ctx, lkc_target* t, const float* points, 
     return LKC_OK;
 }
 
+lkc_status lkc_target_rebuild_async(lkc_ctx* ctx, lkc_target* t, const float* points,
+                                    int64_t n) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (n > 0 && !points) return set_error(ctx, LKC_ERR_INVALID_ARG, "points is NULL");
+    s = lkc::build_into(ctx, t, points, n, true);
+    if (s != LKC_OK) {
+        const lkc_status keep = s;
+        const std::string msg = ctx->err;
+        if (lkc::build_into(ctx, t, nullptr, 0) == LKC_OK) ctx->err = msg;
+        t->status = keep;
+        return keep;
+    }
+    if (!t->host_stale) t->status = LKC_OK;   // else the device's status, when read back
+    return LKC_OK;
+}
+
 lkc_status lkc_target_status(lkc_ctx* ctx, const lkc_target* t) {
     lkc_status s = check_ctx(ctx);
     if (s != LKC_OK) return s;
     if (!t) return set_error(ctx, LKC_ERR_INVALID_ARG, "target is NULL");
     LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (t->host_stale && t->view_dev) {
+        s = lkc::refresh_host_view(ctx, const_cast<lkc_target*>(t));
+        if (s != LKC_OK) return s;
+    }
+    if (t->status == LKC_ERR_UNSUPPORTED)
+        return set_error(ctx, t->status, "the last asynchronous rebuild's cell key outgrew its "
+                                         "sort passes (rebuild synchronously)");
     if (t->status != LKC_OK)
         return set_error(ctx, t->status, "the target's last rebuild failed (status %d)",
                          (int)t->status);
@@ -212,6 +252,8 @@ lkc_status lkc_target_free(lkc_ctx* ctx, lkc_target* t) {
 
 lkc_status lkc_target_get_info(const lkc_target* t, lkc_target_info* info) {
     if (!t || !info) return set_error(nullptr, LKC_ERR_INVALID_ARG, "NULL argument");
+    if (t->host_stale && t->view_dev)
+        (void)lkc::refresh_host_view_device(const_cast<lkc_target*>(t));
     info->n_points = t->view.n;
     info->n_cells = t->view.n_cells;
     info->hash_capacity = t->hash_capacity;
@@ -648,7 +690,7 @@ lkc_status lkc_knn_cov_self(lkc_ctx* ctx, const lkc_target* t, int32_t k, float 
                             const lkc_launch_cfg* cfg) {
     lkc_status s = check_ctx(ctx);
     if (s != LKC_OK) return s;
-    if ((s = check_target(ctx, t)) != LKC_OK) return s;
+    if ((s = check_target_device(ctx, t)) != LKC_OK) return s;
     if ((s = check_k_radius(ctx, k, radius)) != LKC_OK) return s;
     if (valid && (s = check_eps(ctx, plane_eps)) != LKC_OK) return s;
     if (t->view.n > 0 && (!idx || !d2 || !count))

@@ -47,6 +47,7 @@ constexpr int RAW_RUN_BLOCKS = 2048;  // cell-run numbering of up to this many b
 // BuildMeta::nonfinite bits
 constexpr int BAD_NONFINITE = 1;   // a coordinate is NaN or infinite
 constexpr int BAD_RANGE = 2;       // a cell coordinate falls outside [-2^20, 2^20)
+constexpr int BAD_PASSES = 4;      // the cell key outgrew a rebuild's fixed sort passes
 
 struct BuildMeta {
     int cmin[3];
@@ -85,7 +86,7 @@ __device__ __forceinline__ uint32_t wave_maxu(uint32_t v) {
 }
 
 // Per-block partial of the occupied-cell box, the finiteness flag and the
-// largest |coordinate|; one record per block, combined by k_meta_reduce
+// largest |coordinate|; one record per block, combined by the last block
 // (no contended atomics).
 struct MetaPart {
     int cmin[3];
@@ -94,9 +95,101 @@ struct MetaPart {
     uint32_t abs_bits;
 };
 
+// Combines the per-block parts into the meta record, by one whole block:
+// box, finiteness, largest |coordinate|, and the key layout.  With
+// fixed_passes = 0 the layout takes the fewest 8-bit sort passes that hold
+// the cell key and 2 sub-cell bits per axis, then the most sub-cell bits
+// (<= 4) those passes hold; a rebuild passes its previous pass count and the
+// layout fits into it (sub-cell bits only order points inside a cell), or
+// flags BAD_PASSES when even the cell key does not fit.
+__device__ void meta_combine(const MetaPart* __restrict__ parts, int64_t np,
+                             BuildMeta* __restrict__ meta, int fixed_passes) {
+    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
+    int bad = 0;
+    uint32_t ab = 0;
+    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
+        const MetaPart m = parts[i];
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = min(mn[a], m.cmin[a]);
+            mx[a] = max(mx[a], m.cmax[a]);
+        }
+        bad |= m.bad;
+        ab = max(ab, m.abs_bits);
+    }
+    __shared__ int s_mn[3][16], s_mx[3][16], s_bad[16];
+    __shared__ uint32_t s_ab[16];
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    for (int a = 0; a < 3; ++a) {
+        const int vmn = wave_min(mn[a]), vmx = wave_max(mx[a]);
+        if (l == 0) {
+            s_mn[a][w] = vmn;
+            s_mx[a][w] = vmx;
+        }
+    }
+    const uint32_t vab = wave_maxu(ab);
+    const int vbad = wave_or(bad);
+    if (l == 0) {
+        s_ab[w] = vab;
+        s_bad[w] = vbad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / WAVE;
+        for (int a = 0; a < 3; ++a) {
+            int vmn = INT_MAX, vmx = INT_MIN;
+            for (int j = 0; j < nw; ++j) {
+                vmn = min(vmn, s_mn[a][j]);
+                vmx = max(vmx, s_mx[a][j]);
+            }
+            meta->cmin[a] = vmn;
+            meta->cmax[a] = vmx;
+        }
+        int vb = 0;
+        uint32_t va = 0;
+        for (int j = 0; j < nw; ++j) {
+            vb |= s_bad[j];
+            va = max(va, s_ab[j]);
+        }
+        meta->max_abs_bits = va;
+        meta->n_cells = 0;
+        meta->hash_bits = 6;
+        int bits[3] = {0, 0, 0}, wmax = 0;
+        if (!vb)
+            for (int a = 0; a < 3; ++a) {
+                const uint32_t e = (uint32_t)(meta->cmax[a] - meta->cmin[a]);
+                bits[a] = e ? 32 - __clz((int)e) : 0;
+                wmax = max(wmax, bits[a]);
+            }
+        int sub, passes;
+        if (fixed_passes > 0) {
+            const int room = min(63, 8 * fixed_passes);
+            if (3 * wmax > room) vb |= BAD_PASSES;
+            sub = max(0, min(4, (room - 3 * wmax) / 3));
+            passes = fixed_passes;
+        } else {
+            const int sub_lo = max(0, min(2, (63 - 3 * wmax) / 3));
+            const int room = min(63, 8 * ((3 * wmax + 3 * sub_lo + 7) / 8));
+            sub = max(sub_lo, min(4, (room - 3 * wmax) / 3));
+            passes = (3 * wmax + 3 * sub + 7) / 8;
+        }
+        meta->nonfinite = vb;
+        meta->sh_y = bits[0];
+        meta->sh_z = bits[0] + bits[1];
+        meta->sub_bits = sub;
+        meta->key_bits = 3 * wmax + 3 * sub;
+        meta->passes = passes;
+    }
+}
+
+// One record per point (orig, w = 0) and the per-block part of the box;
+// the last block to finish (counted on `done`, which it resets) combines
+// the parts into `meta`.
 __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p, int64_t n,
                                                     float inv_cell, float4* __restrict__ orig,
-                                                    MetaPart* __restrict__ parts) {
+                                                    MetaPart* __restrict__ parts,
+                                                    BuildMeta* __restrict__ meta,
+                                                    uint32_t* __restrict__ done,
+                                                    int fixed_passes) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX};
     int mx[3] = {INT_MIN, INT_MIN, INT_MIN};
@@ -154,79 +247,17 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
         }
         parts[blockIdx.x] = m;
     }
-}
-
-__global__ void __launch_bounds__(1024) k_meta_reduce(const MetaPart* __restrict__ parts,
-                                                      int64_t np, BuildMeta* __restrict__ meta) {
-    int mn[3] = {INT_MAX, INT_MAX, INT_MAX}, mx[3] = {INT_MIN, INT_MIN, INT_MIN};
-    int bad = 0;
-    uint32_t ab = 0;
-    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
-        const MetaPart m = parts[i];
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = min(mn[a], m.cmin[a]);
-            mx[a] = max(mx[a], m.cmax[a]);
-        }
-        bad |= m.bad;
-        ab = max(ab, m.abs_bits);
-    }
-    __shared__ int s_mn[3][16], s_mx[3][16], s_bad[16];
-    __shared__ uint32_t s_ab[16];
-    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
-    for (int a = 0; a < 3; ++a) {
-        const int vmn = wave_min(mn[a]), vmx = wave_max(mx[a]);
-        if (l == 0) {
-            s_mn[a][w] = vmn;
-            s_mx[a][w] = vmx;
-        }
-    }
-    const uint32_t vab = wave_maxu(ab);
-    const int vbad = wave_or(bad);
-    if (l == 0) {
-        s_ab[w] = vab;
-        s_bad[w] = vbad;
-    }
+    // the part is visible device-wide before the block is counted; the last
+    // block's fence makes every part visible to it
+    __shared__ int s_last;
+    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = blockDim.x / WAVE;
-        for (int a = 0; a < 3; ++a) {
-            int vmn = INT_MAX, vmx = INT_MIN;
-            for (int j = 0; j < nw; ++j) {
-                vmn = min(vmn, s_mn[a][j]);
-                vmx = max(vmx, s_mx[a][j]);
-            }
-            meta->cmin[a] = vmn;
-            meta->cmax[a] = vmx;
-        }
-        int vb = 0;
-        uint32_t va = 0;
-        for (int j = 0; j < nw; ++j) {
-            vb |= s_bad[j];
-            va = max(va, s_ab[j]);
-        }
-        meta->nonfinite = vb;
-        meta->max_abs_bits = va;
-        meta->n_cells = 0;
-        meta->hash_bits = 6;
-        // key layout: the cell's Morton key relative to the box, then the
-        // sub-cell's (2^s per axis: the fewest 8-bit passes that hold the
-        // cell key and s = 2, then the largest s <= 4 those passes hold)
-        int bits[3] = {0, 0, 0}, wmax = 0;
-        if (!vb)
-            for (int a = 0; a < 3; ++a) {
-                const uint32_t e = (uint32_t)(meta->cmax[a] - meta->cmin[a]);
-                bits[a] = e ? 32 - __clz((int)e) : 0;
-                wmax = max(wmax, bits[a]);
-            }
-        const int sub_lo = max(0, min(2, (63 - 3 * wmax) / 3));
-        const int room = min(63, 8 * ((3 * wmax + 3 * sub_lo + 7) / 8));
-        const int sub = max(sub_lo, min(4, (room - 3 * wmax) / 3));
-        meta->sh_y = bits[0];
-        meta->sh_z = bits[0] + bits[1];
-        meta->sub_bits = sub;
-        meta->key_bits = 3 * wmax + 3 * sub;
-        meta->passes = (3 * wmax + 3 * sub + 7) / 8;
-    }
+    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    meta_combine(parts, gridDim.x, meta, fixed_passes);
+    if (threadIdx.x == 0) *done = 0u;
 }
 
 // Sort keys; the threads also clear the hash's slots (all `cap` of them,
@@ -511,16 +542,46 @@ __global__ void k_hash_clear(HashSlot* __restrict__ h, const BuildMeta* __restri
     if (i < cap) h[i] = HashSlot{EMPTY_KEY, 0u, 0u};
 }
 
+// The view a build leaves on the device: `base` (pointers, n, cell) with
+// the fields derived on the device; a failed build leaves an empty view.
+// status: {lkc_status, key bits, BAD_* bits}.
+__device__ void write_view(const BuildMeta* __restrict__ meta, const TargetView& base,
+                           TargetView* __restrict__ out, int32_t* __restrict__ status) {
+    TargetView v = base;
+    const int bad = meta->nonfinite;
+    for (int a = 0; a < 3; ++a) {
+        v.cmin[a] = bad ? 0 : meta->cmin[a];
+        v.cmax[a] = bad ? -1 : meta->cmax[a];
+    }
+    v.max_abs = __uint_as_float(meta->max_abs_bits);
+    v.sh_y = meta->sh_y;
+    v.sh_z = meta->sh_z;
+    v.n_cells = bad ? 0 : (int32_t)meta->n_cells;
+    v.hash_bits = meta->hash_bits;
+    v.hash_mask = (uint32_t)((1ull << meta->hash_bits) - 1ull);
+    if (bad) v.n = 0;
+    *out = v;
+    status[0] = (bad & BAD_NONFINITE) ? (int32_t)LKC_ERR_NONFINITE
+                : (bad & BAD_RANGE)   ? (int32_t)LKC_ERR_INVALID_ARG
+                : bad                 ? (int32_t)LKC_ERR_UNSUPPORTED
+                                      : (int32_t)LKC_OK;
+    status[1] = meta->key_bits;
+    status[2] = bad;
+}
+
 __global__ void __launch_bounds__(BT) k_hash_insert(const unsigned long long* __restrict__ tkeys,
                                                     const uint32_t* __restrict__ tstart,
                                                     const BuildMeta* __restrict__ meta, int64_t n,
                                                     unsigned long long* __restrict__ ckeys,
                                                     uint32_t* __restrict__ cstart,
-                                                    HashSlot* __restrict__ hash) {
+                                                    HashSlot* __restrict__ hash,
+                                                    TargetView base, TargetView* __restrict__ vout,
+                                                    int32_t* __restrict__ status) {
     const int64_t n_cells = meta->n_cells;
     const int bits = meta->hash_bits;
     const uint32_t mask = (uint32_t)((1ull << bits) - 1ull);
     const int64_t c = (int64_t)blockIdx.x * BT + threadIdx.x;
+    if (vout && c == 0) write_view(meta, base, vout, status);
     if (c >= n_cells) return;
     const unsigned long long key = tkeys[c];
     const uint32_t st = tstart[c];
@@ -674,7 +735,47 @@ void free_target_memory(lkc_target* t) {
     t->point_bytes = t->cell_bytes = 0;
 }
 
-lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n) {
+size_t view_status_offset() { return (sizeof(TargetView) + 63) & ~size_t(63); }
+size_t view_alloc_bytes() { return view_status_offset() + 64; }
+
+namespace {
+
+// Takes the read-back device view; an asynchronous rebuild that failed on
+// the device left the target empty and its error in t->status (reported by
+// lkc_target_status, as after a failed synchronous rebuild).
+void take_device_view(lkc_target* t) {
+    const int32_t* w = (const int32_t*)((const char*)t->view_host + view_status_offset());
+    const TargetView& d = *(const TargetView*)t->view_host;
+    t->view = d;
+    t->key_bits = w[1];
+    t->hash_capacity = (int64_t)1 << d.hash_bits;
+    t->host_stale = false;
+    t->status = (lkc_status)w[0];
+    if (w[0] != LKC_OK) t->sort_passes = 0;   // the next rebuild lays the key out afresh
+}
+
+}  // namespace
+
+lkc_status refresh_host_view(lkc_ctx* ctx, lkc_target* t) {
+    if (!t->host_stale) return LKC_OK;
+    LKC_HIP_TRY(ctx, hipMemcpyAsync(t->view_host, t->view_dev, view_alloc_bytes(),
+                                    hipMemcpyDeviceToHost, ctx->stream));
+    LKC_HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    take_device_view(t);
+    return LKC_OK;
+}
+
+lkc_status refresh_host_view_device(lkc_target* t) {
+    if (!t->host_stale) return LKC_OK;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(t->view_host, t->view_dev, view_alloc_bytes(), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+        return set_error(nullptr, LKC_ERR_HIP, "reading the target's device view");
+    take_device_view(t);
+    return LKC_OK;
+}
+
+lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n, bool async) {
     hipStream_t st = ctx->stream;
     const float cell = t->cell_size;
     const float inv_cell = 1.0f / cell;
@@ -777,9 +878,21 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     auto* cstart = (uint32_t*)((char*)t->cell_mem + ck_b);
     auto* hash = (HashSlot*)((char*)t->cell_mem + ck_b + cs_b);
 
+    // A rebuild into memory that already holds it may run without any host
+    // round trip: the key layout is fitted to the previous build's sort
+    // passes on the device, the device writes the view, and failures
+    // (non-finite or out-of-range coordinates, a cell key that outgrew the
+    // passes) leave an empty view and a status read at the next call that
+    // needs the host-side view.
+    const bool fast = async && prev_passes > 0 && n > 0 && t->view_dev &&
+                      t->point_bytes >= 2 * pbytes + bx_b && t->cell_bytes >= cbytes &&
+                      ctx->build_scratch_bytes >= off;
+    uint32_t* done_ctr = (uint32_t*)((char*)ctx->meta_dev + 64);
+
     // Steps 2-6 for a sort of `passes` 8-bit passes; every layout parameter
-    // is read from the device meta.
-    auto enqueue = [&](int passes) -> lkc_status {
+    // is read from the device meta.  With `vout` the hash kernel writes the
+    // device view (from `base`) and nothing is read back.
+    auto enqueue = [&](int passes, const TargetView* base) -> lkc_status {
         unsigned long long *ka = keys_a, *kb = keys_b;
         uint32_t *va = vals_a, *vb = vals_b;
         // ---- 2. keys
@@ -803,22 +916,46 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
                            (const float4*)pts, n, inv_cell, bcounts, tkeys, tstart, meta,
                            raw_runs);
         // ---- 6. hash (cleared by k_make_keys)
+        TargetView* vout = base ? t->view_dev : nullptr;
+        int32_t* stw = base ? (int32_t*)((char*)t->view_dev + view_status_offset()) : nullptr;
         hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(n, BT)), dim3(BT), 0, st, tkeys, tstart,
-                           (const BuildMeta*)meta, n, ckeys, cstart, hash);
+                           (const BuildMeta*)meta, n, ckeys, cstart, hash,
+                           base ? *base : TargetView{}, vout, stw);
         LKC_HIP_TRY(ctx, hipGetLastError());
+        if (base) return LKC_OK;
         LKC_HIP_TRY(ctx, hipMemcpyAsync(hmeta, meta, sizeof(BuildMeta), hipMemcpyDeviceToHost, st));
         LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
         return LKC_OK;
     };
+
+    if (fast) {
+        hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
+                           inv_cell, orig, mparts, meta, done_ctr, prev_passes);
+        V.pts = pts;
+        V.orig = orig;
+        V.hash = hash;
+        V.cell_keys = ckeys;
+        V.cell_start = cstart;
+        V.boxes = boxes;
+        V.n = n;
+        for (int a = 0; a < 3; ++a) {
+            V.cmin[a] = 0;
+            V.cmax[a] = -1;
+        }
+        s = enqueue(prev_passes, &V);
+        if (s != LKC_OK) return s;
+        t->sort_passes = prev_passes;
+        t->host_stale = true;
+        t->status = LKC_OK;
+        return LKC_OK;
+    }
 
     int64_t n_cells = 0;
     int hbits = 6;
     if (n > 0) {
         // ---- 1. cell coordinates, bounding box, finiteness, key layout
         hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
-                           inv_cell, orig, mparts);
-        hipLaunchKernelGGL(k_meta_reduce, dim3(1), dim3(1024), 0, st, (const MetaPart*)mparts,
-                           nb_bt, meta);
+                           inv_cell, orig, mparts, meta, done_ctr, 0);
         LKC_HIP_TRY(ctx, hipGetLastError());
         auto refuse = [&]() {
             V.n = 0;
@@ -837,12 +974,12 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
             if (hmeta->nonfinite) return refuse();
             passes = hmeta->passes;
         }
-        s = enqueue(passes);
+        s = enqueue(passes, nullptr);
         if (s != LKC_OK) return s;
         if (hmeta->nonfinite) return refuse();
         if (hmeta->passes > passes) {
             // the key outgrew the previous build's passes: sort again in full
-            s = enqueue(hmeta->passes);
+            s = enqueue(hmeta->passes, nullptr);
             if (s != LKC_OK) return s;
         }
         for (int a = 0; a < 3; ++a) {
@@ -879,9 +1016,10 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     V.hash_bits = hbits;
     V.hash_mask = (uint32_t)(cap - 1);
     t->hash_capacity = cap;
+    t->host_stale = false;
     if (!t->view_dev) {
-        hipError_t e = hipMalloc((void**)&t->view_dev, sizeof(TargetView));
-        if (e == hipSuccess) e = hipHostMalloc(&t->view_host, sizeof(TargetView), hipHostMallocDefault);
+        hipError_t e = hipMalloc((void**)&t->view_dev, view_alloc_bytes());
+        if (e == hipSuccess) e = hipHostMalloc(&t->view_host, view_alloc_bytes(), hipHostMallocDefault);
         if (e != hipSuccess) {
             if (t->view_dev) (void)hipFree(t->view_dev);
             t->view_dev = nullptr;

@@ -55,6 +55,7 @@ struct lkc_target {
     int32_t sort_passes = 0;
     int64_t hash_capacity = 0;
     lkc_status status = LKC_OK;  // of the last build or rebuild
+    bool host_stale = false;     // an asynchronous rebuild left the host-side view behind
     // owned allocations and their capacities (bytes)
     void* point_mem = nullptr;   // pts + orig + run boxes
     size_t point_bytes = 0;
@@ -139,7 +140,15 @@ lkc_status set_error(lkc_ctx* ctx, lkc_status st, const char* fmt, ...);
 lkc_status hip_error(lkc_ctx* ctx, hipError_t e, const char* what);
 
 // implemented in build.hip
-lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n);
+// async: a rebuild into memory large enough runs without a host round trip
+// (the target's host-side view is then stale until refresh_host_view)
+lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t n,
+                      bool async = false);
+// Reads the device view (and the status) of an asynchronous rebuild back
+// into the host-side view; returns that rebuild's error, if any.
+// Synchronises `ctx`'s stream (the _device variant: the whole device).
+lkc_status refresh_host_view(lkc_ctx* ctx, lkc_target* t);
+lkc_status refresh_host_view_device(lkc_target* t);
 void free_target_memory(lkc_target* t);
 size_t sort_count_words(int64_t n);
 // stable LSD radix sort of (key, val) pairs on the low `bits` key bits;

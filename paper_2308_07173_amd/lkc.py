@@ -38,7 +38,8 @@ _STATUS_NAMES = {0: "LKC_OK", -1: "LKC_ERR_INVALID_ARG", -2: "LKC_ERR_OOM", -3: 
 # every symbol include/lkc.h declares
 EXPORTED_SYMBOLS = (
     "lkc_version", "lkc_ctx_create", "lkc_ctx_destroy", "lkc_ctx_set_stream", "lkc_last_error",
-    "lkc_synchronize", "lkc_build_target", "lkc_target_rebuild", "lkc_target_free",
+    "lkc_synchronize", "lkc_build_target", "lkc_target_rebuild", "lkc_target_rebuild_async",
+    "lkc_target_free",
     "lkc_target_get_info", "lkc_target_arrays", "lkc_knn_query", "lkc_covariances",
     "lkc_knn_cov", "lkc_target_set_create", "lkc_target_set_free", "lkc_target_set_stage",
     "lkc_knn_cov_batched", "lkc_knn_cov_self", "lkc_ctx_reserve", "lkc_ctx_search_stats",
@@ -148,6 +149,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_synchronize": ([P], I32),
             "lkc_build_target": ([P, P, I64, F, PP], I32),
             "lkc_target_rebuild": ([P, P, P, I64], I32),
+            "lkc_target_rebuild_async": ([P, P, P, I64], I32),
             "lkc_target_free": ([P, P], I32),
             "lkc_target_get_info": ([P, ctypes.POINTER(TargetInfo)], I32),
             "lkc_target_arrays": ([P, PP, PP, PP], I32),
@@ -324,12 +326,15 @@ class Target:
         ck = _copy_device(c.value, 8 * C, torch.int64) if C else torch.zeros(0, dtype=torch.int64)
         return pts, cs, ck
 
-    def rebuild(self, points):
+    def rebuild(self, points, sync: bool = True):
+        """lkc_target_rebuild, or with sync=False lkc_target_rebuild_async
+        (no host round trip; errors surface at status() or the next call
+        that needs the host-side layout)."""
         _check_dev(points, "points", _torch().float32, (3,))
         self.ctx._bind()
-        self.ctx.check(self.ctx.lib.lkc_target_rebuild(self.ctx.handle, self.handle,
-                                                       ctypes.c_void_p(_ptr(points)),
-                                                       points.shape[0]))
+        fn = self.ctx.lib.lkc_target_rebuild if sync else self.ctx.lib.lkc_target_rebuild_async
+        self.ctx.check(fn(self.ctx.handle, self.handle, ctypes.c_void_p(_ptr(points)),
+                          points.shape[0]))
 
     def status(self) -> int:
         """lkc_target_status: LKC_OK, or the error of the last (re)build

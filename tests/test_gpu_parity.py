@@ -63,7 +63,7 @@ def test_build_cells_partition_points(lk, n, cell, seed):
     t.free()
 
 
-def check_layout(t, p, cell):
+def check_layout(t, p, cell, fixed_passes=None):
     n = p.shape[0]
     info = t.info()
     pts, cs, ck = t.arrays()
@@ -98,10 +98,16 @@ def check_layout(t, p, cell):
     rel = (c - np.array(info["cell_min"])).astype(np.uint64)
     u = p[orig].astype(np.float32) * inv
     wmax = max(int(info["cell_max"][a] - info["cell_min"][a]).bit_length() for a in range(3))
-    lo = max(0, min(2, (63 - 3 * wmax) // 3))
-    room = min(63, 8 * -(-(3 * wmax + 3 * lo) // 8))
-    sb = max(lo, min(4, (room - 3 * wmax) // 3))
-    assert info["sort_passes"] == -(-(3 * wmax + 3 * sb) // 8)
+    if fixed_passes is None:
+        lo = max(0, min(2, (63 - 3 * wmax) // 3))
+        room = min(63, 8 * -(-(3 * wmax + 3 * lo) // 8))
+        sb = max(lo, min(4, (room - 3 * wmax) // 3))
+        assert info["sort_passes"] == -(-(3 * wmax + 3 * sb) // 8)
+    else:
+        # an asynchronous rebuild fits the key into the previous passes
+        sb = max(0, min(4, (min(63, 8 * fixed_passes) - 3 * wmax) // 3))
+        assert info["sort_passes"] == fixed_passes
+    assert info["key_bits"] == 3 * wmax + 3 * sb
     sub = np.clip(((u - np.floor(u)) * np.float32(2 ** sb)).astype(np.int64), 0,
                   2 ** sb - 1).astype(np.uint64)
     mort = ((spread(rel[:, 0]) | spread(rel[:, 1]) << np.uint64(1) | spread(rel[:, 2]) << np.uint64(2))
@@ -150,6 +156,82 @@ def test_rebuild_reuses_the_target(lk):
     t.rebuild(dev(clouds[2]))
     check_layout(t, clouds[2], 1.0)
     assert t.status() == lkc.LKC_OK
+    t.free()
+
+
+def self_out(lkc, ctx, t, k=20, radius=2.0):
+    return {key: v.cpu().numpy() for key, v in lkc.lkc_knn_cov_self(ctx, t, k, radius,
+                                                                      1e-3).items()}
+
+
+def test_async_rebuild_equals_sync_rebuild(lk):
+    """Scans rebuilt without a host round trip, each searched right after on
+    the same stream: every output equals a synchronously built target's, and
+    the layout read back afterwards is the same."""
+    lkc, ctx = lk
+    scans = [workloads.single_scan(seed=s) for s in (1, 7, 8)]
+    t = lkc.lkc_build_target(ctx, dev(scans[0]), 1.0)
+    for rnd, p in enumerate(scans[1:] + scans[:1]):
+        t.rebuild(dev(p), sync=False)
+        got = self_out(lkc, ctx, t)
+        ref_t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+        ref = self_out(lkc, ctx, ref_t)
+        for key in ref:
+            assert np.array_equal(got[key], ref[key]), (rnd, key)
+        a, b = t.info(), ref_t.info()
+        for key in ("n_points", "n_cells", "cell_min", "cell_max", "key_bits", "sort_passes"):
+            assert a[key] == b[key], (rnd, key)
+        check_layout(t, p, 1.0)
+        ref_t.free()
+    assert t.status() == lkc.LKC_OK
+    # a search that reads the host-side layout after an asynchronous rebuild
+    q = scans[2][::53].copy()
+    t.rebuild(dev(scans[2]), sync=False)
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(q), 8, 1.5)
+    parity.check_knn(scans[2], q, 8, 1.5, host(idx), host(d2), host(cnt))
+    t.free()
+
+
+def test_async_rebuild_failures_surface_later(lk):
+    """A non-finite cloud, or a cell key that outgrows the previous sort
+    passes, leaves the target empty (searches return count 0) and is
+    reported by status() until a good rebuild; a synchronous rebuild repairs
+    it."""
+    lkc, ctx = lk
+    small = workloads.random_cloud(3_000, 21, scale=2.0)      # 2 sort passes
+    t = lkc.lkc_build_target(ctx, dev(small), 1.0)
+    assert t.info()["sort_passes"] == 2
+    bad = small.copy()
+    bad[10, 0] = np.nan
+    t.rebuild(dev(bad), sync=False)
+    o = self_out(lkc, ctx, t, 8, 1.0)
+    assert int(o["count"].sum()) == 0
+    assert t.status() == lkc.LKC_ERR_NONFINITE
+    t.rebuild(dev(small))
+    assert t.status() == lkc.LKC_OK
+    wide = workloads.random_cloud(3_000, 22, scale=900.0)    # needs 4 passes
+    t.rebuild(dev(wide), sync=False)
+    o = self_out(lkc, ctx, t, 8, 1.0)
+    assert int(o["count"].sum()) == 0
+    idx, d2, cnt = lkc.lkc_knn_query(ctx, t, dev(wide[:10]), 4)   # reads the layout back
+    assert int(cnt.sum()) == 0 and t.info()["n_points"] == 0
+    assert t.status() == lkc.LKC_ERR_UNSUPPORTED
+    assert t.status() == lkc.LKC_ERR_UNSUPPORTED                  # until a good rebuild
+    t.rebuild(dev(wide))
+    check_layout(t, wide, 1.0)
+    assert t.status() == lkc.LKC_OK
+    # within the passes the layout gives up sub-cell bits, not correctness
+    mid = workloads.random_cloud(3_000, 23, scale=12.0)      # 3 passes when built afresh
+    t.rebuild(dev(small))
+    t.rebuild(dev(mid), sync=False)
+    got = self_out(lkc, ctx, t, 8, 1.0)
+    ref_t = lkc.lkc_build_target(ctx, dev(mid), 1.0)
+    ref = self_out(lkc, ctx, ref_t, 8, 1.0)
+    for key in ref:
+        assert np.array_equal(got[key], ref[key]), key
+    check_layout(t, mid, 1.0, fixed_passes=2)
+    assert ref_t.info()["sort_passes"] == 3
+    ref_t.free()
     t.free()
 
 
