@@ -599,6 +599,30 @@ def main():
         info = tgt.info()
         extra["grid"] = {"cells": info["n_cells"], "hash_capacity": info["hash_capacity"],
                          "sort_passes": info["sort_passes"]}
+        # the same step (rebuild + fused search, nothing synchronised in
+        # between) captured once as a HIP graph and replayed: the launches of
+        # the build no longer wait on the host
+        ref = {key: v.clone() for key, v in out.items()}
+        ctx.set_timing(False)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        ctx.set_timing(True)
+        g.replay()
+        torch.cuda.synchronize()
+        same = all(torch.equal(ref[key], out[key]) for key in ref)
+        glat = []
+        for _ in range(max(K, 20)):
+            s0 = time.perf_counter()
+            g.replay()
+            torch.cuda.synchronize()
+            glat.append(time.perf_counter() - s0)
+        gms, _ = timed_calls(torch, g.replay, K, 2)
+        extra["graph_replay"] = {"ms_per_step": gms, "build_ms": gms - kern_ms,
+                                 "latency_ms": {"p50": pct(glat, 50) * 1e3,
+                                                "p99": pct(glat, 99) * 1e3},
+                                 "equal_to_eager": bool(same)}
+        del g
         baseline_args = (pts, pts, k, radius, np.arange(Q), "the whole scan")
     elif args.workload in ("map", "weighted"):
         m, _ = workloads.build_map(2_000_000, seed=2)

@@ -192,6 +192,42 @@ def test_async_rebuild_equals_sync_rebuild(lk):
     t.free()
 
 
+def test_rebuild_and_search_replayed_from_a_graph(lk):
+    """Asynchronous rebuild + fused self search captured once as a graph and
+    replayed with new scans written into the same point buffer: every replay
+    equals the eager calls on that scan."""
+    lkc, ctx = lk
+    scans = [workloads.single_scan(seed=s) for s in (1, 7, 8)]
+    n = min(x.shape[0] for x in scans)
+    scans = [np.ascontiguousarray(x[:n]) for x in scans]
+    buf = dev(scans[0])
+    t = lkc.lkc_build_target(ctx, buf, 1.0)
+    out = lkc.lkc_knn_cov_self(ctx, t, 20, 2.0, 1e-3)
+
+    def step():
+        t.rebuild(buf, sync=False)
+        lkc.lkc_knn_cov_self(ctx, t, 20, 2.0, 1e-3, out=out)
+
+    step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rnd, p in enumerate(scans[1:] + scans):
+        buf.copy_(torch.from_numpy(p))
+        g.replay()
+        torch.cuda.synchronize()
+        got = {key: v.cpu().numpy() for key, v in out.items()}
+        ref_t = lkc.lkc_build_target(ctx, dev(p), 1.0)
+        ref = self_out(lkc, ctx, ref_t)
+        ref_t.free()
+        for key in ref:
+            assert np.array_equal(got[key], ref[key]), (rnd, key)
+    del g
+    assert t.status() == lkc.LKC_OK
+    t.free()
+
+
 def test_async_rebuild_failures_surface_later(lk):
     """A non-finite cloud, or a cell key that outgrows the previous sort
     passes, leaves the target empty (searches return count 0) and is
