@@ -109,7 +109,7 @@ lkc_status lkc_ctx_create(void* hip_stream, lkc_ctx** out) {
     if (c->num_cus <= 0) c->num_cus = 256;
     if (hipMalloc(&c->meta_dev, META_BYTES) != hipSuccess ||
         hipHostMalloc(&c->meta_host, META_BYTES, hipHostMallocDefault) != hipSuccess ||
-        hipMemset(c->meta_dev, 0, META_BYTES) != hipSuccess) {   // block counters start at 0
+        hipMemset(c->meta_dev, 0, META_BYTES) != hipSuccess) {
         if (c->meta_dev) (void)hipFree(c->meta_dev);
         delete c;
         return set_error(nullptr, LKC_ERR_OOM, "context buffers");

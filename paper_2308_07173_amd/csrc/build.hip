@@ -86,7 +86,7 @@ __device__ __forceinline__ uint32_t wave_maxu(uint32_t v) {
 }
 
 // Per-block partial of the occupied-cell box, the finiteness flag and the
-// largest |coordinate|; one record per block, combined by the last block
+// largest |coordinate|; one record per block, combined by k_meta_reduce
 // (no contended atomics).
 struct MetaPart {
     int cmin[3];
@@ -181,15 +181,10 @@ __device__ void meta_combine(const MetaPart* __restrict__ parts, int64_t np,
     }
 }
 
-// One record per point (orig, w = 0) and the per-block part of the box;
-// the last block to finish (counted on `done`, which it resets) combines
-// the parts into `meta`.
+// One record per point (orig, w = 0) and the per-block part of the box.
 __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p, int64_t n,
                                                     float inv_cell, float4* __restrict__ orig,
-                                                    MetaPart* __restrict__ parts,
-                                                    BuildMeta* __restrict__ meta,
-                                                    uint32_t* __restrict__ done,
-                                                    int fixed_passes) {
+                                                    MetaPart* __restrict__ parts) {
     const int64_t i = (int64_t)blockIdx.x * BT + threadIdx.x;
     int mn[3] = {INT_MAX, INT_MAX, INT_MAX};
     int mx[3] = {INT_MIN, INT_MIN, INT_MIN};
@@ -247,17 +242,15 @@ __global__ void __launch_bounds__(BT) k_scan_points(const float* __restrict__ p,
         }
         parts[blockIdx.x] = m;
     }
-    // the part is visible device-wide before the block is counted; the last
-    // block's fence makes every part visible to it
-    __shared__ int s_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    meta_combine(parts, gridDim.x, meta, fixed_passes);
-    if (threadIdx.x == 0) *done = 0u;
+}
+
+// One workgroup combines the parts (a separate launch: a last-block ticket
+// in the scan kernel needs a device-scope fence in every block, which costs
+// more than the launch at scan sizes).
+__global__ void __launch_bounds__(1024) k_meta_reduce(const MetaPart* __restrict__ parts,
+                                                      int64_t np, BuildMeta* __restrict__ meta,
+                                                      int fixed_passes) {
+    meta_combine(parts, np, meta, fixed_passes);
 }
 
 // Sort keys; the threads also clear the hash's slots (all `cap` of them,
@@ -887,7 +880,6 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     const bool fast = async && prev_passes > 0 && n > 0 && t->view_dev &&
                       t->point_bytes >= 2 * pbytes + bx_b && t->cell_bytes >= cbytes &&
                       ctx->build_scratch_bytes >= off;
-    uint32_t* done_ctr = (uint32_t*)((char*)ctx->meta_dev + 64);
 
     // Steps 2-6 for a sort of `passes` 8-bit passes; every layout parameter
     // is read from the device meta.  With `vout` the hash kernel writes the
@@ -930,7 +922,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
 
     if (fast) {
         hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
-                           inv_cell, orig, mparts, meta, done_ctr, prev_passes);
+                           inv_cell, orig, mparts);
+        hipLaunchKernelGGL(k_meta_reduce, dim3(1), dim3(1024), 0, st, (const MetaPart*)mparts,
+                           nb_bt, meta, prev_passes);
         V.pts = pts;
         V.orig = orig;
         V.hash = hash;
@@ -955,7 +949,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
     if (n > 0) {
         // ---- 1. cell coordinates, bounding box, finiteness, key layout
         hipLaunchKernelGGL(k_scan_points, dim3(grid_for(n, BT)), dim3(BT), 0, st, points, n,
-                           inv_cell, orig, mparts, meta, done_ctr, 0);
+                           inv_cell, orig, mparts);
+        hipLaunchKernelGGL(k_meta_reduce, dim3(1), dim3(1024), 0, st, (const MetaPart*)mparts,
+                           nb_bt, meta, 0);
         LKC_HIP_TRY(ctx, hipGetLastError());
         auto refuse = [&]() {
             V.n = 0;
