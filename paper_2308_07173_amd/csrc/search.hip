@@ -1061,24 +1061,42 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         }
         if (!ballot(bits != 0ull)) continue;
         const uint32_t name0 = (uint32_t)ord << 6;
+        // Each lane's next passing candidate (lane 63 when none: read, not
+        // inserted) is fetched one pop ahead, so the fetch overlaps the
+        // insertion chain of the current one.
+        auto fetch = [&](int jj, float& fx, float& fy, float& fz) {
+            const int ja = jj << 2;
+            fx = __int_as_float(__builtin_amdgcn_ds_bpermute(ja, __float_as_int(c.x)));
+            fy = __int_as_float(__builtin_amdgcn_ds_bpermute(ja, __float_as_int(c.y)));
+            fz = __int_as_float(__builtin_amdgcn_ds_bpermute(ja, __float_as_int(c.z)));
+        };
+        bool has = bits != 0ull;
+        int j = __builtin_ctzll(bits | (1ull << 63));
+        float cx, cy, cz;
+        fetch(j, cx, cy, cz);
+        bits &= bits - 1ull;
         do {
             gp.pops++;
-            const int j = bits ? __builtin_ffsll((long long)bits) - 1 : 0;
-            const float cx = shfl(c.x, j), cy = shfl(c.y, j), cz = shfl(c.z, j);
-            uint32_t x = ~0u;
-            if (bits) {
-                bits &= bits - 1;
-                // d2 <= the lane's bound <= r2: within the radius
-                const uint32_t db = __float_as_uint(dist2(qx, qy, qz, cx, cy, cz));
-                x = (db & ~ID_MASK) | name0 | (uint32_t)j;
-            }
+            const bool has_n = bits != 0ull;
+            const int j_n = __builtin_ctzll(bits | (1ull << 63));
+            float nx, ny, nz;
+            fetch(j_n, nx, ny, nz);
+            bits &= bits - 1ull;
+            // d2 <= the lane's bound <= r2: within the radius
+            const uint32_t db = __float_as_uint(dist2(qx, qy, qz, cx, cy, cz));
+            const uint32_t x = has ? ((db & ~ID_MASK) | name0 | (uint32_t)j) : ~0u;
             if (PROF) {
                 const unsigned long long im = ballot(x < L[K + SLACK - 1]);
                 gp.inserts += (uint32_t)__popcll(im);
                 gp.dead += im ? 0u : 1u;
             }
             pk_insert<K + SLACK>(L, x);
-        } while (ballot(bits != 0ull));
+            has = has_n;
+            j = j_n;
+            cx = nx;
+            cy = ny;
+            cz = nz;
+        } while (ballot(has));
         float own = pk_bound<K>(L, r2, lcap);
         if (sh.split_mask) {
             sh.thr[sh.sub * WAVE + lane] = own;
