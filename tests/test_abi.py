@@ -61,7 +61,23 @@ def test_ctx_create_without_gpu_fails_cleanly(lib):
     assert st == lkc.LKC_ERR_UNSUPPORTED and not h.value
 
 
+def test_raceline_and_async_calls_reject_null_arguments(lib):
+    P = ctypes.c_void_p
+    assert lib.lkc_target_rebuild_async(None, None, None, 0) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_raceline_build(None, None, None, 0, 1.0, 1.0, 1.0,
+                                  ctypes.byref(P())) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_raceline_get_info(None, None) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_raceline_bins(None, None, None) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_submap_window(None, None, None, 1.0, None, None, 0,
+                                 None) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_submap_window_build(None, None, None, 1.0, None, 0, None,
+                                       None) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_raceline_free(None, None) == lkc.LKC_ERR_INVALID_ARG
+
+
 def test_struct_layouts():
+    assert ctypes.sizeof(lkc.RaceLineInfo) == 8 * 5 + 4 * 5 + 4 + 8
+    assert lkc.RaceLineInfo.device_bytes.offset == 64
     assert ctypes.sizeof(lkc.LaunchCfg) == 24
     assert ctypes.sizeof(lkc.ScanDesc) == 24
     assert ctypes.sizeof(lkc.GicpStats) == 4 + 4 + 8 + 8 + 8 + 8
