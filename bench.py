@@ -191,6 +191,9 @@ def served_stream(args, lkc, workloads, torch, duration, time_scale, saturated=T
     warm = reqs[: min(12, len(reqs))]
     serve.serve_loop(warm, ex, time_scale=math.inf)
     serve.serve_loop(reqs, ex, time_scale=math.inf)
+    # batches of a bucket met for the first time inside the timed streams
+    # run eagerly rather than pay a capture
+    ex.capture_new = False
     res = serve.summarize(serve.serve_loop(reqs, ex, time_scale=time_scale))
     plain = serve.summarize(serve.plain_loop(reqs, ex, time_scale=time_scale))
     out = {"requests": res["requests"], "duration_s": duration, "time_scale": time_scale,

@@ -309,6 +309,9 @@ class GpuExecutor(Executor):
         self.n_slots = n_slots
         self.keep_results = keep_results
         self.use_graphs = use_graphs
+        # capture a graph for a buffer set the first time it runs; off, a
+        # set without one runs eagerly (no capture latency inside a stream)
+        self.capture_new = True
         self.max_scans = max_scans
         self.max_batch_requests = max_scans - 1      # one table row for the padding
         self.results: Dict[int, Dict[str, np.ndarray]] = {}
@@ -473,14 +476,14 @@ class GpuExecutor(Executor):
             if total > n:
                 b.q_dev[n:total].fill_(float("nan"))
             s["tset"].stage(scans)
-            if self.use_graphs:
-                g = b.graphs.get(slot)
-                if g is None:
-                    self._call(s, b)              # warm-up outside the capture
-                    g = torch.cuda.CUDAGraph()
-                    with torch.cuda.graph(g, stream=s["stream"]):
-                        self._call(s, b)
-                    b.graphs[slot] = g
+            g = b.graphs.get(slot) if self.use_graphs else None
+            if g is None and self.use_graphs and self.capture_new:
+                self._call(s, b)              # warm-up outside the capture
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=s["stream"]):
+                    self._call(s, b)
+                b.graphs[slot] = g
+            if g is not None:
                 g.replay()
             else:
                 self._call(s, b)
@@ -491,7 +494,8 @@ class GpuExecutor(Executor):
     def warm(self, sizes: Iterable[int]) -> int:
         """Allocate the buffer sets of the buckets of `sizes` and capture
         their graphs on every slot ahead of a stream (zero queries against
-        the first map); returns the number of buckets."""
+        the first map); returns the number of buckets.  Set capture_new to
+        False afterwards to keep captures out of the stream."""
         buckets = sorted({self._rows(int(n)) for n in sizes if 0 < int(n) <= self.capacity})
         if not self.order:
             return 0
