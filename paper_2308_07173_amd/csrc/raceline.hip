@@ -412,29 +412,48 @@ lkc_status raceline_build(lkc_ctx* ctx, const lkc_target* map, const float* line
     }
     const double rc = cover * (1.0 + 1.0e-5) + 1.0e-3 * cell;
     const double rc2 = rc * rc;
-    std::vector<uint32_t> roff((size_t)B + 1, 0), tot((size_t)B, 0), rstart, rpre;
+    // cells bucketed by the 2-D tile of their centre, tiles of edge rc + cell:
+    // a cell within rc of an anchor has its centre in the anchor's tile or
+    // an adjacent one, so a bin tests only the cells of 3 x 3 tiles
+    const double tile = rc + cell;
+    auto tile_key = [&](double x, double y) {
+        return cell_key((int32_t)std::floor(x / tile), (int32_t)std::floor(y / tile));
+    };
+    std::unordered_map<uint64_t, std::vector<uint32_t>> tiles;
+    for (int64_t c = 0; c < C; ++c) {
+        const float* bx = &box[6 * c];
+        tiles[tile_key(0.5 * ((double)bx[0] + bx[3]), 0.5 * ((double)bx[1] + bx[4]))].push_back(
+            (uint32_t)c);
+    }
+    std::vector<uint32_t> roff((size_t)B + 1, 0), tot((size_t)B, 0), rstart, rpre, sel;
     int64_t max_points = 0, sum_points = 0;
     for (int32_t b = 0; b < B; ++b) {
         roff[b] = (uint32_t)rstart.size();
         const double ax = A[3 * (size_t)b], ay = A[3 * (size_t)b + 1], az = A[3 * (size_t)b + 2];
-        int64_t open = -1;   // first cell of the current run
+        const int32_t tx = (int32_t)std::floor(ax / tile), ty = (int32_t)std::floor(ay / tile);
+        sel.clear();
+        for (int32_t ux = tx - 1; ux <= tx + 1; ++ux)
+            for (int32_t uy = ty - 1; uy <= ty + 1; ++uy) {
+                auto it = tiles.find(cell_key(ux, uy));
+                if (it == tiles.end()) continue;
+                for (uint32_t c : it->second) {
+                    const float* bx = &box[6 * (size_t)c];
+                    const double dx = ax < bx[0] ? bx[0] - ax : (ax > bx[3] ? ax - bx[3] : 0.0);
+                    const double dy = ay < bx[1] ? bx[1] - ay : (ay > bx[4] ? ay - bx[4] : 0.0);
+                    const double dz = az < bx[2] ? bx[2] - az : (az > bx[5] ? az - bx[5] : 0.0);
+                    if (dx * dx + dy * dy + dz * dz <= rc2) sel.push_back(c);
+                }
+            }
+        // runs of consecutive cells of the cell table, in table order
+        std::sort(sel.begin(), sel.end());
         uint32_t acc = 0;
-        for (int64_t c = 0; c <= C; ++c) {
-            bool in = false;
-            if (c < C) {
-                const float* bx = &box[6 * c];
-                const double dx = ax < bx[0] ? bx[0] - ax : (ax > bx[3] ? ax - bx[3] : 0.0);
-                const double dy = ay < bx[1] ? bx[1] - ay : (ay > bx[4] ? ay - bx[4] : 0.0);
-                const double dz = az < bx[2] ? bx[2] - az : (az > bx[5] ? az - bx[5] : 0.0);
-                in = dx * dx + dy * dy + dz * dz <= rc2;
-            }
-            if (in && open < 0) open = c;
-            if (!in && open >= 0) {
-                rstart.push_back(cstart[open]);
-                rpre.push_back(acc);
-                acc += cstart[c] - cstart[open];
-                open = -1;
-            }
+        for (size_t i = 0; i < sel.size();) {
+            size_t j = i + 1;
+            while (j < sel.size() && sel[j] == sel[j - 1] + 1) ++j;
+            rstart.push_back(cstart[sel[i]]);
+            rpre.push_back(acc);
+            acc += cstart[sel[j - 1] + 1] - cstart[sel[i]];
+            i = j;
         }
         tot[b] = acc;
         max_points = std::max<int64_t>(max_points, acc);
