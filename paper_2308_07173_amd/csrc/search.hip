@@ -692,12 +692,13 @@ struct KnnPtrs {
 // neighbouring cells), probes the cells of the group's block (its cells
 // grown by R on every side) in parallel, and streams every surviving cell's
 // point run once for the whole group: the candidate address is the same in
-// all lanes, so each load is one broadcast.  Each lane keeps its own sorted
-// top-k in registers as 64-bit keys ((bits(d2) + 1) << 32 | original index;
-// d2 >= 0, so the integer order of the keys is the (d2, index) order).  A
-// lane whose result the block cannot prove exact (the k-th distance, or the
-// radius, reaches past the block) is handed to the wavefront-per-query
-// search through a fallback list.
+// all lanes, so each load is one coalesced read.  Each lane keeps its own
+// sorted top-k (+ SLACK spare entries) in registers as 32-bit packed keys
+// (the float d2 bits with the low ID_BITS replaced by the candidate's name,
+// see below), decoded to the exact (d2, index) order at the end.  A lane
+// whose result the block cannot prove exact (the k-th distance, or the
+// radius, reaches past the block), or whose packed order is ambiguous, is
+// handed to the wavefront-per-query search through a fallback list.
 
 constexpr int GROUP_W = 2;       // lanes within this many cells of a round's anchor take part
 constexpr int64_t WHOLE_N = 4096;  // targets this small are streamed whole by every group

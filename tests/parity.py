@@ -19,7 +19,8 @@ host (by the oracle) and both sides use them.  Tolerances:
 n offsets no longer than A, which enters every deviation; E is the largest
 deviation from the mean -- this term decides only for near-zero
 covariances, e.g. a set of duplicated points),
-``|mu_gpu - mu_or| <= 1e-5 max(|mu_or|, 1 m) + g``; the regularised covariance is
+``|mu_gpu - mu_or| <= 8 * 2^-24 max(|mu_or|, 1 m) + g`` (the float32 sum of the
+query and the relative mean rounds by at most 2^-24 |mu|, with margin); the regularised covariance is
 compared at 1e-4 relative Frobenius where the oracle's eigen-gap
 ``(l1 - l0) / l2 >= 1e-2``, else checked for symmetry, eigenvalues
 {eps, 1, 1} and for its eps-direction being a near-minimiser of C.
@@ -47,7 +48,7 @@ KNN_D2_REL = 1e-6
 KNN_D2_ABS = 1e-12
 NEAR_TIE_REL = 1e-5
 COV_REL = 1e-4
-MEAN_REL = 1e-5
+MEAN_REL = 8 * 2.0 ** -24
 GAP_MIN = 1e-2
 F32_U = 2.0 ** -24
 BAND_REL = 1e-6

@@ -41,13 +41,24 @@ def test_planted_covariance_error_fails(case, rel):
         parity.check_cov(p, idx, cnt, m, c, r, v, search=(q, 16, 1.0))
 
 
-def test_planted_mean_error_fails(case):
+@pytest.mark.parametrize("err", [1e-3, 1e-4])
+def test_planted_mean_error_fails(case, err):
+    # means near (40, -10, 1) m: float32 resolves about 4e-6 m there, and an
+    # error of 0.1 mm is caught
     p, q, idx, d2, cnt, ref = case
     m, c, r, v = outputs(ref)
     m = m.copy()
-    m[0, 1] += np.float32(1e-3)
+    m[0, 1] += np.float32(err)
     with pytest.raises(AssertionError, match="mean"):
         parity.check_cov(p, idx, cnt, m, c, r, v, search=(q, 16, 1.0))
+
+
+def test_mean_within_float32_rounding_passes(case):
+    # one float32 step of the mean's magnitude on every coordinate passes
+    p, q, idx, d2, cnt, ref = case
+    m, c, r, v = outputs(ref)
+    m = np.nextafter(m, np.float32(np.inf))
+    parity.check_cov(p, idx, cnt, m, c, r, v, search=(q, 16, 1.0))
 
 
 def test_rounding_floor_is_rounding_sized(case):
