@@ -477,9 +477,11 @@ lkc_status lkc_submap_window_build(lkc_ctx *ctx, const lkc_raceline *rl, const f
  * floor(y / cell)), evaluated in float32 with correctly rounded division;
  * votes[i] = the number of points in point i's cell, keep[i] = (votes[i] >=
  * tau).  Non-finite points get 0 votes and keep 0.  points device float
- * [n][3]; keep device uint8 [n]; votes device int32 [n] or NULL.
- * LKC_ERR_BUDGET when the occupied 2-D box exceeds 2^28 cells.
- * Synchronises once (box size). */
+ * [n][3]; keep device uint8 [n]; votes device int32 [n] or NULL.  The
+ * counts live in a device hash table of 2^ceil(log2(2n)) 16-byte slots in
+ * the context's scratch; nothing is synchronised once that scratch is as
+ * large as the call needs (growing it synchronises), so the call can be
+ * captured in a graph. */
 lkc_status lkc_zvote(lkc_ctx *ctx, const float *points, int64_t n, float cell, int32_t tau,
                      uint8_t *keep, int32_t *votes);
 

@@ -3,10 +3,13 @@
 //
 // z-vote (Sec. III-D.1, Eq. eq_hash_table, Fig. z_vote): every point votes
 // for its 2-D cell (floor(x / g), floor(y / g)) in float32; a point is a
-// vertical feature when its cell holds at least tau points.  The paper hashes
-// the cells for sparsity; here the counts live in a direct-mapped table over
-// the occupied 2-D box (one 32-bit counter per cell, at most 2^28 cells), so
-// the vote is one atomic add per point and the read-back one load.
+// vertical feature when its cell holds at least tau points.  As in the
+// paper, the counts live in a hash table: open addressing over 2^b >= 2n
+// slots keyed by the two float32 cell coordinates' bits (exact for any
+// finite coordinate, -0 folded into +0), so no pass over the points has to
+// size a table first and nothing waits for the host.  The vote is one
+// compare-and-swap probe sequence and one atomic add per point, the
+// read-back one probe sequence.
 //
 // Clustering (Sec. III-D.2): connected components of the graph joining
 // points closer than eps (d2 <= eps^2, float32, the search's fma order).
@@ -29,8 +32,6 @@ namespace lkc {
 namespace {
 
 constexpr int WT = 256;
-constexpr int UV_CLAMP = 1 << 30;
-constexpr uint64_t ZVOTE_MAX_CELLS = 1ull << 28;
 constexpr int UNION_SPIN_LIMIT = 1 << 20;
 
 inline unsigned grid_of(int64_t n, int bt) { return (unsigned)((n + bt - 1) / bt); }
@@ -38,25 +39,13 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct UvMeta {      // 64 bytes, at offset 192 of the context's metadata words
     int umin, umax, vmin, vmax;
-    uint32_t bad;    // a 2-D cell coordinate outside [-2^30, 2^30)
+    uint32_t bad;
     uint32_t spins;  // union-find retries that hit the limit
     uint32_t n_clusters;
     uint32_t kept;   // points selected by the clustering mask
     uint32_t pad[8];
 };
 static_assert(sizeof(UvMeta) == 64, "UvMeta layout");
-
-__device__ __forceinline__ bool uv_of(const float* p, float g, int& u, int& v, bool& bad) {
-    bad = false;
-    if (!finite3(p[0], p[1], p[2])) return false;
-    const float fu = floorf(p[0] / g), fv = floorf(p[1] / g);
-    const bool ok = fu >= -(float)UV_CLAMP && fu < (float)UV_CLAMP && fv >= -(float)UV_CLAMP &&
-                    fv < (float)UV_CLAMP;
-    bad = !ok;
-    u = ok ? (int)fu : 0;
-    v = ok ? (int)fv : 0;
-    return true;
-}
 
 __global__ void k_uv_init(UvMeta* m) {
     if (threadIdx.x == 0) {
@@ -68,73 +57,71 @@ __global__ void k_uv_init(UvMeta* m) {
     }
 }
 
-__global__ void __launch_bounds__(WT) k_uv_bounds(const float* __restrict__ pts, int64_t n,
-                                                  float g, UvMeta* __restrict__ m) {
-    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
-    int u = 0, v = 0;
-    bool bad = false, fin = false;
-    if (i < n) fin = uv_of(pts + 3 * i, g, u, v, bad);
-    const bool use = fin && !bad;
-    int a = use ? u : INT32_MAX, b = use ? u : INT32_MIN, c = use ? v : INT32_MAX,
-        d = use ? v : INT32_MIN;
-    int nb = fin && bad ? 1 : 0;
-#pragma unroll
-    for (int s = 32; s > 0; s >>= 1) {
-        a = min(a, __shfl_xor(a, s));
-        b = max(b, __shfl_xor(b, s));
-        c = min(c, __shfl_xor(c, s));
-        d = max(d, __shfl_xor(d, s));
-        nb += __shfl_xor(nb, s);
-    }
-    if (threadIdx.x % WAVE == 0) {
-        if (a != INT32_MAX) {
-            atomicMin(&m->umin, a);
-            atomicMax(&m->umax, b);
-            atomicMin(&m->vmin, c);
-            atomicMax(&m->vmax, d);
-        }
-        if (nb) atomicAdd(&m->bad, (uint32_t)nb);
-    }
+// The hash key of a point's 2-D cell: the bits of floor(x / g) and
+// floor(y / g) (float32, correctly rounded division; + 0.0f folds -0 into
+// +0, so equal cells have equal keys).  Never EMPTY_KEY (a NaN pattern).
+__device__ __forceinline__ bool uv_key(const float* p, float g, unsigned long long& key) {
+    if (!finite3(p[0], p[1], p[2])) return false;
+    const float fu = floorf(p[0] / g) + 0.0f, fv = floorf(p[1] / g) + 0.0f;
+    key = ((unsigned long long)__float_as_uint(fu) << 32) | __float_as_uint(fv);
+    return true;
 }
 
-__global__ void k_zero_words(uint32_t* __restrict__ p, int64_t m) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < m) p[i] = 0u;
+__device__ __forceinline__ uint32_t uv_slot(unsigned long long key, int bits) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - bits));
 }
 
 struct VoteArgs {
     const float* pts;
     int64_t n;
     float g;
-    int umin, vmin;
-    uint32_t wu;
-    uint32_t* table;
+    HashSlot* table;   // 2^bits slots: key, -, count
+    int bits;
     int32_t tau;
     uint8_t* keep;
     int32_t* votes;
 };
 
-__device__ __forceinline__ int64_t vote_slot(const VoteArgs& a, int64_t i) {
-    int u, v;
-    bool bad;
-    if (!uv_of(a.pts + 3 * i, a.g, u, v, bad) || bad) return -1;
-    return (int64_t)(uint32_t)(u - a.umin) + (int64_t)a.wu * (int64_t)(uint32_t)(v - a.vmin);
+__global__ void __launch_bounds__(WT) k_vote_clear(HashSlot* __restrict__ t, int64_t cap) {
+    const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
+    if (i < cap) t[i] = HashSlot{EMPTY_KEY, 0u, 0u};
 }
 
 __global__ void __launch_bounds__(WT) k_vote(VoteArgs a) {
     const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
     if (i >= a.n) return;
-    const int64_t s = vote_slot(a, i);
-    if (s >= 0) atomicAdd(&a.table[s], 1u);
+    unsigned long long key;
+    if (!uv_key(a.pts + 3 * i, a.g, key)) return;
+    const uint32_t mask = (1u << a.bits) - 1u;
+    // the table holds at most n < half its slots: an empty slot is reached
+    for (uint32_t s = uv_slot(key, a.bits);; s = (s + 1) & mask) {
+        const unsigned long long old = atomicCAS(&a.table[s].key, EMPTY_KEY, key);
+        if (old == EMPTY_KEY || old == key) {
+            atomicAdd(&a.table[s].count, 1u);
+            return;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(WT) k_vote_read(VoteArgs a) {
     const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
     if (i >= a.n) return;
-    const int64_t s = vote_slot(a, i);
-    const int32_t c = s >= 0 ? (int32_t)a.table[s] : 0;
+    unsigned long long key;
+    int32_t c = 0;
+    if (uv_key(a.pts + 3 * i, a.g, key)) {
+        const uint32_t mask = (1u << a.bits) - 1u;
+        // the point's own vote put its key in the table
+        for (uint32_t s = uv_slot(key, a.bits);; s = (s + 1) & mask) {
+            const unsigned long long k = a.table[s].key;
+            if (k == key) {
+                c = (int32_t)a.table[s].count;
+                break;
+            }
+            if (k == EMPTY_KEY) break;
+        }
+    }
     if (a.votes) a.votes[i] = c;
-    a.keep[i] = (s >= 0 && c >= a.tau) ? 1 : 0;
+    a.keep[i] = (c > 0 && c >= a.tau) ? 1 : 0;
 }
 
 // ---------------------------------------------------------- clustering --
@@ -270,36 +257,14 @@ lkc_status zvote(lkc_ctx* ctx, const float* pts, int64_t n, float g, int32_t tau
                  uint8_t* keep, int32_t* votes) {
     if (n == 0) return LKC_OK;
     hipStream_t st = ctx->stream;
-    UvMeta* md = uv_meta_dev(ctx);
-    UvMeta* mh = uv_meta_host(ctx);
-    hipLaunchKernelGGL(k_uv_init, dim3(1), dim3(64), 0, st, md);
-    hipLaunchKernelGGL(k_uv_bounds, dim3(grid_of(n, WT)), dim3(WT), 0, st, pts, n, g, md);
-    LKC_HIP_TRY(ctx, hipGetLastError());
-    LKC_HIP_TRY(ctx, hipMemcpyAsync(mh, md, sizeof(UvMeta), hipMemcpyDeviceToHost, st));
-    LKC_HIP_TRY(ctx, hipStreamSynchronize(st));
-    if (mh->bad)
-        return set_error(ctx, LKC_ERR_INVALID_ARG,
-                         "%u points fall in a 2-D cell outside [-2^30, 2^30)", mh->bad);
-    VoteArgs a{pts, n, g, 0, 0, 1u, nullptr, tau, keep, votes};
-    uint64_t cells = 0;
-    if (mh->umin <= mh->umax) {
-        const uint64_t wu = (uint64_t)((int64_t)mh->umax - mh->umin) + 1;
-        const uint64_t wv = (uint64_t)((int64_t)mh->vmax - mh->vmin) + 1;
-        if (wu > ZVOTE_MAX_CELLS || wv > ZVOTE_MAX_CELLS || wu * wv > ZVOTE_MAX_CELLS)
-            return set_error(ctx, LKC_ERR_BUDGET,
-                             "the occupied 2-D box has %llu x %llu cells (limit 2^28)",
-                             (unsigned long long)wu, (unsigned long long)wv);
-        cells = wu * wv;
-        a.umin = mh->umin;
-        a.vmin = mh->vmin;
-        a.wu = (uint32_t)wu;
-    }
+    int bits = 6;
+    while (((int64_t)1 << bits) < 2 * n) ++bits;
+    const int64_t cap = (int64_t)1 << bits;
     lkc_status s;
-    a.table = (uint32_t*)aux_scratch(ctx, 4 * (size_t)std::max<uint64_t>(cells, 1), &s);
-    if (!a.table) return s;
-    if (cells)
-        hipLaunchKernelGGL(k_zero_words, dim3(grid_of((int64_t)cells, WT)), dim3(WT), 0, st,
-                           a.table, (int64_t)cells);
+    HashSlot* table = (HashSlot*)aux_scratch(ctx, sizeof(HashSlot) * (size_t)cap, &s);
+    if (!table) return s;
+    VoteArgs a{pts, n, g, table, bits, tau, keep, votes};
+    hipLaunchKernelGGL(k_vote_clear, dim3(grid_of(cap, WT)), dim3(WT), 0, st, table, cap);
     hipLaunchKernelGGL(k_vote, dim3(grid_of(n, WT)), dim3(WT), 0, st, a);
     hipLaunchKernelGGL(k_vote_read, dim3(grid_of(n, WT)), dim3(WT), 0, st, a);
     LKC_HIP_TRY(ctx, hipGetLastError());

@@ -9,6 +9,8 @@ labels are checked under the boundary-band rule (tests/parity.py): the
 components lie between those of eps*(1-1e-6) and eps*(1+1e-6), and each
 component is labelled by its smallest index.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -67,9 +69,46 @@ def test_zvote_errors(lk):
     for cell, tau in ((0.0, 1), (0.5, 0), (float("nan"), 1)):
         with pytest.raises(lkc.LkcError):
             lkc.lkc_zvote(ctx, dev(p), cell, tau)
-    far = np.array([[0, 0, 0], [1e5, 1e5, 0]], np.float32)
-    with pytest.raises(lkc.LkcError, match="BUDGET"):
-        lkc.lkc_zvote(ctx, dev(far), 1e-3, 1)
+    # a sparse, very wide cloud (2-D cells 1e8 apart) and signed zeros: the
+    # hash table needs no box, and -0 and +0 share their cell
+    far = np.array([[0, 0, 0], [1e5, 1e5, 0], [-0.0, -0.0, 1], [1e5, 1e5, 2],
+                    [-1e5, 3e4, 0]], np.float32)
+    keep, votes = lkc.lkc_zvote(ctx, dev(far), 1e-3, 2)
+    ok, ov = oracle.zvote(far, 1e-3, 2)
+    np.testing.assert_array_equal(votes.cpu().numpy(), ov)
+    np.testing.assert_array_equal(keep.cpu().numpy(), ok)
+    assert list(ov) == [2, 2, 2, 2, 1]
+
+
+def test_zvote_replayed_from_a_graph(lk):
+    """The z-vote needs no host round trip: captured once and replayed on
+    new clouds written into the same buffer, every replay equals the
+    oracle."""
+    lkc, ctx = lk
+    clouds = [workloads.random_cloud(20_000, s, scale=10.0) for s in (71, 72, 73)]
+    buf = dev(clouds[0])
+    keep = torch.empty(20_000, dtype=torch.uint8, device="cuda")
+    votes = torch.empty(20_000, dtype=torch.int32, device="cuda")
+
+    def call():
+        ctx._bind()
+        ctx.check(ctx.lib.lkc_zvote(ctx.handle, ctypes.c_void_p(buf.data_ptr()), 20_000,
+                                    0.7, 3, ctypes.c_void_p(keep.data_ptr()),
+                                    ctypes.c_void_p(votes.data_ptr())))
+
+    call()                       # sizes the scratch outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    for p in clouds[1:] + clouds:
+        buf.copy_(torch.from_numpy(p))
+        g.replay()
+        torch.cuda.synchronize()
+        ok, ov = oracle.zvote(p, 0.7, 3)
+        np.testing.assert_array_equal(votes.cpu().numpy(), ov)
+        np.testing.assert_array_equal(keep.cpu().numpy(), ok)
+    del g
 
 
 @pytest.mark.parametrize("n,eps,seed", [(1, 0.5, 0), (2_000, 0.4, 1), (15_000, 0.3, 2)])
