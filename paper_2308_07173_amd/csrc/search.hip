@@ -822,8 +822,8 @@ __device__ __forceinline__ float shared_thr(const SplitShare& sh, int lane, floa
 // the last entry shared the k-th distance's bucket, or because the wave ran
 // out of chunk names; then clock cycles of the first wavefront in the
 // streaming (probes and chunks), in decoding and merging the lists, and in
-// the covariances; then the 16-point runs whose box passed the group's
-// test and those some lane's own bound kept
+// the covariances; then the 16-point runs tested against the members'
+// bounds and those some member's bound kept
 constexpr int PROF_WORDS = 25;
 // A profile counter that compiles away in the unprofiled kernels (their
 // counters are never read, so the arithmetic feeding them is dead).
@@ -875,17 +875,6 @@ __device__ __forceinline__ SlotQuery load_slot(const GroupArgs& a, const TargetV
     return s;
 }
 
-// Squared distance between two axis-aligned boxes (0 if they overlap),
-// shrunk by `margin`.
-__device__ __forceinline__ float box_box_dist2(const float (&a0)[3], const float (&a1)[3],
-                                               float b0x, float b0y, float b0z, float b1x,
-                                               float b1y, float b1z, float margin) {
-    const float gx = fmaxf(fmaxf(b0x - a1[0], a0[0] - b1x) - margin, 0.0f);
-    const float gy = fmaxf(fmaxf(b0y - a1[1], a0[1] - b1y) - margin, 0.0f);
-    const float gz = fmaxf(fmaxf(b0z - a1[2], a0[2] - b1z) - margin, 0.0f);
-    return gx * gx + gy * gy + gz * gz;
-}
-
 // Packed insertion keys.  While a block is streamed, a lane keeps its
 // nearest candidates as 32-bit keys: the float32 bits of d2 with the low
 // ID_BITS bits replaced by the candidate's name (the ordinal of its 64-point
@@ -911,6 +900,25 @@ constexpr int MAX_CHUNKS = 1 << (ID_BITS - 6);   // chunk ordinals (0 unused)
 __device__ __forceinline__ uint32_t med3_u32(uint32_t a, uint32_t x, uint32_t b) {
     uint32_t r;
     asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(x), "v"(b));
+    return r;
+}
+
+// The position of the lowest set bit of x, ~0u when x is 0.
+__device__ __forceinline__ uint32_t ffbl_u32(uint32_t x) {
+    uint32_t r;
+    asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// 2 b + (d <= t): the compare's lane mask is the add's carry in (the two
+// wait states are the ones a mask written by a VALU compare needs before a
+// VALU instruction reads it).
+__device__ __forceinline__ uint32_t shift_in_le(uint32_t b, float d, float t) {
+    uint32_t r;
+    unsigned long long m;
+    asm("v_cmp_le_f32_e64 %1, %3, %4\n\ts_nop 1\n\tv_addc_co_u32_e64 %0, %1, %2, %2, %1"
+        : "=v"(r), "=&s"(m)
+        : "v"(b), "v"(d), "v"(t));
     return r;
 }
 
@@ -967,8 +975,10 @@ __device__ __forceinline__ void sort_u32(uint32_t (&L)[N]) {
 // Stream the reordered points [s0, e0) through every member lane's list.
 // The run is walked in aligned 64-point chunks made of four 16-point runs
 // with their own bounding boxes; a 16-point run whose box is farther from
-// the query box than the radius or the group's largest k-th bound, or from
-// every member's query than its own bound, is skipped.  A kept chunk
+// every member's query than that member's own bound (never above the
+// radius) is skipped.  (A test of the run's box against the members' query
+// box would be implied by this one: it only ever saved the per-lane test,
+// at a cost above that test's.)  A kept chunk
 // is named (its ordinal in this wave's stream, recorded in s_tab; fixed_ord
 // names a chunk the caller registered); each candidate is broadcast from its lane and
 // tested by every lane, which only sets a bit per passing candidate; the
@@ -979,7 +989,6 @@ __device__ __forceinline__ void sort_u32(uint32_t (&L)[N]) {
 template <int K, bool PROF>
 __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bool member,
                                          float qx, float qy, float qz, float r2, float lcap,
-                                         const float (&b0)[3], const float (&b1)[3],
                                          float margin, float& gthr, uint32_t (&L)[K + SLACK],
                                          GroupProf<PROF>& gp, int skip_cb,
                                          const SplitShare& sh, int& n_ch, uint32_t* s_tab,
@@ -1006,9 +1015,6 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             const int sb = cb + q4 * BOX_PTS;
             if (sb + BOX_PTS <= s0 || sb >= e0) continue;
             const float4 blo = bb[2 * q4], bhi = bb[2 * q4 + 1];
-            const float bd =
-                box_box_dist2(b0, b1, blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z, margin);
-            if (!(bd <= r2 && bd * (1.0f - 1e-6f) <= gthr)) continue;
             gp.runs_grp++;
             // and some lane needs it: the run's box is within that lane's own
             // bound
@@ -1041,13 +1047,16 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             if (!((keep >> q4) & 1u)) continue;
             const int t1 = min(hi, (q4 + 1) * BOX_PTS);
             gp.cands += (uint32_t)max(0, t1 - max(lo, q4 * BOX_PTS));
+            // Descending: each test doubles the word and adds its outcome,
+            // so candidate t ends at bit t - t0.
+            const int t0 = max(lo, q4 * BOX_PTS);
             uint32_t b = 0;
 #pragma unroll 2
-            for (int t = max(lo, q4 * BOX_PTS); t < t1; ++t) {
+            for (int t = t1 - 1; t >= t0; --t) {
                 const float cx = readlane(c.x, t), cy = readlane(c.y, t), cz = readlane(c.z, t);
-                const float d = dist2(qx, qy, qz, cx, cy, cz);
-                b |= (d <= tthr ? 1u : 0u) << (t & 31);
+                b = shift_in_le(b, dist2(qx, qy, qz, cx, cy, cz), tthr);
             }
+            b <<= (t0 & 31);
             if (q4 < 2)
                 blo |= b;
             else
@@ -1065,39 +1074,48 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         // Each lane's next passing candidate (lane 63 when none: read, not
         // inserted) is fetched one pop ahead, so the fetch overlaps the
         // insertion chain of the current one.
-        auto fetch = [&](int jj, float& fx, float& fy, float& fz) {
-            const int ja = jj << 2;
+        auto fetch = [&](uint32_t jj, float& fx, float& fy, float& fz) {
+            const int ja = (int)(jj << 2);
             fx = __int_as_float(__builtin_amdgcn_ds_bpermute(ja, __float_as_int(c.x)));
             fy = __int_as_float(__builtin_amdgcn_ds_bpermute(ja, __float_as_int(c.y)));
             fz = __int_as_float(__builtin_amdgcn_ds_bpermute(ja, __float_as_int(c.z)));
         };
-        bool has = bits != 0ull;
-        int j = __builtin_ctzll(bits | (1ull << 63));
-        float cx, cy, cz;
-        fetch(j, cx, cy, cz);
-        bits &= bits - 1ull;
-        do {
+        // The lowest set bit of a lane's mask, ~0u when it is empty: the
+        // empty lane's key is then ~0u, which inserts nothing, and its fetch
+        // reads lane 63.
+        auto first = [](unsigned long long m) -> uint32_t {
+            return min(ffbl_u32((uint32_t)m), ffbl_u32((uint32_t)(m >> 32)) | 32u);
+        };
+        auto insert = [&](uint32_t jj, float px, float py, float pz) {
             gp.pops++;
-            const bool has_n = bits != 0ull;
-            const int j_n = __builtin_ctzll(bits | (1ull << 63));
-            float nx, ny, nz;
-            fetch(j_n, nx, ny, nz);
-            bits &= bits - 1ull;
             // d2 <= the lane's bound <= r2: within the radius
-            const uint32_t db = __float_as_uint(dist2(qx, qy, qz, cx, cy, cz));
-            const uint32_t x = has ? ((db & ~ID_MASK) | name0 | (uint32_t)j) : ~0u;
+            const uint32_t db = __float_as_uint(dist2(qx, qy, qz, px, py, pz));
+            const uint32_t x = (db & ~ID_MASK) | name0 | jj;
             if (PROF) {
                 const unsigned long long im = ballot(x < L[K + SLACK - 1]);
                 gp.inserts += (uint32_t)__popcll(im);
                 gp.dead += im ? 0u : 1u;
             }
             pk_insert<K + SLACK>(L, x);
-            has = has_n;
-            j = j_n;
-            cx = nx;
-            cy = ny;
-            cz = nz;
-        } while (ballot(has));
+        };
+        // Unrolled by two so that the candidate fetched ahead needs no copy.
+        uint32_t j = first(bits);
+        bits &= bits - 1ull;
+        float cx, cy, cz;
+        fetch(j, cx, cy, cz);
+        for (;;) {
+            const uint32_t jn = first(bits);
+            bits &= bits - 1ull;
+            float nx, ny, nz;
+            fetch(jn, nx, ny, nz);
+            insert(j, cx, cy, cz);
+            if (!ballot(jn != ~0u)) break;
+            j = first(bits);
+            bits &= bits - 1ull;
+            fetch(j, cx, cy, cz);
+            insert(jn, nx, ny, nz);
+            if (!ballot(j != ~0u)) break;
+        }
         float own = pk_bound<K>(L, r2, lcap);
         if (sh.split_mask) {
             sh.thr[sh.sub * WAVE + lane] = own;
@@ -1348,14 +1366,14 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                 }
                 const uint32_t i0 = gp.inserts;
                 scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
-                            s.z, r2, lcap, b0, b1, margin, gthr, L, gp, -1, sh, n_ch, s_tab, 1,
+                            s.z, r2, lcap, margin, gthr, L, gp, -1, sh, n_ch, s_tab, 1,
                             win_k, n_act);
                 gp.own += gp.inserts - i0;
             }
         }
         if (whole) {
             const uint32_t i0 = gp.inserts, c0 = gp.cands;
-            scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin, gthr,
+            scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, margin, gthr,
                         L, gp, own_cb, sh, n_ch, s_tab);
             gp.ins2 += gp.inserts - i0;
             gp.cand2 += gp.cands - c0;
@@ -1398,7 +1416,7 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                     const int s0 = readlane((int)st, cl);
                     const int e0 = s0 + readlane((int)cn, cl);
                     gp.cells++;
-                    scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, b0, b1, margin,
+                    scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, margin,
                                 gthr, L, gp, own_cb, sh, n_ch, s_tab);
                 }
                 if (pass == 0) {
