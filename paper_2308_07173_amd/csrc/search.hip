@@ -922,6 +922,18 @@ __device__ __forceinline__ uint32_t shift_in_le(uint32_t b, float d, float t) {
     return r;
 }
 
+typedef uint32_t u32x16 __attribute__((ext_vector_type(16)));
+
+// The 128 bytes at p (wavefront-uniform, read-only) as two 64-byte scalar
+// loads.  The wait stays inside the statement: the compiler takes an asm
+// statement's outputs as written when it ends.
+__device__ __forceinline__ void load_boxes64(const float4* p, u32x16& a, u32x16& b) {
+    asm volatile("s_load_dwordx16 %0, %2, 0x0\n\ts_load_dwordx16 %1, %2, 0x40\n\ts_waitcnt lgkmcnt(0)"
+                 : "=&s"(a), "=&s"(b)
+                 : "s"(p)
+                 : "memory");
+}
+
 // Insert x into the ascending list L; a no-op when x is not below L[N-1].
 template <int N>
 __device__ __forceinline__ void pk_insert(uint32_t (&L)[N], uint32_t x) {
@@ -948,16 +960,15 @@ __device__ __forceinline__ void insert_p(uint32_t (&D)[K], uint32_t (&P)[K], uin
     D[0] = min(D[0], x);
 }
 
-// The largest d2 of a key's bucket (NaN for the bucket of +inf).
-__device__ __forceinline__ float pk_upper(uint32_t key) { return __uint_as_float(key | ID_MASK); }
-
 // A lane's pruning bound: the top of its k-th entry's bucket (the radius
 // while it holds fewer than k entries), never above its bound lcap.  The
 // k-th entry sits at K - 1: k < K lists start with K - k zero pads.
 template <int K>
 __device__ __forceinline__ float pk_bound(const uint32_t (&L)[K + SLACK], float r2, float lcap) {
-    const uint32_t e = L[K - 1];
-    return fminf(e == ~0u ? r2 : fminf(pk_upper(e), r2), lcap);
+    // all three are non-negative floats (an empty entry's ~0u is above
+    // every one), which order as their bits
+    return __uint_as_float(
+        min(min(L[K - 1] | ID_MASK, __float_as_uint(r2)), __float_as_uint(lcap)));
 }
 
 // Sort 32-bit keys ascending in registers.
@@ -989,7 +1000,7 @@ __device__ __forceinline__ void sort_u32(uint32_t (&L)[N]) {
 template <int K, bool PROF>
 __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bool member,
                                          float qx, float qy, float qz, float r2, float lcap,
-                                         float margin, float& gthr, uint32_t (&L)[K + SLACK],
+                                         float3 qlo, float3 qhi, uint32_t (&L)[K + SLACK],
                                          GroupProf<PROF>& gp, int skip_cb,
                                          const SplitShare& sh, int& n_ch, uint32_t* s_tab,
                                          int fixed_ord = -1, int win_k = 0, int win_n = 0) {
@@ -1001,28 +1012,32 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
         // the chunk's load goes out with its boxes' (lane t holds point t,
         // one coalesced read; padded: reads past n stay in bounds)
         const float4 c = gload(T.pts + cb + lane);
-        // and so do the boxes of its four runs (one scalar burst; the boxes
-        // carry 4 spare runs)
-        float4 bb[2 * (WAVE / BOX_PTS)];
-#pragma unroll
-        for (int i = 0; i < 2 * (WAVE / BOX_PTS); ++i)
-            bb[i] = load_uniform(T.boxes + 2 * (cb / BOX_PTS) + i);
+        // and so do the boxes of its four runs (two 64-byte scalar loads; the
+        // boxes carry 4 spare runs)
+        u32x16 bw[2];
+        load_boxes64(T.boxes + 2 * (cb / BOX_PTS), bw[0], bw[1]);
         uint32_t keep = 0;
         float lthr = pk_bound<K>(L, r2, lcap);
         if (sh.split_mask) lthr = shared_thr(sh, lane, lthr);
+        // a run is kept when its box is within some member's bound of that
+        // member's query box widened by the margin (non-members: never)
+        const float bthr = member ? lthr * (1.0f + 2e-6f) : -1.0f;
 #pragma unroll
         for (int q4 = 0; q4 < WAVE / BOX_PTS; ++q4) {
             const int sb = cb + q4 * BOX_PTS;
             if (sb + BOX_PTS <= s0 || sb >= e0) continue;
-            const float4 blo = bb[2 * q4], bhi = bb[2 * q4 + 1];
+            const u32x16& w = bw[q4 >> 1];
+            const int o = 8 * (q4 & 1);
+            const float3 blo = make_float3(__uint_as_float(w[o]), __uint_as_float(w[o + 1]),
+                                           __uint_as_float(w[o + 2]));
+            const float3 bhi = make_float3(__uint_as_float(w[o + 4]), __uint_as_float(w[o + 5]),
+                                           __uint_as_float(w[o + 6]));
             gp.runs_grp++;
-            // and some lane needs it: the run's box is within that lane's own
-            // bound
-            const float gx = fmaxf(fmaxf(blo.x - qx, qx - bhi.x) - margin, 0.0f);
-            const float gy = fmaxf(fmaxf(blo.y - qy, qy - bhi.y) - margin, 0.0f);
-            const float gz = fmaxf(fmaxf(blo.z - qz, qz - bhi.z) - margin, 0.0f);
-            const float ld = gx * gx + gy * gy + gz * gz;
-            if (ballot(member && ld * (1.0f - 1e-6f) <= lthr)) {
+            const float gx = fmaxf(fmaxf(blo.x - qhi.x, qlo.x - bhi.x), 0.0f);
+            const float gy = fmaxf(fmaxf(blo.y - qhi.y, qlo.y - bhi.y), 0.0f);
+            const float gz = fmaxf(fmaxf(blo.z - qhi.z, qlo.z - bhi.z), 0.0f);
+            const float ld = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+            if (ballot(ld <= bthr)) {
                 keep |= 1u << q4;
                 gp.runs_kept++;
             }
@@ -1116,12 +1131,8 @@ __device__ __forceinline__ void scan_run(const TargetView& T, int s0, int e0, bo
             insert(jn, nx, ny, nz);
             if (!ballot(j != ~0u)) break;
         }
-        float own = pk_bound<K>(L, r2, lcap);
-        if (sh.split_mask) {
-            sh.thr[sh.sub * WAVE + lane] = own;
-            own = shared_thr(sh, lane, own);
-        }
-        gthr = wave_max_dpp(member ? own : -INF);
+        // publish the lane's bound to the group's other waves
+        if (sh.split_mask) sh.thr[sh.sub * WAVE + lane] = pk_bound<K>(L, r2, lcap);
     }
 }
 
@@ -1322,8 +1333,9 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
         const float qabs = fmaxf(fmaxf(fmaxf(fabsf(bx0), fabsf(bx1)), fmaxf(fabsf(by0), fabsf(by1))),
                                  fmaxf(fabsf(bz0), fabsf(bz1)));
         const float margin = (fmaxf(qabs, T.max_abs) + 2.0f * T.cell) * 1e-6f;
-        // largest k-th distance bound over the members
-        float gthr = wave_max_dpp(member ? fminf(r2, lcap) : -INF);
+        // the lane's query widened by the margin (the runs' box tests)
+        const float3 qlo = make_float3(s.x - margin, s.y - margin, s.z - margin);
+        const float3 qhi = make_float3(s.x + margin, s.y + margin, s.z + margin);
         // this round's lists: K - k zero pads, then empty entries
         uint32_t L[KP];
 #pragma unroll
@@ -1366,14 +1378,14 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                 }
                 const uint32_t i0 = gp.inserts;
                 scan_run<K>(T, own_cb, (int)min((int64_t)own_cb + WAVE, T.n), member, s.x, s.y,
-                            s.z, r2, lcap, margin, gthr, L, gp, -1, sh, n_ch, s_tab, 1,
+                            s.z, r2, lcap, qlo, qhi, L, gp, -1, sh, n_ch, s_tab, 1,
                             win_k, n_act);
                 gp.own += gp.inserts - i0;
             }
         }
         if (whole) {
             const uint32_t i0 = gp.inserts, c0 = gp.cands;
-            scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, margin, gthr,
+            scan_run<K>(T, 0, (int)T.n, member, s.x, s.y, s.z, r2, lcap, qlo, qhi,
                         L, gp, own_cb, sh, n_ch, s_tab);
             gp.ins2 += gp.inserts - i0;
             gp.cand2 += gp.cands - c0;
@@ -1382,6 +1394,11 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
         for (int pass = 0; pass < (whole ? 0 : 2); ++pass) {
             for (int64_t base = 0; base < total; base += WAVE) {
                 gp.probes++;
+                // the members' largest k-th bound (their lists only tighten
+                // between probes)
+                float own = pk_bound<K>(L, r2, lcap);
+                if (sh.split_mask) own = shared_thr(sh, lane, own);
+                const float gthr = wave_max_dpp(member ? own : -INF);
                 const int64_t t = base + lane;
                 bool want = false;
                 uint32_t st = 0, cn = 0;
@@ -1416,8 +1433,8 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
                     const int s0 = readlane((int)st, cl);
                     const int e0 = s0 + readlane((int)cn, cl);
                     gp.cells++;
-                    scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, margin,
-                                gthr, L, gp, own_cb, sh, n_ch, s_tab);
+                    scan_run<K>(T, s0, e0, member, s.x, s.y, s.z, r2, lcap, qlo, qhi, L, gp,
+                                own_cb, sh, n_ch, s_tab);
                 }
                 if (pass == 0) {
                     gp.ins0 += gp.inserts - i0;
@@ -1569,13 +1586,17 @@ __device__ __forceinline__ void group_body(const GroupArgs& a, int64_t group, co
     if (sh.sub) return;   // the other waves of a split group are done
     to_fb = to_fb || (fin && !placed);
     const unsigned long long fm = ballot(to_fb);
-    if (PROF && lane == 0) {
-        uint32_t* pw = a.prof + group * PROF_WORDS;
-        pw[0] = (uint32_t)(__builtin_amdgcn_s_memtime() - t_start);
-        pw[1] = gp.probes;
-        pw[2] = gp.cells;
-        pw[6] = (uint32_t)__popcll(ballot(placed));
-        pw[7] = (uint32_t)__popcll(fm);
+    if (PROF) {
+        // (the ballot outside the lane-0 branch, so that it sees every lane)
+        const unsigned long long pm = ballot(placed);
+        if (lane == 0) {
+            uint32_t* pw = a.prof + group * PROF_WORDS;
+            pw[0] = (uint32_t)(__builtin_amdgcn_s_memtime() - t_start);
+            pw[1] = gp.probes;
+            pw[2] = gp.cells;
+            pw[6] = (uint32_t)__popcll(pm);
+            pw[7] = (uint32_t)__popcll(fm);
+        }
     }
     if (fm) {
         const int leader = __builtin_ffsll((long long)fm) - 1;
@@ -1616,7 +1637,8 @@ template <int K, int FUSED, bool PROF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 20 ? 4 : 2)))
 k_group(GroupArgs a) {
     const int wpb = blockDim.x / WAVE;
-    const int wid = threadIdx.x / WAVE;
+    // (wavefront-uniform: scalar registers and branches for what follows)
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int64_t n_groups = (a.n_slots + WAVE - 1) / WAVE;
     extern __shared__ uint32_t s_dyn[];
     uint32_t* s_tab = s_dyn + wid * MAX_CHUNKS;
@@ -1729,9 +1751,31 @@ struct QueryKeyArgs {
     const BatchHeader* hdr;
     int tshift;
     int sub_bits;
+    int w[3];   // bits of each axis's clamped cell coordinate
     unsigned long long* keys;
     uint32_t* vals;
 };
+
+// The cell coordinates' bits interleaved from the lowest level up, x first,
+// an axis dropping out once its w[a] bits are used: the Morton order of the
+// cells in w[0] + w[1] + w[2] bits (a flat box needs no key bits for the
+// levels only its long axes have).
+__device__ __forceinline__ unsigned long long morton_compact(const uint32_t (&v)[3],
+                                                             const int (&w)[3]) {
+    unsigned long long key = 0;
+    int pos = 0;
+    const int wm = max(w[0], max(w[1], w[2]));
+    for (int i = 0; i < wm; ++i) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (i < w[d]) {
+                key |= (unsigned long long)((v[d] >> i) & 1u) << pos;
+                ++pos;
+            }
+        }
+    }
+    return key;
+}
 
 __global__ void __launch_bounds__(256) k_query_keys(QueryKeyArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1760,7 +1804,7 @@ __global__ void __launch_bounds__(256) k_query_keys(QueryKeyArgs a) {
             v[d] = (uint32_t)min(max(c - (T.cmin[d] - 1), 0), range);
         }
         const int sb = a.sub_bits;
-        key = (morton3(v[0], v[1], v[2]) << (3 * sb)) |
+        key = (morton_compact(v, a.w) << (3 * sb)) |
               morton3(sub_cell(x, T.inv_cell, sb), sub_cell(y, T.inv_cell, sb),
                       sub_cell(z, T.inv_cell, sb));
     } else {
@@ -2017,25 +2061,26 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg,
     // top bits (the wavefront-per-query search reads it unsorted).
     int tshift = 0, tbits = 0;
     if (j.queries && (group || j.n_targets > 1)) {
-        int wmax = 1;
+        int w[3] = {1, 1, 1};
         for (int t = 0; t < j.n_targets; ++t) {
             const TargetView& V = j.host_views[t];
             for (int d = 0; d < 3; ++d)
-                wmax = std::max(wmax, bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2)));
+                w[d] = std::max(w[d], bitw((uint32_t)(std::max(V.cmax[d] - V.cmin[d], 0) + 2)));
         }
+        const int wsum = w[0] + w[1] + w[2];
         // Morton key of the (clamped) query cell, then of its sub-cell (as
         // many sub-cell bits, from 2 to 4 per axis, as the fewest 8-bit sort
         // passes holding the key with 2 of them allow)
         tbits = j.n_targets > 1 ? bitw((uint32_t)(j.n_targets - 1)) : 0;
-        const int sub_lo = std::max(0, std::min(2, (63 - tbits - 3 * wmax) / 3));
-        const int room = std::min(63, 8 * ((tbits + 3 * wmax + 3 * sub_lo + 7) / 8)) - tbits;
-        const int sub_bits = std::max(sub_lo, std::min(4, (room - 3 * wmax) / 3));
-        tshift = 3 * wmax + 3 * sub_bits;
+        const int sub_lo = std::max(0, std::min(2, (63 - tbits - wsum) / 3));
+        const int room = std::min(63, 8 * ((tbits + wsum + 3 * sub_lo + 7) / 8)) - tbits;
+        const int sub_bits = std::max(sub_lo, std::min(4, (room - wsum) / 3));
+        tshift = wsum + 3 * sub_bits;
         if (tshift + tbits > 63)
             return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",
                              tshift + tbits);
         QueryKeyArgs qa{j.queries, j.n_slots, j.views_dev, j.scans_dev, j.hdr_dev, tshift,
-                        sub_bits, sc.ka, sc.va};
+                        sub_bits, {w[0], w[1], w[2]}, sc.ka, sc.va};
         hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256), 0,
                            st, qa);
     }
