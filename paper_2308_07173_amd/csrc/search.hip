@@ -1705,7 +1705,7 @@ k_group(GroupArgs a) {
 // Persistent: waves stride over the list (its length is only known on the
 // device).
 template <int FUSED>
-__global__ void __launch_bounds__(256) k_fallback(GroupArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_fallback(GroupArgs a) {
     const int lane = lane_id();
     const uint32_t nfb = *(volatile uint32_t*)a.fb_count;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
@@ -2147,8 +2147,10 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg,
         if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[1], st));
     }
     if (ctx->timing) LKC_HIP_TRY(ctx, hipEventRecord(ctx->ev[2], st));
-    // persistent: five 4-wave workgroups per CU fill the kernel's occupancy
-    const dim3 fgrid((unsigned)(ctx->num_cus * 5));
+    // persistent: six 4-wave workgroups per CU fill the kernel's occupancy
+    // (at most 80 registers a lane; a query's search is a chain of dependent
+    // loads, so more resident waves shorten the list each one works through)
+    const dim3 fgrid((unsigned)(ctx->num_cus * 6));
     if (j.fused == 2)
         hipLaunchKernelGGL(k_fallback<2>, fgrid, dim3(256), 0, st, a);
     else if (j.fused == 1)
