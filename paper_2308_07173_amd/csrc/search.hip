@@ -1778,20 +1778,34 @@ __device__ __forceinline__ unsigned long long morton_compact(const uint32_t (&v)
 }
 
 __global__ void __launch_bounds__(256) k_query_keys(QueryKeyArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.q) return;
+    __shared__ int s_lo;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t i = i0 + threadIdx.x;
     int tg = 0;
     if (a.scans) {
-        int lo = 0, hi = a.hdr->n_scans - 1;
-        while (lo < hi) {   // last scan with q_offset <= i
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.scans[mid].q_offset <= i)
-                lo = mid;
-            else
-                hi = mid - 1;
+        // The last scan starting at or before the workgroup's first query,
+        // found once; each thread then steps to its own (the scans are
+        // consecutive ranges, so a workgroup spans few of them).
+        if (threadIdx.x == 0) {
+            int lo = 0, hi = a.hdr->n_scans - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.scans[mid].q_offset <= i0)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            s_lo = lo;
         }
-        tg = a.scans[lo].target_index;
+        __syncthreads();
+        if (i < a.q) {
+            const int ns = a.hdr->n_scans;
+            int lo = s_lo;
+            while (lo + 1 < ns && a.scans[lo + 1].q_offset <= i) ++lo;
+            tg = a.scans[lo].target_index;
+        }
     }
+    if (i >= a.q) return;
     const TargetView& T = a.views[tg];
     const float x = a.queries[3 * i], y = a.queries[3 * i + 1], z = a.queries[3 * i + 2];
     unsigned long long key;
@@ -2079,7 +2093,9 @@ lkc_status run_search(lkc_ctx* ctx, const SearchJob& j, const LaunchCfg& cfg,
         if (tshift + tbits > 63)
             return set_error(ctx, LKC_ERR_UNSUPPORTED, "query sort key needs %d bits",
                              tshift + tbits);
-        QueryKeyArgs qa{j.queries, j.n_slots, j.views_dev, j.scans_dev, j.hdr_dev, tshift,
+        // (one target: every scan's target is 0, no lookup)
+        QueryKeyArgs qa{j.queries, j.n_slots, j.views_dev, j.n_targets > 1 ? j.scans_dev : nullptr,
+                        j.hdr_dev, tshift,
                         sub_bits, {w[0], w[1], w[2]}, sc.ka, sc.va};
         hipLaunchKernelGGL(k_query_keys, dim3((unsigned)((j.n_slots + 255) / 256)), dim3(256), 0,
                            st, qa);
