@@ -17,7 +17,9 @@
  *                       the same with kernel-descriptor neighbour weights
  *   lkc_gicp_linearize / lkc_gicp_align
  *                       GICP correspondences, Gauss-Newton system, iterations
- *   lkc_voxel_filter    voxel centroids of a cloud
+ *   lkc_voxel_filter / lkc_voxel_filter_async
+ *                       voxel centroids of a cloud (the second without a
+ *                       host wait)
  *   lkc_submap_extract / lkc_submap_build
  *                       the map points within a radius of a pose
  *   lkc_raceline_build / lkc_submap_window / lkc_submap_window_build
@@ -367,6 +369,27 @@ lkc_status lkc_gicp_align(lkc_ctx *ctx, const lkc_target *target, const float *t
 lkc_status lkc_voxel_filter(lkc_ctx *ctx, const float *points, int64_t n, const float *origin,
                             float leaf, float *centroid, int32_t *count, int32_t *voxel,
                             int64_t capacity, int64_t *n_out);
+
+/* The same voxel filter with no host wait, for a per-frame pipeline on a
+ * stream or in a captured graph: the results of lkc_voxel_filter (bit for
+ * bit, same order) for a cloud whose occupied voxels span fewer than
+ * 2^axis_bits voxels along each axis (1 <= axis_bits <= 21; the sort key
+ * holds 3 axis_bits + 1 bits, so 10 bits -- 1,024 voxels -- take four radix
+ * passes).  The voxel count and the call's status go to device memory:
+ * n_out device int64 [1], status device int32 [1].  Status LKC_OK;
+ * LKC_ERR_BUDGET when the voxel count exceeds capacity (*n_out then holds
+ * the count) or the occupied box reaches 2^axis_bits voxels along some axis
+ * (*n_out = 0); LKC_ERR_INVALID_ARG when a voxel coordinate falls outside
+ * [-2^20, 2^20) (*n_out = 0).  On any error status nothing is written to
+ * centroid, count or voxel.  The return value reports only argument errors
+ * found on the host (nothing is enqueued then).  Scratch comes from the
+ * context's grow-only auxiliary buffer: nothing is synchronised once it
+ * holds the call (growing it synchronises, so call once before capturing).
+ * Calls on one context share that scratch and run in stream order. */
+lkc_status lkc_voxel_filter_async(lkc_ctx *ctx, const float *points, int64_t n,
+                                  const float *origin, float leaf, int32_t axis_bits,
+                                  float *centroid, int32_t *count, int32_t *voxel,
+                                  int64_t capacity, int64_t *n_out, int32_t *status);
 
 /* Sliding-window submap around an arbitrary centre (Sec. III-C.3: only the
  * map points near the current pose are queried), by a pass over every map

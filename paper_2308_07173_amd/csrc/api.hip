@@ -474,6 +474,30 @@ lkc_status lkc_voxel_filter(lkc_ctx* ctx, const float* points, int64_t n, const 
     return lkc::voxel_filter(ctx, points, n, o, leaf, centroid, count, voxel, capacity, n_out);
 }
 
+lkc_status lkc_voxel_filter_async(lkc_ctx* ctx, const float* points, int64_t n,
+                                  const float* origin, float leaf, int32_t axis_bits,
+                                  float* centroid, int32_t* count, int32_t* voxel,
+                                  int64_t capacity, int64_t* n_out, int32_t* status) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!n_out || !status) return set_error(ctx, LKC_ERR_INVALID_ARG, "n_out or status is NULL");
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (!(leaf > 0.0f) || !std::isfinite(leaf))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "leaf must be finite and > 0");
+    if (axis_bits < 1 || axis_bits > 21)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "axis_bits = %d outside [1, 21]", axis_bits);
+    const float zero[3] = {0.0f, 0.0f, 0.0f};
+    const float* o = origin ? origin : zero;
+    for (int d = 0; d < 3; ++d)
+        if (!std::isfinite(o[d])) return set_error(ctx, LKC_ERR_INVALID_ARG, "origin not finite");
+    if (capacity < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "capacity < 0");
+    if (n > 0 && (!points || (capacity > 0 && !centroid)))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL points or centroid pointer");
+    return lkc::voxel_filter_async(ctx, points, n, o, leaf, axis_bits, centroid, count, voxel,
+                                   capacity, n_out, status);
+}
+
 namespace {
 
 lkc_status check_window(lkc_ctx* ctx, const lkc_target* map, const float* center, float radius,

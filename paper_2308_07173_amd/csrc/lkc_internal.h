@@ -166,6 +166,9 @@ void* aux_scratch(lkc_ctx* ctx, size_t bytes, lkc_status* st);
 lkc_status voxel_filter(lkc_ctx* ctx, const float* pts, int64_t n, const float* origin,
                         float leaf, float* centroid, int32_t* count, int32_t* voxel, int64_t cap,
                         int64_t* n_out);
+lkc_status voxel_filter_async(lkc_ctx* ctx, const float* pts, int64_t n, const float* origin,
+                              float leaf, int axis_bits, float* centroid, int32_t* count,
+                              int32_t* voxel, int64_t cap, int64_t* n_out, int32_t* status);
 lkc_status submap_extract(lkc_ctx* ctx, const lkc_target* t, const float* center, float radius,
                           int32_t* idx, float* gathered, int64_t cap, int64_t* n_out);
 lkc_status submap_build(lkc_ctx* ctx, const lkc_target* map, const float* center, float radius,

@@ -254,6 +254,119 @@ __global__ void __launch_bounds__(VT) k_vox_reduce(VoxOutArgs a) {
     }
 }
 
+// ---- the voxel filter without a host wait.  The key is (vz, vy, vx)
+// relative to the device-side box minimum with power-of-two strides of
+// `b` bits (the same (vz, vy, vx) order as the compact row-major key);
+// bit 3b marks the points left out (non-finite, outside [-2^20, 2^20), or
+// past 2^b in some axis: `over`), so they sort last.
+struct VoxAsyncArgs {
+    const float* pts;
+    int64_t n;
+    float ox, oy, oz, leaf;
+    int b;                  // bits per axis
+    VoxMeta* meta;          // bounds (k_vox_bounds_final), n_vox, over
+    unsigned long long* keys;
+    uint32_t* vals;
+    const uint32_t* offs;   // scanned run flags
+    uint32_t* starts;
+    float* centroid;
+    int32_t* count;
+    int32_t* voxel;
+    int64_t cap;
+    int64_t* n_out;         // device
+    int32_t* status;        // device
+};
+
+__global__ void __launch_bounds__(VT) k_vox_keys_async(VoxAsyncArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= a.n) return;
+    const unsigned long long left_out = 1ull << (3 * a.b);
+    int v[3];
+    bool bad;
+    unsigned long long key = left_out;
+    if (voxel_of(a.pts + 3 * i, a.ox, a.oy, a.oz, a.leaf, v, bad) && !bad) {
+        const uint32_t lim = 1u << a.b;
+        const uint32_t r0 = (uint32_t)(v[0] - a.meta->vmin[0]);
+        const uint32_t r1 = (uint32_t)(v[1] - a.meta->vmin[1]);
+        const uint32_t r2 = (uint32_t)(v[2] - a.meta->vmin[2]);
+        if (r0 < lim && r1 < lim && r2 < lim)
+            key = (unsigned long long)r0 | ((unsigned long long)r1 << a.b) |
+                  ((unsigned long long)r2 << (2 * a.b));
+        else
+            atomicOr(&a.meta->pad[0], 1u);   // over
+    }
+    a.keys[i] = key;
+    a.vals[i] = (uint32_t)i;
+}
+
+// flag[i] = 1 where sorted position i starts a voxel (left-out points: 0)
+__global__ void __launch_bounds__(VT) k_vox_flags_async(const unsigned long long* __restrict__ keys,
+                                                        int64_t n, unsigned long long left_out,
+                                                        uint32_t* __restrict__ flags) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= n) return;
+    flags[i] = keys[i] < left_out && (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+// Run starts; the last kept position records the voxel count (none kept:
+// the count stays the 0 the bounds reduction wrote).
+__global__ void __launch_bounds__(VT) k_vox_starts_async(const unsigned long long* __restrict__ keys,
+                                                         const uint32_t* __restrict__ offs,
+                                                         int64_t n, unsigned long long left_out,
+                                                         uint32_t* __restrict__ starts,
+                                                         VoxMeta* __restrict__ meta) {
+    const int64_t i = (int64_t)blockIdx.x * VT + threadIdx.x;
+    if (i >= n || keys[i] >= left_out) return;
+    const bool first = i == 0 || keys[i] != keys[i - 1];
+    if (first) starts[offs[i]] = (uint32_t)i;
+    if (i == n - 1 || keys[i + 1] >= left_out) {
+        const uint32_t nv = offs[i] + (first ? 1u : 0u);
+        starts[nv] = (uint32_t)(i + 1);
+        meta->n_vox = nv;
+    }
+}
+
+// The call's status from the device-side counts (one thread).
+__device__ __forceinline__ int32_t vox_async_status(const VoxMeta* m, int64_t cap) {
+    if (m->bad) return (int32_t)LKC_ERR_INVALID_ARG;
+    if (m->pad[0]) return (int32_t)LKC_ERR_BUDGET;
+    return (int64_t)m->n_vox > cap ? (int32_t)LKC_ERR_BUDGET : (int32_t)LKC_OK;
+}
+
+// One thread per voxel, as k_vox_reduce, when the status is LKC_OK; thread
+// 0 also writes the count and the status.
+__global__ void __launch_bounds__(VT) k_vox_reduce_async(VoxAsyncArgs a) {
+    const int64_t v = (int64_t)blockIdx.x * VT + threadIdx.x;
+    const VoxMeta* m = a.meta;
+    const int32_t status = vox_async_status(m, a.cap);
+    const int64_t nv = (int64_t)m->n_vox;
+    if (v == 0) {
+        *a.status = status;
+        *a.n_out = (m->bad || m->pad[0]) ? 0 : nv;
+    }
+    if (status != (int32_t)LKC_OK || v >= nv) return;
+    const uint32_t s = a.starts[v], e = a.starts[v + 1];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (uint32_t j = s; j < e; ++j) {
+        const int64_t i = a.vals[j];
+        sx += (double)a.pts[3 * i];
+        sy += (double)a.pts[3 * i + 1];
+        sz += (double)a.pts[3 * i + 2];
+    }
+    const double c = (double)(e - s);
+    a.centroid[3 * v] = (float)(sx / c);
+    a.centroid[3 * v + 1] = (float)(sy / c);
+    a.centroid[3 * v + 2] = (float)(sz / c);
+    if (a.count) a.count[v] = (int32_t)(e - s);
+    if (a.voxel) {
+        const unsigned long long k = a.keys[s];
+        const unsigned long long mask = (1ull << a.b) - 1ull;
+        a.voxel[3 * v] = (int32_t)(k & mask) + m->vmin[0];
+        a.voxel[3 * v + 1] = (int32_t)((k >> a.b) & mask) + m->vmin[1];
+        a.voxel[3 * v + 2] = (int32_t)(k >> (2 * a.b)) + m->vmin[2];
+    }
+}
+
 __global__ void __launch_bounds__(VT) k_submap_flags(const float4* __restrict__ orig, int64_t n,
                                                      float cx, float cy, float cz, float r2,
                                                      uint32_t* __restrict__ flags) {
@@ -390,6 +503,63 @@ lkc_status voxel_filter(lkc_ctx* ctx, const float* pts, int64_t n, const float* 
     VoxOutArgs oa{pts, sk, sv, starts, nv, {mh->vmin[0], mh->vmin[1], mh->vmin[2]}, w[0], w[1],
                   centroid, count, voxel};
     hipLaunchKernelGGL(k_vox_reduce, dim3(grid_of(nv, VT)), dim3(VT), 0, st, oa);
+    LKC_HIP_TRY(ctx, hipGetLastError());
+    return LKC_OK;
+}
+
+lkc_status voxel_filter_async(lkc_ctx* ctx, const float* pts, int64_t n, const float* origin,
+                              float leaf, int axis_bits, float* centroid, int32_t* count,
+                              int32_t* voxel, int64_t cap, int64_t* n_out, int32_t* status) {
+    hipStream_t st = ctx->stream;
+    const int64_t nb = grid_of(std::max<int64_t>(n, 1), VT);
+    size_t off = 0;
+    auto carve = [&](size_t b) {
+        const size_t o = off;
+        off += align256(b);
+        return o;
+    };
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    const size_t o_ka = carve(8 * nn), o_kb = carve(8 * nn), o_va = carve(4 * nn),
+                 o_vb = carve(4 * nn), o_cnt = carve(4 * sort_count_words(n)),
+                 o_fl = carve(4 * nn), o_tmp = carve(4 * (nn / 4096 + 2)),
+                 o_st = carve(4 * (nn + 1)), o_pp = carve(sizeof(VoxPart) * (size_t)nb);
+    lkc_status s;
+    char* b = (char*)aux_scratch(ctx, off, &s);
+    if (!b) return s;
+    auto* ka = (unsigned long long*)(b + o_ka);
+    auto* kb = (unsigned long long*)(b + o_kb);
+    auto* va = (uint32_t*)(b + o_va);
+    auto* vb = (uint32_t*)(b + o_vb);
+    auto* cnts = (uint32_t*)(b + o_cnt);
+    auto* flags = (uint32_t*)(b + o_fl);
+    auto* tmp = (uint32_t*)(b + o_tmp);
+    auto* starts = (uint32_t*)(b + o_st);
+    auto* parts = (VoxPart*)(b + o_pp);
+    VoxMeta* md = vox_meta_dev(ctx);
+    VoxAsyncArgs a{pts, n, origin[0], origin[1], origin[2], leaf, axis_bits, md, ka, va,
+                   flags, starts, centroid, count, voxel, cap, n_out, status};
+    // (n = 0: the bounds reduction still runs over no points and writes a
+    // zeroed meta, so the last launch reports 0 voxels and LKC_OK)
+    hipLaunchKernelGGL(k_vox_bounds, dim3((unsigned)nb), dim3(VT), 0, st, pts, n, origin[0],
+                       origin[1], origin[2], leaf, parts);
+    hipLaunchKernelGGL(k_vox_bounds_final, dim3(1), dim3(1024), 0, st, (const VoxPart*)parts,
+                       (int)nb, md);
+    const unsigned long long left_out = 1ull << (3 * axis_bits);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_vox_keys_async, dim3((unsigned)nb), dim3(VT), 0, st, a);
+        bool in_b = false;
+        s = sort_pairs(ctx, ka, va, kb, vb, n, 3 * axis_bits + 1, cnts, &in_b);
+        if (s != LKC_OK) return s;
+        a.keys = in_b ? kb : ka;
+        a.vals = in_b ? vb : va;
+        hipLaunchKernelGGL(k_vox_flags_async, dim3((unsigned)nb), dim3(VT), 0, st,
+                           (const unsigned long long*)a.keys, n, left_out, flags);
+        scan_words(st, flags, n, tmp);
+        hipLaunchKernelGGL(k_vox_starts_async, dim3((unsigned)nb), dim3(VT), 0, st,
+                           (const unsigned long long*)a.keys, (const uint32_t*)flags, n, left_out,
+                           starts, md);
+    }
+    hipLaunchKernelGGL(k_vox_reduce_async, dim3((unsigned)nb), dim3(VT), 0, st, a);
     LKC_HIP_TRY(ctx, hipGetLastError());
     return LKC_OK;
 }

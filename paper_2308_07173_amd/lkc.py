@@ -48,7 +48,7 @@ EXPORTED_SYMBOLS = (
     "lkc_submap_extract", "lkc_submap_build", "lkc_zvote", "lkc_euclid_cluster",
     "lkc_target_status", "lkc_autotune", "lkc_knn_cov_noalloc", "lkc_raceline_build",
     "lkc_raceline_free", "lkc_raceline_get_info", "lkc_raceline_bins", "lkc_submap_window",
-    "lkc_submap_window_build",
+    "lkc_submap_window_build", "lkc_voxel_filter_async",
 )
 
 # window statuses (info[2] of lkc_submap_window)
@@ -174,6 +174,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                 ctypes.POINTER(GicpStats), P], I32),
             "lkc_voxel_filter": ([P, P, I64, P, F, P, P, P, I64, ctypes.POINTER(ctypes.c_int64)],
                                  I32),
+            "lkc_voxel_filter_async": ([P, P, I64, P, F, I32, P, P, P, I64, P, P], I32),
             "lkc_submap_extract": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64)], I32),
             "lkc_submap_build": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64), PP], I32),
             "lkc_zvote": ([P, P, I64, F, I32, P, P], I32),
@@ -593,6 +594,36 @@ def lkc_voxel_filter(ctx: Context, points, leaf: float, origin=None, capacity=No
         ctypes.byref(m)))
     k = m.value
     return dict(centroid=cen[:k], count=cnt[:k], voxel=vox[:k])
+
+
+def lkc_voxel_filter_async(ctx: Context, points, leaf: float, axis_bits: int, origin=None,
+                           capacity=None, out: Optional[Dict] = None):
+    """lkc_voxel_filter with no host wait: dict of device tensors centroid
+    [capacity, 3], count [capacity], voxel [capacity, 3], n_out int64 [1]
+    and status int32 [1] (rows past n_out are untouched).  Pass `out` (a
+    dict from an earlier call of the same capacity) to reuse its tensors,
+    e.g. in a captured graph."""
+    import numpy as np
+    torch = _torch()
+    _check_dev(points, "points", torch.float32, (3,))
+    n = points.shape[0]
+    dev = points.device
+    if out is None:
+        cap = n if capacity is None else int(capacity)
+        out = dict(centroid=torch.empty(max(cap, 1), 3, dtype=torch.float32, device=dev),
+                   count=torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                   voxel=torch.empty(max(cap, 1), 3, dtype=torch.int32, device=dev),
+                   n_out=torch.zeros(1, dtype=torch.int64, device=dev),
+                   status=torch.zeros(1, dtype=torch.int32, device=dev), capacity=cap)
+    o = None if origin is None else np.ascontiguousarray(origin, np.float32)
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_voxel_filter_async(
+        ctx.handle, ctypes.c_void_p(_ptr(points)), n,
+        None if o is None else o.ctypes.data_as(ctypes.c_void_p), float(leaf), int(axis_bits),
+        ctypes.c_void_p(_ptr(out["centroid"])), ctypes.c_void_p(_ptr(out["count"])),
+        ctypes.c_void_p(_ptr(out["voxel"])), int(out["capacity"]),
+        ctypes.c_void_p(_ptr(out["n_out"])), ctypes.c_void_p(_ptr(out["status"]))))
+    return out
 
 
 def lkc_submap_extract(ctx: Context, target: Target, center, radius: float, capacity=None):

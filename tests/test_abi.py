@@ -73,6 +73,8 @@ def test_raceline_and_async_calls_reject_null_arguments(lib):
     assert lib.lkc_submap_window_build(None, None, None, 1.0, None, 0, None,
                                        None) == lkc.LKC_ERR_INVALID_ARG
     assert lib.lkc_raceline_free(None, None) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_voxel_filter_async(None, None, 0, None, 0.5, 4, None, None, None, 0, None,
+                                      None) == lkc.LKC_ERR_INVALID_ARG
 
 
 def test_struct_layouts():

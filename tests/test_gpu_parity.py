@@ -697,3 +697,42 @@ def test_batched_equals_per_scan_bitwise(lk, map_c3):
     tset.free()
     tm.free()
     ts.free()
+
+
+def test_batched_many_tiny_scans(lk, map_c3):
+    """Hundreds of scans of 0 to 3 queries over three targets: a query's
+    target is found from its workgroup's first scan by stepping over the
+    scans between (many per workgroup here); every row against the oracle."""
+    lkc, ctx = lk
+    m, s = map_c3
+    rng = np.random.default_rng(41)
+    clouds = [s[:20000], workloads.plane_wall(3000, seed=4), workloads.random_cloud(500, 7, scale=2.0)]
+    targets = [lkc.lkc_build_target(ctx, dev(c), cell) for c, cell in zip(clouds, (1.0, 0.5, 0.3))]
+    scans, parts, off = [], [], 0
+    for i in range(700):
+        ti = int(rng.integers(3))
+        n = int(rng.integers(0, 4))
+        src = clouds[ti]
+        part = src[rng.integers(0, src.shape[0], n)] + rng.normal(0, 0.05, (n, 3))
+        parts.append(np.ascontiguousarray(part, np.float32).reshape(-1, 3))
+        scans.append((off, n, ti))
+        off += n
+    allq = np.concatenate(parts)
+    tset = lkc.TargetSet(ctx, targets, max_scans=len(scans))
+    tset.stage(scans)
+    got = lkc.lkc_knn_cov_batched(ctx, tset, dev(allq), 8, 1.5, 1e-3)
+    torch.cuda.synchronize()
+    g = {k: host(v) for k, v in got.items()}
+    for ti in range(3):
+        # every row of the scans against target ti, checked together
+        sel = np.concatenate([np.arange(o, o + n) for o, n, t in scans if t == ti and n] or
+                             [np.zeros(0, np.int64)])
+        if sel.size == 0:
+            continue
+        q = allq[sel]
+        parity.check_knn(clouds[ti], q, 8, 1.5, g["idx"][sel], g["d2"][sel], g["count"][sel])
+        parity.check_cov(clouds[ti], g["idx"][sel], g["count"][sel], g["mean"][sel],
+                         g["cov"][sel], g["reg"][sel], g["valid"][sel], search=(q, 8, 1.5))
+    tset.free()
+    for t in targets:
+        t.free()

@@ -137,3 +137,96 @@ def test_submap_build_queries_like_the_window(lk):
     parity.check_knn(w, q, 10, 1.0, i.cpu().numpy(), d2.cpu().numpy(), cnt.cpu().numpy())
     sub.free()
     t.free()
+
+
+# ------------------------------------------------ voxel filter, no host wait --
+
+def async_rows(out):
+    """The rows the call wrote, after checking its status is LKC_OK."""
+    torch.cuda.synchronize()
+    assert int(out["status"].item()) == 0
+    k = int(out["n_out"].item())
+    return {"centroid": out["centroid"][:k], "count": out["count"][:k], "voxel": out["voxel"][:k]}
+
+
+@pytest.mark.parametrize("n,leaf,seed,bits", [(1, 0.5, 0, 1), (777, 0.25, 1, 8),
+                                              (100_003, 0.2, 2, 8), (300_000, 1.0, 3, 5)])
+def test_voxel_filter_async_random(lk, n, leaf, seed, bits):
+    """Against the oracle, and bit for bit against the synchronising call."""
+    lkc, ctx = lk
+    p = workloads.random_cloud(n, seed, scale=15.0, offset=(120.0, -40.0, 3.0))
+    got = async_rows(lkc.lkc_voxel_filter_async(ctx, dev(p), leaf, bits))
+    check_voxels(p, leaf, None, got)
+    ref = lkc.lkc_voxel_filter(ctx, dev(p), leaf)
+    for k in ref:
+        assert torch.equal(ref[k], got[k]), k
+
+
+def test_voxel_filter_async_scan_and_lattice(lk):
+    lkc, ctx = lk
+    p = workloads.single_scan(seed=5).copy()
+    p[::101, 2] = np.inf
+    p[::103, 0] = np.nan
+    origin = (0.05, -0.1, 0.02)
+    check_voxels(p, 0.2, origin,
+                 async_rows(lkc.lkc_voxel_filter_async(ctx, dev(p), 0.2, 11, origin=origin)))
+    g = np.arange(-20, 20, dtype=np.float32) * np.float32(0.25)
+    x = np.concatenate([g, np.nextafter(g, np.float32(-np.inf))])
+    q = np.stack(np.meshgrid(x, x[:17], x[:9], indexing="ij"), -1).reshape(-1, 3)
+    check_voxels(q, 0.25, None, async_rows(lkc.lkc_voxel_filter_async(ctx, dev(q), 0.25, 6)))
+
+
+def test_voxel_filter_async_statuses(lk):
+    """Errors found on the device come back as the status word, with
+    nothing written to the outputs; the host still rejects bad arguments."""
+    lkc, ctx = lk
+    p = workloads.random_cloud(5000, 6, scale=3.0)          # 12 voxels per axis at 0.5
+    n_vox = oracle.voxel_filter(p, 0.5)["count"].shape[0]
+
+    def run(pts, leaf, bits, cap):
+        out = lkc.lkc_voxel_filter_async(ctx, dev(pts), leaf, bits, capacity=cap)
+        out["centroid"].fill_(-7.0)
+        out["count"].fill_(-7)
+        out = lkc.lkc_voxel_filter_async(ctx, dev(pts), leaf, bits, out=out)
+        torch.cuda.synchronize()
+        return int(out["status"].item()), int(out["n_out"].item()), out
+
+    st, k, out = run(p, 0.5, 4, n_vox - 1)                  # over capacity
+    assert st == lkc.LKC_ERR_BUDGET and k == n_vox
+    assert bool((out["centroid"] == -7.0).all()) and bool((out["count"] == -7).all())
+    st, k, out = run(p, 0.5, 3, n_vox)                      # 12 voxels need 4 bits
+    assert st == lkc.LKC_ERR_BUDGET and k == 0 and bool((out["count"] == -7).all())
+    st, k, out = run(p * np.float32(1e6), 0.01, 21, 5000)   # voxel out of range
+    assert st == lkc.LKC_ERR_INVALID_ARG and k == 0 and bool((out["count"] == -7).all())
+    st, k, _ = run(np.full((10, 3), np.nan, np.float32), 0.5, 4, 10)
+    assert st == 0 and k == 0
+    st, k, out = run(p, 0.5, 4, n_vox)
+    assert st == 0 and k == n_vox
+    check_voxels(p, 0.5, None, async_rows(out))
+    empty = lkc.lkc_voxel_filter_async(ctx, dev(np.zeros((0, 3), np.float32)), 0.5, 4, capacity=4)
+    torch.cuda.synchronize()
+    assert int(empty["status"].item()) == 0 and int(empty["n_out"].item()) == 0
+    for leaf, bits in [(0.0, 4), (0.5, 0), (0.5, 22)]:
+        with pytest.raises(lkc.LkcError):
+            lkc.lkc_voxel_filter_async(ctx, dev(p), leaf, bits)
+
+
+def test_voxel_filter_async_replayed_from_a_graph(lk):
+    """Captured once, replayed on new clouds written into the same buffer:
+    every replay equals the oracle."""
+    lkc, ctx = lk
+    n = 40_000
+    clouds = [workloads.random_cloud(n, s, scale=12.0, offset=(30.0, 5.0, 0.0))
+              for s in (81, 82, 83)]
+    clouds[2][::97] = np.nan
+    buf = dev(clouds[0])
+    out = lkc.lkc_voxel_filter_async(ctx, buf, 0.3, 7)    # sizes the scratch outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        lkc.lkc_voxel_filter_async(ctx, buf, 0.3, 7, out=out)
+    for p in clouds[1:] + clouds:
+        buf.copy_(torch.from_numpy(p))
+        g.replay()
+        check_voxels(p, 0.3, None, async_rows(out))
+    del g
