@@ -24,7 +24,7 @@
  *                       the map points within a radius of a pose
  *   lkc_raceline_build / lkc_submap_window / lkc_submap_window_build
  *                       race-line keyed map parts and the sliding window
- *   lkc_zvote / lkc_euclid_cluster
+ *   lkc_zvote / lkc_euclid_cluster / lkc_euclid_cluster_async
  *                       vertical-feature filter and distance clustering
  *   lkc_knn_cov_batched many scans against several targets in one persistent
  *                       launch (graph-capturable)
@@ -520,6 +520,28 @@ lkc_status lkc_zvote(lkc_ctx *ctx, const float *points, int64_t n, float cell, i
  * Synchronises. */
 lkc_status lkc_euclid_cluster(lkc_ctx *ctx, const float *points, int64_t n, float eps,
                               const uint8_t *mask, int32_t *labels, int64_t *n_clusters);
+
+/* The same clustering with no host wait, for a per-frame pipeline on a
+ * stream or in a captured graph: the labels of lkc_euclid_cluster, with the
+ * number of components and the call's status in device memory
+ * (n_clusters device int64 [1], status device int32 [1]).  The context's
+ * grid is rebuilt on the device over every point (the mask applies to the
+ * joins and the labels), so every point must be finite, kept or not.  The
+ * first call on a context, a call with a new eps and a call with more
+ * points than any before build the grid synchronously (once; then call it
+ * outside a capture); later calls enqueue device work only, the grid's key
+ * laid out in as many sort passes as the last synchronous build took.
+ * Status LKC_OK; LKC_ERR_NONFINITE (a non-finite point),
+ * LKC_ERR_UNSUPPORTED (the cloud's grid key needs more sort passes than
+ * that layout: one lkc_euclid_cluster call lays it out afresh),
+ * LKC_ERR_INVALID_ARG (eps below the cloud's extent / 2^20) or LKC_ERR_HIP
+ * (join retries exhausted); labels and *n_clusters (0) are meaningless on an
+ * error status.  A build error found on the host is returned as usual.
+ * Scratch: the context's grow-only auxiliary buffer (growing it
+ * synchronises). */
+lkc_status lkc_euclid_cluster_async(lkc_ctx *ctx, const float *points, int64_t n, float eps,
+                                    const uint8_t *mask, int32_t *labels, int64_t *n_clusters,
+                                    int32_t *status);
 
 /* A set of targets addressable by the batched call.  Creating a set uploads
  * one small descriptor per target and sizes the set's scan table for at

@@ -577,6 +577,22 @@ lkc_status lkc_euclid_cluster(lkc_ctx* ctx, const float* points, int64_t n, floa
     return lkc::euclid_cluster(ctx, points, n, eps, mask, labels, n_clusters);
 }
 
+lkc_status lkc_euclid_cluster_async(lkc_ctx* ctx, const float* points, int64_t n, float eps,
+                                    const uint8_t* mask, int32_t* labels, int64_t* n_clusters,
+                                    int32_t* status) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (!n_clusters || !status)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n_clusters or status is NULL");
+    if (n < 0 || n > 0x7ffffffeLL)
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "n = %lld outside [0, 2^31 - 2]", (long long)n);
+    if (!(eps > 0.0f) || !std::isfinite(eps * eps) || !std::isfinite(1.0f / (1.25f * eps)))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "eps must be finite and > 0");
+    if (n > 0 && (!points || !labels))
+        return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL points or labels pointer");
+    return lkc::euclid_cluster_async(ctx, points, n, eps, mask, labels, n_clusters, status);
+}
+
 lkc_status lkc_target_set_create(lkc_ctx* ctx, const lkc_target* const* targets,
                                  int32_t n_targets, int32_t max_scans, lkc_target_set** out) {
     lkc_status s = check_ctx(ctx);

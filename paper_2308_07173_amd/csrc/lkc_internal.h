@@ -149,6 +149,9 @@ lkc_status build_into(lkc_ctx* ctx, lkc_target* t, const float* points, int64_t 
 // Synchronises `ctx`'s stream (the _device variant: the whole device).
 lkc_status refresh_host_view(lkc_ctx* ctx, lkc_target* t);
 lkc_status refresh_host_view_device(lkc_target* t);
+// byte offset of the status words {lkc_status, key bits, BAD_* bits} that a
+// build on the device writes after the target's device view
+size_t view_status_offset();
 void free_target_memory(lkc_target* t);
 size_t sort_count_words(int64_t n);
 // stable LSD radix sort of (key, val) pairs on the low `bits` key bits;
@@ -183,6 +186,9 @@ lkc_status launch_window(lkc_ctx* ctx, const lkc_raceline* rl, const float* pose
                          int32_t* idx, float* pts, int64_t cap, int64_t* info);
 
 // implemented in walls.hip
+lkc_status euclid_cluster_async(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
+                                const uint8_t* mask, int32_t* labels, int64_t* n_clusters,
+                                int32_t* status);
 lkc_status zvote(lkc_ctx* ctx, const float* pts, int64_t n, float g, int32_t tau,
                  uint8_t* keep, int32_t* votes);
 lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,

@@ -165,14 +165,18 @@ __global__ void k_parent_init(int32_t* __restrict__ par, int64_t n) {
 
 // One thread per reordered point: join it with every point of the 27
 // surrounding cells that has a smaller original index and lies within eps.
+// With `mask` (the grid then holds every point, indexed by original index)
+// only kept points join.
 __global__ void __launch_bounds__(WT) k_cluster_union(const TargetView* __restrict__ Tp,
-                                                      float e2, int32_t* __restrict__ par,
+                                                      float e2, const uint8_t* __restrict__ mask,
+                                                      int32_t* __restrict__ par,
                                                       UvMeta* __restrict__ m) {
     const TargetView T = load_uniform(Tp);
     const int64_t s = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * WT + threadIdx.x;
     if (s >= T.n) return;
     const float4 p = T.pts[s];
     const int32_t i = __float_as_int(p.w);
+    if (mask && !mask[i]) return;
     const int cx = cell_coord(p.x, T.inv_cell), cy = cell_coord(p.y, T.inv_cell),
               cz = cell_coord(p.z, T.inv_cell);
     for (int dz = -1; dz <= 1; ++dz)
@@ -187,7 +191,7 @@ __global__ void __launch_bounds__(WT) k_cluster_union(const TargetView* __restri
                 for (uint32_t t = st; t < st + cn; ++t) {
                     const float4 q = T.pts[t];
                     const int32_t j = __float_as_int(q.w);
-                    if (j < i && dist2(p.x, p.y, p.z, q.x, q.y, q.z) <= e2)
+                    if (j < i && (!mask || mask[j]) && dist2(p.x, p.y, p.z, q.x, q.y, q.z) <= e2)
                         uf_union(par, i, j, m);
                 }
             }
@@ -232,10 +236,13 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
 __global__ void __launch_bounds__(WT) k_cluster_labels(int32_t* __restrict__ par, int64_t n,
                                                        const int32_t* __restrict__ cidx,
                                                        int32_t* __restrict__ label,
-                                                       UvMeta* __restrict__ m) {
+                                                       UvMeta* __restrict__ m,
+                                                       const uint8_t* __restrict__ mask) {
     const int64_t i = (int64_t)blockIdx.x * WT + threadIdx.x;
     bool root = false;
-    if (i < n) {
+    if (i < n && mask && !mask[i]) {
+        label[i] = -1;   // (uncompacted masked call: a point left out)
+    } else if (i < n) {
         int32_t x = (int32_t)i;
         while (par[x] != x) x = par[x];
         if (cidx)
@@ -246,6 +253,24 @@ __global__ void __launch_bounds__(WT) k_cluster_labels(int32_t* __restrict__ par
     }
     const unsigned long long b = ballot(root);
     if (threadIdx.x % WAVE == 0 && b) atomicAdd(&m->n_clusters, (uint32_t)__popcll(b));
+}
+
+// The status of a clustering with no host wait (one thread): the grid
+// rebuild's (build_status, when the rebuild ran on the device), then the
+// cell range of the grid, then the join retries.
+__global__ void k_cluster_status(const TargetView* __restrict__ Tp,
+                                 const int32_t* __restrict__ build_status,
+                                 const UvMeta* __restrict__ m, int64_t* __restrict__ n_clusters,
+                                 int32_t* __restrict__ status) {
+    if (threadIdx.x != 0) return;
+    int32_t st = build_status ? build_status[0] : (int32_t)LKC_OK;
+    if (st == (int32_t)LKC_OK && Tp) {
+        const TargetView T = *Tp;
+        if (!(T.max_abs * T.inv_cell < (float)((1 << 20) - 4))) st = (int32_t)LKC_ERR_INVALID_ARG;
+    }
+    if (st == (int32_t)LKC_OK && m->spins) st = (int32_t)LKC_ERR_HIP;
+    *status = st;
+    *n_clusters = st == (int32_t)LKC_OK ? (int64_t)m->n_clusters : 0;
 }
 
 UvMeta* uv_meta_dev(lkc_ctx* ctx) { return (UvMeta*)((char*)ctx->meta_dev + 192); }
@@ -330,9 +355,10 @@ lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
     if (s == LKC_OK) {
         hipLaunchKernelGGL(k_parent_init, dim3(grid_of(m, WT)), dim3(WT), 0, st, par, m);
         hipLaunchKernelGGL(k_cluster_union, dim3(grid_of(m, WT)), dim3(WT), 0, st,
-                           (const TargetView*)grid.view_dev, eps * eps, par, md);
+                           (const TargetView*)grid.view_dev, eps * eps, (const uint8_t*)nullptr,
+                           par, md);
         hipLaunchKernelGGL(k_cluster_labels, dim3(grid_of(m, WT)), dim3(WT), 0, st, par, m,
-                           cidx, labels, md);
+                           cidx, labels, md, (const uint8_t*)nullptr);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(mh, md, sizeof(UvMeta), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -346,6 +372,52 @@ lkc_status euclid_cluster(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
         }
     }
     return s;
+}
+
+lkc_status euclid_cluster_async(lkc_ctx* ctx, const float* pts, int64_t n, float eps,
+                                const uint8_t* mask, int32_t* labels, int64_t* n_clusters,
+                                int32_t* status) {
+    hipStream_t st = ctx->stream;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_uv_init, dim3(1), dim3(64), 0, st, uv_meta_dev(ctx));
+        hipLaunchKernelGGL(k_cluster_status, dim3(1), dim3(64), 0, st, (const TargetView*)nullptr,
+                           (const int32_t*)nullptr, (const UvMeta*)uv_meta_dev(ctx), n_clusters,
+                           status);
+        LKC_HIP_TRY(ctx, hipGetLastError());
+        return LKC_OK;
+    }
+    if (!ctx->cluster_grid) {
+        ctx->cluster_grid = new (std::nothrow) lkc_target();
+        if (!ctx->cluster_grid) return set_error(ctx, LKC_ERR_OOM, "host allocation");
+    }
+    lkc_status s;
+    auto* par = (int32_t*)aux_scratch(ctx, 4 * (size_t)n, &s);
+    if (!par) return s;
+    UvMeta* md = uv_meta_dev(ctx);
+    hipLaunchKernelGGL(k_uv_init, dim3(1), dim3(64), 0, st, md);
+    // The grid over every point (the mask applies in the joins and labels,
+    // so no count comes back); a new cell size lays the key out afresh,
+    // with one synchronous build.
+    lkc_target& grid = *ctx->cluster_grid;
+    const float cell = 1.25f * eps;
+    if (grid.cell_size != cell) grid.sort_passes = 0;
+    grid.cell_size = cell;
+    s = build_into(ctx, &grid, pts, n, true);
+    if (s != LKC_OK) return s;
+    // the rebuild ran on the device (its status there) or on the host (and succeeded)
+    const int32_t* bst =
+        grid.host_stale ? (const int32_t*)((const char*)grid.view_dev + view_status_offset())
+                        : nullptr;
+    hipLaunchKernelGGL(k_parent_init, dim3(grid_of(n, WT)), dim3(WT), 0, st, par, n);
+    hipLaunchKernelGGL(k_cluster_union, dim3(grid_of(n, WT)), dim3(WT), 0, st,
+                       (const TargetView*)grid.view_dev, eps * eps, mask, par, md);
+    hipLaunchKernelGGL(k_cluster_labels, dim3(grid_of(n, WT)), dim3(WT), 0, st, par, n,
+                       (const int32_t*)nullptr, labels, md, mask);
+    hipLaunchKernelGGL(k_cluster_status, dim3(1), dim3(64), 0, st,
+                       (const TargetView*)grid.view_dev, bst, (const UvMeta*)md, n_clusters,
+                       status);
+    LKC_HIP_TRY(ctx, hipGetLastError());
+    return LKC_OK;
 }
 
 }  // namespace lkc

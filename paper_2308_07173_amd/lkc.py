@@ -48,7 +48,7 @@ EXPORTED_SYMBOLS = (
     "lkc_submap_extract", "lkc_submap_build", "lkc_zvote", "lkc_euclid_cluster",
     "lkc_target_status", "lkc_autotune", "lkc_knn_cov_noalloc", "lkc_raceline_build",
     "lkc_raceline_free", "lkc_raceline_get_info", "lkc_raceline_bins", "lkc_submap_window",
-    "lkc_submap_window_build", "lkc_voxel_filter_async",
+    "lkc_submap_window_build", "lkc_voxel_filter_async", "lkc_euclid_cluster_async",
 )
 
 # window statuses (info[2] of lkc_submap_window)
@@ -175,6 +175,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_voxel_filter": ([P, P, I64, P, F, P, P, P, I64, ctypes.POINTER(ctypes.c_int64)],
                                  I32),
             "lkc_voxel_filter_async": ([P, P, I64, P, F, I32, P, P, P, I64, P, P], I32),
+            "lkc_euclid_cluster_async": ([P, P, I64, F, P, P, P, P], I32),
             "lkc_submap_extract": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64)], I32),
             "lkc_submap_build": ([P, P, P, F, P, I64, ctypes.POINTER(ctypes.c_int64), PP], I32),
             "lkc_zvote": ([P, P, I64, F, I32, P, P], I32),
@@ -804,6 +805,30 @@ def lkc_euclid_cluster(ctx: Context, points, eps: float, mask=None):
                                          float(eps), ctypes.c_void_p(_ptr(mask)),
                                          ctypes.c_void_p(_ptr(labels)), ctypes.byref(k)))
     return labels, k.value
+
+
+def lkc_euclid_cluster_async(ctx: Context, points, eps: float, mask=None,
+                             out: Optional[Dict] = None):
+    """lkc_euclid_cluster with no host wait: dict of device tensors labels
+    int32 [n], n_clusters int64 [1], status int32 [1].  Pass `out` (from an
+    earlier call on as many points) to reuse its tensors, e.g. in a
+    captured graph."""
+    torch = _torch()
+    _check_dev(points, "points", torch.float32, (3,))
+    _check_dev(mask, "mask", torch.uint8)
+    n = points.shape[0]
+    if mask is not None and mask.shape[0] != n:
+        raise ValueError("mask must have one entry per point")
+    if out is None:
+        out = dict(labels=torch.empty(n, dtype=torch.int32, device=points.device),
+                   n_clusters=torch.zeros(1, dtype=torch.int64, device=points.device),
+                   status=torch.zeros(1, dtype=torch.int32, device=points.device))
+    ctx._bind()
+    ctx.check(ctx.lib.lkc_euclid_cluster_async(
+        ctx.handle, ctypes.c_void_p(_ptr(points)), n, float(eps), ctypes.c_void_p(_ptr(mask)),
+        ctypes.c_void_p(_ptr(out["labels"])), ctypes.c_void_p(_ptr(out["n_clusters"])),
+        ctypes.c_void_p(_ptr(out["status"]))))
+    return out
 
 
 def lkc_knn_cov_self(ctx: Context, target: Target, k: int, radius: float = math.inf,

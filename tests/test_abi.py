@@ -75,6 +75,8 @@ def test_raceline_and_async_calls_reject_null_arguments(lib):
     assert lib.lkc_raceline_free(None, None) == lkc.LKC_ERR_INVALID_ARG
     assert lib.lkc_voxel_filter_async(None, None, 0, None, 0.5, 4, None, None, None, 0, None,
                                       None) == lkc.LKC_ERR_INVALID_ARG
+    assert lib.lkc_euclid_cluster_async(None, None, 0, 0.5, None, None, None,
+                                        None) == lkc.LKC_ERR_INVALID_ARG
 
 
 def test_struct_layouts():

@@ -208,3 +208,96 @@ def test_cluster_errors_and_grid_reuse(lk):
         lkc.lkc_euclid_cluster(ctx, dev(p * np.float32(1e4)), 1e-3)   # eps below extent / 2^20
     with pytest.raises(lkc.LkcError):
         lkc.lkc_euclid_cluster(ctx, dev(p), 0.0)
+
+
+# ------------------------------------------------ clustering, no host wait --
+
+def async_labels(out):
+    torch.cuda.synchronize()
+    return (int(out["status"].item()), out["labels"].cpu().numpy(), int(out["n_clusters"].item()))
+
+
+@pytest.mark.parametrize("n,eps,seed", [(2_000, 0.4, 1), (15_000, 0.3, 2)])
+def test_cluster_async_equals_the_synchronous_call(lk, n, eps, seed):
+    """Twice (the second call rebuilds the grid on the device): the labels
+    and count of lkc_euclid_cluster, and the oracle's."""
+    lkc, ctx = lk
+    p = workloads.random_cloud(n, seed, scale=6.0, offset=(100.0, -50.0, 0.0))
+    ref, kref = lkc.lkc_euclid_cluster(ctx, dev(p), eps)
+    for _ in range(2):
+        st, lab, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(p), eps))
+        assert st == 0 and k == kref
+        np.testing.assert_array_equal(lab, ref.cpu().numpy())
+    parity.check_clusters(p, eps, lab, k)
+
+
+def test_cluster_async_masks(lk):
+    lkc, ctx = lk
+    p = workloads.random_cloud(4000, 8, scale=4.0)
+    mask = np.ones(4000, np.uint8)
+    mask[::50] = 0
+    mask[7::9] = 0
+    lkc.lkc_euclid_cluster_async(ctx, dev(p), 0.35)          # grid laid out (synchronous)
+    st, lab, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(p), 0.35, mask=dev(mask)))
+    assert st == 0
+    check_masked(p, mask, 0.35, lab, k)
+    ref, kref = lkc.lkc_euclid_cluster(ctx, dev(p), 0.35, mask=dev(mask))
+    np.testing.assert_array_equal(lab, ref.cpu().numpy())
+    assert k == kref
+    st, lab, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(p), 0.35,
+                                                           mask=dev(np.zeros(4000, np.uint8))))
+    assert st == 0 and k == 0 and np.all(lab == -1)
+    st, lab, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(p[:0]), 0.35))
+    assert st == 0 and k == 0
+
+
+def test_cluster_async_statuses(lk):
+    """Errors found on the device come back in the status word; a
+    synchronous call lays out a grid the cloud outgrew."""
+    lkc, ctx = lk
+    small = workloads.random_cloud(3000, 9, scale=2.0)
+    lkc.lkc_euclid_cluster_async(ctx, dev(small), 0.3)       # lays the grid out
+    bad = small.copy()
+    bad[17] = np.nan
+    st, _, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(bad), 0.3))
+    assert st == lkc.LKC_ERR_NONFINITE and k == 0
+    wide = workloads.random_cloud(3000, 10, scale=3000.0)    # its key needs more sort passes
+    st, _, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(wide), 0.3))
+    assert st == lkc.LKC_ERR_UNSUPPORTED and k == 0
+    ref, kref = lkc.lkc_euclid_cluster(ctx, dev(wide), 0.3)  # lays it out afresh
+    st, lab, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(wide), 0.3))
+    assert st == 0 and k == kref
+    np.testing.assert_array_equal(lab, ref.cpu().numpy())
+    lkc.lkc_euclid_cluster_async(ctx, dev(small), 0.02)      # lays the grid out at this eps
+    far = small.copy()
+    far[0] = (3.0e4, 0.0, 0.0)                               # eps below extent / 2^20
+    st, _, k = async_labels(lkc.lkc_euclid_cluster_async(ctx, dev(far), 0.02))
+    assert st == lkc.LKC_ERR_INVALID_ARG and k == 0
+    with pytest.raises(lkc.LkcError):                        # found by a synchronous build
+        lkc.lkc_euclid_cluster_async(ctx, dev(far), 0.021)
+    with pytest.raises(lkc.LkcError):
+        lkc.lkc_euclid_cluster_async(ctx, dev(small), 0.0)
+
+
+def test_cluster_async_replayed_from_a_graph(lk):
+    """Captured once, replayed on new clouds written into the same buffer
+    (with a mask): every replay equals the oracle."""
+    lkc, ctx = lk
+    n = 12_000
+    clouds = [workloads.random_cloud(n, s, scale=5.0) for s in (91, 92, 93)]
+    masks = [(np.random.default_rng(s).uniform(size=n) < 0.8).astype(np.uint8) for s in (1, 2, 3)]
+    buf, mbuf = dev(clouds[0]), dev(masks[0])
+    out = lkc.lkc_euclid_cluster_async(ctx, buf, 0.25, mask=mbuf)   # grid and scratch sized
+    lkc.lkc_euclid_cluster_async(ctx, buf, 0.25, mask=mbuf, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        lkc.lkc_euclid_cluster_async(ctx, buf, 0.25, mask=mbuf, out=out)
+    for p, m in list(zip(clouds, masks))[1:] + list(zip(clouds, masks)):
+        buf.copy_(torch.from_numpy(p))
+        mbuf.copy_(torch.from_numpy(m))
+        g.replay()
+        st, lab, k = async_labels(out)
+        assert st == 0
+        check_masked(p, m, 0.25, lab, k)
+    del g
