@@ -226,7 +226,46 @@ __device__ int knn_query_wave(const TargetView& T, float qx, float qy, float qz,
     int r0 = 0;
     for (int a = 0; a < 3; ++a) r0 = max(r0, max(T.cmin[a] - cq[a], cq[a] - T.cmax[a]));
     const float qabs = fmaxf(fabsf(qx), fmaxf(fabsf(qy), fabsf(qz)));
-    for (int R = r0; R <= rmax; ++R) {
+    int r_first = r0;
+    if (r0 == 0 && rmax >= 1) {
+        // The query's own cell and its first ring: their hash probes go out
+        // together (one chain of dependent loads rather than two); the own
+        // cell is streamed first and its k-th distance prunes the ring's
+        // cells, as when the rings are taken one at a time.
+        int lo[3], ext[3];
+        int total = 1;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = max(cq[a] - 1, T.cmin[a]);
+            ext[a] = max(min(cq[a] + 1, T.cmax[a]) - lo[a] + 1, 0);
+            total *= ext[a];
+        }
+        const float margin = (fmaxf(qabs, T.max_abs) + 3.0f * T.cell) * 1e-6f;
+        bool found = false, own = false;
+        uint32_t st = 0, cn = 0;
+        float bd = INF;
+        if (lane < total) {
+            const uint32_t t = (uint32_t)lane, e0 = (uint32_t)ext[0], e1 = (uint32_t)ext[1];
+            const uint32_t v = t / e0, w = v / e1;
+            const int cx = lo[0] + (int)(t - v * e0), cy = lo[1] + (int)(v - w * e1),
+                      cz = lo[2] + (int)w;
+            own = cx == cq[0] && cy == cq[1] && cz == cq[2];
+            bd = box_dist2(T, qx, qy, qz, cx, cy, cz, margin);
+            if (bd <= sp.r2) found = hash_find(T, pack_key(T, cx, cy, cz), st, cn) && cn > 0;
+        }
+        scan_cells(T, qx, qy, qz, sp, found && own, st, cn, L);
+        scan_cells(T, qx, qy, qz, sp, found && !own && bd * (1.0f - 1e-6f) <= L.thr_d, st, cn, L);
+        r_first = 2;
+        // the exact stop of ring 1 (the loop's, below)
+        float f = INF;
+        for (int a = 0; a < 3; ++a)
+            f = fminf(f, fminf(q[a] - (float)(cq[a] - 1) * T.cell, (float)(cq[a] + 2) * T.cell - q[a]));
+        f -= margin;
+        if (f > 0.0f) {
+            const float f2 = f * f * (1.0f - 1e-6f);
+            if ((sp.capped && f2 > sp.r2) || f2 > L.thr_d) r_first = rmax + 1;
+        }
+    }
+    for (int R = r_first; R <= rmax; ++R) {
         int lo[3], ext[3];
         int64_t total = 1;
         for (int a = 0; a < 3; ++a) {
