@@ -710,7 +710,7 @@ def main():
                           "it hands over (k_fallback)"}
         if not args.no_autotune and not args.cfg:
             from paper_2308_07173_amd import autotune
-            tune = autotune.autotune(m, allq, k, radius, sample=allq.shape[0], ctx=ctx)
+            tune = autotune.autotune(m, allq, k, radius, sample=allq.shape[0], reps=5, ctx=ctx)
             cell, cfg = tune["cell"], (tune["cfg"] or None)
             config["cell_m"] = cell
             config["autotune"] = {"cell_m": cell, "cfg": tune["cfg"], "sample": tune["sample"],

@@ -96,7 +96,7 @@ typedef enum lkc_status {
  *                   bit-identical results.
  *  group_reach      cells the group search looks beyond its queries' cells
  *                   (0 = auto: ceil(radius / cell) clamped to [1, 2]; 1..4)
- *  waves_per_block  wavefronts per workgroup (0 = 4; 1..4)
+ *  waves_per_block  wavefronts per workgroup (0 = 2; 1..4)
  *  merge_min        the wavefront search merges a candidate batch with at
  *                   least this many entries below the k-th distance by a
  *                   bitonic network instead of one insertion per entry

@@ -19,11 +19,11 @@ import numpy as np
 
 DEFAULT_CELLS = (0.5, 0.75, 1.0, 1.5, 2.0)
 DEFAULT_CFGS = (
-    dict(),                                   # group search, reach auto, 4 waves/WG
+    dict(),                                   # group search, reach auto, 2 waves/WG
     dict(group_reach=1),
-    dict(waves_per_block=2),
+    dict(waves_per_block=4),
     dict(waves_per_block=1),
-    dict(persistent=4),
+    dict(persistent=4, waves_per_block=4),
     dict(persistent=8, waves_per_block=2),
     dict(algorithm=2),                        # one wavefront per query (small launches)
 )

@@ -25,11 +25,11 @@ const float kDefaultCells[] = {0.5f, 0.75f, 1.0f, 1.5f, 2.0f};
 
 // algorithm, group_reach, waves_per_block, merge_min, persistent, group_split
 const lkc_launch_cfg kDefaultCfgs[] = {
-    {0, 0, 0, 0, 0, 0},  // group search, reach auto, 4 waves per workgroup
+    {0, 0, 0, 0, 0, 0},  // group search, reach auto, 2 waves per workgroup
     {0, 1, 0, 0, 0, 0},
-    {0, 0, 2, 0, 0, 0},
+    {0, 0, 4, 0, 0, 0},
     {0, 0, 1, 0, 0, 0},
-    {0, 0, 0, 0, 4, 0},
+    {0, 0, 4, 0, 4, 0},
     {0, 0, 2, 0, 8, 0},
     {2, 0, 0, 0, 0, 0},  // one wavefront per query (small launches)
 };

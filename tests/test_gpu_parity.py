@@ -400,6 +400,7 @@ def test_knn_bad_arguments_raise(lk):
 @pytest.mark.parametrize("cfg", [dict(algorithm=2), dict(algorithm=2, merge_min=65),
                                  dict(algorithm=2, merge_min=1, waves_per_block=1),
                                  dict(group_reach=1), dict(group_reach=3, waves_per_block=2),
+                                 dict(waves_per_block=4), dict(group_split=1, waves_per_block=4),
                                  dict(persistent=2), dict(persistent=1, waves_per_block=2),
                                  dict(group_split=1), dict(group_split=2), dict(group_split=4),
                                  dict(group_split=2, group_reach=1)])

@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 CFGS = [dict(), dict(group_split=1), dict(group_split=2), dict(group_split=4),
-        dict(group_reach=1), dict(group_reach=3), dict(group_reach=4, waves_per_block=2),
+        dict(group_reach=1), dict(group_reach=3), dict(group_reach=4, waves_per_block=4),
+        dict(waves_per_block=4), dict(group_split=1, waves_per_block=1),
         dict(persistent=1), dict(persistent=8, waves_per_block=2),
         dict(persistent=3, waves_per_block=1), dict(algorithm=2), dict(algorithm=2, merge_min=1),
         dict(algorithm=2, merge_min=65), dict(algorithm=1)]
