@@ -267,7 +267,6 @@ struct VoxAsyncArgs {
     VoxMeta* meta;          // bounds (k_vox_bounds_final), n_vox, over
     unsigned long long* keys;
     uint32_t* vals;
-    const uint32_t* offs;   // scanned run flags
     uint32_t* starts;
     float* centroid;
     int32_t* count;
@@ -537,7 +536,7 @@ lkc_status voxel_filter_async(lkc_ctx* ctx, const float* pts, int64_t n, const f
     auto* parts = (VoxPart*)(b + o_pp);
     VoxMeta* md = vox_meta_dev(ctx);
     VoxAsyncArgs a{pts, n, origin[0], origin[1], origin[2], leaf, axis_bits, md, ka, va,
-                   flags, starts, centroid, count, voxel, cap, n_out, status};
+                   starts, centroid, count, voxel, cap, n_out, status};
     // (n = 0: the bounds reduction still runs over no points and writes a
     // zeroed meta, so the last launch reports 0 voxels and LKC_OK)
     hipLaunchKernelGGL(k_vox_bounds, dim3((unsigned)nb), dim3(VT), 0, st, pts, n, origin[0],
