@@ -98,7 +98,9 @@ def committed_traffic(workload: str):
 
 def committed_valu(workload: str):
     """VALU instructions (wavefront level) per search-kernel launch from the
-    committed PMC summary, under the same source check as the traffic."""
+    committed PMC summary, under the same source check as the traffic, with
+    the cell size and launch configuration they were counted at ({} = the
+    default configuration)."""
     path = os.path.join(ROOT, "profiles", f"pmc_search_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -106,7 +108,10 @@ def committed_valu(workload: str):
         d = json.load(fh)
     if d.get("kernel_src_sha") != kernel_src_sha():
         return None
-    return d.get("valu_insts_per_dispatch")
+    if d.get("valu_insts_per_dispatch") is None:
+        return None
+    return d["valu_insts_per_dispatch"], {"cell_m": d.get("valu_cell_m"),
+                                          "launch_cfg": d.get("valu_launch_cfg", {})}
 
 
 def copy_bandwidth(torch, dev, mib: int = 1024, reps: int = 10) -> float:
@@ -803,11 +808,18 @@ def main():
         pairs = 64 * gc["chunk_candidates"]    # each broadcast candidate meets 64 lanes
         cand = {"pairs_tested": pairs, "pairs_per_s": pairs / (group_ms * 1e-3),
                 "insertion_steps": gc["pops"], "lane_insertions": gc["lane_inserts"]}
-        vi = committed_valu(args.workload)
-        if vi is not None:
-            lane_ops = 64 * vi / (group_ms * 1e-3)
-            cand["valu"] = {"insts_per_launch": vi, "lane_ops_per_s": lane_ops,
-                            "peak": VALU_LANE_OPS_PEAK, "frac": lane_ops / VALU_LANE_OPS_PEAK}
+        cv = committed_valu(args.workload)
+        if cv is not None:
+            vi, counted_at = cv
+            cand["valu"] = {"insts_per_launch": vi, "counted_at": counted_at,
+                            "peak": VALU_LANE_OPS_PEAK}
+            # the count depends on the launch shape (reach and cell size change
+            # the walk), so a rate is given only for the shape it was counted at
+            if counted_at == {"cell_m": config.get("cell_m"), "launch_cfg": cfg or {}}:
+                lane_ops = 64 * vi / (group_ms * 1e-3)
+                cand["valu"].update(lane_ops_per_s=lane_ops, frac=lane_ops / VALU_LANE_OPS_PEAK)
+            else:
+                cand["valu"].update(lane_ops_per_s=None, frac=None)
         extra["group_search_work"] = cand
     if args.workload == "weighted":
         config["note"] = "roofline bytes as the plain path: the weights add no HBM traffic"
@@ -827,6 +839,8 @@ def main():
         "config": config,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_counted_at": ((committed_valu(args.workload) or (None, None))[1]
+                                            if traffic is not None else None),
                      "kernel": dom[0], "bytes_per_query": b_alg(k),
                      "queries_per_launch": int(dom[1]), "kernel_ms": dom[2],
                      "measured_peak": hbm_meas, "frac_of_measured": achieved / hbm_meas,
