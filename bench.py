@@ -512,6 +512,10 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, launch one plain device copy of this many MiB "
                          "(reference dispatch for HBM byte counters)")
+    ap.add_argument("--calib-gather-mib", type=int, default=0,
+                    help="after the run, launch one float4 row gather of this many MiB "
+                         "(rows read through a permutation inside every 64-row block): "
+                         "a second reference dispatch, for reads shaped like the searches'")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this path has no multi-GPU mode "
@@ -890,6 +894,24 @@ def main():
         torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         res["calib_copy_bytes"] = nb
+    if args.calib_gather_mib > 0:
+        # 16-byte rows gathered by the library's lkc_calib_gather through a
+        # uint32 index: each 64-row block is read in a shuffled order (one
+        # wavefront's rows, as the searches read a chunk's points), so
+        # every line fetched is used whole
+        rows = (args.calib_gather_mib << 20) // 16 // 64 * 64
+        g = torch.Generator().manual_seed(7)
+        blk = torch.arange(rows, dtype=torch.int64).view(-1, 64)
+        shuf = torch.argsort(torch.rand(blk.shape, generator=g), dim=1)
+        idx = torch.gather(blk, 1, shuf).reshape(-1).to(torch.int32).to(dev)
+        src4 = torch.ones(rows, 4, dtype=torch.float32, device=dev)
+        out4 = torch.empty_like(src4)
+        torch.cuda.synchronize()
+        ctx.calib_gather(src4, idx, out4)
+        ctx.synchronize()
+        assert bool((out4 == 1.0).all())
+        res["calib_gather"] = {"rows": rows, "bytes_read": rows * (16 + 4),
+                               "bytes_written": rows * 16}
     print(json.dumps(res))
     ctx.synchronize()
 

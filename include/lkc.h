@@ -608,6 +608,17 @@ lkc_status lkc_ctx_search_stats(lkc_ctx *ctx, lkc_search_stats *out);
  * events are not captured-graph safe, so keep timing off under capture. */
 lkc_status lkc_ctx_set_timing(lkc_ctx *ctx, int32_t on);
 
+/* Measurement aid, not part of the method: dst[i] = src[idx[i]] for i < n,
+ * one 16-byte row (four floats) per thread, on the context's stream, no
+ * synchronisation.  src holds n_src rows, idx n uint32 row numbers and dst
+ * n rows, all device memory the caller owns; a row number >= n_src gives a
+ * zero row.  Its algorithmic traffic is 20 bytes read and 16 written per
+ * row, a known reference for the HBM byte counters of gathers shaped like
+ * the searches' reads of a chunk's points.  LKC_ERR_INVALID_ARG for NULL
+ * pointers or negative sizes. */
+lkc_status lkc_calib_gather(lkc_ctx *ctx, const float *src, int64_t n_src, const uint32_t *idx,
+                            int64_t n, float *dst);
+
 /* Diagnostics: when `buffer` (device, 25 uint32 per group) holds at least
  * the number of 64-query groups of a search, the group search writes per
  * group: clock cycles, probe rounds, cells streamed, 64-point chunks

@@ -761,6 +761,33 @@ lkc_status lkc_ctx_set_timing(lkc_ctx* ctx, int32_t on) {
     return LKC_OK;
 }
 
+namespace {
+__global__ void __launch_bounds__(256) k_calib_gather(const float4* __restrict__ src,
+                                                      int64_t n_src,
+                                                      const uint32_t* __restrict__ idx, int64_t n,
+                                                      float4* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = idx[i];
+    dst[i] = (int64_t)j < n_src ? src[j] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+}  // namespace
+
+lkc_status lkc_calib_gather(lkc_ctx* ctx, const float* src, int64_t n_src, const uint32_t* idx,
+                            int64_t n, float* dst) {
+    lkc_status s = check_ctx(ctx);
+    if (s != LKC_OK) return s;
+    if (n < 0 || n_src < 0) return set_error(ctx, LKC_ERR_INVALID_ARG, "negative size");
+    if (n == 0) return LKC_OK;
+    if (!src || !idx || !dst) return set_error(ctx, LKC_ERR_INVALID_ARG, "NULL pointer");
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > INT32_MAX) return set_error(ctx, LKC_ERR_INVALID_ARG, "n too large");
+    hipLaunchKernelGGL(k_calib_gather, dim3((unsigned)blocks), dim3(256), 0, ctx->stream,
+                       (const float4*)src, n_src, idx, n, (float4*)dst);
+    LKC_HIP_TRY(ctx, hipGetLastError());
+    return LKC_OK;
+}
+
 lkc_status lkc_ctx_search_stats(lkc_ctx* ctx, lkc_search_stats* out) {
     lkc_status s = check_ctx(ctx);
     if (s != LKC_OK) return s;

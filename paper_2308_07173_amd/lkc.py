@@ -49,6 +49,7 @@ EXPORTED_SYMBOLS = (
     "lkc_target_status", "lkc_autotune", "lkc_knn_cov_noalloc", "lkc_raceline_build",
     "lkc_raceline_free", "lkc_raceline_get_info", "lkc_raceline_bins", "lkc_submap_window",
     "lkc_submap_window_build", "lkc_voxel_filter_async", "lkc_euclid_cluster_async",
+    "lkc_calib_gather",
 )
 
 # window statuses (info[2] of lkc_submap_window)
@@ -165,6 +166,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             "lkc_ctx_reserve": ([P, I64], I32),
             "lkc_ctx_search_stats": ([P, P], I32),
             "lkc_ctx_set_timing": ([P, I32], I32),
+            "lkc_calib_gather": ([P, P, I64, P, I64, P], I32),
             "lkc_ctx_set_profile": ([P, P, I64], I32),
             "lkc_covariances_weighted": ([P, P, P, P, P, I64, I32, I32, F, F, P, P, P, P], I32),
             "lkc_knn_cov_weighted": ([P, P, P, I64, I32, F, I32, F, F, P, P, P, P, P, P, P, P],
@@ -280,6 +282,15 @@ class Context:
 
     def set_timing(self, on: bool):
         self.check(self.lib.lkc_ctx_set_timing(self.handle, 1 if on else 0))
+
+    def calib_gather(self, src, idx, dst):
+        """dst[i] = src[idx[i]] over float32 [*, 4] rows (device tensors;
+        idx int32 holding row numbers), on the context's stream."""
+        self._bind()
+        assert src.dim() == 2 and src.shape[1] == 4 and dst.shape == (idx.shape[0], 4)
+        self.check(self.lib.lkc_calib_gather(
+            self.handle, ctypes.c_void_p(src.data_ptr()), src.shape[0],
+            ctypes.c_void_p(idx.data_ptr()), idx.shape[0], ctypes.c_void_p(dst.data_ptr())))
 
     def synchronize(self):
         self._bind()
