@@ -51,7 +51,12 @@ def run_knn(lk, target_np, queries_np, k, radius, cell, cfg=None):
 # ------------------------------------------------------------ grid build --
 
 @pytest.mark.parametrize("n,cell,seed", [(1, 1.0, 0), (777, 0.25, 1), (40_000, 0.5, 2),
-                                         (70_001, 3.0, 3)])
+                                         (70_001, 3.0, 3),
+                                         # the radix sort's modes change at these sizes:
+                                         # one 2,048-key tile, then up to 96 tiles whose
+                                         # offsets need no scan launch, then more
+                                         (2_048, 0.5, 4), (2_049, 0.5, 5),
+                                         (196_608, 1.0, 6), (196_609, 1.0, 7)])
 def test_build_cells_partition_points(lk, n, cell, seed):
     """Every point lies in exactly one cell run; the runs tile [0, n); each
     point's cell is the floor of its coordinates; within a cell the original
